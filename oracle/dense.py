@@ -1,0 +1,146 @@
+"""O(N^3) textbook GP (test infrastructure only; see the package header).
+
+This is the plain definition every faster route must reproduce:
+  K_f[i, j] = k(t_i - t_j),   K_y = K_f + s2 I        (eq. k2 with G K G^T = K_f)
+  logML = -1/2 y^T K_y^-1 y - 1/2 log det K_y - N/2 log 2 pi     (eq. ml2, n read as N)
+  mean  = K_f K_y^-1 y                                 (eq. mean2 at t* = t)
+  var_i = (K_f - K_f K_y^-1 K_f)_ii                    (diagonal of eq. k3: latent f, no s2)
+  dlogML/dtheta = 1/2 tr((a a^T - K_y^-1) dK_y/dtheta),  a = K_y^-1 y
+The state-level posterior (mean of z_n and the blocks Cov(z_n, z_n | y),
+Cov(z_{n+1}, z_n | y)) uses the stacked prior covariance of Sec. 2.1:
+Cov(z_i, z_j) = A[t_i - t_j] P0 for t_i >= t_j, conditioned on y by the same
+dense formulas.  `stacked_prior_cov` also builds the paper's  A Q A^T  product
+(eq. k1) so tests can check Theorem 1 directly.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+from .ssm import SumModel
+
+
+def gp_dense(model: SumModel, t, y, want_grad: bool = True) -> dict:
+    t = np.asarray(t, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = t.shape[0]
+    tau = t[:, None] - t[None, :]
+    Kf = model.kernel(tau)
+    Ky = Kf + model.noise * np.eye(n)
+    L = scipy.linalg.cholesky(Ky, lower=True)
+    alpha = scipy.linalg.cho_solve((L, True), y)
+    logdet = 2.0 * np.sum(np.log(np.diag(L)))
+    datafit = float(y @ alpha)
+    out = {
+        "logml": -0.5 * datafit - 0.5 * logdet - 0.5 * n * np.log(2.0 * np.pi),
+        "datafit": datafit,
+        "logdet": logdet,
+        "f_mean": Kf @ alpha,
+    }
+    V = scipy.linalg.solve_triangular(L, Kf, lower=True)
+    out["f_var"] = np.diag(Kf) - np.sum(V * V, axis=0)
+    if want_grad:
+        Kinv = scipy.linalg.cho_solve((L, True), np.eye(n))
+        W = np.outer(alpha, alpha) - Kinv
+        g = [0.5 * np.sum(W * dK) for dK in model.dkernel(tau)]
+        g.append(0.5 * np.trace(W))          # dK_y / d s2 = I
+        out["grad"] = np.array(g)
+    return out
+
+
+def stacked_prior_cov(model: SumModel, t) -> np.ndarray:
+    """Prior covariance of the stacked states [z_0; ...; z_{N-1}] (N b x N b)."""
+    t = np.asarray(t, dtype=np.float64)
+    n, b = t.shape[0], model.b
+    P = model.Pinf()
+    K = np.zeros((n * b, n * b))
+    for i in range(n):
+        for j in range(i + 1):
+            blk = model.A(t[i] - t[j]) @ P
+            K[i * b:(i + 1) * b, j * b:(j + 1) * b] = blk
+            K[j * b:(j + 1) * b, i * b:(i + 1) * b] = blk.T
+    return K
+
+
+def paper_AQA(model: SumModel, t):
+    """The factors of eq. k1: the block lower-triangular A, block-diagonal Q and A Q A^T."""
+    t = np.asarray(t, dtype=np.float64)
+    n, b = t.shape[0], model.b
+    Abig = np.zeros((n * b, n * b))
+    Qbig = np.zeros((n * b, n * b))
+    for i in range(n):
+        Abig[i * b:(i + 1) * b, i * b:(i + 1) * b] = np.eye(b)
+        for j in range(i):
+            Abig[i * b:(i + 1) * b, j * b:(j + 1) * b] = model.A(t[i] - t[j])
+        Qbig[i * b:(i + 1) * b, i * b:(i + 1) * b] = model.Pinf() if i == 0 else model.Q(t[i] - t[i - 1])
+    return Abig, Qbig, Abig @ Qbig @ Abig.T
+
+
+def state_posterior_dense(model: SumModel, t, y) -> dict:
+    """Dense posterior of the stacked states: means and the tridiagonal blocks of the covariance."""
+    t = np.asarray(t, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n, b = t.shape[0], model.b
+    K = stacked_prior_cov(model, t)
+    G = np.kron(np.eye(n), model.H()[None, :])
+    Ky = G @ K @ G.T + model.noise * np.eye(n)
+    KG = K @ G.T
+    sol = np.linalg.solve(Ky, np.column_stack([y, KG.T]))
+    mu = KG @ sol[:, 0]
+    S = K - KG @ sol[:, 1:]
+    S = 0.5 * (S + S.T)
+    z_mean = mu.reshape(n, b)
+    S_diag = np.stack([S[i * b:(i + 1) * b, i * b:(i + 1) * b] for i in range(n)])
+    S_sub = np.stack([S[(i + 1) * b:(i + 2) * b, i * b:(i + 1) * b] for i in range(n - 1)]) \
+        if n > 1 else np.zeros((0, b, b))
+    return {"z_mean": z_mean, "S_diag": S_diag, "S_sub": S_sub, "S_full": S}
+
+
+def gp_dense_mp(model: SumModel, t, y, dps: int = 50) -> dict:
+    """High-precision dense GP (mpmath) for small N: logML, mean and variance.
+
+    The closed-form kernel is evaluated in mpmath arithmetic from the float64
+    inputs, so the only rounding left is mpmath's own at `dps` digits.
+    """
+    import mpmath as mp
+
+    with mp.workdps(dps):
+        n = len(t)
+        tt = [mp.mpf(float(v)) for v in t]
+        yy = mp.matrix([mp.mpf(float(v)) for v in y])
+
+        def k(tau):
+            tau = abs(tau)
+            total = mp.mpf(0)
+            for m in model.parts:
+                if hasattr(m, "lam"):
+                    nu = mp.mpf(3) / 2 if m.b == 2 else mp.mpf(5) / 2
+                    lam = mp.sqrt(2 * nu) / mp.mpf(m.ell)
+                    r = lam * tau
+                    poly = (1 + r) if m.b == 2 else (1 + r + r * r / 3)
+                    total += mp.mpf(m.var) * poly * mp.e ** (-r)
+                else:
+                    z = 1 / mp.mpf(m.ell) ** 2
+                    w0 = 2 * mp.pi / mp.mpf(m.period)
+                    for j in range(m.J + 1):
+                        q = mp.besseli(j, z) * mp.e ** (-z) * (1 if j == 0 else 2)
+                        total += mp.mpf(m.var) * q * mp.cos(j * w0 * tau)
+            return total
+
+        Kf = mp.matrix(n, n)
+        for i in range(n):
+            for j in range(n):
+                Kf[i, j] = k(tt[i] - tt[j])
+        Ky = Kf + mp.mpf(model.noise) * mp.eye(n)
+        L = mp.cholesky(Ky)
+        logdet = 2 * mp.fsum(mp.log(L[i, i]) for i in range(n))
+        Kinv = mp.inverse(Ky)
+        alpha = Kinv * yy
+        datafit = mp.fsum(yy[i] * alpha[i] for i in range(n))
+        logml = -datafit / 2 - logdet / 2 - n * mp.log(2 * mp.pi) / 2
+        mean = Kf * alpha
+        X = Kinv * Kf
+        var = [Kf[i, i] - mp.fsum(Kf[i, j] * X[j, i] for j in range(n)) for i in range(n)]
+        return {"logml": float(logml), "datafit": float(datafit), "logdet": float(logdet),
+                "f_mean": np.array([float(mean[i]) for i in range(n)]),
+                "f_var": np.array([float(v) for v in var])}

@@ -1,0 +1,274 @@
+"""Oracle state-space models (test infrastructure only; see the package header).
+
+Paper Sec. 2.1: a temporal GP is the output H z(t) of a linear SDE
+dz = F z dt + L dW.  Between two time points the state moves by the
+transition A[dt] = expm(F dt) (the paper writes this for Matern-3/2 in
+eq. ss_matern) and picks up Gaussian noise with covariance
+Q[dt] = P0 - A[dt] P0 A[dt]^T, where P0 is the stationary covariance.
+
+Readings adopted where the paper is silent or garbled:
+  * P0 carries the signal variance: P0 = var * diag(1, lam^2) for Matern-3/2
+    (eq. ss_matern drops the variance), and the kernel uses |tau|.
+  * Matern-5/2 (b = 3) and the periodic kernel (b = 2(J+1)) are not written
+    out in the paper; both follow the same construction.  P0 of Matern-5/2
+    holds the derivatives of k at 0: E[f f]=k(0), E[f' f']=-k''(0),
+    E[f f'']=k''(0), E[f'' f'']=k''''(0).
+  * The periodic term is the J-harmonic truncation of
+    var * exp(-2 sin^2(pi tau / p) / l^2): harmonic j is a rotation at
+    angular rate j*2*pi/p with stationary covariance var * q_j^2 * I2, where
+    q_0^2 = I_0(z) e^-z, q_j^2 = 2 I_j(z) e^-z, z = l^-2 (the Bessel
+    generating function of e^{z cos x}).  Its Q is zero: a rotation keeps q_j^2 I2.
+  * A sum of kernels stacks the states: F, P0, A, Q block-diagonal, H side by side.
+
+Transitions come from scipy.linalg.expm and their parameter derivatives from
+scipy.linalg.expm_frechet, so this module never uses a hand-derived closed
+form for A[dt]; the closed forms it does hold (P0, the kernel functions) are
+pinned by tests against the Lyapunov equation and H expm(F tau) P0 H^T.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+import scipy.special
+
+MATERN32, MATERN52, PERIODIC = 1, 2, 3
+
+
+class Matern:
+    """Matern-nu, nu in {3/2, 5/2}; hyperparameters (lengthscale, variance)."""
+
+    n_params = 2
+
+    def __init__(self, kind: int, lengthscale: float, variance: float):
+        if kind not in (MATERN32, MATERN52):
+            raise ValueError("Matern kind must be 1 (nu=3/2) or 2 (nu=5/2)")
+        self.kind = kind
+        self.ell = float(lengthscale)
+        self.var = float(variance)
+        self.b = 2 if kind == MATERN32 else 3
+        nu = 1.5 if kind == MATERN32 else 2.5
+        self.lam = np.sqrt(2.0 * nu) / self.ell
+
+    # --- SDE ---------------------------------------------------------------
+    def F(self):
+        l = self.lam
+        if self.kind == MATERN32:
+            return np.array([[0.0, 1.0], [-l * l, -2.0 * l]])
+        return np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [-l ** 3, -3.0 * l * l, -3.0 * l]])
+
+    def dF_dlam(self):
+        l = self.lam
+        if self.kind == MATERN32:
+            return np.array([[0.0, 0.0], [-2.0 * l, -2.0]])
+        return np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [-3.0 * l * l, -6.0 * l, -3.0]])
+
+    def H(self):
+        h = np.zeros(self.b)
+        h[0] = 1.0
+        return h
+
+    def Pinf(self):
+        l, v = self.lam, self.var
+        if self.kind == MATERN32:
+            return v * np.diag([1.0, l * l])
+        return v * np.array([[1.0, 0.0, -l * l / 3.0],
+                             [0.0, l * l / 3.0, 0.0],
+                             [-l * l / 3.0, 0.0, l ** 4]])
+
+    def dPinf_dlam(self):
+        l, v = self.lam, self.var
+        if self.kind == MATERN32:
+            return v * np.diag([0.0, 2.0 * l])
+        return v * np.array([[0.0, 0.0, -2.0 * l / 3.0],
+                             [0.0, 2.0 * l / 3.0, 0.0],
+                             [-2.0 * l / 3.0, 0.0, 4.0 * l ** 3]])
+
+    # derivatives with respect to the raw hyperparameters (lengthscale, variance)
+    def dF(self):
+        dlam_dell = -self.lam / self.ell
+        return [self.dF_dlam() * dlam_dell, np.zeros((self.b, self.b))]
+
+    def dPinf(self):
+        dlam_dell = -self.lam / self.ell
+        return [self.dPinf_dlam() * dlam_dell, self.Pinf() / self.var]
+
+    # --- covariance function --------------------------------------------------
+    def kernel(self, tau):
+        r = np.abs(tau) * self.lam
+        if self.kind == MATERN32:
+            return self.var * (1.0 + r) * np.exp(-r)
+        return self.var * (1.0 + r + r * r / 3.0) * np.exp(-r)
+
+    def dkernel(self, tau):
+        """[dk/dlengthscale, dk/dvariance] of the closed-form kernel."""
+        tau = np.abs(tau)
+        l = self.lam
+        e = np.exp(-l * tau)
+        if self.kind == MATERN32:
+            dk_dlam = -self.var * l * tau * tau * e
+        else:
+            dk_dlam = -self.var * (l * tau * tau / 3.0) * (1.0 + l * tau) * e
+        return [dk_dlam * (-l / self.ell), self.kernel(tau) / self.var]
+
+
+class Periodic:
+    """J-harmonic periodic term; hyperparameters (lengthscale, variance, period)."""
+
+    n_params = 3
+
+    def __init__(self, harmonics: int, lengthscale: float, variance: float, period: float):
+        self.J = int(harmonics)
+        self.ell = float(lengthscale)
+        self.var = float(variance)
+        self.period = float(period)
+        self.b = 2 * (self.J + 1)
+        self.w0 = 2.0 * np.pi / self.period
+        self.z = 1.0 / (self.ell * self.ell)
+
+    def q2(self):
+        j = np.arange(self.J + 1)
+        return scipy.special.ive(j, self.z) * np.where(j == 0, 1.0, 2.0)
+
+    def dq2_dz(self):
+        j = np.arange(self.J + 1)
+        dive = 0.5 * (scipy.special.ive(j - 1, self.z) + scipy.special.ive(j + 1, self.z)) \
+            - scipy.special.ive(j, self.z)
+        return dive * np.where(j == 0, 1.0, 2.0)
+
+    def F(self):
+        F = np.zeros((self.b, self.b))
+        for j in range(self.J + 1):
+            F[2 * j, 2 * j + 1] = -j * self.w0
+            F[2 * j + 1, 2 * j] = j * self.w0
+        return F
+
+    def H(self):
+        h = np.zeros(self.b)
+        h[0::2] = 1.0
+        return h
+
+    def Pinf(self):
+        return np.diag(np.repeat(self.var * self.q2(), 2))
+
+    def dF(self):
+        z = np.zeros((self.b, self.b))
+        return [z, z.copy(), -self.F() / self.period]
+
+    def dPinf(self):
+        dz_dell = -2.0 / self.ell ** 3
+        return [np.diag(np.repeat(self.var * self.dq2_dz() * dz_dell, 2)),
+                self.Pinf() / self.var,
+                np.zeros((self.b, self.b))]
+
+    def kernel(self, tau):
+        tau = np.asarray(tau, dtype=np.float64)
+        out = np.zeros_like(tau)
+        for j, q in enumerate(self.q2()):
+            out = out + q * np.cos(j * self.w0 * tau)
+        return self.var * out
+
+    def kernel_untruncated(self, tau):
+        s = np.sin(np.pi * np.asarray(tau) / self.period)
+        return self.var * np.exp(-2.0 * s * s / (self.ell * self.ell))
+
+    def dkernel(self, tau):
+        tau = np.asarray(tau, dtype=np.float64)
+        q2, dq = self.q2(), self.dq2_dz()
+        dz_dell = -2.0 / self.ell ** 3
+        d_ell = np.zeros_like(tau)
+        d_per = np.zeros_like(tau)
+        for j in range(self.J + 1):
+            d_ell = d_ell + dq[j] * dz_dell * np.cos(j * self.w0 * tau)
+            # d cos(j w0 tau)/dp = sin(j w0 tau) * j * tau * w0 / p
+            d_per = d_per + q2[j] * np.sin(j * self.w0 * tau) * j * tau * self.w0 / self.period
+        return [self.var * d_ell, self.kernel(tau) / self.var, self.var * d_per]
+
+
+class SumModel:
+    """Sum of terms: block-diagonal state space.  Parameters are the terms' in order."""
+
+    def __init__(self, terms, hyper_row):
+        """terms: [(kind, harmonics)], hyper_row: term parameters then the noise variance."""
+        self.parts = []
+        p = 0
+        for kind, harm in terms:
+            if kind in (MATERN32, MATERN52):
+                self.parts.append(Matern(kind, hyper_row[p], hyper_row[p + 1]))
+                p += 2
+            elif kind == PERIODIC:
+                self.parts.append(Periodic(harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2]))
+                p += 3
+            else:
+                raise ValueError(f"unknown kind {kind}")
+        self.noise = float(hyper_row[p])
+        self.n_kernel_params = p
+        self.n_params = p + 1
+        self.b = sum(m.b for m in self.parts)
+        self._F = scipy.linalg.block_diag(*[m.F() for m in self.parts])
+        self._P = scipy.linalg.block_diag(*[m.Pinf() for m in self.parts])
+        self._h = np.concatenate([m.H() for m in self.parts])
+        self._dF, self._dP = [], []
+        for i, m in enumerate(self.parts):
+            for dF, dP in zip(m.dF(), m.dPinf()):
+                blocksF = [np.zeros((q.b, q.b)) for q in self.parts]
+                blocksP = [np.zeros((q.b, q.b)) for q in self.parts]
+                blocksF[i] = dF
+                blocksP[i] = dP
+                self._dF.append(scipy.linalg.block_diag(*blocksF))
+                self._dP.append(scipy.linalg.block_diag(*blocksP))
+
+    # --- model matrices -------------------------------------------------------
+    def F(self):
+        return self._F
+
+    def H(self):
+        return self._h
+
+    def Pinf(self):
+        return self._P
+
+    def dPinf(self):
+        """d Pinf / d theta_i for every kernel parameter (noise excluded)."""
+        return self._dP
+
+    def A(self, dt):
+        """Transition over a gap dt: expm(F dt)."""
+        return scipy.linalg.expm(self._F * dt)
+
+    def Q(self, dt):
+        """Process noise over a gap dt: P0 - A P0 A^T (eq. ss_matern)."""
+        A = self.A(dt)
+        Q = self._P - A @ self._P @ A.T
+        return 0.5 * (Q + Q.T)
+
+    def dA(self, dt):
+        """[d expm(F dt)/d theta_i] via the Frechet derivative of expm."""
+        out = []
+        for dF in self._dF:
+            if not dF.any():
+                out.append(np.zeros_like(self._F))
+            else:
+                out.append(scipy.linalg.expm_frechet(self._F * dt, dF * dt, compute_expm=False))
+        return out
+
+    def dQ(self, dt):
+        A = self.A(dt)
+        out = []
+        for dA, dP in zip(self.dA(dt), self._dP):
+            d = dP - dA @ self._P @ A.T - A @ dP @ A.T - A @ self._P @ dA.T
+            out.append(0.5 * (d + d.T))
+        return out
+
+    # --- covariance function --------------------------------------------------
+    def kernel(self, tau):
+        return sum(m.kernel(tau) for m in self.parts)
+
+    def dkernel(self, tau):
+        out = []
+        for m in self.parts:
+            out.extend(m.dkernel(tau))
+        return out
+
+
+def model_for(terms, hyper_row) -> SumModel:
+    return SumModel(terms, hyper_row)

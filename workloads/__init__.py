@@ -1,0 +1,16 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle scripts.
+
+This package draws times and observations only.  It holds none of the
+inference arithmetic (no precision blocks, no reduction, no likelihood); both
+the oracle and the device path receive its arrays as plain inputs.
+"""
+from .generate import (  # noqa: F401
+    KIND_MATERN32,
+    KIND_MATERN52,
+    KIND_PERIODIC,
+    Workload,
+    make_config,
+    make_series,
+    n_hyper,
+    state_dim,
+)

@@ -1,0 +1,247 @@
+"""Seeded synthetic workloads for temporal-GP inference.
+
+Every array is drawn from ``numpy.random.default_rng`` (PCG64) with the
+configuration number as the seed, so a workload is reproduced bit for bit
+from its name and sizes alone.  Draw order per series: (i) times, (ii) for the
+batched workload the lengths, lengthscales and noise variances first, then one
+child stream per series, (iii) the initial latent state, (iv) the transition
+noise, (v) periodic amplitudes, (vi) the observation noise.
+
+The latent signal is a sample of the GP prior.  Matern terms are simulated as
+white noise through a cascade of first-order low-pass stages (the Jordan form
+of the Matern-(p+1/2) SDE, whose transfer function is (s + lam)^-(p+1)); this
+is a different state basis from the companion form the inference code uses,
+and its stationary covariance comes from scipy's Lyapunov solver.  Periodic
+terms are sums of random-phase harmonics with the Bessel weights of the
+truncated periodic kernel.  Nothing here computes a likelihood, a mean or a
+variance: the module only draws data.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg
+import scipy.special
+
+KIND_MATERN32 = 1
+KIND_MATERN52 = 2
+KIND_PERIODIC = 3
+
+_MATERN_ORDER = {KIND_MATERN32: 2, KIND_MATERN52: 3}
+_MATERN_NU = {KIND_MATERN32: 1.5, KIND_MATERN52: 2.5}
+
+
+def state_dim(terms) -> int:
+    """State dimension b of a sum of terms ``[(kind, harmonics), ...]``."""
+    b = 0
+    for kind, harm in terms:
+        if kind in _MATERN_ORDER:
+            b += _MATERN_ORDER[kind]
+        elif kind == KIND_PERIODIC:
+            b += 2 * (harm + 1)
+        else:
+            raise ValueError(f"unknown term kind {kind}")
+    return b
+
+
+def n_hyper(terms) -> int:
+    """Hyperparameters per series: (l, var) per Matern, (l, var, period) per periodic, then noise."""
+    n = 0
+    for kind, _ in terms:
+        n += 3 if kind == KIND_PERIODIC else 2
+    return n + 1
+
+
+@dataclass
+class Workload:
+    name: str
+    terms: list
+    t: np.ndarray          # [n_points] float64, series concatenated, non-decreasing per series
+    y: np.ndarray          # [n_points] float64
+    offsets: np.ndarray    # [n_series + 1] int64
+    hyper: np.ndarray      # [n_series, n_hyper] float64
+    notes: dict = field(default_factory=dict)
+
+    @property
+    def n_series(self) -> int:
+        return int(self.offsets.shape[0] - 1)
+
+    @property
+    def n_points(self) -> int:
+        return int(self.t.shape[0])
+
+    @property
+    def b(self) -> int:
+        return state_dim(self.terms)
+
+    def series(self, i):
+        a, e = int(self.offsets[i]), int(self.offsets[i + 1])
+        return self.t[a:e], self.y[a:e], self.hyper[i]
+
+
+# --------------------------------------------------------------------------
+# prior simulation (data generation only)
+# --------------------------------------------------------------------------
+
+def _cascade_stationary_cov(order: int, lam: float) -> np.ndarray:
+    """Stationary covariance of white noise (unit intensity) through `order` stages (s+lam)^-1."""
+    F = -lam * np.eye(order) + np.diag(np.ones(order - 1), -1)
+    W = np.zeros((order, order))
+    W[0, 0] = 1.0
+    P = scipy.linalg.solve_continuous_lyapunov(F, -W)
+    return 0.5 * (P + P.T)
+
+
+def _cascade_transition(order: int, lam: float, dt: np.ndarray) -> np.ndarray:
+    """exp(F dt) for F = -lam I + S (S the sub-diagonal shift): e^{-lam dt} sum_k (S dt)^k / k!."""
+    dt = np.asarray(dt, dtype=np.float64)
+    out = np.zeros(dt.shape + (order, order))
+    e = np.exp(-lam * dt)
+    for i in range(order):
+        for j in range(i + 1):
+            k = i - j
+            out[..., i, j] = e * dt ** k / float(np.prod(np.arange(1, k + 1)))
+    return out
+
+
+def _matern_prior_path(t: np.ndarray, kind: int, ell: float, var: float,
+                       rng: np.random.Generator) -> np.ndarray:
+    """One sample path of a Matern GP at sorted times t (exact in distribution)."""
+    order = _MATERN_ORDER[kind]
+    lam = np.sqrt(2.0 * _MATERN_NU[kind]) / ell
+    P = _cascade_stationary_cov(order, lam)
+    P *= var / P[order - 1, order - 1]
+    n = t.shape[0]
+    # (iii) initial state
+    x0 = np.linalg.cholesky(P) @ rng.standard_normal(order)
+    # (iv) transition noise, drawn in one piece so the blocking never changes the stream
+    xi = rng.standard_normal((max(n - 1, 0), order))
+    if n == 1:
+        return np.array([x0[order - 1]])
+    dt = np.diff(t)
+
+    # noise_n = sqrt(Qc_n) xi_n with Qc_n = P - A P A^T, eigenvalues clipped at 0
+    def noise(idx):
+        A = _cascade_transition(order, lam, dt[idx])
+        Q = P[None] - A @ P[None] @ np.swapaxes(A, -1, -2)
+        Q = 0.5 * (Q + np.swapaxes(Q, -1, -2))
+        w, V = np.linalg.eigh(Q)
+        w = np.sqrt(np.clip(w, 0.0, None))
+        return A, np.einsum("kij,kj->ki", V * w[:, None, :], xi[idx])
+
+    # blocked exact linear recurrence x_{n+1} = A_n x_n + w_n (about sqrt(n) blocks of sqrt(n))
+    block = max(16, int(np.sqrt(n)) + 1)
+    nb = (n + block - 1) // block
+    local = np.zeros((nb, block, order))
+    ell_state = np.zeros((nb, order))
+    phi = np.broadcast_to(np.eye(order), (nb, order, order)).copy()
+    starts = np.arange(nb) * block
+    for j in range(block):
+        local[:, j] = ell_state
+        idx = starts + j
+        ok = idx < n - 1
+        if not ok.any():
+            continue
+        A, w = noise(idx[ok])
+        ell_state[ok] = np.einsum("kij,kj->ki", A, ell_state[ok]) + w
+        phi[ok] = A @ phi[ok]
+    X = np.zeros((nb, order))
+    X[0] = x0
+    for k in range(nb - 1):
+        X[k + 1] = phi[k] @ X[k] + ell_state[k]
+    out = np.zeros((nb, block))
+    phi = np.broadcast_to(np.eye(order), (nb, order, order)).copy()
+    for j in range(block):
+        idx = starts + j
+        out[:, j] = (phi[:, order - 1, :] * X).sum(-1) + local[:, j, order - 1]
+        ok = idx < n - 1
+        if ok.any():
+            A = _cascade_transition(order, lam, dt[idx[ok]])
+            phi[ok] = A @ phi[ok]
+    return out.reshape(-1)[:n]
+
+
+def _periodic_prior_path(t, harmonics, ell, var, period, rng):
+    """Random-phase harmonic sum with Bessel weights q_j^2 (truncated periodic kernel)."""
+    z = 1.0 / (ell * ell)
+    j = np.arange(harmonics + 1)
+    q2 = scipy.special.ive(j, z) * np.where(j == 0, 1.0, 2.0)
+    amp = rng.standard_normal((harmonics + 1, 2))
+    w0 = 2.0 * np.pi / period
+    f = np.zeros_like(t)
+    for jj in range(harmonics + 1):
+        s = np.sqrt(var * q2[jj])
+        f += s * (amp[jj, 0] * np.cos(jj * w0 * t) + amp[jj, 1] * np.sin(jj * w0 * t))
+    return f
+
+
+def make_series(t, terms, hyper_row, rng):
+    """Draw y = f + eps at times t for one series with hyperparameter row `hyper_row`."""
+    t = np.asarray(t, dtype=np.float64)
+    f = np.zeros_like(t)
+    p = 0
+    for kind, harm in terms:
+        if kind in _MATERN_ORDER:
+            f += _matern_prior_path(t, kind, hyper_row[p], hyper_row[p + 1], rng)
+            p += 2
+        else:
+            f += _periodic_prior_path(t, harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2], rng)
+            p += 3
+    noise = hyper_row[p]
+    # (vi) observation noise
+    return f + np.sqrt(noise) * rng.standard_normal(t.shape[0])
+
+
+def _single(name, terms, t, hyper_row, rng, notes):
+    y = make_series(t, terms, hyper_row, rng)
+    return Workload(name=name, terms=list(terms), t=t, y=y,
+                    offsets=np.array([0, t.shape[0]], dtype=np.int64),
+                    hyper=np.asarray(hyper_row, dtype=np.float64)[None, :].copy(), notes=notes)
+
+
+def make_config(k: int, n: int | None = None, n_series: int | None = None,
+                max_len: int | None = None) -> Workload:
+    """Workload k in 1..5; `n`, `n_series`, `max_len` shrink it for small test cases."""
+    if k == 1:
+        n = 1000 if n is None else n
+        rng = np.random.default_rng(1)
+        t = np.sort(rng.uniform(0.0, 100.0, n))
+        return _single("matern32_n%d_uniform100" % n, [(KIND_MATERN32, 0)], t,
+                       [1.0, 1.0, 0.1], rng, {"grid": "sorted U[0,100]"})
+    if k in (2, 5):
+        n = (1 << 20 if k == 2 else 1 << 24) if n is None else n
+        rng = np.random.default_rng(k)
+        t = np.cumsum(rng.exponential(1.0, n))
+        return _single("matern52_n%d_exp1gaps" % n, [(KIND_MATERN52, 0)], t,
+                       [5.0, 2.0, 0.05], rng, {"grid": "cumsum Exp(1)"})
+    if k == 3:
+        n = (1 << 18) if n is None else n
+        rng = np.random.default_rng(3)
+        t = np.sort(rng.uniform(0.0, 1.0e4, n))
+        terms = [(KIND_MATERN32, 0), (KIND_PERIODIC, 3)]
+        return _single("matern32+periodic3_n%d_uniform1e4" % n, terms, t,
+                       [50.0, 1.0, 1.0, 1.0, 24.0, 0.1], rng, {"grid": "sorted U[0,1e4]"})
+    if k == 4:
+        S = 4096 if n_series is None else n_series
+        rng = np.random.default_rng(4)
+        lens = np.round(np.exp(rng.uniform(np.log(64.0), np.log(16384.0), S))).astype(np.int64)
+        if max_len is not None:
+            lens = np.minimum(lens, max_len)
+        ells = np.exp(rng.uniform(np.log(0.5), np.log(20.0), S))
+        noises = rng.uniform(0.01, 0.5, S)
+        children = np.random.SeedSequence(4).spawn(S)
+        ts, ys = [], []
+        hyper = np.zeros((S, 3))
+        for i in range(S):
+            r = np.random.default_rng(children[i])
+            t = np.cumsum(r.exponential(1.0, int(lens[i])))
+            hyper[i] = (ells[i], 1.0, noises[i])
+            ts.append(t)
+            ys.append(make_series(t, [(KIND_MATERN52, 0)], hyper[i], r))
+        offsets = np.zeros(S + 1, dtype=np.int64)
+        offsets[1:] = np.cumsum(lens)
+        return Workload(name="batched_matern52_%dseries" % S, terms=[(KIND_MATERN52, 0)],
+                        t=np.concatenate(ts), y=np.concatenate(ys), offsets=offsets, hyper=hyper,
+                        notes={"grid": "cumsum Exp(1) per series", "lengths": "log-U[64,16384]"})
+    raise ValueError("config must be 1..5")
