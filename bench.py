@@ -1,0 +1,135 @@
+"""Benchmark: log marginal likelihood + gradient of a Matern-5/2 GP at N = 2^20 in FP64.
+
+One step = one pass of the whole hot path on one batch of resident synthetic input:
+spingp_assemble (bind + device validation) followed by spingp_logml_grad (chunk fold and
+work-group tree, top-level tree and down-sweeps, chunk elimination + adjoint sweep, gradient
+finalize).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Arithmetic per point of the two per-point kernels, counted from their formulas (FMA = 2 flops,
+# a divide, exp or log = 1), b = 3.  The O(N/R) work-group and top-level trees are parallel
+# overhead and are not counted as algorithmic work.
+FLOPS_PER_POINT = {
+    "fwd_fold_tree": 259.0,     # rank-one fold of one node into the chunk element
+    "bwd_elim_adjoint": 542.0,  # Kalman elimination step (170) + adjoint step (372)
+}
+PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
+PEAK_HBM_GBS = 8000.0
+
+
+def cpu_baseline(w, budget_s=10.0):
+    """The C oracle (sequential elimination + tangent-linear gradient), timed on the host.
+
+    The sample is the whole series, repeated until about `budget_s` seconds of CPU work
+    (a single pass over 2^20 points takes well under a second)."""
+    from oracle import native
+    t, y, hyp = w.series(0)
+    reps, total, pts = 0, 0.0, 0
+    while total < budget_s and reps < 1000:
+        t0 = time.perf_counter()
+        native.tangent_grad(w.terms, hyp, t, y)
+        total += time.perf_counter() - t0
+        pts += t.shape[0]
+        reps += 1
+    return {"value": pts / total, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": f"all {t.shape[0]} points x {reps} repetitions ({total:.1f} s): logML + 3-parameter "
+                      f"gradient by the single-threaded C sequential elimination with tangent-linear derivatives"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the hot path runs on a single MI355X; "
+              "multi-GPU runs are not part of this benchmark", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1610_08035_amd as spg
+    from paper_1610_08035_amd.spingp import spingp_profile, spingp_profile_read
+    from workloads import make_config
+
+    w = make_config(2)              # Matern-5/2, N = 2^20, Exp(1) gaps, l = 5, var = 2, s2 = 0.05
+    n = w.n_points
+    t, y, hyp = w.series(0)
+    dev = torch.device("cuda:0")
+    td = torch.as_tensor(t, device=dev)
+    yd = torch.as_tensor(y, device=dev)
+    hd = torch.as_tensor(hyp, device=dev)
+    h = spg.Handle(w.terms, n)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(1, 3, dtype=torch.float64, device=dev)
+
+    def step():
+        spg.spingp_assemble(h._h, td, yd, hd)
+        spg.spingp_logml_grad(h._h, ll, g)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    rc, bad = h.status()
+    if rc != 0:
+        raise RuntimeError(f"device status {rc} at {bad}")
+
+    spingp_profile(h._h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = spingp_profile_read(h._h)
+    spingp_profile(h._h, 0)
+
+    ms_step = 1e3 * elapsed / args.steps
+    value = n * args.steps / elapsed
+    per_kernel = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
+    dom = max(FLOPS_PER_POINT, key=lambda k: per_kernel[k])
+    achieved = FLOPS_PER_POINT[dom] * n / (per_kernel[dom] * 1e-3) / 1e12
+    out = {
+        "metric": "time points/sec, logML+grad, Matern-5/2 N=2^20 FP64; % HBM roofline",
+        "value": value,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded GP prior sample + noise, Exp(1) gaps)",
+        "config": {"workload": "matern52_n1048576_exp1gaps_logml_grad", "n_points": n, "state_dim": 3,
+                   "n_hyper": 3, "hyper": [float(v) for v in hyp]},
+        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "flops_per_point": FLOPS_PER_POINT[dom]},
+        "kernel_ms": {k: round(v, 5) for k, v in per_kernel.items()},
+        "logml": float(ll.item()),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * spingp.h - C ABI of the MI355X (gfx950) library for temporal Gaussian-process inference
+ * in sparse-precision form (SpInGP, Grigorievskiy, Lawrence & Sarkka, arXiv:1610.08035).
+ *
+ * Model (paper Sec. 2.1, eq. ss1): a GP with a Matern covariance is the output y_n = h^T z_n
+ * + eps_n of a linear state-space chain z_{n+1} = A_n z_n + q_n, q_n ~ N(0, Q_n),
+ * z_0 ~ N(0, P0), eps_n ~ N(0, s2), with A_n = expm(F (t_{n+1} - t_n)) and
+ * Q_n = P0 - A_n P0 A_n^T (eq. ss_matern).  The posterior precision of the stacked states is
+ * block tridiagonal with b x b blocks (Theorem 1): Kinv + I (x) h h^T / s2.
+ *
+ * Conventions shared by every call
+ *   - Every array argument is a DEVICE pointer (e.g. torch tensor data) owned by the caller,
+ *     float64, contiguous, and must stay valid until the handle's stream has executed the
+ *     work.  All calls enqueue on the handle's stream and return without synchronising,
+ *     except spingp_create, spingp_destroy and spingp_status.
+ *   - The library owns its workspace; it is allocated once in spingp_create, so the other
+ *     calls never allocate device memory.
+ *   - Host-detectable errors (null handle or pointer, sizes above the handle's maximum,
+ *     unsupported model, call order) are returned synchronously as a spingp_status_t.
+ *     Data errors (decreasing or non-finite t, non-finite y, non-positive or non-finite
+ *     hyperparameters) are detected on the device, recorded in a status word and reported
+ *     by spingp_status; results of such a call are unspecified.
+ *   - Nothing is printed, thrown across the ABI or exits the process.
+ *   - One handle per host thread and stream.
+ *
+ * Layouts
+ *   - Series are concatenated (t, y have n_points entries).
+ *   - State-level outputs are structure-of-arrays with leading dimension ld = n_points:
+ *     component c of node n is at base[c * ld + n].  Symmetric b x b blocks are packed upper
+ *     triangle, row-major (for b = 3: 00 01 02 11 12 22); general blocks row-major.
+ *   - Hyperparameter row (one per series, device memory): per term, in order,
+ *     Matern: (lengthscale, signal variance); then the noise variance s2.
+ */
+#ifndef SPINGP_H
+#define SPINGP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spingp_ctx* spingp_handle;
+
+typedef enum {
+  SPINGP_OK = 0,
+  SPINGP_E_INVALID = 1,     /* bad argument (null pointer, size, value) */
+  SPINGP_E_ORDER = 2,       /* call made before the calls it depends on */
+  SPINGP_E_UNSORTED = 3,    /* t decreases inside a series (device-detected) */
+  SPINGP_E_NONFINITE = 4,   /* NaN/Inf in t or y (device-detected) */
+  SPINGP_E_HYPER = 5,       /* hyperparameter not finite or not > 0 (device-detected) */
+  SPINGP_E_NOMEM = 6,       /* workspace allocation failed in spingp_create */
+  SPINGP_E_HIP = 7,         /* a HIP runtime call failed */
+  SPINGP_E_UNSUPPORTED = 8  /* model or size the library does not implement */
+} spingp_status_t;
+
+typedef enum { SPINGP_MATERN32 = 1, SPINGP_MATERN52 = 2, SPINGP_PERIODIC = 3 } spingp_kind_t;
+
+/* One additive covariance term; `harmonics` is used by periodic terms only. */
+typedef struct {
+  int32_t kind;
+  int32_t harmonics;
+} spingp_term;
+
+/*
+ * Create a handle for a model given as a sum of terms (host array of n_terms entries) and the
+ * largest problem it will see.  `stream` is a hipStream_t (NULL = the default stream).
+ * Supported models: a single Matern-3/2 (b = 2) or Matern-5/2 (b = 3) term, one series.
+ * Allocates all device workspace; returns SPINGP_E_UNSUPPORTED for other models.
+ */
+int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,
+                  int32_t max_series, void* stream);
+
+/* Release the handle and its workspace (synchronises the stream first). */
+int spingp_destroy(spingp_handle h);
+
+/* State dimension b and hyperparameters per series of the handle's model. */
+int spingp_state_dim(spingp_handle h);
+int spingp_n_hyper(spingp_handle h);
+
+/*
+ * Assemble: bind the inputs and build the factored block-tridiagonal precision (Theorem 1
+ * with G^T Sigma^-1 G = I (x) h h^T / s2, Sec. 2.2).  t, y: [n_points]; offsets: NULL or
+ * [n_series + 1] int64 with offsets[0] = 0, offsets[n_series] = n_points; hyper:
+ * [n_series x n_hyper].  The blocks (A_n, Q_n, J, eta_n) are recomputed from t, y and hyper
+ * inside the kernels that use them, so this call only validates and records the inputs;
+ * device-side validation results are read with spingp_status.  flags: reserved, pass 0.
+ * Invalidates any earlier factorisation.
+ */
+int spingp_assemble(spingp_handle h, const double* t, const double* y, const int64_t* offsets, int32_t n_series,
+                    int64_t n_points, const double* hyper, uint32_t flags);
+
+/*
+ * Factor: odd-even block cyclic reduction of the precision (Sec. 3.1, subproblems 1 and 3).
+ * Folds each chunk of consecutive nodes, reduces the chunk elements with a balanced tree and
+ * runs the down-sweeps that hand every chunk its exact boundary state.  Needs assemble.
+ */
+int spingp_factor(spingp_handle h);
+
+/*
+ * Log marginal likelihood (eq. ml2 via the determinant lemma eq. det_1) of the factored
+ * problem.  logml: [n_series]; datafit: NULL or [n_series] = y^T K_y^-1 y; logdet: NULL or
+ * [n_series] = log det K_y.  Needs factor.
+ */
+int spingp_logml(spingp_handle h, double* logml, double* datafit, double* logdet);
+
+/*
+ * Posterior mean (subproblem 1, eq. mean3/mean6 at the training times): f_mean: NULL or
+ * [n_points] = E[f(t_n) | y]; z_mean: NULL or [b x n_points] SoA = E[z_n | y].  Needs factor.
+ */
+int spingp_solve(spingp_handle h, double* f_mean, double* z_mean);
+
+/*
+ * Selected inverse (subproblems 2 and 4: the block-tridiagonal part of the inverse precision,
+ * Sec. 3.1): f_var: NULL or [n_points] = Var[f(t_n) | y] (latent, eq. k3, no noise);
+ * S_diag: NULL or [b(b+1)/2 x n_points] = Cov(z_n | y); S_sub: NULL or [b*b x n_points], entry n
+ * = Cov(z_{n+1}, z_n | y) for n < n_points - 1 (entry n_points - 1 is left untouched).
+ * Needs factor.
+ */
+int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, double* S_sub);
+
+/*
+ * Log marginal likelihood and its gradient (Sec. 2.4) with respect to the raw hyperparameters
+ * of the hyperparameter row: grad: [n_series x n_hyper].  Runs the factorisation itself when
+ * the current one is missing or stale, then the adjoint of the reduction.  logml: [n_series].
+ */
+int spingp_logml_grad(spingp_handle h, double* logml, double* grad);
+
+/*
+ * Synchronise the handle's stream and report the first device-detected data error since the
+ * last assemble: returns SPINGP_OK or the error code; *first_bad (host, may be NULL) receives
+ * the offending point index (or -1 for a hyperparameter error / no error).
+ */
+int spingp_status(spingp_handle h, int64_t* first_bad);
+
+/*
+ * Diagnostics: per-kernel timing with HIP events recorded on the handle's stream around every
+ * launch the library makes.  spingp_profile(h, 1) creates the events and starts recording,
+ * spingp_profile(h, 0) stops and releases them.  spingp_profile_read synchronises and returns,
+ * per kernel id (0 validate, 1 forward fold + work-group tree, 2 top-level tree and
+ * down-sweeps, 3 work-group down-sweep + chunk elimination + adjoint, 4 finalize), the total
+ * milliseconds and launch counts since the last read (host arrays of SPINGP_N_KERNELS).
+ */
+#define SPINGP_N_KERNELS 5
+int spingp_profile(spingp_handle h, int enable);
+int spingp_profile_read(spingp_handle h, double* total_ms, int64_t* launches);
+
+/* Static description of a status code. */
+const char* spingp_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPINGP_H */

@@ -1,0 +1,23 @@
+"""SpInGP hot path for MI355X: temporal-GP inference in sparse-precision form.
+
+The computation lives in the gfx950 library ``libspingp.so`` behind the C ABI of
+``include/spingp.h``; ``spingp`` is its thin Python binding and ``autograd`` wraps the log
+marginal likelihood and its hand-written gradient as a torch.autograd.Function.
+"""
+from .spingp import (  # noqa: F401
+    MATERN32,
+    MATERN52,
+    PERIODIC,
+    Handle,
+    SpinGPError,
+    load_library,
+    spingp_assemble,
+    spingp_create,
+    spingp_destroy,
+    spingp_factor,
+    spingp_logml,
+    spingp_logml_grad,
+    spingp_selinv,
+    spingp_solve,
+    spingp_status,
+)

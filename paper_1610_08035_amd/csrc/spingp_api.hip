@@ -1,0 +1,343 @@
+// Host side of the C ABI declared in include/spingp.h: handle, workspace, validation and the
+// launch sequence of the hot path.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/spingp.h"
+#include "spingp_kernels.hpp"
+
+namespace {
+
+constexpr int kR = 8;        // points folded sequentially per lane
+constexpr int kL = 128;      // lanes (chunks) per work-group
+constexpr int kTopT = 256;   // threads of the single-work-group top kernel
+constexpr int kFinT = 256;
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Device-side validation: key = (index << 4) | code, minimised over offending points.
+__global__ void k_validate(const double* __restrict__ t, const double* __restrict__ y, int64_t n,
+                           const double* __restrict__ hyper, int n_hyper, unsigned long long* key) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    for (int k = 0; k < n_hyper; ++k) {
+      const double h = hyper[k];
+      if (!(isfinite(h) && h > 0.0)) atomicMin(key, (unsigned long long)SPINGP_E_HYPER);
+    }
+  }
+  if (i >= n) return;
+  const double ti = t[i], yi = y[i];
+  unsigned long long code = 0;
+  if (!isfinite(ti) || !isfinite(yi)) code = SPINGP_E_NONFINITE;
+  else if (i + 1 < n && t[i + 1] < ti) code = SPINGP_E_UNSORTED;
+  if (code) atomicMin(key, ((unsigned long long)(i + 1) << 4) | code);
+}
+
+__global__ void k_fill_key(unsigned long long* key) { *key = ~0ull; }
+
+__global__ void k_copy_scalars(const double* __restrict__ scal, int64_t n_pts, double* logml, double* datafit,
+                               double* logdet) {
+  if (threadIdx.x == 0) {
+    if (logml) logml[0] = scal[0];
+    if (datafit) datafit[0] = -2.0 * scal[1];
+    if (logdet) logdet[0] = -2.0 * scal[2] - (double)n_pts * spg::kLog2Pi;
+  }
+}
+
+}  // namespace
+
+struct spingp_ctx {
+  int b = 0;
+  int n_hyper = 0;
+  int64_t max_points = 0;
+  hipStream_t stream = nullptr;
+  // workspace
+  double* lane = nullptr;
+  double* wg = nullptr;
+  double* tree = nullptr;
+  double* msgs = nullptr;
+  double* scal = nullptr;
+  double* gpart = nullptr;
+  unsigned long long* key = nullptr;
+  int64_t lane_ld = 0, wg_ld = 0, tree_ld = 0, G_max = 0;
+  // bound inputs
+  const double* t = nullptr;
+  const double* y = nullptr;
+  const double* hyper = nullptr;
+  int64_t n_points = 0;
+  int64_t G = 0;
+  bool assembled = false;
+  bool factored = false;
+  // profiling (optional)
+  static constexpr int kPool = 64;
+  bool prof = false;
+  int prof_n = 0;
+  int prof_kid[kPool];
+  hipEvent_t prof_ev[2 * kPool];
+  double prof_ms[SPINGP_N_KERNELS];
+  int64_t prof_cnt[SPINGP_N_KERNELS];
+};
+
+static void prof_flush(spingp_ctx* h) {
+  if (!h->prof || h->prof_n == 0) return;
+  (void)hipEventSynchronize(h->prof_ev[2 * h->prof_n - 1]);
+  for (int i = 0; i < h->prof_n; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->prof_ev[2 * i], h->prof_ev[2 * i + 1]) == hipSuccess) {
+      h->prof_ms[h->prof_kid[i]] += ms;
+      h->prof_cnt[h->prof_kid[i]] += 1;
+    }
+  }
+  h->prof_n = 0;
+}
+static void prof_begin(spingp_ctx* h) {
+  if (!h->prof) return;
+  if (h->prof_n == spingp_ctx::kPool) prof_flush(h);
+  (void)hipEventRecord(h->prof_ev[2 * h->prof_n], h->stream);
+}
+static void prof_end(spingp_ctx* h, int kid) {
+  if (!h->prof) return;
+  (void)hipEventRecord(h->prof_ev[2 * h->prof_n + 1], h->stream);
+  h->prof_kid[h->prof_n] = kid;
+  h->prof_n += 1;
+}
+
+static int hip_ok(hipError_t e) { return e == hipSuccess ? SPINGP_OK : SPINGP_E_HIP; }
+
+extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,
+                             int32_t max_series, void* stream) {
+  if (!out || !terms || n_terms < 1 || max_points < 1 || max_series < 1) return SPINGP_E_INVALID;
+  *out = nullptr;
+  if (n_terms != 1 || max_series != 1) return SPINGP_E_UNSUPPORTED;
+  int b;
+  if (terms[0].kind == SPINGP_MATERN32) b = 2;
+  else if (terms[0].kind == SPINGP_MATERN52) b = 3;
+  else return SPINGP_E_UNSUPPORTED;
+  spingp_ctx* h = new (std::nothrow) spingp_ctx();
+  if (!h) return SPINGP_E_NOMEM;
+  h->b = b;
+  h->n_hyper = 3;
+  h->max_points = max_points;
+  h->stream = (hipStream_t)stream;
+  const int NF = (b == 2) ? spg::ElemLayout<2>::kFields : spg::ElemLayout<3>::kFields;
+  const int MF = (b == 2) ? spg::msg_fields<2>() : spg::msg_fields<3>();
+  const int64_t chunks = ceil_div(max_points, kR);
+  h->G_max = ceil_div(chunks, kL);
+  h->lane_ld = h->G_max * kL;
+  h->wg_ld = h->G_max;
+  h->tree_ld = 2 * next_pow2(h->G_max);
+  bool ok = true;
+  ok = ok && hipMalloc(&h->lane, sizeof(double) * NF * h->lane_ld) == hipSuccess;
+  ok = ok && hipMalloc(&h->wg, sizeof(double) * NF * h->wg_ld) == hipSuccess;
+  ok = ok && hipMalloc(&h->tree, sizeof(double) * NF * h->tree_ld) == hipSuccess;
+  ok = ok && hipMalloc(&h->msgs, sizeof(double) * MF * h->tree_ld) == hipSuccess;
+  ok = ok && hipMalloc(&h->scal, sizeof(double) * 8) == hipSuccess;
+  ok = ok && hipMalloc(&h->gpart, sizeof(double) * 3 * h->G_max) == hipSuccess;
+  ok = ok && hipMalloc(&h->key, sizeof(unsigned long long)) == hipSuccess;
+  if (!ok) {
+    spingp_destroy(h);
+    return SPINGP_E_NOMEM;
+  }
+  *out = h;
+  return SPINGP_OK;
+}
+
+extern "C" int spingp_profile(spingp_handle h, int enable) {
+  if (!h) return SPINGP_E_INVALID;
+  if (enable && !h->prof) {
+    for (int i = 0; i < 2 * spingp_ctx::kPool; ++i)
+      if (hipEventCreate(&h->prof_ev[i]) != hipSuccess) return SPINGP_E_HIP;
+    for (int k = 0; k < SPINGP_N_KERNELS; ++k) {
+      h->prof_ms[k] = 0.0;
+      h->prof_cnt[k] = 0;
+    }
+    h->prof_n = 0;
+    h->prof = true;
+  } else if (!enable && h->prof) {
+    prof_flush(h);
+    for (int i = 0; i < 2 * spingp_ctx::kPool; ++i) (void)hipEventDestroy(h->prof_ev[i]);
+    h->prof = false;
+  }
+  return SPINGP_OK;
+}
+
+extern "C" int spingp_profile_read(spingp_handle h, double* total_ms, int64_t* launches) {
+  if (!h || !total_ms || !launches) return SPINGP_E_INVALID;
+  if (!h->prof) return SPINGP_E_ORDER;
+  prof_flush(h);
+  for (int k = 0; k < SPINGP_N_KERNELS; ++k) {
+    total_ms[k] = h->prof_ms[k];
+    launches[k] = h->prof_cnt[k];
+    h->prof_ms[k] = 0.0;
+    h->prof_cnt[k] = 0;
+  }
+  return SPINGP_OK;
+}
+
+extern "C" int spingp_destroy(spingp_handle h) {
+  if (!h) return SPINGP_E_INVALID;
+  (void)spingp_profile(h, 0);
+  if (h->stream || h->lane) (void)hipStreamSynchronize(h->stream);
+  (void)hipFree(h->lane);
+  (void)hipFree(h->wg);
+  (void)hipFree(h->tree);
+  (void)hipFree(h->msgs);
+  (void)hipFree(h->scal);
+  (void)hipFree(h->gpart);
+  (void)hipFree(h->key);
+  delete h;
+  return SPINGP_OK;
+}
+
+extern "C" int spingp_state_dim(spingp_handle h) { return h ? h->b : -1; }
+extern "C" int spingp_n_hyper(spingp_handle h) { return h ? h->n_hyper : -1; }
+
+extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y, const int64_t* offsets,
+                               int32_t n_series, int64_t n_points, const double* hyper, uint32_t flags) {
+  if (!h || !t || !y || !hyper || flags != 0) return SPINGP_E_INVALID;
+  if (n_series != 1) return SPINGP_E_UNSUPPORTED;
+  if (n_points < 1 || n_points > h->max_points) return SPINGP_E_INVALID;
+  (void)offsets;  // one series: the whole array
+  h->t = t;
+  h->y = y;
+  h->hyper = hyper;
+  h->n_points = n_points;
+  h->G = ceil_div(ceil_div(n_points, kR), kL);
+  h->assembled = true;
+  h->factored = false;
+  hipLaunchKernelGGL(k_fill_key, dim3(1), dim3(1), 0, h->stream, h->key);
+  const int T = 256;
+  prof_begin(h);
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)ceil_div(n_points, T)), dim3(T), 0, h->stream, t, y, n_points,
+                     hyper, h->n_hyper, h->key);
+  prof_end(h, 0);
+  return hip_ok(hipGetLastError());
+}
+
+template <int B>
+static int launch_factor(spingp_ctx* h) {
+  constexpr int NF = spg::ElemLayout<B>::kFields;
+  (void)NF;
+  prof_begin(h);
+  hipLaunchKernelGGL((spg::k_fwd<B, kR, kL>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t, h->y,
+                     h->n_points, h->hyper, h->lane, h->lane_ld, h->wg, h->wg_ld);
+  prof_end(h, 1);
+  const int64_t G2 = next_pow2(h->G);
+  prof_begin(h);
+  hipLaunchKernelGGL((spg::k_top<B, kTopT>), dim3(1), dim3(kTopT), 0, h->stream, h->hyper, h->wg, h->wg_ld, h->G,
+                     G2, h->tree, h->tree_ld, h->msgs, h->tree_ld, h->scal);
+  prof_end(h, 2);
+  return hip_ok(hipGetLastError());
+}
+
+extern "C" int spingp_factor(spingp_handle h) {
+  if (!h) return SPINGP_E_INVALID;
+  if (!h->assembled) return SPINGP_E_ORDER;
+  const int rc = (h->b == 2) ? launch_factor<2>(h) : launch_factor<3>(h);
+  if (rc == SPINGP_OK) h->factored = true;
+  return rc;
+}
+
+extern "C" int spingp_logml(spingp_handle h, double* logml, double* datafit, double* logdet) {
+  if (!h || !logml) return SPINGP_E_INVALID;
+  if (!h->factored) return SPINGP_E_ORDER;
+  hipLaunchKernelGGL(k_copy_scalars, dim3(1), dim3(64), 0, h->stream, h->scal, h->n_points, logml, datafit, logdet);
+  return hip_ok(hipGetLastError());
+}
+
+template <int B, int MODE>
+static int launch_bwd(spingp_ctx* h, const spg::BwdOut& o) {
+  prof_begin(h);
+  hipLaunchKernelGGL((spg::k_bwd<B, kR, kL, MODE>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t, h->y,
+                     h->n_points, h->hyper, h->lane, h->lane_ld, h->msgs, h->tree_ld, o);
+  prof_end(h, 3);
+  return hip_ok(hipGetLastError());
+}
+
+static spg::BwdOut make_out(spingp_ctx* h) {
+  spg::BwdOut o;
+  memset(&o, 0, sizeof(o));
+  o.ld = h->n_points;
+  o.grad_part = h->gpart;
+  o.gp_ld = h->G_max;
+  return o;
+}
+
+extern "C" int spingp_solve(spingp_handle h, double* f_mean, double* z_mean) {
+  if (!h) return SPINGP_E_INVALID;
+  if (!h->factored) return SPINGP_E_ORDER;
+  if (!f_mean && !z_mean) return SPINGP_OK;
+  spg::BwdOut o = make_out(h);
+  o.f_mean = f_mean;
+  o.z_mean = z_mean;
+  return (h->b == 2) ? launch_bwd<2, spg::kWantMean>(h, o) : launch_bwd<3, spg::kWantMean>(h, o);
+}
+
+extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, double* S_sub) {
+  if (!h) return SPINGP_E_INVALID;
+  if (!h->factored) return SPINGP_E_ORDER;
+  if (!f_var && !S_diag && !S_sub) return SPINGP_OK;
+  spg::BwdOut o = make_out(h);
+  o.f_var = f_var;
+  o.S_diag = S_diag;
+  o.S_sub = S_sub;
+  if (S_sub)
+    return (h->b == 2) ? launch_bwd<2, spg::kWantVar | spg::kWantSub>(h, o)
+                       : launch_bwd<3, spg::kWantVar | spg::kWantSub>(h, o);
+  return (h->b == 2) ? launch_bwd<2, spg::kWantVar>(h, o) : launch_bwd<3, spg::kWantVar>(h, o);
+}
+
+extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
+  if (!h || !logml || !grad) return SPINGP_E_INVALID;
+  if (!h->assembled) return SPINGP_E_ORDER;
+  int rc = SPINGP_OK;
+  if (!h->factored) {
+    rc = spingp_factor(h);
+    if (rc) return rc;
+  }
+  spg::BwdOut o = make_out(h);
+  rc = (h->b == 2) ? launch_bwd<2, spg::kWantGrad>(h, o) : launch_bwd<3, spg::kWantGrad>(h, o);
+  if (rc) return rc;
+  prof_begin(h);
+  hipLaunchKernelGGL((spg::k_finalize<kFinT>), dim3(1), dim3(kFinT), 0, h->stream, h->gpart, h->G_max, h->G, 3,
+                     h->scal, logml, grad);
+  prof_end(h, 4);
+  return hip_ok(hipGetLastError());
+}
+
+extern "C" int spingp_status(spingp_handle h, int64_t* first_bad) {
+  if (!h) return SPINGP_E_INVALID;
+  if (first_bad) *first_bad = -1;
+  if (hipStreamSynchronize(h->stream) != hipSuccess) return SPINGP_E_HIP;
+  if (!h->assembled) return SPINGP_OK;
+  unsigned long long key = 0;
+  if (hipMemcpy(&key, h->key, sizeof(key), hipMemcpyDeviceToHost) != hipSuccess) return SPINGP_E_HIP;
+  if (key == ~0ull) return SPINGP_OK;
+  const int code = (int)(key & 15ull);
+  const int64_t idx = (int64_t)(key >> 4) - 1;
+  if (first_bad) *first_bad = idx;
+  return code;
+}
+
+extern "C" const char* spingp_strerror(int code) {
+  switch (code) {
+    case SPINGP_OK: return "ok";
+    case SPINGP_E_INVALID: return "invalid argument";
+    case SPINGP_E_ORDER: return "call made before the calls it depends on";
+    case SPINGP_E_UNSORTED: return "time points decrease inside a series";
+    case SPINGP_E_NONFINITE: return "non-finite time or observation";
+    case SPINGP_E_HYPER: return "hyperparameter not finite or not positive";
+    case SPINGP_E_NOMEM: return "device workspace allocation failed";
+    case SPINGP_E_HIP: return "HIP runtime error";
+    case SPINGP_E_UNSUPPORTED: return "model or size not supported";
+    default: return "unknown status";
+  }
+}

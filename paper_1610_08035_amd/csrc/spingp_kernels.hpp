@@ -1,0 +1,687 @@
+// Kernels of the single-series hot path: chunk fold + work-group reduction (fwd), reduction
+// over work-group aggregates with the two down-sweeps (top), work-group down-sweep + chunk
+// elimination + adjoint sweep (bwd), and a fixed-order sum of gradient partials (finalize).
+//
+// Work decomposition for N points, R points per lane and L lanes per work-group:
+//   chunk j covers nodes [j R, min((j+1) R, N)); element E_j spans edge-wise from the chunk's
+//   first node to the next chunk's first node (the last chunk ends in a terminal edge A = 0).
+//   Work-group g owns chunks [g L, (g+1) L).  The reduction tree is: a sequential fold inside a
+//   lane (R nodes), a balanced tree over the L lanes in LDS, a balanced tree over the G
+//   work-groups in the top kernel.  Down-sweeps deliver, for every chunk, the predicted state
+//   (m, P) at its first node (prefix from the prior) and the information (J, eta) on its
+//   successor (suffix from the end); those seed the chunk's elimination and adjoint sweep.
+#pragma once
+#include "spingp_device.hpp"
+
+namespace spg {
+
+// Hyperparameters are read from device memory, so replays of a captured launch pick up
+// new values.  Row layout: (lengthscale, signal variance, noise variance).
+template <int B>
+SPG_DEV SeriesPar load_par(const double* hyper) {
+  SeriesPar p;
+  p.ell = hyper[0];
+  p.var = hyper[1];
+  p.s2 = hyper[2];
+  p.lam = (B == 2 ? 1.7320508075688772935 : 2.2360679774997896964) / p.ell;
+  return p;
+}
+
+// Edge n -> n+1 of a series with n_pts points: transition and e = exp(-lam dt); the edge after
+// the last point is terminal (A = 0, Q = 0).  Returns false for the terminal edge.
+template <int B>
+SPG_DEV bool edge_of(const SeriesPar& p, const double* __restrict__ t, int64_t n, int64_t n_pts,
+                     double& dt, double& e, double (&A)[B][B]) {
+  if (n + 1 < n_pts) {
+    dt = t[n + 1] - t[n];
+    Matern<B>::transition(p, dt, e, A);
+    return true;
+  }
+  dt = 0.0;
+  e = 0.0;
+  mat_zero<B>(A);
+  return false;
+}
+
+// Sequential fold of the chunk's nodes into its element (rank-one observation information).
+// Q of the running element is carried as D = Q - P0 so that Q_n = P0 - A_n P0 A_n^T is never
+// formed: Q_new = A (Q - q q^T/s) A^T + Q_n  <=>  D_new = A (D - q q^T/s) A^T.
+template <int B, int R>
+SPG_DEV void fold_chunk(const SeriesPar& p, const double (&P0)[B][B], const double* __restrict__ t,
+                        const double* __restrict__ y, int64_t n_pts, int64_t start, int len, Elem<B>& E) {
+  const double is2 = 1.0 / p.s2;
+  double D[B][B];
+  {
+    // first node: element (A_s, 0, Q_s, J, eta_s) with the node's constants
+    double dt, e, A[B][B];
+    const bool ok = edge_of<B>(p, t, start, n_pts, dt, e, A);
+    mat_copy<B>(A, E.A);
+    if (ok) {
+      double T[B][B];
+      mm<B>(A, P0, T);
+      mmt_sym<B>(T, A, D);
+      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -D[i][j];
+    } else {
+      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -P0[i][j];
+    }
+    const double y0 = y[start];
+    mat_zero<B>(E.J);
+    E.J[0][0] = is2;
+    SPG_UNROLL for (int i = 0; i < B; ++i) {
+      E.b[i] = 0.0;
+      E.eta[i] = 0.0;
+    }
+    E.eta[0] = y0 * is2;
+    E.cf = -0.5 * y0 * y0 * is2;
+    E.cl = -0.5 * (kLog2Pi + log(p.s2));
+  }
+  SPG_UNROLL for (int k = 1; k < R; ++k) {
+    if (k < len) {
+      const int64_t n = start + k;
+      const double yn = y[n];
+      double q[B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) q[i] = D[i][0] + P0[i][0];
+      const double s = q[0] + p.s2;
+      const double is = 1.0 / s;
+      double a[B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) a[i] = E.A[0][i];
+      const double v = yn - E.b[0];
+      const double vis = v * is;
+      double Ap[B][B], bp[B], Dp[B][B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) {
+        const double ki = q[i] * is;
+        bp[i] = fma(ki, v, E.b[i]);
+        SPG_UNROLL for (int j = 0; j < B; ++j) Ap[i][j] = fma(-ki, a[j], E.A[i][j]);
+        SPG_UNROLL for (int j = i; j < B; ++j) Dp[i][j] = fma(-q[i] * is, q[j], D[i][j]);
+        E.eta[i] = fma(a[i], vis, E.eta[i]);
+        SPG_UNROLL for (int j = i; j < B; ++j) E.J[i][j] = fma(a[i] * is, a[j], E.J[i][j]);
+      }
+      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < i; ++j) {
+        Dp[i][j] = Dp[j][i];
+        E.J[i][j] = E.J[j][i];
+      }
+      E.cl += -0.5 * (kLog2Pi + log(s));
+      E.cf += -0.5 * v * vis;
+      double dt, e, A[B][B];
+      const bool ok = edge_of<B>(p, t, n, n_pts, dt, e, A);
+      if (ok) {
+        double T[B][B];
+        mm<B>(A, Ap, E.A);
+        mv<B>(A, bp, E.b);
+        mm<B>(A, Dp, T);
+        mmt_sym<B>(T, A, D);
+      } else {
+        mat_zero<B>(E.A);
+        SPG_UNROLL for (int i = 0; i < B; ++i) E.b[i] = 0.0;
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -P0[i][j];
+      }
+    }
+  }
+  SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) E.Q[i][j] = D[i][j] + P0[i][j];
+}
+
+// ---------------------------------------------------------------------------- LDS element pool
+// Field-major: field f of slot i lives at pool[f * NS + i].
+template <int B, int NS>
+SPG_DEV void lds_store(double* pool, int i, const Elem<B>& E) {
+  using Lay = ElemLayout<B>;
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = 0; c < B; ++c)
+    pool[(Lay::kA + r * B + c) * NS + i] = E.A[r][c];
+  SPG_UNROLL for (int r = 0; r < B; ++r) {
+    pool[(Lay::kb + r) * NS + i] = E.b[r];
+    pool[(Lay::keta + r) * NS + i] = E.eta[r];
+  }
+  int s = 0;
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) {
+    pool[(Lay::kQ + s) * NS + i] = E.Q[r][c];
+    pool[(Lay::kJ + s) * NS + i] = E.J[r][c];
+    ++s;
+  }
+  pool[Lay::kcf * NS + i] = E.cf;
+  pool[Lay::kcl * NS + i] = E.cl;
+}
+template <int B, int NS>
+SPG_DEV void lds_load(const double* pool, int i, Elem<B>& E) {
+  using Lay = ElemLayout<B>;
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = 0; c < B; ++c)
+    E.A[r][c] = pool[(Lay::kA + r * B + c) * NS + i];
+  SPG_UNROLL for (int r = 0; r < B; ++r) {
+    E.b[r] = pool[(Lay::kb + r) * NS + i];
+    E.eta[r] = pool[(Lay::keta + r) * NS + i];
+  }
+  int s = 0;
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) {
+    const double q = pool[(Lay::kQ + s) * NS + i];
+    const double j = pool[(Lay::kJ + s) * NS + i];
+    E.Q[r][c] = E.Q[c][r] = q;
+    E.J[r][c] = E.J[c][r] = j;
+    ++s;
+  }
+  E.cf = pool[Lay::kcf * NS + i];
+  E.cl = pool[Lay::kcl * NS + i];
+}
+// Messages (alpha = predicted (m, P) at the slot's first node, beta = information (J, eta) on
+// the slot's successor) overwrite a slot once its element is no longer needed.
+template <int B>
+struct Msg {
+  double m[B];
+  double P[B][B];
+  double J[B][B];
+  double eta[B];
+};
+template <int B, int NS>
+SPG_DEV void lds_store_msg(double* pool, int i, const Msg<B>& g) {
+  int f = 0;
+  SPG_UNROLL for (int r = 0; r < B; ++r) pool[(f++) * NS + i] = g.m[r];
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) pool[(f++) * NS + i] = g.P[r][c];
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) pool[(f++) * NS + i] = g.J[r][c];
+  SPG_UNROLL for (int r = 0; r < B; ++r) pool[(f++) * NS + i] = g.eta[r];
+}
+template <int B, int NS>
+SPG_DEV void lds_load_msg(const double* pool, int i, Msg<B>& g) {
+  int f = 0;
+  SPG_UNROLL for (int r = 0; r < B; ++r) g.m[r] = pool[(f++) * NS + i];
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) {
+    g.P[r][c] = g.P[c][r] = pool[(f++) * NS + i];
+  }
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) {
+    g.J[r][c] = g.J[c][r] = pool[(f++) * NS + i];
+  }
+  SPG_UNROLL for (int r = 0; r < B; ++r) g.eta[r] = pool[(f++) * NS + i];
+}
+template <int B>
+constexpr int msg_fields() { return 2 * B + B * (B + 1); }
+
+// Global message arrays (one per work-group): same packing, field-major with stride ld.
+template <int B>
+SPG_DEV void gmsg_store(double* base, int64_t ld, int64_t i, const Msg<B>& g) {
+  int f = 0;
+  SPG_UNROLL for (int r = 0; r < B; ++r) base[(f++) * ld + i] = g.m[r];
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) base[(f++) * ld + i] = g.P[r][c];
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) base[(f++) * ld + i] = g.J[r][c];
+  SPG_UNROLL for (int r = 0; r < B; ++r) base[(f++) * ld + i] = g.eta[r];
+}
+template <int B>
+SPG_DEV void gmsg_load(const double* base, int64_t ld, int64_t i, Msg<B>& g) {
+  int f = 0;
+  SPG_UNROLL for (int r = 0; r < B; ++r) g.m[r] = base[(f++) * ld + i];
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) {
+    g.P[r][c] = g.P[c][r] = base[(f++) * ld + i];
+  }
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) {
+    g.J[r][c] = g.J[c][r] = base[(f++) * ld + i];
+  }
+  SPG_UNROLL for (int r = 0; r < B; ++r) g.eta[r] = base[(f++) * ld + i];
+}
+
+// Children messages from a parent's message and the two children's elements:
+//   alpha(left) = alpha(parent),        alpha(right) = alpha(parent) pushed through T(left)
+//   beta(right) = beta(parent),         beta(left)   = beta(parent) pulled back through T(right)
+template <int B>
+SPG_DEV void split_msg(const Msg<B>& par, const Elem<B>& Tl, const Elem<B>& Tr, Msg<B>& gl, Msg<B>& gr) {
+  double dcf, dcl;
+  SPG_UNROLL for (int i = 0; i < B; ++i) gl.m[i] = par.m[i];
+  mat_copy<B>(par.P, gl.P);
+  prefix_combine<B>(par.m, par.P, Tl, gr.m, gr.P, dcf, dcl);
+  mat_copy<B>(par.J, gr.J);
+  SPG_UNROLL for (int i = 0; i < B; ++i) gr.eta[i] = par.eta[i];
+  suffix_combine<B>(Tr, par.J, par.eta, gl.J, gl.eta);
+}
+
+// ---------------------------------------------------------------------------- kernel: forward
+// One lane per chunk; a work-group reduces its L lane elements with a balanced tree in LDS.
+template <int B, int R, int L>
+__global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const double* __restrict__ y,
+                                            int64_t n_pts, const double* __restrict__ hyper,
+                                            double* __restrict__ lane_elems, int64_t lane_ld,
+                                            double* __restrict__ wg_elems, int64_t wg_ld) {
+  constexpr int NF = ElemLayout<B>::kFields;
+  __shared__ double pool[NF * L];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (int64_t)blockIdx.x * L + tid;
+  const int64_t start = chunk * R;
+  const SeriesPar p = load_par<B>(hyper);
+  double P0[B][B];
+  Matern<B>::pinf(p, P0);
+  Elem<B> E;
+  if (start < n_pts) {
+    const int len = (int)((n_pts - start) < R ? (n_pts - start) : R);
+    fold_chunk<B, R>(p, P0, t, y, n_pts, start, len, E);
+  } else {
+    elem_identity<B>(E);
+  }
+  elem_store<B>(lane_elems, lane_ld, chunk, E);
+  lds_store<B, L>(pool, tid, E);
+  __syncthreads();
+  SPG_UNROLL for (int stride = 1; stride < L; stride *= 2) {
+    const int i = tid * 2 * stride;
+    if (i < L) {
+      Elem<B> E1, E2, Rr;
+      lds_load<B, L>(pool, i, E1);
+      lds_load<B, L>(pool, i + stride, E2);
+      elem_combine<B>(E1, E2, Rr);
+      lds_store<B, L>(pool, i, Rr);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    lds_load<B, L>(pool, 0, E);
+    elem_store<B>(wg_elems, wg_ld, blockIdx.x, E);
+  }
+}
+
+// ---------------------------------------------------------------------------- kernel: top
+// Single work-group.  Balanced tree over G work-group aggregates in global scratch (levels
+// stored back to back), then the prefix and suffix down-sweeps; writes the message entering
+// every work-group and the log marginal likelihood (fit, log-det) parts.
+template <int B, int T>
+__global__ __launch_bounds__(T) void k_top(const double* __restrict__ hyper, const double* __restrict__ wg_elems,
+                                            int64_t wg_ld, int64_t G, int64_t G2, double* __restrict__ tree,
+                                            int64_t tree_ld, double* __restrict__ msgs, int64_t msg_ld,
+                                            double* __restrict__ scal) {
+  const int tid = threadIdx.x;
+  const SeriesPar p = load_par<B>(hyper);
+  double P0[B][B];
+  Matern<B>::pinf(p, P0);
+  // level 0
+  for (int64_t i = tid; i < G2; i += T) {
+    Elem<B> E;
+    if (i < G) elem_load<B>(wg_elems, wg_ld, i, E);
+    else elem_identity<B>(E);
+    elem_store<B>(tree, tree_ld, i, E);
+  }
+  __threadfence_block();
+  __syncthreads();
+  // up-sweep: level l occupies [off, off + cnt)
+  int64_t off = 0, cnt = G2;
+  while (cnt > 1) {
+    const int64_t noff = off + cnt, ncnt = cnt / 2;
+    for (int64_t i = tid; i < ncnt; i += T) {
+      Elem<B> E1, E2, Rr;
+      elem_load<B>(tree, tree_ld, off + 2 * i, E1);
+      elem_load<B>(tree, tree_ld, off + 2 * i + 1, E2);
+      elem_combine<B>(E1, E2, Rr);
+      elem_store<B>(tree, tree_ld, noff + i, Rr);
+    }
+    __threadfence_block();
+    __syncthreads();
+    off = noff;
+    cnt = ncnt;
+  }
+  // root: the prior N(0, P0) pushed through the whole chain gives the log normaliser
+  if (tid == 0) {
+    Elem<B> Troot;
+    elem_load<B>(tree, tree_ld, off, Troot);
+    double m0[B], mo[B], Po[B][B], dcf, dcl;
+    SPG_UNROLL for (int i = 0; i < B; ++i) m0[i] = 0.0;
+    prefix_combine<B>(m0, P0, Troot, mo, Po, dcf, dcl);
+    scal[0] = dcf + dcl;  // log marginal likelihood
+    scal[1] = dcf;
+    scal[2] = dcl;
+    Msg<B> g;
+    SPG_UNROLL for (int i = 0; i < B; ++i) {
+      g.m[i] = 0.0;
+      g.eta[i] = 0.0;
+    }
+    mat_copy<B>(P0, g.P);
+    mat_zero<B>(g.J);
+    // the root's message is kept in the message array at the root's slot
+    gmsg_store<B>(msgs, msg_ld, off, g);
+  }
+  __threadfence_block();
+  __syncthreads();
+  // down-sweep: from the root level to level 0
+  while (cnt < G2) {
+    const int64_t ncnt = cnt * 2, noff = off - ncnt;
+    for (int64_t i = tid; i < cnt; i += T) {
+      Msg<B> par, gl, gr;
+      Elem<B> Tl, Tr;
+      gmsg_load<B>(msgs, msg_ld, off + i, par);
+      elem_load<B>(tree, tree_ld, noff + 2 * i, Tl);
+      elem_load<B>(tree, tree_ld, noff + 2 * i + 1, Tr);
+      split_msg<B>(par, Tl, Tr, gl, gr);
+      gmsg_store<B>(msgs, msg_ld, noff + 2 * i, gl);
+      gmsg_store<B>(msgs, msg_ld, noff + 2 * i + 1, gr);
+    }
+    __threadfence_block();
+    __syncthreads();
+    off = noff;
+    cnt = ncnt;
+  }
+}
+
+// ---------------------------------------------------------------------------- kernel: backward
+// Output selection for the reverse sweep.
+enum : int { kWantGrad = 1, kWantMean = 2, kWantVar = 4, kWantSub = 8 };
+
+struct BwdOut {
+  double* f_mean;   // [N] or null
+  double* f_var;    // [N] or null
+  double* z_mean;   // [B][ld] or null
+  double* S_diag;   // [B(B+1)/2][ld] or null
+  double* S_sub;    // [B*B][ld] or null (row n = Cov(z_{n+1}, z_n | y))
+  int64_t ld;
+  double* grad_part;  // [3][G] per work-group partial gradients (lengthscale, variance, noise)
+  int64_t gp_ld;
+};
+
+template <int B, int R, int L, int MODE>
+__global__ __launch_bounds__(L) void k_bwd(const double* __restrict__ t, const double* __restrict__ y,
+                                            int64_t n_pts, const double* __restrict__ hyper,
+                                            const double* __restrict__ lane_elems, int64_t lane_ld,
+                                            const double* __restrict__ wg_msgs, int64_t wg_msg_ld, BwdOut out) {
+  constexpr int NS = 2 * L;   // tree slots: level 0 at [0, L), level 1 at [L, L + L/2), ...
+  constexpr int NF = ElemLayout<B>::kFields;
+  __shared__ double pool[NF * NS];
+  const int tid = threadIdx.x;
+  const int64_t chunk = (int64_t)blockIdx.x * L + tid;
+  const SeriesPar p = load_par<B>(hyper);
+  double P0[B][B];
+  Matern<B>::pinf(p, P0);
+
+  // ---- rebuild the work-group tree from the stored lane elements
+  {
+    Elem<B> E;
+    elem_load<B>(lane_elems, lane_ld, chunk, E);
+    lds_store<B, NS>(pool, tid, E);
+  }
+  __syncthreads();
+  {
+    int off = 0;
+    SPG_UNROLL for (int cnt = L; cnt > 1; cnt /= 2) {
+      const int noff = off + cnt;
+      if (tid < cnt / 2) {
+        Elem<B> E1, E2, Rr;
+        lds_load<B, NS>(pool, off + 2 * tid, E1);
+        lds_load<B, NS>(pool, off + 2 * tid + 1, E2);
+        elem_combine<B>(E1, E2, Rr);
+        lds_store<B, NS>(pool, noff + tid, Rr);
+      }
+      __syncthreads();
+      off = noff;
+    }
+    // root message of this work-group (replaces the root element)
+    if (tid == 0) {
+      Msg<B> g;
+      gmsg_load<B>(wg_msgs, wg_msg_ld, blockIdx.x, g);
+      lds_store_msg<B, NS>(pool, off, g);
+    }
+    __syncthreads();
+    // down-sweep
+    SPG_UNROLL for (int cnt = 1; cnt < L; cnt *= 2) {
+      const int ncnt = cnt * 2, noff = off - ncnt;
+      if (tid < cnt) {
+        Msg<B> par, gl, gr;
+        Elem<B> Tl, Tr;
+        lds_load_msg<B, NS>(pool, off + tid, par);
+        lds_load<B, NS>(pool, noff + 2 * tid, Tl);
+        lds_load<B, NS>(pool, noff + 2 * tid + 1, Tr);
+        split_msg<B>(par, Tl, Tr, gl, gr);
+        // both children are read by this thread only; write after reading
+        lds_store_msg<B, NS>(pool, noff + 2 * tid, gl);
+        lds_store_msg<B, NS>(pool, noff + 2 * tid + 1, gr);
+      }
+      __syncthreads();
+      off = noff;
+    }
+  }
+  Msg<B> g;
+  lds_load_msg<B, NS>(pool, tid, g);
+
+  // ---- chunk elimination (natural order) from the exact predicted state at its first node
+  const int64_t start = chunk * R;
+  const int len = start < n_pts ? (int)((n_pts - start) < R ? (n_pts - start) : R) : 0;
+  double sm[R][B];        // predicted means
+  double sD[R][B][B];     // predicted covariances minus P0
+  double sdt[R], se[R];   // gap and exp(-lam dt) of the edge leaving each node
+  double m[B], D[B][B];
+  SPG_UNROLL for (int i = 0; i < B; ++i) {
+    m[i] = g.m[i];
+    SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = g.P[i][j] - P0[i][j];
+  }
+  SPG_UNROLL for (int k = 0; k < R; ++k) {
+    if (k < len) {
+      const int64_t n = start + k;
+      SPG_UNROLL for (int i = 0; i < B; ++i) {
+        sm[k][i] = m[i];
+        SPG_UNROLL for (int j = 0; j < B; ++j) sD[k][i][j] = D[i][j];
+      }
+      double u[B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = D[i][0] + P0[i][0];
+      const double s = u[0] + p.s2, is = 1.0 / s;
+      const double v = y[n] - m[0];
+      double mp[B], Dp[B][B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) {
+        mp[i] = fma(u[i] * is, v, m[i]);
+        SPG_UNROLL for (int j = 0; j < B; ++j) Dp[i][j] = fma(-u[i] * is, u[j], D[i][j]);
+      }
+      double A[B][B];
+      const bool ok = edge_of<B>(p, t, n, n_pts, sdt[k], se[k], A);
+      if (ok) {
+        double T[B][B];
+        mv<B>(A, mp, m);
+        mm<B>(A, Dp, T);
+        mmt_sym<B>(T, A, D);
+      } else {
+        SPG_UNROLL for (int i = 0; i < B; ++i) {
+          m[i] = 0.0;
+          SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -P0[i][j];
+        }
+      }
+    }
+  }
+  // ---- adjoint seed at the successor of the chunk's last node:
+  //      L_rest(m, P) = log int N(z; m, P) exp(-1/2 z^T Jb z + etab^T z) dz
+  //      dL/dm = Gam^T etab - W m,  dL/dP = 1/2 (lam lam^T - W),  Gam = (I + P Jb)^-1, W = Jb Gam;
+  //      the smoothing information Lhat = lam lam^T - 2 dL/dP is W itself.
+  constexpr bool kGrad = (MODE & kWantGrad) != 0;
+  constexpr bool kCov = (MODE & (kWantVar | kWantSub)) != 0;
+  constexpr bool kSub = (MODE & kWantSub) != 0;
+  double lam[B], Lam[B][B], Lhat[B][B], Pn[B][B];
+  {
+    SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pn[i][j] = D[i][j] + P0[i][j];
+    double M[B][B], Gm[B][B], W[B][B], Gte[B], Wm[B];
+    mm<B>(Pn, g.J, M);
+    SPG_UNROLL for (int i = 0; i < B; ++i) M[i][i] += 1.0;
+    (void)inv_logdet<B>(M, Gm);
+    mm<B>(g.J, Gm, W);
+    symmetrize<B>(W);
+    mtv<B>(Gm, g.eta, Gte);
+    mv<B>(W, m, Wm);
+    SPG_UNROLL for (int i = 0; i < B; ++i) lam[i] = Gte[i] - Wm[i];
+    SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) {
+      Lam[i][j] = 0.5 * (lam[i] * lam[j] - W[i][j]);
+      Lhat[i][j] = W[i][j];
+    }
+  }
+  // ---- reverse sweep.  Per node n (newest first): prediction adjoint through edge n, smoothed
+  //      moments from the filtered state, then the update adjoint.  lam/Lam (gradient) follow
+  //      reverse-mode differentiation of the elimination; Lhat (covariances) follows the
+  //      modified Bryson-Frazier recursion Lhat_n = (I - K h^T)^T A^T Lhat_{n+1} A (I - K h^T)
+  //      + h h^T / s, which avoids forming lam lam^T - 2 Lam.
+  double gl_lam = 0.0, g_s2 = 0.0;   // <A_bar, dA/dlam> summed, d/d s2
+  double Pb[B][B];                   // adjoint of P0
+  mat_zero<B>(Pb);
+  SPG_UNROLL for (int k = R - 1; k >= 0; --k) {
+    if (k < len) {
+      const int64_t n = start + k;
+      double mk[B], Dk[B][B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) {
+        mk[i] = sm[k][i];
+        SPG_UNROLL for (int j = 0; j < B; ++j) Dk[i][j] = sD[k][i][j];
+      }
+      double u[B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = Dk[i][0] + P0[i][0];
+      const double s = u[0] + p.s2, is = 1.0 / s;
+      const double v = y[n] - mk[0];
+      double mp[B], Dp[B][B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) {
+        mp[i] = fma(u[i] * is, v, mk[i]);
+        SPG_UNROLL for (int j = 0; j < B; ++j) Dp[i][j] = fma(-u[i] * is, u[j], Dk[i][j]);
+      }
+      // prediction adjoint through edge n (nothing flows through the terminal edge)
+      double mbp[B], Pbp[B][B], Lhp[B][B];
+      const bool edge_ok = (n + 1 < n_pts);
+      double A[B][B];
+      if (edge_ok) {
+        const double dt = sdt[k], e = se[k];
+        Matern<B>::transition_e(p, dt, e, A);
+        mtv<B>(A, lam, mbp);            // A^T lam'
+        if (kGrad) {
+          double T[B][B], TD[B][B], Ab[B][B];
+          mm<B>(Lam, A, T);             // Lam' A
+          mtm_sym<B>(A, T, Pbp);        // A^T Lam' A
+          mm<B>(T, Dp, TD);
+          // A_bar = lam' m+^T + 2 Lam' A (P+ - P0): the A-dependence of Q = P0 - A P0 A^T included
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+            Ab[i][j] = fma(lam[i], mp[j], 2.0 * TD[i][j]);
+          gl_lam += Matern<B>::dA_dlam_dot(p, dt, e, Ab);
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+            Pb[i][j] += Lam[i][j] - Pbp[i][j];
+        }
+        if (kCov) {
+          double T[B][B];
+          mm<B>(Lhat, A, T);
+          mtm_sym<B>(A, T, Lhp);        // A^T Lhat' A
+        }
+      } else {
+        mat_zero<B>(A);
+        SPG_UNROLL for (int i = 0; i < B; ++i) {
+          mbp[i] = 0.0;
+          SPG_UNROLL for (int j = 0; j < B; ++j) {
+            Pbp[i][j] = 0.0;
+            Lhp[i][j] = 0.0;
+          }
+        }
+      }
+      // smoothed moments of node n from the filtered state (m+, P+):
+      //   mu = m+ + P+ A^T lam',   S = P+ - P+ (A^T Lhat' A) P+,
+      //   Cov(z_{n+1}, z_n | y) = (I - P_{n+1} Lhat_{n+1}) A P+
+      if (MODE & (kWantMean | kWantVar | kWantSub)) {
+        double Ppl[B][B], Pl[B], mu[B];
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Ppl[i][j] = Dp[i][j] + P0[i][j];
+        mv<B>(Ppl, mbp, Pl);
+        SPG_UNROLL for (int i = 0; i < B; ++i) mu[i] = mp[i] + Pl[i];
+        if (out.f_mean) out.f_mean[n] = mu[0];
+        if (out.z_mean) SPG_UNROLL for (int i = 0; i < B; ++i) out.z_mean[(int64_t)i * out.ld + n] = mu[i];
+        if (kCov) {
+          double X[B][B], S[B][B];
+          mm<B>(Ppl, Lhp, X);
+          mmt_sym<B>(X, Ppl, S);
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) S[i][j] = Ppl[i][j] - S[i][j];
+          if (out.f_var) out.f_var[n] = S[0][0];
+          if (out.S_diag) {
+            int s_ = 0;
+            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j)
+              out.S_diag[(int64_t)(s_++) * out.ld + n] = S[i][j];
+          }
+          if (kSub && edge_ok && out.S_sub) {
+            double Y[B][B], AP[B][B], Ssub[B][B];
+            mm<B>(Pn, Lhat, Y);
+            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+              Y[i][j] = (i == j ? 1.0 : 0.0) - Y[i][j];
+            mm<B>(A, Ppl, AP);
+            mm<B>(Y, AP, Ssub);
+            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+              out.S_sub[(int64_t)(i * B + j) * out.ld + n] = Ssub[i][j];
+          }
+        }
+      }
+      // update adjoint at node n (h = e_0): adjoints of the predicted state (m_n, P_n)
+      const double kl = dot<B>(u, mbp) * is;      // K^T lam+
+      const double vbar = kl - v * is;
+      if (kGrad) {
+        double w[B];
+        mv<B>(Pbp, u, w);
+        const double uw = dot<B>(u, w);
+        const double sbar = (uw - kl * s * v) * is * is - 0.5 * is + 0.5 * v * v * is * is;
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Lam[i][j] = Pbp[i][j];
+        Lam[0][0] += sbar;
+        SPG_UNROLL for (int i = 0; i < B; ++i) {
+          const double ub = (mbp[i] * v - 2.0 * w[i]) * is;
+          Lam[0][i] += 0.5 * ub;
+          Lam[i][0] += 0.5 * ub;
+        }
+        g_s2 += sbar;
+      }
+      if (kCov) {
+        // Lhat = (I - K e0^T)^T Lhp (I - K e0^T) + e0 e0^T / s,  K = u / s
+        double Lk[B], Y[B][B];
+        SPG_UNROLL for (int i = 0; i < B; ++i) {
+          double t_ = 0.0;
+          SPG_UNROLL for (int j = 0; j < B; ++j) t_ = fma(Lhp[i][j], u[j], t_);
+          Lk[i] = t_ * is;                         // Lhp K
+        }
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Y[i][j] = Lhp[i][j];
+        SPG_UNROLL for (int i = 0; i < B; ++i) Y[i][0] -= Lk[i];          // Lhp (I - K e0^T)
+        double KY[B];
+        SPG_UNROLL for (int j = 0; j < B; ++j) {
+          double t_ = 0.0;
+          SPG_UNROLL for (int i = 0; i < B; ++i) t_ = fma(u[i], Y[i][j], t_);
+          KY[j] = t_ * is;                         // K^T Y
+        }
+        SPG_UNROLL for (int j = 0; j < B; ++j) Y[0][j] -= KY[j];
+        Y[0][0] += is;
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j) {
+          Lhat[i][j] = 0.5 * (Y[i][j] + Y[j][i]);
+          Lhat[j][i] = Lhat[i][j];
+        }
+        if (kSub) SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pn[i][j] = Dk[i][j] + P0[i][j];
+      }
+      SPG_UNROLL for (int i = 0; i < B; ++i) lam[i] = mbp[i];
+      lam[0] -= vbar;
+      // the first node of the series is drawn from the prior N(0, P0)
+      if (kGrad && n == 0) {
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pb[i][j] += Lam[i][j];
+      }
+    }
+  }
+  // ---- gradient partials: lengthscale, signal variance, noise variance
+  if (MODE & kWantGrad) {
+    double dP[B][B];
+    Matern<B>::dpinf_dlam(p, dP);
+    const double dlam_dell = -p.lam / p.ell;
+    double gr[3];
+    gr[0] = (gl_lam + frob<B>(Pb, dP)) * dlam_dell;
+    gr[1] = frob<B>(Pb, P0) / p.var;
+    gr[2] = g_s2;
+    // fixed-order work-group reduction (reuses the pool)
+    __syncthreads();
+    SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] = gr[c];
+    __syncthreads();
+    SPG_UNROLL for (int stride = L / 2; stride > 0; stride /= 2) {
+      if (tid < stride) {
+        SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] += pool[c * L + tid + stride];
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      SPG_UNROLL for (int c = 0; c < 3; ++c) out.grad_part[c * out.gp_ld + blockIdx.x] = pool[c * L];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- kernel: finalize
+// Fixed-order sum of the per-work-group partials; copies the log marginal likelihood.
+template <int T>
+__global__ __launch_bounds__(T) void k_finalize(const double* __restrict__ grad_part, int64_t gp_ld, int64_t G,
+                                                 int n_grad, const double* __restrict__ scal,
+                                                 double* __restrict__ logml, double* __restrict__ grad) {
+  __shared__ double red[T];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < n_grad; ++c) {
+    double s = 0.0;
+    for (int64_t i = tid; i < G; i += T) s += grad_part[c * gp_ld + i];
+    red[tid] = s;
+    __syncthreads();
+    for (int stride = T / 2; stride > 0; stride /= 2) {
+      if (tid < stride) red[tid] += red[tid + stride];
+      __syncthreads();
+    }
+    if (tid == 0 && grad) grad[c] = red[0];
+    __syncthreads();
+  }
+  if (tid == 0 && logml) logml[0] = scal[0];
+}
+
+}  // namespace spg

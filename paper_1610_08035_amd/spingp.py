@@ -1,0 +1,238 @@
+"""Thin Python binding of the C ABI in include/spingp.h (argument marshalling only).
+
+Every step of the computation runs in the gfx950 library ``libspingp.so``; this module only
+turns torch tensors into device pointers and the current HIP stream into the handle's
+stream.  It raises if the library is missing or no GPU is present: there is no CPU path.
+The functions carry the C names; `Handle` bundles them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspingp.so")
+
+MATERN32, MATERN52, PERIODIC = 1, 2, 3
+
+ERRORS = {
+    0: "ok", 1: "invalid argument", 2: "call order", 3: "unsorted times", 4: "non-finite input",
+    5: "bad hyperparameter", 6: "out of device memory", 7: "HIP runtime error", 8: "unsupported",
+}
+
+
+class SpinGPError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {ERRORS.get(code, code)} (status {code})")
+        self.code = code
+
+
+class _Term(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("harmonics", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def library_loaded() -> bool:
+    return _lib is not None
+
+
+def load_library():
+    """Load libspingp.so (built in-tree by __graft_entry__.build()); raise loudly otherwise."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    lib.spingp_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Term), i32, i64, i32, vp]
+    lib.spingp_destroy.argtypes = [vp]
+    lib.spingp_state_dim.argtypes = [vp]
+    lib.spingp_n_hyper.argtypes = [vp]
+    lib.spingp_assemble.argtypes = [vp, vp, vp, vp, i32, i64, vp, u32]
+    lib.spingp_factor.argtypes = [vp]
+    lib.spingp_logml.argtypes = [vp, vp, vp, vp]
+    lib.spingp_solve.argtypes = [vp, vp, vp]
+    lib.spingp_selinv.argtypes = [vp, vp, vp, vp]
+    lib.spingp_logml_grad.argtypes = [vp, vp, vp]
+    lib.spingp_status.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.spingp_profile.argtypes = [vp, ctypes.c_int]
+    lib.spingp_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.spingp_strerror.argtypes = [ctypes.c_int]
+    lib.spingp_strerror.restype = ctypes.c_char_p
+    for name in ("spingp_create", "spingp_destroy", "spingp_state_dim", "spingp_n_hyper", "spingp_assemble",
+                 "spingp_factor", "spingp_logml", "spingp_solve", "spingp_selinv", "spingp_logml_grad",
+                 "spingp_status", "spingp_profile", "spingp_profile_read"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise SpinGPError(rc, where)
+
+
+def _dev(x, name, n=None):
+    if x is None:
+        return None
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor on the GPU")
+    if n is not None and x.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, has {x.numel()}")
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# --------------------------------------------------------------------------- C-named calls
+def spingp_create(terms, max_points, max_series=1, stream=None):
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: the SpInGP library runs on the GPU only")
+    arr = (_Term * len(terms))(*[_Term(k, h) for k, h in terms])
+    h = ctypes.c_void_p()
+    _check(lib.spingp_create(ctypes.byref(h), arr, len(terms), int(max_points), int(max_series),
+                             _stream_ptr(stream)), "spingp_create")
+    return h
+
+
+def spingp_destroy(h):
+    _check(load_library().spingp_destroy(h), "spingp_destroy")
+
+
+def spingp_assemble(h, t, y, hyper, offsets=None, n_series=1):
+    n = t.numel()
+    off = None
+    if offsets is not None:
+        if offsets.dtype != torch.int64 or not offsets.is_cuda:
+            raise ValueError("offsets must be an int64 tensor on the GPU")
+        off = ctypes.c_void_p(offsets.data_ptr())
+    _check(load_library().spingp_assemble(h, _dev(t, "t"), _dev(y, "y", n), off, int(n_series), int(n),
+                                          _dev(hyper, "hyper"), 0), "spingp_assemble")
+
+
+def spingp_factor(h):
+    _check(load_library().spingp_factor(h), "spingp_factor")
+
+
+def spingp_logml(h, logml, datafit=None, logdet=None):
+    _check(load_library().spingp_logml(h, _dev(logml, "logml"), _dev(datafit, "datafit"), _dev(logdet, "logdet")),
+           "spingp_logml")
+
+
+def spingp_solve(h, f_mean=None, z_mean=None):
+    _check(load_library().spingp_solve(h, _dev(f_mean, "f_mean"), _dev(z_mean, "z_mean")), "spingp_solve")
+
+
+def spingp_selinv(h, f_var=None, S_diag=None, S_sub=None):
+    _check(load_library().spingp_selinv(h, _dev(f_var, "f_var"), _dev(S_diag, "S_diag"), _dev(S_sub, "S_sub")),
+           "spingp_selinv")
+
+
+def spingp_logml_grad(h, logml, grad):
+    _check(load_library().spingp_logml_grad(h, _dev(logml, "logml"), _dev(grad, "grad")), "spingp_logml_grad")
+
+
+def spingp_status(h):
+    bad = ctypes.c_int64(-1)
+    rc = load_library().spingp_status(h, ctypes.byref(bad))
+    return rc, bad.value
+
+
+N_KERNELS = 5
+KERNEL_NAMES = ("validate", "fwd_fold_tree", "top_tree", "bwd_elim_adjoint", "finalize")
+
+
+def spingp_profile(h, enable):
+    _check(load_library().spingp_profile(h, int(bool(enable))), "spingp_profile")
+
+
+def spingp_profile_read(h):
+    ms = (ctypes.c_double * N_KERNELS)()
+    cnt = (ctypes.c_int64 * N_KERNELS)()
+    _check(load_library().spingp_profile_read(h, ms, cnt), "spingp_profile_read")
+    return {KERNEL_NAMES[i]: (ms[i], cnt[i]) for i in range(N_KERNELS)}
+
+
+# --------------------------------------------------------------------------- convenience
+class Handle:
+    """One model, one stream, workspace sized for `max_points`."""
+
+    def __init__(self, terms, max_points, max_series=1, stream=None):
+        self.terms = [tuple(x) for x in terms]
+        self._h = spingp_create(self.terms, max_points, max_series, stream)
+        lib = load_library()
+        self.b = lib.spingp_state_dim(self._h)
+        self.n_hyper = lib.spingp_n_hyper(self._h)
+        self.n = 0
+        self.n_series = 1
+        self._keep = ()
+
+    def close(self):
+        if self._h is not None:
+            spingp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def assemble(self, t, y, hyper, offsets=None):
+        n_series = 1 if offsets is None else offsets.numel() - 1
+        spingp_assemble(self._h, t, y, hyper, offsets, n_series)
+        self.n = t.numel()
+        self.n_series = n_series
+        self._keep = (t, y, hyper, offsets)   # keep the bound buffers alive
+
+    def factor(self):
+        spingp_factor(self._h)
+
+    def logml(self, parts=False):
+        dev = self._keep[0].device
+        out = torch.empty(self.n_series, dtype=torch.float64, device=dev)
+        if not parts:
+            spingp_logml(self._h, out)
+            return out
+        fit = torch.empty_like(out)
+        ld = torch.empty_like(out)
+        spingp_logml(self._h, out, fit, ld)
+        return out, fit, ld
+
+    def solve(self, states=False):
+        dev = self._keep[0].device
+        f = torch.empty(self.n, dtype=torch.float64, device=dev)
+        z = torch.empty(self.b, self.n, dtype=torch.float64, device=dev) if states else None
+        spingp_solve(self._h, f, z)
+        return (f, z) if states else f
+
+    def selinv(self, blocks=False):
+        dev = self._keep[0].device
+        v = torch.empty(self.n, dtype=torch.float64, device=dev)
+        if not blocks:
+            spingp_selinv(self._h, v)
+            return v
+        sd = torch.empty(self.b * (self.b + 1) // 2, self.n, dtype=torch.float64, device=dev)
+        ss = torch.zeros(self.b * self.b, self.n, dtype=torch.float64, device=dev)
+        spingp_selinv(self._h, v, sd, ss)
+        return v, sd, ss
+
+    def logml_grad(self):
+        dev = self._keep[0].device
+        ll = torch.empty(self.n_series, dtype=torch.float64, device=dev)
+        g = torch.empty(self.n_series, self.n_hyper, dtype=torch.float64, device=dev)
+        spingp_logml_grad(self._h, ll, g)
+        return ll, g
+
+    def status(self):
+        return spingp_status(self._h)
