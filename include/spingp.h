@@ -121,8 +121,10 @@ int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, double* S_sub)
 
 /*
  * Log marginal likelihood and its gradient (Sec. 2.4) with respect to the raw hyperparameters
- * of the hyperparameter row: grad: [n_series x n_hyper].  Runs the factorisation itself when
- * the current one is missing or stale, then the adjoint of the reduction.  logml: [n_series].
+ * of the hyperparameter row: grad: [n_series x n_hyper], logml: [n_series].  Always runs the
+ * forward reduction itself (it reads the hyperparameters from device memory, so an optimiser may
+ * update them between calls without a new assemble), then the adjoint sweep; leaves the handle
+ * factored.  Needs assemble.
  */
 int spingp_logml_grad(spingp_handle h, double* logml, double* grad);
 
@@ -138,8 +140,9 @@ int spingp_status(spingp_handle h, int64_t* first_bad);
  * launch the library makes.  spingp_profile(h, 1) creates the events and starts recording,
  * spingp_profile(h, 0) stops and releases them.  spingp_profile_read synchronises and returns,
  * per kernel id (0 validate, 1 forward fold + work-group tree, 2 top-level tree and
- * down-sweeps, 3 work-group down-sweep + chunk elimination + adjoint, 4 finalize), the total
- * milliseconds and launch counts since the last read (host arrays of SPINGP_N_KERNELS).
+ * down-sweeps, 3 work-group down-sweep + chunk elimination + adjoint (+ gradient sum),
+ * 4 reserved), the total milliseconds and launch counts since the last read (host arrays of
+ * SPINGP_N_KERNELS).
  */
 #define SPINGP_N_KERNELS 5
 int spingp_profile(spingp_handle h, int enable);

@@ -13,8 +13,6 @@ namespace {
 
 constexpr int kR = 8;        // points folded sequentially per lane
 constexpr int kL = 128;      // lanes (chunks) per work-group
-constexpr int kTopT = 256;   // threads of the single-work-group top kernel
-constexpr int kFinT = 256;
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int64_t next_pow2(int64_t x) {
@@ -60,14 +58,15 @@ struct spingp_ctx {
   int64_t max_points = 0;
   hipStream_t stream = nullptr;
   // workspace
-  double* lane = nullptr;
-  double* wg = nullptr;
-  double* tree = nullptr;
-  double* msgs = nullptr;
+  double* lane = nullptr;          // work-group trees of the forward kernel (2L slots each)
+  double* top = nullptr;           // top-level tree over the work-group aggregates
+  unsigned int* top_cnt = nullptr; // arrival counters of the top-level bands
+  int64_t top_ld = 0, top_cnt_n = 0;
+  unsigned int* done = nullptr;     // finished work-groups of the backward kernel
   double* scal = nullptr;
   double* gpart = nullptr;
   unsigned long long* key = nullptr;
-  int64_t lane_ld = 0, wg_ld = 0, tree_ld = 0, G_max = 0;
+  int64_t lane_ld = 0, G_max = 0;
   // bound inputs
   const double* t = nullptr;
   const double* y = nullptr;
@@ -128,20 +127,29 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   h->max_points = max_points;
   h->stream = (hipStream_t)stream;
   const int NF = (b == 2) ? spg::ElemLayout<2>::kFields : spg::ElemLayout<3>::kFields;
-  const int MF = (b == 2) ? spg::msg_fields<2>() : spg::msg_fields<3>();
   const int64_t chunks = ceil_div(max_points, kR);
   h->G_max = ceil_div(chunks, kL);
-  h->lane_ld = h->G_max * kL;
-  h->wg_ld = h->G_max;
-  h->tree_ld = 2 * next_pow2(h->G_max);
+  h->lane_ld = h->G_max * 2 * kL;
+  int64_t ltop = 32;
+  while (ltop < h->G_max) ltop *= 32;
+  h->top_ld = 2 * ltop;
+  h->top_cnt_n = 0;
+  for (int64_t n = h->G_max; ; n = ceil_div(n, 32)) {
+    h->top_cnt_n += ceil_div(n, 32);
+    if (n <= 32) break;
+  }
   bool ok = true;
   ok = ok && hipMalloc(&h->lane, sizeof(double) * NF * h->lane_ld) == hipSuccess;
-  ok = ok && hipMalloc(&h->wg, sizeof(double) * NF * h->wg_ld) == hipSuccess;
-  ok = ok && hipMalloc(&h->tree, sizeof(double) * NF * h->tree_ld) == hipSuccess;
-  ok = ok && hipMalloc(&h->msgs, sizeof(double) * MF * h->tree_ld) == hipSuccess;
+  ok = ok && hipMalloc(&h->top, sizeof(double) * NF * h->top_ld) == hipSuccess;
+  ok = ok && hipMalloc(&h->top_cnt, sizeof(unsigned int) * h->top_cnt_n) == hipSuccess;
+  ok = ok && hipMemset(h->top_cnt, 0, sizeof(unsigned int) * h->top_cnt_n) == hipSuccess;
   ok = ok && hipMalloc(&h->scal, sizeof(double) * 8) == hipSuccess;
   ok = ok && hipMalloc(&h->gpart, sizeof(double) * 3 * h->G_max) == hipSuccess;
   ok = ok && hipMalloc(&h->key, sizeof(unsigned long long)) == hipSuccess;
+  ok = ok && hipMalloc(&h->done, sizeof(unsigned int)) == hipSuccess;
+  ok = ok && hipMemset(h->done, 0, sizeof(unsigned int)) == hipSuccess;
+  ok = ok && hipMemset(h->key, 0xff, sizeof(unsigned long long)) == hipSuccess;
+  ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     spingp_destroy(h);
     return SPINGP_E_NOMEM;
@@ -187,12 +195,12 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)spingp_profile(h, 0);
   if (h->stream || h->lane) (void)hipStreamSynchronize(h->stream);
   (void)hipFree(h->lane);
-  (void)hipFree(h->wg);
-  (void)hipFree(h->tree);
-  (void)hipFree(h->msgs);
+  (void)hipFree(h->top);
+  (void)hipFree(h->top_cnt);
   (void)hipFree(h->scal);
   (void)hipFree(h->gpart);
   (void)hipFree(h->key);
+  (void)hipFree(h->done);
   delete h;
   return SPINGP_OK;
 }
@@ -222,18 +230,40 @@ extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y
   return hip_ok(hipGetLastError());
 }
 
+static spg::TopTree make_top(spingp_ctx* h) {
+  spg::TopTree T;
+  memset(&T, 0, sizeof(T));
+  T.elems = h->top;
+  T.ld = h->top_ld;
+  T.G = h->G;
+  T.cnt = h->top_cnt;
+  int nb = 1;
+  int64_t ltop = 32;
+  while (ltop < h->G) {
+    ltop *= 32;
+    ++nb;
+  }
+  T.Ltop = ltop;
+  T.n_bands = nb;
+  int64_t off = 0, n = h->G;
+  for (int b = 0; b < nb; ++b) {
+    T.cnt_off[b] = off;
+    off += ceil_div(n, 32);
+    n = ceil_div(n, 32);
+  }
+  return T;
+}
+
 template <int B>
 static int launch_factor(spingp_ctx* h) {
-  constexpr int NF = spg::ElemLayout<B>::kFields;
-  (void)NF;
+  const spg::TopTree top = make_top(h);
   prof_begin(h);
   hipLaunchKernelGGL((spg::k_fwd<B, kR, kL>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t, h->y,
-                     h->n_points, h->hyper, h->lane, h->lane_ld, h->wg, h->wg_ld);
+                     h->n_points, h->hyper, h->lane, h->lane_ld, top, h->key);
   prof_end(h, 1);
-  const int64_t G2 = next_pow2(h->G);
   prof_begin(h);
-  hipLaunchKernelGGL((spg::k_top<B, kTopT>), dim3(1), dim3(kTopT), 0, h->stream, h->hyper, h->wg, h->wg_ld, h->G,
-                     G2, h->tree, h->tree_ld, h->msgs, h->tree_ld, h->scal);
+  hipLaunchKernelGGL((spg::k_top_bands<B>), dim3((unsigned)ceil_div(h->G, 32)), dim3(64), 0, h->stream, h->hyper,
+                     top, h->scal);
   prof_end(h, 2);
   return hip_ok(hipGetLastError());
 }
@@ -257,7 +287,7 @@ template <int B, int MODE>
 static int launch_bwd(spingp_ctx* h, const spg::BwdOut& o) {
   prof_begin(h);
   hipLaunchKernelGGL((spg::k_bwd<B, kR, kL, MODE>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t, h->y,
-                     h->n_points, h->hyper, h->lane, h->lane_ld, h->msgs, h->tree_ld, o);
+                     h->n_points, h->hyper, h->lane, h->lane_ld, make_top(h), o);
   prof_end(h, 3);
   return hip_ok(hipGetLastError());
 }
@@ -268,6 +298,8 @@ static spg::BwdOut make_out(spingp_ctx* h) {
   o.ld = h->n_points;
   o.grad_part = h->gpart;
   o.gp_ld = h->G_max;
+  o.done = h->done;
+  o.scal = h->scal;
   return o;
 }
 
@@ -298,19 +330,13 @@ extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, dou
 extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
   if (!h || !logml || !grad) return SPINGP_E_INVALID;
   if (!h->assembled) return SPINGP_E_ORDER;
-  int rc = SPINGP_OK;
-  if (!h->factored) {
-    rc = spingp_factor(h);
-    if (rc) return rc;
-  }
-  spg::BwdOut o = make_out(h);
-  rc = (h->b == 2) ? launch_bwd<2, spg::kWantGrad>(h, o) : launch_bwd<3, spg::kWantGrad>(h, o);
+  // the forward pass always runs: hyperparameters live in device memory and may have changed
+  int rc = spingp_factor(h);
   if (rc) return rc;
-  prof_begin(h);
-  hipLaunchKernelGGL((spg::k_finalize<kFinT>), dim3(1), dim3(kFinT), 0, h->stream, h->gpart, h->G_max, h->G, 3,
-                     h->scal, logml, grad);
-  prof_end(h, 4);
-  return hip_ok(hipGetLastError());
+  spg::BwdOut o = make_out(h);
+  o.logml = logml;
+  o.grad = grad;
+  return (h->b == 2) ? launch_bwd<2, spg::kWantGrad>(h, o) : launch_bwd<3, spg::kWantGrad>(h, o);
 }
 
 extern "C" int spingp_status(spingp_handle h, int64_t* first_bad) {

@@ -136,7 +136,7 @@ SPG_DEV double inv_logdet(const double (&Min)[B][B], double (&G)[B][B]) {
   double a[B][B];
   mat_copy<B>(Min, a);
   mat_eye<B>(G);
-  double ld = 0.0;
+  double pivprod = 1.0;
   SPG_UNROLL for (int c = 0; c < B; ++c) {
     // pivot row p >= c with the largest |a[p][c]|; exchange rows c and p of a and G
     SPG_UNROLL for (int r = c + 1; r < B; ++r) {
@@ -151,7 +151,7 @@ SPG_DEV double inv_logdet(const double (&Min)[B][B], double (&G)[B][B]) {
       }
     }
     const double piv = a[c][c];
-    ld += log(fabs(piv));
+    pivprod *= piv;
     const double ip = 1.0 / piv;
     SPG_UNROLL for (int k = 0; k < B; ++k) {
       a[c][k] *= ip;
@@ -166,7 +166,8 @@ SPG_DEV double inv_logdet(const double (&Min)[B][B], double (&G)[B][B]) {
       }
     }
   }
-  return ld;
+  // |det| = product of the pivots; for b <= 16 and M = I + Q J it stays far from overflow
+  return log(fabs(pivprod));
 }
 
 // ------------------------------------------------------------------ state-space models

@@ -189,58 +189,58 @@ SPG_DEV void lds_load_msg(const double* pool, int i, Msg<B>& g) {
   }
   SPG_UNROLL for (int r = 0; r < B; ++r) g.eta[r] = pool[(f++) * NS + i];
 }
+template <int B, int NS>
+SPG_DEV void lds_store_prefix(double* pool, int i, const double (&m)[B], const double (&P)[B][B]) {
+  int f = 0;
+  SPG_UNROLL for (int r = 0; r < B; ++r) pool[(f++) * NS + i] = m[r];
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) pool[(f++) * NS + i] = P[r][c];
+}
+template <int B, int NS>
+SPG_DEV void lds_store_suffix(double* pool, int i, const double (&J)[B][B], const double (&eta)[B]) {
+  int f = B + B * (B + 1) / 2;
+  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) pool[(f++) * NS + i] = J[r][c];
+  SPG_UNROLL for (int r = 0; r < B; ++r) pool[(f++) * NS + i] = eta[r];
+}
 template <int B>
 constexpr int msg_fields() { return 2 * B + B * (B + 1); }
 
-// Global message arrays (one per work-group): same packing, field-major with stride ld.
-template <int B>
-SPG_DEV void gmsg_store(double* base, int64_t ld, int64_t i, const Msg<B>& g) {
-  int f = 0;
-  SPG_UNROLL for (int r = 0; r < B; ++r) base[(f++) * ld + i] = g.m[r];
-  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) base[(f++) * ld + i] = g.P[r][c];
-  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) base[(f++) * ld + i] = g.J[r][c];
-  SPG_UNROLL for (int r = 0; r < B; ++r) base[(f++) * ld + i] = g.eta[r];
-}
-template <int B>
-SPG_DEV void gmsg_load(const double* base, int64_t ld, int64_t i, Msg<B>& g) {
-  int f = 0;
-  SPG_UNROLL for (int r = 0; r < B; ++r) g.m[r] = base[(f++) * ld + i];
-  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) {
-    g.P[r][c] = g.P[c][r] = base[(f++) * ld + i];
-  }
-  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) {
-    g.J[r][c] = g.J[c][r] = base[(f++) * ld + i];
-  }
-  SPG_UNROLL for (int r = 0; r < B; ++r) g.eta[r] = base[(f++) * ld + i];
-}
-
-// Children messages from a parent's message and the two children's elements:
-//   alpha(left) = alpha(parent),        alpha(right) = alpha(parent) pushed through T(left)
-//   beta(right) = beta(parent),         beta(left)   = beta(parent) pulled back through T(right)
-template <int B>
-SPG_DEV void split_msg(const Msg<B>& par, const Elem<B>& Tl, const Elem<B>& Tr, Msg<B>& gl, Msg<B>& gr) {
-  double dcf, dcl;
-  SPG_UNROLL for (int i = 0; i < B; ++i) gl.m[i] = par.m[i];
-  mat_copy<B>(par.P, gl.P);
-  prefix_combine<B>(par.m, par.P, Tl, gr.m, gr.P, dcf, dcl);
-  mat_copy<B>(par.J, gr.J);
-  SPG_UNROLL for (int i = 0; i < B; ++i) gr.eta[i] = par.eta[i];
-  suffix_combine<B>(Tr, par.J, par.eta, gl.J, gl.eta);
-}
+// ---------------------------------------------------------------------------- top-level tree
+// The work-group aggregates are the leaves of a complete binary tree with Ltop = 32^n_bands
+// leaves (identity elements pad it), reduced band by band, 5 levels per band, by k_top_bands.
+// Level l of the tree starts at slot 2 Ltop - 2 (Ltop >> l); the reverse sweep walks it from
+// the root to its own leaf.
+struct TopTree {
+  double* elems;          // field-major elements, leading dimension ld
+  int64_t ld;             // 2 * Ltop slots
+  int64_t G;              // real leaves (work-groups of the forward kernel)
+  int64_t Ltop;           // 32^n_bands
+  int n_bands;
+  unsigned int* cnt;      // arrival counters; band b, group q at cnt[cnt_off[b] + q]
+  int64_t cnt_off[7];
+};
+SPG_DEV int64_t top_level_off(const TopTree& T, int l) { return 2 * T.Ltop - 2 * (T.Ltop >> l); }
 
 // ---------------------------------------------------------------------------- kernel: forward
 // One lane per chunk; a work-group reduces its L lane elements with a balanced tree in LDS.
+// Every element of the tree is also written to global memory (lane elements at slot i < L,
+// internal nodes at slot L + level offset), so the backward kernel's down-sweep reuses it.
+// Tree slots: level 0 = [0, L), level 1 = [L, L + L/2), ..., root = 2L - 2.
 template <int B, int R, int L>
 __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const double* __restrict__ y,
                                             int64_t n_pts, const double* __restrict__ hyper,
-                                            double* __restrict__ lane_elems, int64_t lane_ld,
-                                            double* __restrict__ wg_elems, int64_t wg_ld) {
+                                            double* __restrict__ tree_elems, int64_t tree_ld, TopTree top,
+                                            unsigned long long* __restrict__ status) {
   constexpr int NF = ElemLayout<B>::kFields;
   __shared__ double pool[NF * L];
   const int tid = threadIdx.x;
   const int64_t chunk = (int64_t)blockIdx.x * L + tid;
   const int64_t start = chunk * R;
+  const int64_t gbase = (int64_t)blockIdx.x * (2 * L);
   const SeriesPar p = load_par<B>(hyper);
+  if (blockIdx.x == 0 && tid == 0) {
+    if (!(isfinite(p.ell) && p.ell > 0.0 && isfinite(p.var) && p.var > 0.0 && isfinite(p.s2) && p.s2 > 0.0))
+      atomicMin(status, 5ull);   // SPINGP_E_HYPER, no point index
+  }
   double P0[B][B];
   Matern<B>::pinf(p, P0);
   Elem<B> E;
@@ -250,9 +250,10 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
   } else {
     elem_identity<B>(E);
   }
-  elem_store<B>(lane_elems, lane_ld, chunk, E);
+  elem_store<B>(tree_elems, tree_ld, gbase + tid, E);
   lds_store<B, L>(pool, tid, E);
   __syncthreads();
+  int off = L;   // slot offset of the level being produced
   SPG_UNROLL for (int stride = 1; stride < L; stride *= 2) {
     const int i = tid * 2 * stride;
     if (i < L) {
@@ -261,92 +262,86 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
       lds_load<B, L>(pool, i + stride, E2);
       elem_combine<B>(E1, E2, Rr);
       lds_store<B, L>(pool, i, Rr);
+      elem_store<B>(tree_elems, tree_ld, gbase + off + tid, Rr);
     }
+    off += L / (2 * stride);
     __syncthreads();
   }
+  // this work-group's aggregate is leaf blockIdx.x of the top-level tree
   if (tid == 0) {
     lds_load<B, L>(pool, 0, E);
-    elem_store<B>(wg_elems, wg_ld, blockIdx.x, E);
+    elem_store<B>(top.elems, top.ld, blockIdx.x, E);
   }
 }
 
-// ---------------------------------------------------------------------------- kernel: top
-// Single work-group.  Balanced tree over G work-group aggregates in global scratch (levels
-// stored back to back), then the prefix and suffix down-sweeps; writes the message entering
-// every work-group and the log marginal likelihood (fit, log-det) parts.
-template <int B, int T>
-__global__ __launch_bounds__(T) void k_top(const double* __restrict__ hyper, const double* __restrict__ wg_elems,
-                                            int64_t wg_ld, int64_t G, int64_t G2, double* __restrict__ tree,
-                                            int64_t tree_ld, double* __restrict__ msgs, int64_t msg_ld,
-                                            double* __restrict__ scal) {
+// ---------------------------------------------------------------------------- kernel: top bands
+// One 64-thread work-group per group of 32 leaves of band 0.  Each reduces its group in LDS and
+// writes every node; then the last work-group of each group of 32 band-0 groups (atomic ticket,
+// no waiting) reduces band 1, and so on.  The work-group that completes the last band holds the
+// root and evaluates the log marginal likelihood.  Fences here only have to publish the few
+// nodes this small kernel writes.
+template <int B>
+__global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyper, TopTree top,
+                                                   double* __restrict__ scal) {
+  constexpr int NF = ElemLayout<B>::kFields;
+  __shared__ double pool[NF * 32];
+  __shared__ unsigned int s_ticket;
   const int tid = threadIdx.x;
-  const SeriesPar p = load_par<B>(hyper);
-  double P0[B][B];
-  Matern<B>::pinf(p, P0);
-  // level 0
-  for (int64_t i = tid; i < G2; i += T) {
-    Elem<B> E;
-    if (i < G) elem_load<B>(wg_elems, wg_ld, i, E);
-    else elem_identity<B>(E);
-    elem_store<B>(tree, tree_ld, i, E);
-  }
-  __threadfence_block();
-  __syncthreads();
-  // up-sweep: level l occupies [off, off + cnt)
-  int64_t off = 0, cnt = G2;
-  while (cnt > 1) {
-    const int64_t noff = off + cnt, ncnt = cnt / 2;
-    for (int64_t i = tid; i < ncnt; i += T) {
-      Elem<B> E1, E2, Rr;
-      elem_load<B>(tree, tree_ld, off + 2 * i, E1);
-      elem_load<B>(tree, tree_ld, off + 2 * i + 1, E2);
-      elem_combine<B>(E1, E2, Rr);
-      elem_store<B>(tree, tree_ld, noff + i, Rr);
+  int64_t group = blockIdx.x, nb = top.G;
+  for (int band = 0; band < top.n_bands; ++band) {
+    const int64_t glo = group << 5;
+    const int real = (int)((nb - glo) < 32 ? (nb - glo) : 32);
+    if (band > 0) {
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) s_ticket = atomicAdd(&top.cnt[top.cnt_off[band] + group], 1u);
+      __syncthreads();
+      if (s_ticket != (unsigned int)(real - 1)) return;     // not the last of its group
+      __threadfence();
     }
-    __threadfence_block();
+    const int lev0 = 5 * band;
+    const int64_t off0 = top_level_off(top, lev0);
+    if (tid < 32) {
+      Elem<B> Eg;
+      if (tid < real) {
+        elem_load<B>(top.elems, top.ld, off0 + glo + tid, Eg);
+      } else {
+        elem_identity<B>(Eg);
+        elem_store<B>(top.elems, top.ld, off0 + glo + tid, Eg);
+      }
+      lds_store<B, 32>(pool, tid, Eg);
+    }
     __syncthreads();
-    off = noff;
-    cnt = ncnt;
+    SPG_UNROLL for (int k = 0; k < 5; ++k) {
+      const int stride = 1 << k;
+      const int i = tid * 2 * stride;
+      if (i < 32) {
+        Elem<B> E1, E2, Rr;
+        lds_load<B, 32>(pool, i, E1);
+        lds_load<B, 32>(pool, i + stride, E2);
+        elem_combine<B>(E1, E2, Rr);
+        lds_store<B, 32>(pool, i, Rr);
+        elem_store<B>(top.elems, top.ld, top_level_off(top, lev0 + k + 1) + (glo >> (k + 1)) + tid, Rr);
+      }
+      __syncthreads();
+    }
+    if (band > 0 && tid == 0) top.cnt[top.cnt_off[band] + group] = 0u;   // ready for the next call
+    group = group >> 5;
+    nb = (nb + 31) >> 5;
   }
-  // root: the prior N(0, P0) pushed through the whole chain gives the log normaliser
+  // the prior N(0, P0) pushed through the whole chain gives the log normaliser
   if (tid == 0) {
+    const SeriesPar p = load_par<B>(hyper);
+    double P0[B][B];
+    Matern<B>::pinf(p, P0);
     Elem<B> Troot;
-    elem_load<B>(tree, tree_ld, off, Troot);
+    lds_load<B, 32>(pool, 0, Troot);
     double m0[B], mo[B], Po[B][B], dcf, dcl;
     SPG_UNROLL for (int i = 0; i < B; ++i) m0[i] = 0.0;
     prefix_combine<B>(m0, P0, Troot, mo, Po, dcf, dcl);
-    scal[0] = dcf + dcl;  // log marginal likelihood
+    scal[0] = dcf + dcl;
     scal[1] = dcf;
     scal[2] = dcl;
-    Msg<B> g;
-    SPG_UNROLL for (int i = 0; i < B; ++i) {
-      g.m[i] = 0.0;
-      g.eta[i] = 0.0;
-    }
-    mat_copy<B>(P0, g.P);
-    mat_zero<B>(g.J);
-    // the root's message is kept in the message array at the root's slot
-    gmsg_store<B>(msgs, msg_ld, off, g);
-  }
-  __threadfence_block();
-  __syncthreads();
-  // down-sweep: from the root level to level 0
-  while (cnt < G2) {
-    const int64_t ncnt = cnt * 2, noff = off - ncnt;
-    for (int64_t i = tid; i < cnt; i += T) {
-      Msg<B> par, gl, gr;
-      Elem<B> Tl, Tr;
-      gmsg_load<B>(msgs, msg_ld, off + i, par);
-      elem_load<B>(tree, tree_ld, noff + 2 * i, Tl);
-      elem_load<B>(tree, tree_ld, noff + 2 * i + 1, Tr);
-      split_msg<B>(par, Tl, Tr, gl, gr);
-      gmsg_store<B>(msgs, msg_ld, noff + 2 * i, gl);
-      gmsg_store<B>(msgs, msg_ld, noff + 2 * i + 1, gr);
-    }
-    __threadfence_block();
-    __syncthreads();
-    off = noff;
-    cnt = ncnt;
   }
 }
 
@@ -363,14 +358,20 @@ struct BwdOut {
   int64_t ld;
   double* grad_part;  // [3][G] per work-group partial gradients (lengthscale, variance, noise)
   int64_t gp_ld;
+  unsigned int* done;        // work-groups finished (the last one sums the partials, then resets it)
+  const double* scal;        // log-likelihood scalars of the forward pass
+  double* logml;             // [1] or null
+  double* grad;              // [3] or null
 };
 
 template <int B, int R, int L, int MODE>
 __global__ __launch_bounds__(L) void k_bwd(const double* __restrict__ t, const double* __restrict__ y,
                                             int64_t n_pts, const double* __restrict__ hyper,
-                                            const double* __restrict__ lane_elems, int64_t lane_ld,
-                                            const double* __restrict__ wg_msgs, int64_t wg_msg_ld, BwdOut out) {
-  constexpr int NS = 2 * L;   // tree slots: level 0 at [0, L), level 1 at [L, L + L/2), ...
+                                            const double* __restrict__ tree_elems, int64_t tree_ld,
+                                            const TopTree top, BwdOut out) {
+  // LDS slots: work-group tree level 0 at [0, L), level 1 at [L, L + L/2), ..., root 2L - 2;
+  // the siblings along the top-level path at [2L, 2L + 32)
+  constexpr int NS = 2 * L + 32;
   constexpr int NF = ElemLayout<B>::kFields;
   __shared__ double pool[NF * NS];
   const int tid = threadIdx.x;
@@ -379,47 +380,96 @@ __global__ __launch_bounds__(L) void k_bwd(const double* __restrict__ t, const d
   double P0[B][B];
   Matern<B>::pinf(p, P0);
 
-  // ---- rebuild the work-group tree from the stored lane elements
+  // ---- the work-group tree written by the forward kernel (the root element is not needed) and
+  //      the top-level siblings of the path from the top-level root to this work-group's leaf
+  const int64_t wg = blockIdx.x;
+  const int nlev = 5 * top.n_bands;
   {
+    const int64_t gbase = wg * (2 * L);
     Elem<B> E;
-    elem_load<B>(lane_elems, lane_ld, chunk, E);
+    elem_load<B>(tree_elems, tree_ld, gbase + tid, E);
     lds_store<B, NS>(pool, tid, E);
+    if (tid < L - 2) {
+      elem_load<B>(tree_elems, tree_ld, gbase + L + tid, E);
+      lds_store<B, NS>(pool, L + tid, E);
+    }
+    if (tid < nlev) {
+      // child level l = tid: the path node is wg >> l, its sibling (wg >> l) ^ 1
+      elem_load<B>(top.elems, top.ld, top_level_off(top, tid) + ((wg >> tid) ^ 1), E);
+      lds_store<B, NS>(pool, 2 * L + tid, E);
+    }
   }
   __syncthreads();
   {
-    int off = 0;
-    SPG_UNROLL for (int cnt = L; cnt > 1; cnt /= 2) {
-      const int noff = off + cnt;
-      if (tid < cnt / 2) {
-        Elem<B> E1, E2, Rr;
-        lds_load<B, NS>(pool, off + 2 * tid, E1);
-        lds_load<B, NS>(pool, off + 2 * tid + 1, E2);
-        elem_combine<B>(E1, E2, Rr);
-        lds_store<B, NS>(pool, noff + tid, Rr);
-      }
-      __syncthreads();
-      off = noff;
-    }
-    // root message of this work-group (replaces the root element)
+    int off = 2 * L - 2;   // root slot: receives the message entering this work-group
+    // message entering this work-group, walked down the top-level tree: the prefix part
+    // (predicted state from the prior) on wave 0, the suffix part (information from the end)
+    // on wave 1, one combine per level
     if (tid == 0) {
-      Msg<B> g;
-      gmsg_load<B>(wg_msgs, wg_msg_ld, blockIdx.x, g);
-      lds_store_msg<B, NS>(pool, off, g);
+      double m_[B], P_[B][B];
+      SPG_UNROLL for (int i = 0; i < B; ++i) m_[i] = 0.0;
+      mat_copy<B>(P0, P_);
+      for (int l = nlev - 1; l >= 0; --l) {
+        if ((wg >> l) & 1) {
+          Elem<B> Tl;
+          lds_load<B, NS>(pool, 2 * L + l, Tl);
+          double mo[B], Po[B][B], dcf, dcl;
+          prefix_combine<B>(m_, P_, Tl, mo, Po, dcf, dcl);
+          SPG_UNROLL for (int i = 0; i < B; ++i) m_[i] = mo[i];
+          mat_copy<B>(Po, P_);
+        }
+      }
+      lds_store_prefix<B, NS>(pool, off, m_, P_);
+    }
+    if (tid == L / 2) {
+      double J_[B][B], e_[B];
+      mat_zero<B>(J_);
+      SPG_UNROLL for (int i = 0; i < B; ++i) e_[i] = 0.0;
+      for (int l = nlev - 1; l >= 0; --l) {
+        if (!((wg >> l) & 1)) {
+          Elem<B> Tr;
+          lds_load<B, NS>(pool, 2 * L + l, Tr);
+          double Jo[B][B], eo[B];
+          suffix_combine<B>(Tr, J_, e_, Jo, eo);
+          mat_copy<B>(Jo, J_);
+          SPG_UNROLL for (int i = 0; i < B; ++i) e_[i] = eo[i];
+        }
+      }
+      lds_store_suffix<B, NS>(pool, off, J_, e_);
     }
     __syncthreads();
-    // down-sweep
+    // down-sweep: thread i < cnt carries the prefix of parent i into its right child, thread
+    // L/2 + i (another wavefront) the suffix of parent i into its left child.  Messages overwrite
+    // the children's element slots, so all reads of a level finish before its writes.
     SPG_UNROLL for (int cnt = 1; cnt < L; cnt *= 2) {
       const int ncnt = cnt * 2, noff = off - ncnt;
-      if (tid < cnt) {
-        Msg<B> par, gl, gr;
-        Elem<B> Tl, Tr;
-        lds_load_msg<B, NS>(pool, off + tid, par);
-        lds_load<B, NS>(pool, noff + 2 * tid, Tl);
-        lds_load<B, NS>(pool, noff + 2 * tid + 1, Tr);
-        split_msg<B>(par, Tl, Tr, gl, gr);
-        // both children are read by this thread only; write after reading
-        lds_store_msg<B, NS>(pool, noff + 2 * tid, gl);
-        lds_store_msg<B, NS>(pool, noff + 2 * tid + 1, gr);
+      const bool suf = tid >= L / 2;
+      const int i = suf ? tid - L / 2 : tid;
+      const bool active = i < cnt;
+      Msg<B> par;
+      double mo[B], Po[B][B], Jo[B][B], eo[B];
+      if (active) {
+        lds_load_msg<B, NS>(pool, off + i, par);
+        if (!suf) {
+          Elem<B> Tl;
+          lds_load<B, NS>(pool, noff + 2 * i, Tl);
+          double dcf, dcl;
+          prefix_combine<B>(par.m, par.P, Tl, mo, Po, dcf, dcl);
+        } else {
+          Elem<B> Tr;
+          lds_load<B, NS>(pool, noff + 2 * i + 1, Tr);
+          suffix_combine<B>(Tr, par.J, par.eta, Jo, eo);
+        }
+      }
+      __syncthreads();
+      if (active) {
+        if (!suf) {
+          lds_store_prefix<B, NS>(pool, noff + 2 * i, par.m, par.P);
+          lds_store_prefix<B, NS>(pool, noff + 2 * i + 1, mo, Po);
+        } else {
+          lds_store_suffix<B, NS>(pool, noff + 2 * i + 1, par.J, par.eta);
+          lds_store_suffix<B, NS>(pool, noff + 2 * i, Jo, eo);
+        }
       }
       __syncthreads();
       off = noff;
@@ -433,7 +483,6 @@ __global__ __launch_bounds__(L) void k_bwd(const double* __restrict__ t, const d
   const int len = start < n_pts ? (int)((n_pts - start) < R ? (n_pts - start) : R) : 0;
   double sm[R][B];        // predicted means
   double sD[R][B][B];     // predicted covariances minus P0
-  double sdt[R], se[R];   // gap and exp(-lam dt) of the edge leaving each node
   double m[B], D[B][B];
   SPG_UNROLL for (int i = 0; i < B; ++i) {
     m[i] = g.m[i];
@@ -455,8 +504,8 @@ __global__ __launch_bounds__(L) void k_bwd(const double* __restrict__ t, const d
         mp[i] = fma(u[i] * is, v, m[i]);
         SPG_UNROLL for (int j = 0; j < B; ++j) Dp[i][j] = fma(-u[i] * is, u[j], D[i][j]);
       }
-      double A[B][B];
-      const bool ok = edge_of<B>(p, t, n, n_pts, sdt[k], se[k], A);
+      double A[B][B], dt_, e_;
+      const bool ok = edge_of<B>(p, t, n, n_pts, dt_, e_, A);
       if (ok) {
         double T[B][B];
         mv<B>(A, mp, m);
@@ -524,8 +573,8 @@ __global__ __launch_bounds__(L) void k_bwd(const double* __restrict__ t, const d
       const bool edge_ok = (n + 1 < n_pts);
       double A[B][B];
       if (edge_ok) {
-        const double dt = sdt[k], e = se[k];
-        Matern<B>::transition_e(p, dt, e, A);
+        double dt, e;
+        (void)edge_of<B>(p, t, n, n_pts, dt, e, A);   // recomputed: cheaper than keeping it live
         mtv<B>(A, lam, mbp);            // A^T lam'
         if (kGrad) {
           double T[B][B], TD[B][B], Ab[B][B];
@@ -655,33 +704,38 @@ __global__ __launch_bounds__(L) void k_bwd(const double* __restrict__ t, const d
       }
       __syncthreads();
     }
+    // publish this work-group's partial; the last work-group to finish sums all partials in a
+    // fixed order (independent of which one is last) and resets the counter for the next call
+    __shared__ unsigned int ticket;
     if (tid == 0) {
       SPG_UNROLL for (int c = 0; c < 3; ++c) out.grad_part[c * out.gp_ld + blockIdx.x] = pool[c * L];
+      __threadfence();
+      ticket = atomicAdd(out.done, 1u);
     }
-  }
-}
-
-// ---------------------------------------------------------------------------- kernel: finalize
-// Fixed-order sum of the per-work-group partials; copies the log marginal likelihood.
-template <int T>
-__global__ __launch_bounds__(T) void k_finalize(const double* __restrict__ grad_part, int64_t gp_ld, int64_t G,
-                                                 int n_grad, const double* __restrict__ scal,
-                                                 double* __restrict__ logml, double* __restrict__ grad) {
-  __shared__ double red[T];
-  const int tid = threadIdx.x;
-  for (int c = 0; c < n_grad; ++c) {
-    double s = 0.0;
-    for (int64_t i = tid; i < G; i += T) s += grad_part[c * gp_ld + i];
-    red[tid] = s;
     __syncthreads();
-    for (int stride = T / 2; stride > 0; stride /= 2) {
-      if (tid < stride) red[tid] += red[tid + stride];
+    if (ticket == gridDim.x - 1) {
+      __threadfence();
+      const int64_t G = gridDim.x;
+      double acc[3] = {0.0, 0.0, 0.0};
+      for (int64_t i = tid; i < G; i += L) {
+        SPG_UNROLL for (int c = 0; c < 3; ++c) acc[c] += out.grad_part[c * out.gp_ld + i];
+      }
       __syncthreads();
+      SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] = acc[c];
+      __syncthreads();
+      SPG_UNROLL for (int stride = L / 2; stride > 0; stride /= 2) {
+        if (tid < stride) {
+          SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] += pool[c * L + tid + stride];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        if (out.grad) SPG_UNROLL for (int c = 0; c < 3; ++c) out.grad[c] = pool[c * L];
+        if (out.logml) out.logml[0] = out.scal[0];
+        *out.done = 0u;
+      }
     }
-    if (tid == 0 && grad) grad[c] = red[0];
-    __syncthreads();
   }
-  if (tid == 0 && logml) logml[0] = scal[0];
 }
 
 }  // namespace spg
