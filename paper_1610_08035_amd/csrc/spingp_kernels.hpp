@@ -365,108 +365,93 @@ struct BwdOut {
 };
 
 template <int B, int R, int L, int MODE>
-__global__ __launch_bounds__(L) void k_bwd(const double* __restrict__ t, const double* __restrict__ y,
+__global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, const double* __restrict__ y,
                                             int64_t n_pts, const double* __restrict__ hyper,
                                             const double* __restrict__ tree_elems, int64_t tree_ld,
                                             const TopTree top, BwdOut out) {
-  // LDS slots: work-group tree level 0 at [0, L), level 1 at [L, L + L/2), ..., root 2L - 2;
-  // the siblings along the top-level path at [2L, 2L + 32)
-  constexpr int NS = 2 * L + 32;
-  constexpr int NF = ElemLayout<B>::kFields;
-  __shared__ double pool[NF * NS];
+  // LDS holds messages only (the tree elements are read from global memory): message slot s
+  // follows the work-group tree's level-major layout (level 0 at [0, L), ..., root 2L - 2).
+  // Before the down-sweep the same space holds the top-level path siblings, field-major with
+  // stride 32.
+  constexpr int NS = 2 * L;
+  constexpr int MF = msg_fields<B>();
+  static_assert(MF * NS >= (ElemLayout<B>::kFields) * 32, "path siblings must fit in the message pool");
+  __shared__ double pool[MF * NS];
   const int tid = threadIdx.x;
   const int64_t chunk = (int64_t)blockIdx.x * L + tid;
   const SeriesPar p = load_par<B>(hyper);
   double P0[B][B];
   Matern<B>::pinf(p, P0);
-
-  // ---- the work-group tree written by the forward kernel (the root element is not needed) and
-  //      the top-level siblings of the path from the top-level root to this work-group's leaf
   const int64_t wg = blockIdx.x;
+  const int64_t gbase = wg * (2 * L);
   const int nlev = 5 * top.n_bands;
   {
-    const int64_t gbase = wg * (2 * L);
-    Elem<B> E;
-    elem_load<B>(tree_elems, tree_ld, gbase + tid, E);
-    lds_store<B, NS>(pool, tid, E);
-    if (tid < L - 2) {
-      elem_load<B>(tree_elems, tree_ld, gbase + L + tid, E);
-      lds_store<B, NS>(pool, L + tid, E);
-    }
+    // ---- top-level path: child level l = tid holds sibling (wg >> l) ^ 1 of the path node
     if (tid < nlev) {
-      // child level l = tid: the path node is wg >> l, its sibling (wg >> l) ^ 1
+      Elem<B> E;
       elem_load<B>(top.elems, top.ld, top_level_off(top, tid) + ((wg >> tid) ^ 1), E);
-      lds_store<B, NS>(pool, 2 * L + tid, E);
+      lds_store<B, 32>(pool, tid, E);
     }
-  }
-  __syncthreads();
-  {
-    int off = 2 * L - 2;   // root slot: receives the message entering this work-group
+    __syncthreads();
     // message entering this work-group, walked down the top-level tree: the prefix part
     // (predicted state from the prior) on wave 0, the suffix part (information from the end)
     // on wave 1, one combine per level
+    double m_[B], P_[B][B], J_[B][B], e_[B];
     if (tid == 0) {
-      double m_[B], P_[B][B];
       SPG_UNROLL for (int i = 0; i < B; ++i) m_[i] = 0.0;
       mat_copy<B>(P0, P_);
       for (int l = nlev - 1; l >= 0; --l) {
         if ((wg >> l) & 1) {
           Elem<B> Tl;
-          lds_load<B, NS>(pool, 2 * L + l, Tl);
+          lds_load<B, 32>(pool, l, Tl);
           double mo[B], Po[B][B], dcf, dcl;
           prefix_combine<B>(m_, P_, Tl, mo, Po, dcf, dcl);
           SPG_UNROLL for (int i = 0; i < B; ++i) m_[i] = mo[i];
           mat_copy<B>(Po, P_);
         }
       }
-      lds_store_prefix<B, NS>(pool, off, m_, P_);
     }
     if (tid == L / 2) {
-      double J_[B][B], e_[B];
       mat_zero<B>(J_);
       SPG_UNROLL for (int i = 0; i < B; ++i) e_[i] = 0.0;
       for (int l = nlev - 1; l >= 0; --l) {
         if (!((wg >> l) & 1)) {
           Elem<B> Tr;
-          lds_load<B, NS>(pool, 2 * L + l, Tr);
+          lds_load<B, 32>(pool, l, Tr);
           double Jo[B][B], eo[B];
           suffix_combine<B>(Tr, J_, e_, Jo, eo);
           mat_copy<B>(Jo, J_);
           SPG_UNROLL for (int i = 0; i < B; ++i) e_[i] = eo[i];
         }
       }
-      lds_store_suffix<B, NS>(pool, off, J_, e_);
     }
     __syncthreads();
-    // down-sweep: thread i < cnt carries the prefix of parent i into its right child, thread
-    // L/2 + i (another wavefront) the suffix of parent i into its left child.  Messages overwrite
-    // the children's element slots, so all reads of a level finish before its writes.
+    int off = 2 * L - 2;   // root slot: the message entering this work-group
+    if (tid == 0) lds_store_prefix<B, NS>(pool, off, m_, P_);
+    if (tid == L / 2) lds_store_suffix<B, NS>(pool, off, J_, e_);
+    __syncthreads();
+    // ---- work-group down-sweep: thread i < cnt carries the prefix of parent i into its right
+    //      child, thread L/2 + i (another wavefront) the suffix of parent i into its left child;
+    //      the children's elements come from the tree the forward kernel stored
     SPG_UNROLL for (int cnt = 1; cnt < L; cnt *= 2) {
       const int ncnt = cnt * 2, noff = off - ncnt;
       const bool suf = tid >= L / 2;
       const int i = suf ? tid - L / 2 : tid;
-      const bool active = i < cnt;
-      Msg<B> par;
-      double mo[B], Po[B][B], Jo[B][B], eo[B];
-      if (active) {
+      if (i < cnt) {
+        Msg<B> par;
         lds_load_msg<B, NS>(pool, off + i, par);
         if (!suf) {
           Elem<B> Tl;
-          lds_load<B, NS>(pool, noff + 2 * i, Tl);
-          double dcf, dcl;
+          elem_load<B>(tree_elems, tree_ld, gbase + noff + 2 * i, Tl);
+          double mo[B], Po[B][B], dcf, dcl;
           prefix_combine<B>(par.m, par.P, Tl, mo, Po, dcf, dcl);
-        } else {
-          Elem<B> Tr;
-          lds_load<B, NS>(pool, noff + 2 * i + 1, Tr);
-          suffix_combine<B>(Tr, par.J, par.eta, Jo, eo);
-        }
-      }
-      __syncthreads();
-      if (active) {
-        if (!suf) {
           lds_store_prefix<B, NS>(pool, noff + 2 * i, par.m, par.P);
           lds_store_prefix<B, NS>(pool, noff + 2 * i + 1, mo, Po);
         } else {
+          Elem<B> Tr;
+          elem_load<B>(tree_elems, tree_ld, gbase + noff + 2 * i + 1, Tr);
+          double Jo[B][B], eo[B];
+          suffix_combine<B>(Tr, par.J, par.eta, Jo, eo);
           lds_store_suffix<B, NS>(pool, noff + 2 * i + 1, par.J, par.eta);
           lds_store_suffix<B, NS>(pool, noff + 2 * i, Jo, eo);
         }
