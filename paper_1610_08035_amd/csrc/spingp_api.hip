@@ -13,6 +13,7 @@ namespace {
 
 constexpr int kR = 8;        // points folded sequentially per lane
 constexpr int kL = 128;      // lanes (chunks) per work-group
+constexpr int kT = 256;      // threads of the element-wise helper kernels
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 int64_t next_pow2(int64_t x) {
@@ -56,22 +57,29 @@ struct spingp_ctx {
   int b = 0;
   int n_hyper = 0;
   int64_t max_points = 0;
+  int32_t max_series = 0;
   hipStream_t stream = nullptr;
   // workspace
   double* lane = nullptr;          // work-group trees of the forward kernel (2L slots each)
   double* top = nullptr;           // top-level tree over the work-group aggregates
   unsigned int* top_cnt = nullptr; // arrival counters of the top-level bands
   int64_t top_ld = 0, top_cnt_n = 0;
-  unsigned int* done = nullptr;     // finished work-groups of the backward kernel
-  double* scal = nullptr;
-  double* gpart = nullptr;
+  unsigned int* done = nullptr;    // finished work-groups of the backward kernel
+  double* scal = nullptr;          // one series: log-likelihood terms at the root
+  double* part = nullptr;          // gradient / log-likelihood partials
+  int64_t part_ld = 0;
+  int32_t* chunk_series = nullptr; // several series: series of every chunk slot
+  int64_t* chunk_first = nullptr;  // several series: first chunk of every series
   unsigned long long* key = nullptr;
-  int64_t lane_ld = 0, G_max = 0;
+  int64_t lane_ld = 0, G_max = 0, slots_max = 0;
   // bound inputs
   const double* t = nullptr;
   const double* y = nullptr;
   const double* hyper = nullptr;
+  const int64_t* offsets = nullptr;
   int64_t n_points = 0;
+  int32_t n_series = 0;
+  bool batched = false;
   int64_t G = 0;
   bool assembled = false;
   bool factored = false;
@@ -111,24 +119,36 @@ static void prof_end(spingp_ctx* h, int kid) {
 
 static int hip_ok(hipError_t e) { return e == hipSuccess ? SPINGP_OK : SPINGP_E_HIP; }
 
+// Work-groups of the forward and reverse kernels for n points in s series: one lane per chunk
+// of R consecutive nodes of one series; with several series every series starts a new chunk,
+// so there are at most ceil(n / R) + s chunks (the unused slots at the end are padding).
+static int64_t groups_for(int64_t n, int64_t s, bool batched) {
+  const int64_t chunks = ceil_div(n, kR) + (batched ? s : 0);
+  return ceil_div(chunks, kL);
+}
+
 extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,
                              int32_t max_series, void* stream) {
   if (!out || !terms || n_terms < 1 || max_points < 1 || max_series < 1) return SPINGP_E_INVALID;
   *out = nullptr;
-  if (n_terms != 1 || max_series != 1) return SPINGP_E_UNSUPPORTED;
+  if (n_terms != 1) return SPINGP_E_UNSUPPORTED;
   int b;
   if (terms[0].kind == SPINGP_MATERN32) b = 2;
   else if (terms[0].kind == SPINGP_MATERN52) b = 3;
   else return SPINGP_E_UNSUPPORTED;
+  // grid sizes are 32-bit: at most 2^31 - 1 work-groups of the largest launch
+  if (max_points > (int64_t(1) << 40) || groups_for(max_points, max_series, max_series > 1) >= (int64_t(1) << 31))
+    return SPINGP_E_UNSUPPORTED;
   spingp_ctx* h = new (std::nothrow) spingp_ctx();
   if (!h) return SPINGP_E_NOMEM;
   h->b = b;
   h->n_hyper = 3;
   h->max_points = max_points;
+  h->max_series = max_series;
   h->stream = (hipStream_t)stream;
   const int NF = (b == 2) ? spg::ElemLayout<2>::kFields : spg::ElemLayout<3>::kFields;
-  const int64_t chunks = ceil_div(max_points, kR);
-  h->G_max = ceil_div(chunks, kL);
+  h->G_max = groups_for(max_points, max_series, max_series > 1);
+  h->slots_max = h->G_max * kL;
   h->lane_ld = h->G_max * 2 * kL;
   int64_t ltop = 32;
   while (ltop < h->G_max) ltop *= 32;
@@ -138,17 +158,23 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
     h->top_cnt_n += ceil_div(n, 32);
     if (n <= 32) break;
   }
+  h->part_ld = max_series > 1 ? h->slots_max : h->G_max;
+  const int64_t part_n = max_series > 1 ? 5 * h->slots_max : 3 * h->G_max;
   bool ok = true;
   ok = ok && hipMalloc(&h->lane, sizeof(double) * NF * h->lane_ld) == hipSuccess;
   ok = ok && hipMalloc(&h->top, sizeof(double) * NF * h->top_ld) == hipSuccess;
   ok = ok && hipMalloc(&h->top_cnt, sizeof(unsigned int) * h->top_cnt_n) == hipSuccess;
   ok = ok && hipMemset(h->top_cnt, 0, sizeof(unsigned int) * h->top_cnt_n) == hipSuccess;
   ok = ok && hipMalloc(&h->scal, sizeof(double) * 8) == hipSuccess;
-  ok = ok && hipMalloc(&h->gpart, sizeof(double) * 3 * h->G_max) == hipSuccess;
+  ok = ok && hipMalloc(&h->part, sizeof(double) * part_n) == hipSuccess;
   ok = ok && hipMalloc(&h->key, sizeof(unsigned long long)) == hipSuccess;
   ok = ok && hipMalloc(&h->done, sizeof(unsigned int)) == hipSuccess;
   ok = ok && hipMemset(h->done, 0, sizeof(unsigned int)) == hipSuccess;
   ok = ok && hipMemset(h->key, 0xff, sizeof(unsigned long long)) == hipSuccess;
+  if (max_series > 1) {
+    ok = ok && hipMalloc(&h->chunk_series, sizeof(int32_t) * h->slots_max) == hipSuccess;
+    ok = ok && hipMalloc(&h->chunk_first, sizeof(int64_t) * ((int64_t)max_series + 1)) == hipSuccess;
+  }
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     spingp_destroy(h);
@@ -198,9 +224,11 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)hipFree(h->top);
   (void)hipFree(h->top_cnt);
   (void)hipFree(h->scal);
-  (void)hipFree(h->gpart);
+  (void)hipFree(h->part);
   (void)hipFree(h->key);
   (void)hipFree(h->done);
+  (void)hipFree(h->chunk_series);
+  (void)hipFree(h->chunk_first);
   delete h;
   return SPINGP_OK;
 }
@@ -208,26 +236,56 @@ extern "C" int spingp_destroy(spingp_handle h) {
 extern "C" int spingp_state_dim(spingp_handle h) { return h ? h->b : -1; }
 extern "C" int spingp_n_hyper(spingp_handle h) { return h ? h->n_hyper : -1; }
 
+static spg::SeriesMap make_map(const spingp_ctx* h) {
+  spg::SeriesMap sm;
+  memset(&sm, 0, sizeof(sm));
+  sm.n_series = h->n_series;
+  if (h->batched) {
+    sm.offsets = h->offsets;
+    sm.chunk_series = h->chunk_series;
+    sm.chunk_first = h->chunk_first;
+    sm.slots = h->G * kL;
+  }
+  return sm;
+}
+
 extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y, const int64_t* offsets,
                                int32_t n_series, int64_t n_points, const double* hyper, uint32_t flags) {
   if (!h || !t || !y || !hyper || flags != 0) return SPINGP_E_INVALID;
-  if (n_series != 1) return SPINGP_E_UNSUPPORTED;
+  if (n_series < 1 || n_series > h->max_series) return SPINGP_E_INVALID;
   if (n_points < 1 || n_points > h->max_points) return SPINGP_E_INVALID;
-  (void)offsets;  // one series: the whole array
+  if (n_series > 1 && !offsets) return SPINGP_E_INVALID;
+  h->assembled = false;
+  h->factored = false;
   h->t = t;
   h->y = y;
   h->hyper = hyper;
+  h->offsets = offsets;
   h->n_points = n_points;
-  h->G = ceil_div(ceil_div(n_points, kR), kL);
-  h->assembled = true;
-  h->factored = false;
+  h->n_series = n_series;
+  // one series is the whole array (offsets, if given, are not read)
+  h->batched = n_series > 1;
+  h->G = groups_for(n_points, n_series, h->batched);
   hipLaunchKernelGGL(k_fill_key, dim3(1), dim3(1), 0, h->stream, h->key);
-  const int T = 256;
   prof_begin(h);
-  hipLaunchKernelGGL(k_validate, dim3((unsigned)ceil_div(n_points, T)), dim3(T), 0, h->stream, t, y, n_points,
-                     hyper, h->n_hyper, h->key);
+  if (!h->batched) {
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)ceil_div(n_points, kT)), dim3(kT), 0, h->stream, t, y, n_points,
+                       hyper, h->n_hyper, h->key);
+  } else {
+    const int64_t slots = h->G * kL;
+    hipLaunchKernelGGL(spg::k_chunk_first, dim3(1), dim3(256), 0, h->stream, offsets, n_series, n_points, kR,
+                       h->chunk_first, h->key);
+    hipLaunchKernelGGL(spg::k_chunk_fill, dim3((unsigned)ceil_div(slots, kT)), dim3(kT), 0, h->stream,
+                       h->chunk_series, slots);
+    hipLaunchKernelGGL(spg::k_chunk_map, dim3((unsigned)ceil_div(n_series, kT)), dim3(kT), 0, h->stream,
+                       h->chunk_first, n_series, slots, h->chunk_series);
+    hipLaunchKernelGGL(spg::k_validate_chunks<kR>, dim3((unsigned)ceil_div(slots, kT)), dim3(kT), 0, h->stream, t,
+                       y, n_points, hyper, make_map(h), h->key);
+  }
   prof_end(h, 0);
-  return hip_ok(hipGetLastError());
+  const int rc = hip_ok(hipGetLastError());
+  h->assembled = rc == SPINGP_OK;
+  return rc;
 }
 
 static spg::TopTree make_top(spingp_ctx* h) {
@@ -254,41 +312,55 @@ static spg::TopTree make_top(spingp_ctx* h) {
   return T;
 }
 
-template <int B>
+template <int B, bool BATCHED>
 static int launch_factor(spingp_ctx* h) {
   const spg::TopTree top = make_top(h);
+  const spg::SeriesMap sm = make_map(h);
   prof_begin(h);
-  hipLaunchKernelGGL((spg::k_fwd<B, kR, kL>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t, h->y,
-                     h->n_points, h->hyper, h->lane, h->lane_ld, top, h->key);
+  hipLaunchKernelGGL((spg::k_fwd<B, kR, kL, BATCHED>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t, h->y,
+                     h->n_points, h->hyper, sm, h->lane, h->lane_ld, top, h->key);
   prof_end(h, 1);
   prof_begin(h);
-  hipLaunchKernelGGL((spg::k_top_bands<B>), dim3((unsigned)ceil_div(h->G, 32)), dim3(64), 0, h->stream, h->hyper,
-                     top, h->scal);
+  hipLaunchKernelGGL((spg::k_top_bands<B, BATCHED>), dim3((unsigned)ceil_div(h->G, 32)), dim3(64), 0, h->stream,
+                     h->hyper, sm, top, h->scal);
   prof_end(h, 2);
   return hip_ok(hipGetLastError());
+}
+
+static int do_factor(spingp_ctx* h) {
+  if (h->b == 2) return h->batched ? launch_factor<2, true>(h) : launch_factor<2, false>(h);
+  return h->batched ? launch_factor<3, true>(h) : launch_factor<3, false>(h);
 }
 
 extern "C" int spingp_factor(spingp_handle h) {
   if (!h) return SPINGP_E_INVALID;
   if (!h->assembled) return SPINGP_E_ORDER;
-  const int rc = (h->b == 2) ? launch_factor<2>(h) : launch_factor<3>(h);
-  if (rc == SPINGP_OK) h->factored = true;
+  const int rc = do_factor(h);
+  h->factored = rc == SPINGP_OK;
   return rc;
 }
 
-extern "C" int spingp_logml(spingp_handle h, double* logml, double* datafit, double* logdet) {
-  if (!h || !logml) return SPINGP_E_INVALID;
-  if (!h->factored) return SPINGP_E_ORDER;
-  hipLaunchKernelGGL(k_copy_scalars, dim3(1), dim3(64), 0, h->stream, h->scal, h->n_points, logml, datafit, logdet);
+template <int B, int MODE, bool BATCHED>
+static int launch_bwd(spingp_ctx* h, const spg::BwdOut& o) {
+  prof_begin(h);
+  hipLaunchKernelGGL((spg::k_bwd<B, kR, kL, MODE, BATCHED>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t,
+                     h->y, h->n_points, h->hyper, make_map(h), h->lane, h->lane_ld, make_top(h), o);
+  prof_end(h, 3);
   return hip_ok(hipGetLastError());
 }
 
-template <int B, int MODE>
-static int launch_bwd(spingp_ctx* h, const spg::BwdOut& o) {
+template <int MODE>
+static int run_bwd(spingp_ctx* h, const spg::BwdOut& o) {
+  if (h->b == 2) return h->batched ? launch_bwd<2, MODE, true>(h, o) : launch_bwd<2, MODE, false>(h, o);
+  return h->batched ? launch_bwd<3, MODE, true>(h, o) : launch_bwd<3, MODE, false>(h, o);
+}
+
+// several series: per-series fixed-order sums of the reverse kernel's per-chunk partials
+static int series_reduce(spingp_ctx* h, double* logml, double* datafit, double* logdet, double* grad) {
   prof_begin(h);
-  hipLaunchKernelGGL((spg::k_bwd<B, kR, kL, MODE>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t, h->y,
-                     h->n_points, h->hyper, h->lane, h->lane_ld, make_top(h), o);
-  prof_end(h, 3);
+  hipLaunchKernelGGL(spg::k_series_reduce, dim3((unsigned)h->n_series), dim3(64), 0, h->stream, make_map(h),
+                     h->part, h->part_ld, h->n_points, logml, datafit, logdet, grad);
+  prof_end(h, 4);
   return hip_ok(hipGetLastError());
 }
 
@@ -296,11 +368,25 @@ static spg::BwdOut make_out(spingp_ctx* h) {
   spg::BwdOut o;
   memset(&o, 0, sizeof(o));
   o.ld = h->n_points;
-  o.grad_part = h->gpart;
-  o.gp_ld = h->G_max;
+  o.part = h->part;
+  o.part_ld = h->part_ld;
   o.done = h->done;
   o.scal = h->scal;
   return o;
+}
+
+extern "C" int spingp_logml(spingp_handle h, double* logml, double* datafit, double* logdet) {
+  if (!h || !logml) return SPINGP_E_INVALID;
+  if (!h->factored) return SPINGP_E_ORDER;
+  if (!h->batched) {
+    hipLaunchKernelGGL(k_copy_scalars, dim3(1), dim3(64), 0, h->stream, h->scal, h->n_points, logml, datafit,
+                       logdet);
+    return hip_ok(hipGetLastError());
+  }
+  // several series: the per-series terms come from an elimination sweep over every chunk
+  const int rc = run_bwd<spg::kWantLogml>(h, make_out(h));
+  if (rc) return rc;
+  return series_reduce(h, logml, datafit, logdet, nullptr);
 }
 
 extern "C" int spingp_solve(spingp_handle h, double* f_mean, double* z_mean) {
@@ -310,7 +396,7 @@ extern "C" int spingp_solve(spingp_handle h, double* f_mean, double* z_mean) {
   spg::BwdOut o = make_out(h);
   o.f_mean = f_mean;
   o.z_mean = z_mean;
-  return (h->b == 2) ? launch_bwd<2, spg::kWantMean>(h, o) : launch_bwd<3, spg::kWantMean>(h, o);
+  return run_bwd<spg::kWantMean>(h, o);
 }
 
 extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, double* S_sub) {
@@ -321,10 +407,8 @@ extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, dou
   o.f_var = f_var;
   o.S_diag = S_diag;
   o.S_sub = S_sub;
-  if (S_sub)
-    return (h->b == 2) ? launch_bwd<2, spg::kWantVar | spg::kWantSub>(h, o)
-                       : launch_bwd<3, spg::kWantVar | spg::kWantSub>(h, o);
-  return (h->b == 2) ? launch_bwd<2, spg::kWantVar>(h, o) : launch_bwd<3, spg::kWantVar>(h, o);
+  if (S_sub) return run_bwd<spg::kWantVar | spg::kWantSub>(h, o);
+  return run_bwd<spg::kWantVar>(h, o);
 }
 
 extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
@@ -334,9 +418,13 @@ extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
   int rc = spingp_factor(h);
   if (rc) return rc;
   spg::BwdOut o = make_out(h);
-  o.logml = logml;
-  o.grad = grad;
-  return (h->b == 2) ? launch_bwd<2, spg::kWantGrad>(h, o) : launch_bwd<3, spg::kWantGrad>(h, o);
+  if (!h->batched) {
+    o.logml = logml;
+    o.grad = grad;
+  }
+  rc = run_bwd<spg::kWantGrad>(h, o);
+  if (rc || !h->batched) return rc;
+  return series_reduce(h, logml, nullptr, nullptr, grad);
 }
 
 extern "C" int spingp_status(spingp_handle h, int64_t* first_bad) {

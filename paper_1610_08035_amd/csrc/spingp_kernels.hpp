@@ -1,22 +1,25 @@
-// Kernels of the single-series hot path: chunk fold + work-group reduction (fwd), reduction
-// over work-group aggregates with the two down-sweeps (top), work-group down-sweep + chunk
-// elimination + adjoint sweep (bwd), and a fixed-order sum of gradient partials (finalize).
+// Kernels of the hot path: chunk fold + work-group tree (k_fwd), banded reduction of the
+// work-group aggregates (k_top_bands), top-level path walk + work-group down-sweep + chunk
+// elimination + adjoint sweep (k_bwd), and for several series a fixed-order per-series sum
+// (k_series_reduce) plus the assemble-time chunk map.
 //
-// Work decomposition for N points, R points per lane and L lanes per work-group:
-//   chunk j covers nodes [j R, min((j+1) R, N)); element E_j spans edge-wise from the chunk's
-//   first node to the next chunk's first node (the last chunk ends in a terminal edge A = 0).
-//   Work-group g owns chunks [g L, (g+1) L).  The reduction tree is: a sequential fold inside a
-//   lane (R nodes), a balanced tree over the L lanes in LDS, a balanced tree over the G
-//   work-groups in the top kernel.  Down-sweeps deliver, for every chunk, the predicted state
-//   (m, P) at its first node (prefix from the prior) and the information (J, eta) on its
-//   successor (suffix from the end); those seed the chunk's elimination and adjoint sweep.
+// Work decomposition, R points per lane and L lanes per work-group.  A chunk is R consecutive
+// nodes of one series (the last chunk of a series may be shorter); its element spans from the
+// chunk's first node to the next chunk's first node.  Series are concatenated: the edge after
+// the last node of a series carries A = 0 and Q = P0 of the next series (no information crosses
+// it, and the next series starts from its own prior), the edge after the very last node A = 0,
+// Q = 0.  Work-group g owns chunk slots [g L, (g+1) L).  The reduction tree is a sequential fold
+// inside a lane (R nodes), a balanced tree over the L lanes in LDS, and a banded tree over the
+// work-group aggregates.  The reverse kernel hands every chunk the predicted state (m, P) at its
+// first node (prefix from the prior) and the information (J, eta) on its successor (suffix from
+// the end); those seed the chunk's elimination and its adjoint sweep.
 #pragma once
 #include "spingp_device.hpp"
 
 namespace spg {
 
-// Hyperparameters are read from device memory, so replays of a captured launch pick up
-// new values.  Row layout: (lengthscale, signal variance, noise variance).
+// Hyperparameter row: (lengthscale, signal variance, noise variance).  Read from device memory,
+// so replays of a captured launch pick up new values.
 template <int B>
 SPG_DEV SeriesPar load_par(const double* hyper) {
   SeriesPar p;
@@ -27,14 +30,95 @@ SPG_DEV SeriesPar load_par(const double* hyper) {
   return p;
 }
 
-// Edge n -> n+1 of a series with n_pts points: transition and e = exp(-lam dt); the edge after
-// the last point is terminal (A = 0, Q = 0).  Returns false for the terminal edge.
+// Layout of several series (device arrays built by spingp_assemble); unused for one series.
+struct SeriesMap {
+  const int64_t* offsets;       // [S + 1] first node of every series, offsets[S] = N
+  const int32_t* chunk_series;  // [slots] series of every chunk slot, -1 past the last chunk
+  const int64_t* chunk_first;   // [S + 1] first chunk of every series
+  int64_t slots;                // entries of chunk_series (launched chunk slots)
+  int32_t n_series;
+};
+
+// Hyperparameter row of the series that owns node 0 (its prior is the root of the chain): the
+// series of chunk 0, which skips leading empty series.
+template <bool BATCHED>
+SPG_DEV const double* root_hyper(const double* __restrict__ hyper, const SeriesMap& sm) {
+  if (!BATCHED) return hyper;
+  const int32_t s = sm.chunk_series[0];
+  return hyper + 3 * (int64_t)(s < 0 ? 0 : s);
+}
+
+// What a lane works on.
 template <int B>
-SPG_DEV bool edge_of(const SeriesPar& p, const double* __restrict__ t, int64_t n, int64_t n_pts,
-                     double& dt, double& e, double (&A)[B][B]) {
-  if (n + 1 < n_pts) {
+struct Lane {
+  SeriesPar p;          // hyperparameters of the lane's series
+  int64_t series;       // its index
+  int64_t start;        // first node of the chunk
+  int len;              // nodes in the chunk (0 for a padding slot)
+  int64_t s_begin;      // first node of the series
+  int64_t s_end;        // one past its last node
+  bool has_next;        // another series follows (boundary edge carries its prior)
+  const double* hyper_next;
+};
+
+template <int B, int R, bool BATCHED>
+SPG_DEV Lane<B> lane_of(int64_t chunk, int64_t n_pts, const double* __restrict__ hyper, const SeriesMap& sm) {
+  Lane<B> ln;
+  if (!BATCHED) {
+    ln.series = 0;
+    ln.start = chunk * R;
+    ln.len = ln.start < n_pts ? (int)((n_pts - ln.start) < R ? (n_pts - ln.start) : R) : 0;
+    ln.s_begin = 0;
+    ln.s_end = n_pts;
+    ln.has_next = false;
+    ln.hyper_next = hyper;
+    ln.p = load_par<B>(hyper);
+    return ln;
+  }
+  const int32_t s = sm.chunk_series[chunk];
+  if (s < 0) {
+    ln.series = 0;
+    ln.start = 0;
+    ln.len = 0;
+    ln.s_begin = 0;
+    ln.s_end = 0;
+    ln.has_next = false;
+    ln.hyper_next = hyper;
+    ln.p = load_par<B>(hyper);
+    return ln;
+  }
+  // clamped so that invalid offsets (reported by the assemble-time checks) never index outside
+  // [0, n_pts); valid offsets pass through unchanged
+  ln.series = s;
+  const int64_t ob = sm.offsets[s], oe = sm.offsets[s + 1];
+  ln.s_begin = ob < 0 ? 0 : (ob > n_pts ? n_pts : ob);
+  ln.s_end = oe < ln.s_begin ? ln.s_begin : (oe > n_pts ? n_pts : oe);
+  ln.start = ln.s_begin + (chunk - sm.chunk_first[s]) * R;
+  if (ln.start < ln.s_begin || ln.start > ln.s_end) ln.start = ln.s_end;
+  ln.len = (int)((ln.s_end - ln.start) < R ? (ln.s_end - ln.start) : R);
+  // the node after the series' last one opens the next non-empty series, whose first chunk is
+  // the next slot
+  ln.has_next = false;
+  ln.hyper_next = hyper;
+  if (ln.start + ln.len == ln.s_end && chunk + 1 < sm.slots) {
+    const int32_t s2 = sm.chunk_series[chunk + 1];
+    if (s2 >= 0) {
+      ln.has_next = true;
+      ln.hyper_next = hyper + 3 * (int64_t)s2;
+    }
+  }
+  ln.p = load_par<B>(hyper + 3 * (int64_t)s);
+  return ln;
+}
+
+// Edge n -> n+1: the transition and e = exp(-lam dt) for a model edge (returns true); the
+// boundary or terminal edge after a series' last node has A = 0 (returns false).
+template <int B>
+SPG_DEV bool edge_at(const Lane<B>& ln, const double* __restrict__ t, int64_t n, double& dt, double& e,
+                     double (&A)[B][B]) {
+  if (n + 1 < ln.s_end) {
     dt = t[n + 1] - t[n];
-    Matern<B>::transition(p, dt, e, A);
+    Matern<B>::transition(ln.p, dt, e, A);
     return true;
   }
   dt = 0.0;
@@ -43,18 +127,31 @@ SPG_DEV bool edge_of(const SeriesPar& p, const double* __restrict__ t, int64_t n
   return false;
 }
 
+// Q - P0 after the non-model edge leaving a series: P0(next) - P0, or -P0 after the last series.
+template <int B>
+SPG_DEV void end_edge_D(const Lane<B>& ln, const double (&P0)[B][B], double (&D)[B][B]) {
+  if (ln.has_next) {
+    double Pn[B][B];
+    Matern<B>::pinf(load_par<B>(ln.hyper_next), Pn);
+    SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = Pn[i][j] - P0[i][j];
+  } else {
+    SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -P0[i][j];
+  }
+}
+
 // Sequential fold of the chunk's nodes into its element (rank-one observation information).
 // Q of the running element is carried as D = Q - P0 so that Q_n = P0 - A_n P0 A_n^T is never
 // formed: Q_new = A (Q - q q^T/s) A^T + Q_n  <=>  D_new = A (D - q q^T/s) A^T.
 template <int B, int R>
-SPG_DEV void fold_chunk(const SeriesPar& p, const double (&P0)[B][B], const double* __restrict__ t,
-                        const double* __restrict__ y, int64_t n_pts, int64_t start, int len, Elem<B>& E) {
+SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const double* __restrict__ t,
+                        const double* __restrict__ y, Elem<B>& E) {
+  const SeriesPar& p = ln.p;
   const double is2 = 1.0 / p.s2;
   double D[B][B];
   {
     // first node: element (A_s, 0, Q_s, J, eta_s) with the node's constants
     double dt, e, A[B][B];
-    const bool ok = edge_of<B>(p, t, start, n_pts, dt, e, A);
+    const bool ok = edge_at<B>(ln, t, ln.start, dt, e, A);
     mat_copy<B>(A, E.A);
     if (ok) {
       double T[B][B];
@@ -62,9 +159,9 @@ SPG_DEV void fold_chunk(const SeriesPar& p, const double (&P0)[B][B], const doub
       mmt_sym<B>(T, A, D);
       SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -D[i][j];
     } else {
-      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -P0[i][j];
+      end_edge_D<B>(ln, P0, D);
     }
-    const double y0 = y[start];
+    const double y0 = y[ln.start];
     mat_zero<B>(E.J);
     E.J[0][0] = is2;
     SPG_UNROLL for (int i = 0; i < B; ++i) {
@@ -76,8 +173,8 @@ SPG_DEV void fold_chunk(const SeriesPar& p, const double (&P0)[B][B], const doub
     E.cl = -0.5 * (kLog2Pi + log(p.s2));
   }
   SPG_UNROLL for (int k = 1; k < R; ++k) {
-    if (k < len) {
-      const int64_t n = start + k;
+    if (k < ln.len) {
+      const int64_t n = ln.start + k;
       const double yn = y[n];
       double q[B];
       SPG_UNROLL for (int i = 0; i < B; ++i) q[i] = D[i][0] + P0[i][0];
@@ -92,7 +189,7 @@ SPG_DEV void fold_chunk(const SeriesPar& p, const double (&P0)[B][B], const doub
         const double ki = q[i] * is;
         bp[i] = fma(ki, v, E.b[i]);
         SPG_UNROLL for (int j = 0; j < B; ++j) Ap[i][j] = fma(-ki, a[j], E.A[i][j]);
-        SPG_UNROLL for (int j = i; j < B; ++j) Dp[i][j] = fma(-q[i] * is, q[j], D[i][j]);
+        SPG_UNROLL for (int j = i; j < B; ++j) Dp[i][j] = fma(-ki, q[j], D[i][j]);
         E.eta[i] = fma(a[i], vis, E.eta[i]);
         SPG_UNROLL for (int j = i; j < B; ++j) E.J[i][j] = fma(a[i] * is, a[j], E.J[i][j]);
       }
@@ -103,7 +200,7 @@ SPG_DEV void fold_chunk(const SeriesPar& p, const double (&P0)[B][B], const doub
       E.cl += -0.5 * (kLog2Pi + log(s));
       E.cf += -0.5 * v * vis;
       double dt, e, A[B][B];
-      const bool ok = edge_of<B>(p, t, n, n_pts, dt, e, A);
+      const bool ok = edge_at<B>(ln, t, n, dt, e, A);
       if (ok) {
         double T[B][B];
         mm<B>(A, Ap, E.A);
@@ -113,7 +210,7 @@ SPG_DEV void fold_chunk(const SeriesPar& p, const double (&P0)[B][B], const doub
       } else {
         mat_zero<B>(E.A);
         SPG_UNROLL for (int i = 0; i < B; ++i) E.b[i] = 0.0;
-        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -P0[i][j];
+        end_edge_D<B>(ln, P0, D);
       }
     }
   }
@@ -160,8 +257,9 @@ SPG_DEV void lds_load(const double* pool, int i, Elem<B>& E) {
   E.cf = pool[Lay::kcf * NS + i];
   E.cl = pool[Lay::kcl * NS + i];
 }
-// Messages (alpha = predicted (m, P) at the slot's first node, beta = information (J, eta) on
-// the slot's successor) overwrite a slot once its element is no longer needed.
+
+// Messages: the predicted state (m, P) entering a node range and the information (J, eta) on the
+// range's successor.  LDS layout per slot: m, P upper, J upper, eta.
 template <int B>
 struct Msg {
   double m[B];
@@ -169,14 +267,8 @@ struct Msg {
   double J[B][B];
   double eta[B];
 };
-template <int B, int NS>
-SPG_DEV void lds_store_msg(double* pool, int i, const Msg<B>& g) {
-  int f = 0;
-  SPG_UNROLL for (int r = 0; r < B; ++r) pool[(f++) * NS + i] = g.m[r];
-  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) pool[(f++) * NS + i] = g.P[r][c];
-  SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) pool[(f++) * NS + i] = g.J[r][c];
-  SPG_UNROLL for (int r = 0; r < B; ++r) pool[(f++) * NS + i] = g.eta[r];
-}
+template <int B>
+constexpr int msg_fields() { return 2 * B + B * (B + 1); }
 template <int B, int NS>
 SPG_DEV void lds_load_msg(const double* pool, int i, Msg<B>& g) {
   int f = 0;
@@ -201,8 +293,6 @@ SPG_DEV void lds_store_suffix(double* pool, int i, const double (&J)[B][B], cons
   SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) pool[(f++) * NS + i] = J[r][c];
   SPG_UNROLL for (int r = 0; r < B; ++r) pool[(f++) * NS + i] = eta[r];
 }
-template <int B>
-constexpr int msg_fields() { return 2 * B + B * (B + 1); }
 
 // ---------------------------------------------------------------------------- top-level tree
 // The work-group aggregates are the leaves of a complete binary tree with Ltop = 32^n_bands
@@ -223,33 +313,29 @@ SPG_DEV int64_t top_level_off(const TopTree& T, int l) { return 2 * T.Ltop - 2 *
 // ---------------------------------------------------------------------------- kernel: forward
 // One lane per chunk; a work-group reduces its L lane elements with a balanced tree in LDS.
 // Every element of the tree is also written to global memory (lane elements at slot i < L,
-// internal nodes at slot L + level offset), so the backward kernel's down-sweep reuses it.
+// internal nodes at slot L + level offset) so that the reverse kernel's down-sweep reuses it.
 // Tree slots: level 0 = [0, L), level 1 = [L, L + L/2), ..., root = 2L - 2.
-template <int B, int R, int L>
+template <int B, int R, int L, bool BATCHED>
 __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const double* __restrict__ y,
-                                            int64_t n_pts, const double* __restrict__ hyper,
+                                            int64_t n_pts, const double* __restrict__ hyper, SeriesMap sm,
                                             double* __restrict__ tree_elems, int64_t tree_ld, TopTree top,
                                             unsigned long long* __restrict__ status) {
   constexpr int NF = ElemLayout<B>::kFields;
   __shared__ double pool[NF * L];
   const int tid = threadIdx.x;
   const int64_t chunk = (int64_t)blockIdx.x * L + tid;
-  const int64_t start = chunk * R;
   const int64_t gbase = (int64_t)blockIdx.x * (2 * L);
-  const SeriesPar p = load_par<B>(hyper);
-  if (blockIdx.x == 0 && tid == 0) {
+  const Lane<B> ln = lane_of<B, R, BATCHED>(chunk, n_pts, hyper, sm);
+  if (ln.len > 0 && ln.start == ln.s_begin) {
+    const SeriesPar& p = ln.p;
     if (!(isfinite(p.ell) && p.ell > 0.0 && isfinite(p.var) && p.var > 0.0 && isfinite(p.s2) && p.s2 > 0.0))
       atomicMin(status, 5ull);   // SPINGP_E_HYPER, no point index
   }
   double P0[B][B];
-  Matern<B>::pinf(p, P0);
+  Matern<B>::pinf(ln.p, P0);
   Elem<B> E;
-  if (start < n_pts) {
-    const int len = (int)((n_pts - start) < R ? (n_pts - start) : R);
-    fold_chunk<B, R>(p, P0, t, y, n_pts, start, len, E);
-  } else {
-    elem_identity<B>(E);
-  }
+  if (ln.len > 0) fold_chunk<B, R>(ln, P0, t, y, E);
+  else elem_identity<B>(E);
   elem_store<B>(tree_elems, tree_ld, gbase + tid, E);
   lds_store<B, L>(pool, tid, E);
   __syncthreads();
@@ -278,10 +364,10 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
 // One 64-thread work-group per group of 32 leaves of band 0.  Each reduces its group in LDS and
 // writes every node; then the last work-group of each group of 32 band-0 groups (atomic ticket,
 // no waiting) reduces band 1, and so on.  The work-group that completes the last band holds the
-// root and evaluates the log marginal likelihood.  Fences here only have to publish the few
-// nodes this small kernel writes.
-template <int B>
-__global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyper, TopTree top,
+// root and, for one series, evaluates the log marginal likelihood (the prior N(0, P0) pushed
+// through the whole chain).  Fences here only have to publish the few nodes this kernel writes.
+template <int B, bool BATCHED>
+__global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyper, SeriesMap sm, TopTree top,
                                                    double* __restrict__ scal) {
   constexpr int NF = ElemLayout<B>::kFields;
   __shared__ double pool[NF * 32];
@@ -329,8 +415,7 @@ __global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyp
     group = group >> 5;
     nb = (nb + 31) >> 5;
   }
-  // the prior N(0, P0) pushed through the whole chain gives the log normaliser
-  if (tid == 0) {
+  if (!BATCHED && tid == 0) {
     const SeriesPar p = load_par<B>(hyper);
     double P0[B][B];
     Matern<B>::pinf(p, P0);
@@ -347,7 +432,7 @@ __global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyp
 
 // ---------------------------------------------------------------------------- kernel: backward
 // Output selection for the reverse sweep.
-enum : int { kWantGrad = 1, kWantMean = 2, kWantVar = 4, kWantSub = 8 };
+enum : int { kWantGrad = 1, kWantMean = 2, kWantVar = 4, kWantSub = 8, kWantLogml = 16 };
 
 struct BwdOut {
   double* f_mean;   // [N] or null
@@ -356,19 +441,20 @@ struct BwdOut {
   double* S_diag;   // [B(B+1)/2][ld] or null
   double* S_sub;    // [B*B][ld] or null (row n = Cov(z_{n+1}, z_n | y))
   int64_t ld;
-  double* grad_part;  // [3][G] per work-group partial gradients (lengthscale, variance, noise)
-  int64_t gp_ld;
-  unsigned int* done;        // work-groups finished (the last one sums the partials, then resets it)
-  const double* scal;        // log-likelihood scalars of the forward pass
-  double* logml;             // [1] or null
-  double* grad;              // [3] or null
+  double* part;     // one series: [3][G] work-group gradient partials; several series: [5][slots]
+                    // per-chunk (sum v^2/s, sum log s, d/dlengthscale, d/dvariance, d/dnoise)
+  int64_t part_ld;
+  unsigned int* done;        // one series: finished work-groups (the last sums the partials)
+  const double* scal;        // one series: log-likelihood scalars of the forward pass
+  double* logml;             // one series: [1] or null
+  double* grad;              // one series: [3] or null
 };
 
-template <int B, int R, int L, int MODE>
+template <int B, int R, int L, int MODE, bool BATCHED>
 __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, const double* __restrict__ y,
-                                            int64_t n_pts, const double* __restrict__ hyper,
-                                            const double* __restrict__ tree_elems, int64_t tree_ld,
-                                            const TopTree top, BwdOut out) {
+                                               int64_t n_pts, const double* __restrict__ hyper, SeriesMap sm,
+                                               const double* __restrict__ tree_elems, int64_t tree_ld,
+                                               const TopTree top, BwdOut out) {
   // LDS holds messages only (the tree elements are read from global memory): message slot s
   // follows the work-group tree's level-major layout (level 0 at [0, L), ..., root 2L - 2).
   // Before the down-sweep the same space holds the top-level path siblings, field-major with
@@ -376,10 +462,16 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
   constexpr int NS = 2 * L;
   constexpr int MF = msg_fields<B>();
   static_assert(MF * NS >= (ElemLayout<B>::kFields) * 32, "path siblings must fit in the message pool");
+  constexpr bool kGrad = (MODE & kWantGrad) != 0;
+  constexpr bool kCov = (MODE & (kWantVar | kWantSub)) != 0;
+  constexpr bool kSub = (MODE & kWantSub) != 0;
+  constexpr bool kLl = BATCHED && ((MODE & (kWantGrad | kWantLogml)) != 0);   // per-chunk logML
+  constexpr bool kAdjoint = (MODE & (kWantGrad | kWantMean | kWantVar | kWantSub)) != 0;
   __shared__ double pool[MF * NS];
   const int tid = threadIdx.x;
   const int64_t chunk = (int64_t)blockIdx.x * L + tid;
-  const SeriesPar p = load_par<B>(hyper);
+  const Lane<B> ln = lane_of<B, R, BATCHED>(chunk, n_pts, hyper, sm);
+  const SeriesPar p = ln.p;
   double P0[B][B];
   Matern<B>::pinf(p, P0);
   const int64_t wg = blockIdx.x;
@@ -394,12 +486,14 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
     }
     __syncthreads();
     // message entering this work-group, walked down the top-level tree: the prefix part
-    // (predicted state from the prior) on wave 0, the suffix part (information from the end)
-    // on wave 1, one combine per level
+    // (predicted state from the first prior) on wave 0, the suffix part (information from the
+    // end) on wave 1, one combine per level
     double m_[B], P_[B][B], J_[B][B], e_[B];
     if (tid == 0) {
+      double Pr[B][B];
+      Matern<B>::pinf(load_par<B>(root_hyper<BATCHED>(hyper, sm)), Pr);
       SPG_UNROLL for (int i = 0; i < B; ++i) m_[i] = 0.0;
-      mat_copy<B>(P0, P_);
+      mat_copy<B>(Pr, P_);
       for (int l = nlev - 1; l >= 0; --l) {
         if ((wg >> l) & 1) {
           Elem<B> Tl;
@@ -464,11 +558,13 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
   lds_load_msg<B, NS>(pool, tid, g);
 
   // ---- chunk elimination (natural order) from the exact predicted state at its first node
-  const int64_t start = chunk * R;
-  const int len = start < n_pts ? (int)((n_pts - start) < R ? (n_pts - start) : R) : 0;
-  double sm[R][B];        // predicted means
+  const int64_t start = ln.start;
+  const int len = ln.len;
+  double sm_[R][B];       // predicted means
   double sD[R][B][B];     // predicted covariances minus P0
   double m[B], D[B][B];
+  double fit_chunk = 0.0;  // sum over the chunk of v_n^2 / s_n
+  double ldet_chunk = 0.0; // sum over the chunk of log s_n
   SPG_UNROLL for (int i = 0; i < B; ++i) {
     m[i] = g.m[i];
     SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = g.P[i][j] - P0[i][j];
@@ -477,209 +573,217 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
     if (k < len) {
       const int64_t n = start + k;
       SPG_UNROLL for (int i = 0; i < B; ++i) {
-        sm[k][i] = m[i];
+        sm_[k][i] = m[i];
         SPG_UNROLL for (int j = 0; j < B; ++j) sD[k][i][j] = D[i][j];
       }
       double u[B];
       SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = D[i][0] + P0[i][0];
       const double s = u[0] + p.s2, is = 1.0 / s;
       const double v = y[n] - m[0];
+      if (kLl) {
+        fit_chunk = fma(v * v, is, fit_chunk);
+        ldet_chunk += log(s);
+      }
       double mp[B], Dp[B][B];
       SPG_UNROLL for (int i = 0; i < B; ++i) {
         mp[i] = fma(u[i] * is, v, m[i]);
         SPG_UNROLL for (int j = 0; j < B; ++j) Dp[i][j] = fma(-u[i] * is, u[j], D[i][j]);
       }
       double A[B][B], dt_, e_;
-      const bool ok = edge_of<B>(p, t, n, n_pts, dt_, e_, A);
+      const bool ok = edge_at<B>(ln, t, n, dt_, e_, A);
       if (ok) {
         double T[B][B];
         mv<B>(A, mp, m);
         mm<B>(A, Dp, T);
         mmt_sym<B>(T, A, D);
       } else {
+        SPG_UNROLL for (int i = 0; i < B; ++i) m[i] = 0.0;
+        end_edge_D<B>(ln, P0, D);
+      }
+    }
+  }
+  double gr[3] = {0.0, 0.0, 0.0};
+  if (kAdjoint) {
+    // ---- adjoint seed at the successor of the chunk's last node:
+    //      L_rest(m, P) = log int N(z; m, P) exp(-1/2 z^T Jb z + etab^T z) dz
+    //      dL/dm = Gam^T etab - W m,  dL/dP = 1/2 (lam lam^T - W),  Gam = (I + P Jb)^-1,
+    //      W = Jb Gam; the smoothing information Lhat = lam lam^T - 2 dL/dP is W itself.  (After
+    //      a series' last node the edge has A = 0, so nothing of this seed reaches the series.)
+    double lam[B], Lam[B][B], Lhat[B][B], Pn[B][B];
+    {
+      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pn[i][j] = D[i][j] + P0[i][j];
+      double M[B][B], Gm[B][B], W[B][B], Gte[B], Wm[B];
+      mm<B>(Pn, g.J, M);
+      SPG_UNROLL for (int i = 0; i < B; ++i) M[i][i] += 1.0;
+      (void)inv_logdet<B>(M, Gm);
+      mm<B>(g.J, Gm, W);
+      symmetrize<B>(W);
+      mtv<B>(Gm, g.eta, Gte);
+      mv<B>(W, m, Wm);
+      SPG_UNROLL for (int i = 0; i < B; ++i) lam[i] = Gte[i] - Wm[i];
+      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) {
+        Lam[i][j] = 0.5 * (lam[i] * lam[j] - W[i][j]);
+        Lhat[i][j] = W[i][j];
+      }
+    }
+    // ---- reverse sweep.  Per node n (newest first): prediction adjoint through edge n,
+    //      smoothed moments from the filtered state, then the update adjoint.  lam/Lam
+    //      (gradient) follow reverse-mode differentiation of the elimination; Lhat
+    //      (covariances) follows the modified Bryson-Frazier recursion
+    //      Lhat_n = (I - K h^T)^T A^T Lhat_{n+1} A (I - K h^T) + h h^T / s,
+    //      which avoids forming lam lam^T - 2 Lam.
+    double gl_lam = 0.0, g_s2 = 0.0;   // <A_bar, dA/dlam> summed, d/d s2
+    double Pb[B][B];                   // adjoint of P0
+    mat_zero<B>(Pb);
+    SPG_UNROLL for (int k = R - 1; k >= 0; --k) {
+      if (k < len) {
+        const int64_t n = start + k;
+        double mk[B], Dk[B][B];
         SPG_UNROLL for (int i = 0; i < B; ++i) {
-          m[i] = 0.0;
-          SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -P0[i][j];
+          mk[i] = sm_[k][i];
+          SPG_UNROLL for (int j = 0; j < B; ++j) Dk[i][j] = sD[k][i][j];
         }
-      }
-    }
-  }
-  // ---- adjoint seed at the successor of the chunk's last node:
-  //      L_rest(m, P) = log int N(z; m, P) exp(-1/2 z^T Jb z + etab^T z) dz
-  //      dL/dm = Gam^T etab - W m,  dL/dP = 1/2 (lam lam^T - W),  Gam = (I + P Jb)^-1, W = Jb Gam;
-  //      the smoothing information Lhat = lam lam^T - 2 dL/dP is W itself.
-  constexpr bool kGrad = (MODE & kWantGrad) != 0;
-  constexpr bool kCov = (MODE & (kWantVar | kWantSub)) != 0;
-  constexpr bool kSub = (MODE & kWantSub) != 0;
-  double lam[B], Lam[B][B], Lhat[B][B], Pn[B][B];
-  {
-    SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pn[i][j] = D[i][j] + P0[i][j];
-    double M[B][B], Gm[B][B], W[B][B], Gte[B], Wm[B];
-    mm<B>(Pn, g.J, M);
-    SPG_UNROLL for (int i = 0; i < B; ++i) M[i][i] += 1.0;
-    (void)inv_logdet<B>(M, Gm);
-    mm<B>(g.J, Gm, W);
-    symmetrize<B>(W);
-    mtv<B>(Gm, g.eta, Gte);
-    mv<B>(W, m, Wm);
-    SPG_UNROLL for (int i = 0; i < B; ++i) lam[i] = Gte[i] - Wm[i];
-    SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) {
-      Lam[i][j] = 0.5 * (lam[i] * lam[j] - W[i][j]);
-      Lhat[i][j] = W[i][j];
-    }
-  }
-  // ---- reverse sweep.  Per node n (newest first): prediction adjoint through edge n, smoothed
-  //      moments from the filtered state, then the update adjoint.  lam/Lam (gradient) follow
-  //      reverse-mode differentiation of the elimination; Lhat (covariances) follows the
-  //      modified Bryson-Frazier recursion Lhat_n = (I - K h^T)^T A^T Lhat_{n+1} A (I - K h^T)
-  //      + h h^T / s, which avoids forming lam lam^T - 2 Lam.
-  double gl_lam = 0.0, g_s2 = 0.0;   // <A_bar, dA/dlam> summed, d/d s2
-  double Pb[B][B];                   // adjoint of P0
-  mat_zero<B>(Pb);
-  SPG_UNROLL for (int k = R - 1; k >= 0; --k) {
-    if (k < len) {
-      const int64_t n = start + k;
-      double mk[B], Dk[B][B];
-      SPG_UNROLL for (int i = 0; i < B; ++i) {
-        mk[i] = sm[k][i];
-        SPG_UNROLL for (int j = 0; j < B; ++j) Dk[i][j] = sD[k][i][j];
-      }
-      double u[B];
-      SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = Dk[i][0] + P0[i][0];
-      const double s = u[0] + p.s2, is = 1.0 / s;
-      const double v = y[n] - mk[0];
-      double mp[B], Dp[B][B];
-      SPG_UNROLL for (int i = 0; i < B; ++i) {
-        mp[i] = fma(u[i] * is, v, mk[i]);
-        SPG_UNROLL for (int j = 0; j < B; ++j) Dp[i][j] = fma(-u[i] * is, u[j], Dk[i][j]);
-      }
-      // prediction adjoint through edge n (nothing flows through the terminal edge)
-      double mbp[B], Pbp[B][B], Lhp[B][B];
-      const bool edge_ok = (n + 1 < n_pts);
-      double A[B][B];
-      if (edge_ok) {
-        double dt, e;
-        (void)edge_of<B>(p, t, n, n_pts, dt, e, A);   // recomputed: cheaper than keeping it live
-        mtv<B>(A, lam, mbp);            // A^T lam'
+        double u[B];
+        SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = Dk[i][0] + P0[i][0];
+        const double s = u[0] + p.s2, is = 1.0 / s;
+        const double v = y[n] - mk[0];
+        double mp[B], Dp[B][B];
+        SPG_UNROLL for (int i = 0; i < B; ++i) {
+          mp[i] = fma(u[i] * is, v, mk[i]);
+          SPG_UNROLL for (int j = 0; j < B; ++j) Dp[i][j] = fma(-u[i] * is, u[j], Dk[i][j]);
+        }
+        // prediction adjoint through edge n (nothing flows through the edge leaving a series)
+        double mbp[B], Pbp[B][B], Lhp[B][B];
+        double A[B][B], dt, e;
+        const bool edge_ok = edge_at<B>(ln, t, n, dt, e, A);   // recomputed: cheaper than keeping it live
+        if (edge_ok) {
+          mtv<B>(A, lam, mbp);            // A^T lam'
+          if (kGrad) {
+            double T[B][B], TD[B][B], Ab[B][B];
+            mm<B>(Lam, A, T);             // Lam' A
+            mtm_sym<B>(A, T, Pbp);        // A^T Lam' A
+            mm<B>(T, Dp, TD);
+            // A_bar = lam' m+^T + 2 Lam' A (P+ - P0): the A-dependence of Q = P0 - A P0 A^T included
+            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+              Ab[i][j] = fma(lam[i], mp[j], 2.0 * TD[i][j]);
+            gl_lam += Matern<B>::dA_dlam_dot(p, dt, e, Ab);
+            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+              Pb[i][j] += Lam[i][j] - Pbp[i][j];
+          }
+          if (kCov) {
+            double T[B][B];
+            mm<B>(Lhat, A, T);
+            mtm_sym<B>(A, T, Lhp);        // A^T Lhat' A
+          }
+        } else {
+          SPG_UNROLL for (int i = 0; i < B; ++i) {
+            mbp[i] = 0.0;
+            SPG_UNROLL for (int j = 0; j < B; ++j) {
+              Pbp[i][j] = 0.0;
+              Lhp[i][j] = 0.0;
+            }
+          }
+        }
+        // smoothed moments of node n from the filtered state (m+, P+):
+        //   mu = m+ + P+ A^T lam',   S = P+ - P+ (A^T Lhat' A) P+,
+        //   Cov(z_{n+1}, z_n | y) = (I - P_{n+1} Lhat_{n+1}) A P+
+        if (MODE & (kWantMean | kWantVar | kWantSub)) {
+          double Ppl[B][B], Pl[B], mu[B];
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Ppl[i][j] = Dp[i][j] + P0[i][j];
+          mv<B>(Ppl, mbp, Pl);
+          SPG_UNROLL for (int i = 0; i < B; ++i) mu[i] = mp[i] + Pl[i];
+          if (out.f_mean) out.f_mean[n] = mu[0];
+          if (out.z_mean) SPG_UNROLL for (int i = 0; i < B; ++i) out.z_mean[(int64_t)i * out.ld + n] = mu[i];
+          if (kCov) {
+            double X[B][B], S[B][B];
+            mm<B>(Ppl, Lhp, X);
+            mmt_sym<B>(X, Ppl, S);
+            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) S[i][j] = Ppl[i][j] - S[i][j];
+            if (out.f_var) out.f_var[n] = S[0][0];
+            if (out.S_diag) {
+              int s_ = 0;
+              SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j)
+                out.S_diag[(int64_t)(s_++) * out.ld + n] = S[i][j];
+            }
+            if (kSub && edge_ok && out.S_sub) {
+              double Y[B][B], AP[B][B], Ssub[B][B];
+              mm<B>(Pn, Lhat, Y);
+              SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+                Y[i][j] = (i == j ? 1.0 : 0.0) - Y[i][j];
+              mm<B>(A, Ppl, AP);
+              mm<B>(Y, AP, Ssub);
+              SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+                out.S_sub[(int64_t)(i * B + j) * out.ld + n] = Ssub[i][j];
+            }
+          }
+        }
+        // update adjoint at node n (h = e_0): adjoints of the predicted state (m_n, P_n)
+        const double kl = dot<B>(u, mbp) * is;      // K^T lam+
+        const double vbar = kl - v * is;
         if (kGrad) {
-          double T[B][B], TD[B][B], Ab[B][B];
-          mm<B>(Lam, A, T);             // Lam' A
-          mtm_sym<B>(A, T, Pbp);        // A^T Lam' A
-          mm<B>(T, Dp, TD);
-          // A_bar = lam' m+^T + 2 Lam' A (P+ - P0): the A-dependence of Q = P0 - A P0 A^T included
-          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
-            Ab[i][j] = fma(lam[i], mp[j], 2.0 * TD[i][j]);
-          gl_lam += Matern<B>::dA_dlam_dot(p, dt, e, Ab);
-          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
-            Pb[i][j] += Lam[i][j] - Pbp[i][j];
+          double w[B];
+          mv<B>(Pbp, u, w);
+          const double uw = dot<B>(u, w);
+          const double sbar = (uw - kl * s * v) * is * is - 0.5 * is + 0.5 * v * v * is * is;
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Lam[i][j] = Pbp[i][j];
+          Lam[0][0] += sbar;
+          SPG_UNROLL for (int i = 0; i < B; ++i) {
+            const double ub = (mbp[i] * v - 2.0 * w[i]) * is;
+            Lam[0][i] += 0.5 * ub;
+            Lam[i][0] += 0.5 * ub;
+          }
+          g_s2 += sbar;
         }
         if (kCov) {
-          double T[B][B];
-          mm<B>(Lhat, A, T);
-          mtm_sym<B>(A, T, Lhp);        // A^T Lhat' A
-        }
-      } else {
-        mat_zero<B>(A);
-        SPG_UNROLL for (int i = 0; i < B; ++i) {
-          mbp[i] = 0.0;
+          // Lhat = (I - K e0^T)^T Lhp (I - K e0^T) + e0 e0^T / s,  K = u / s
+          double Lk[B], Y[B][B];
+          SPG_UNROLL for (int i = 0; i < B; ++i) {
+            double t_ = 0.0;
+            SPG_UNROLL for (int j = 0; j < B; ++j) t_ = fma(Lhp[i][j], u[j], t_);
+            Lk[i] = t_ * is;                         // Lhp K
+          }
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Y[i][j] = Lhp[i][j];
+          SPG_UNROLL for (int i = 0; i < B; ++i) Y[i][0] -= Lk[i];          // Lhp (I - K e0^T)
+          double KY[B];
           SPG_UNROLL for (int j = 0; j < B; ++j) {
-            Pbp[i][j] = 0.0;
-            Lhp[i][j] = 0.0;
+            double t_ = 0.0;
+            SPG_UNROLL for (int i = 0; i < B; ++i) t_ = fma(u[i], Y[i][j], t_);
+            KY[j] = t_ * is;                         // K^T Y
           }
-        }
-      }
-      // smoothed moments of node n from the filtered state (m+, P+):
-      //   mu = m+ + P+ A^T lam',   S = P+ - P+ (A^T Lhat' A) P+,
-      //   Cov(z_{n+1}, z_n | y) = (I - P_{n+1} Lhat_{n+1}) A P+
-      if (MODE & (kWantMean | kWantVar | kWantSub)) {
-        double Ppl[B][B], Pl[B], mu[B];
-        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Ppl[i][j] = Dp[i][j] + P0[i][j];
-        mv<B>(Ppl, mbp, Pl);
-        SPG_UNROLL for (int i = 0; i < B; ++i) mu[i] = mp[i] + Pl[i];
-        if (out.f_mean) out.f_mean[n] = mu[0];
-        if (out.z_mean) SPG_UNROLL for (int i = 0; i < B; ++i) out.z_mean[(int64_t)i * out.ld + n] = mu[i];
-        if (kCov) {
-          double X[B][B], S[B][B];
-          mm<B>(Ppl, Lhp, X);
-          mmt_sym<B>(X, Ppl, S);
-          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) S[i][j] = Ppl[i][j] - S[i][j];
-          if (out.f_var) out.f_var[n] = S[0][0];
-          if (out.S_diag) {
-            int s_ = 0;
-            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j)
-              out.S_diag[(int64_t)(s_++) * out.ld + n] = S[i][j];
+          SPG_UNROLL for (int j = 0; j < B; ++j) Y[0][j] -= KY[j];
+          Y[0][0] += is;
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j) {
+            Lhat[i][j] = 0.5 * (Y[i][j] + Y[j][i]);
+            Lhat[j][i] = Lhat[i][j];
           }
-          if (kSub && edge_ok && out.S_sub) {
-            double Y[B][B], AP[B][B], Ssub[B][B];
-            mm<B>(Pn, Lhat, Y);
-            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
-              Y[i][j] = (i == j ? 1.0 : 0.0) - Y[i][j];
-            mm<B>(A, Ppl, AP);
-            mm<B>(Y, AP, Ssub);
-            SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
-              out.S_sub[(int64_t)(i * B + j) * out.ld + n] = Ssub[i][j];
-          }
+          if (kSub) SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pn[i][j] = Dk[i][j] + P0[i][j];
         }
-      }
-      // update adjoint at node n (h = e_0): adjoints of the predicted state (m_n, P_n)
-      const double kl = dot<B>(u, mbp) * is;      // K^T lam+
-      const double vbar = kl - v * is;
-      if (kGrad) {
-        double w[B];
-        mv<B>(Pbp, u, w);
-        const double uw = dot<B>(u, w);
-        const double sbar = (uw - kl * s * v) * is * is - 0.5 * is + 0.5 * v * v * is * is;
-        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Lam[i][j] = Pbp[i][j];
-        Lam[0][0] += sbar;
-        SPG_UNROLL for (int i = 0; i < B; ++i) {
-          const double ub = (mbp[i] * v - 2.0 * w[i]) * is;
-          Lam[0][i] += 0.5 * ub;
-          Lam[i][0] += 0.5 * ub;
+        SPG_UNROLL for (int i = 0; i < B; ++i) lam[i] = mbp[i];
+        lam[0] -= vbar;
+        // the first node of the series is drawn from the prior N(0, P0)
+        if (kGrad && n == ln.s_begin) {
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pb[i][j] += Lam[i][j];
         }
-        g_s2 += sbar;
-      }
-      if (kCov) {
-        // Lhat = (I - K e0^T)^T Lhp (I - K e0^T) + e0 e0^T / s,  K = u / s
-        double Lk[B], Y[B][B];
-        SPG_UNROLL for (int i = 0; i < B; ++i) {
-          double t_ = 0.0;
-          SPG_UNROLL for (int j = 0; j < B; ++j) t_ = fma(Lhp[i][j], u[j], t_);
-          Lk[i] = t_ * is;                         // Lhp K
-        }
-        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Y[i][j] = Lhp[i][j];
-        SPG_UNROLL for (int i = 0; i < B; ++i) Y[i][0] -= Lk[i];          // Lhp (I - K e0^T)
-        double KY[B];
-        SPG_UNROLL for (int j = 0; j < B; ++j) {
-          double t_ = 0.0;
-          SPG_UNROLL for (int i = 0; i < B; ++i) t_ = fma(u[i], Y[i][j], t_);
-          KY[j] = t_ * is;                         // K^T Y
-        }
-        SPG_UNROLL for (int j = 0; j < B; ++j) Y[0][j] -= KY[j];
-        Y[0][0] += is;
-        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j) {
-          Lhat[i][j] = 0.5 * (Y[i][j] + Y[j][i]);
-          Lhat[j][i] = Lhat[i][j];
-        }
-        if (kSub) SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pn[i][j] = Dk[i][j] + P0[i][j];
-      }
-      SPG_UNROLL for (int i = 0; i < B; ++i) lam[i] = mbp[i];
-      lam[0] -= vbar;
-      // the first node of the series is drawn from the prior N(0, P0)
-      if (kGrad && n == 0) {
-        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Pb[i][j] += Lam[i][j];
       }
     }
+    if (kGrad) {
+      double dP[B][B];
+      Matern<B>::dpinf_dlam(p, dP);
+      const double dlam_dell = -p.lam / p.ell;
+      gr[0] = (gl_lam + frob<B>(Pb, dP)) * dlam_dell;
+      gr[1] = frob<B>(Pb, P0) / p.var;
+      gr[2] = g_s2;
+    }
   }
-  // ---- gradient partials: lengthscale, signal variance, noise variance
-  if (MODE & kWantGrad) {
-    double dP[B][B];
-    Matern<B>::dpinf_dlam(p, dP);
-    const double dlam_dell = -p.lam / p.ell;
-    double gr[3];
-    gr[0] = (gl_lam + frob<B>(Pb, dP)) * dlam_dell;
-    gr[1] = frob<B>(Pb, P0) / p.var;
-    gr[2] = g_s2;
-    // fixed-order work-group reduction (reuses the pool)
+  if (BATCHED) {
+    // ---- per-chunk partials; k_series_reduce sums them per series in a fixed order
+    if (kLl) {
+      out.part[chunk] = fit_chunk;
+      out.part[out.part_ld + chunk] = ldet_chunk;
+    }
+    if (kGrad) SPG_UNROLL for (int c = 0; c < 3; ++c) out.part[(int64_t)(c + 2) * out.part_ld + chunk] = gr[c];
+  } else if (kGrad) {
+    // ---- one series: fixed-order work-group reduction of the gradient partials (reuses the pool)
     __syncthreads();
     SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] = gr[c];
     __syncthreads();
@@ -693,7 +797,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
     // fixed order (independent of which one is last) and resets the counter for the next call
     __shared__ unsigned int ticket;
     if (tid == 0) {
-      SPG_UNROLL for (int c = 0; c < 3; ++c) out.grad_part[c * out.gp_ld + blockIdx.x] = pool[c * L];
+      SPG_UNROLL for (int c = 0; c < 3; ++c) out.part[c * out.part_ld + blockIdx.x] = pool[c * L];
       __threadfence();
       ticket = atomicAdd(out.done, 1u);
     }
@@ -703,7 +807,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
       const int64_t G = gridDim.x;
       double acc[3] = {0.0, 0.0, 0.0};
       for (int64_t i = tid; i < G; i += L) {
-        SPG_UNROLL for (int c = 0; c < 3; ++c) acc[c] += out.grad_part[c * out.gp_ld + i];
+        SPG_UNROLL for (int c = 0; c < 3; ++c) acc[c] += out.part[c * out.part_ld + i];
       }
       __syncthreads();
       SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] = acc[c];
@@ -721,6 +825,119 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------- several series
+// Fixed-order per-series sum of the per-chunk partials: one 64-lane work-group per series; lane i
+// adds chunks first + i, first + i + 64, ... in order, then a fixed tree over the lanes.  Writes
+// logml[s] (eq. ml2), and datafit[s] = y^T K_y^-1 y, logdet[s] = log det K_y, grad[s][0..2] where
+// not null.  An empty series gets logml 0 and a zero gradient.
+__global__ __launch_bounds__(64) void k_series_reduce(SeriesMap sm, const double* __restrict__ part,
+                                                       int64_t part_ld, int64_t n_pts, double* __restrict__ logml,
+                                                       double* __restrict__ datafit, double* __restrict__ logdet,
+                                                       double* __restrict__ grad) {
+  __shared__ double red[5][64];
+  const int tid = threadIdx.x;
+  const int64_t s = blockIdx.x;
+  const int64_t c0 = sm.chunk_first[s];
+  const int64_t c1 = sm.chunk_first[s + 1] < sm.slots ? sm.chunk_first[s + 1] : sm.slots;
+  const int nf = grad ? 5 : 2;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = c0 + tid; c < c1; c += 64) {
+    for (int f = 0; f < nf; ++f) acc[f] += part[f * part_ld + c];
+  }
+  for (int f = 0; f < 5; ++f) red[f][tid] = acc[f];
+  __syncthreads();
+  for (int stride = 32; stride > 0; stride /= 2) {
+    if (tid < stride) for (int f = 0; f < 5; ++f) red[f][tid] += red[f][tid + stride];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int64_t ob = sm.offsets[s], oe = sm.offsets[s + 1];
+    const double ns = (oe > ob && ob >= 0 && oe <= n_pts) ? (double)(oe - ob) : 0.0;
+    const double fit = red[0][0], ld = red[1][0];
+    if (logml) logml[s] = -0.5 * fit - 0.5 * ld - 0.5 * ns * kLog2Pi;
+    if (datafit) datafit[s] = fit;
+    if (logdet) logdet[s] = ld;
+    if (grad) for (int f = 0; f < 3; ++f) grad[s * 3 + f] = red[f + 2][0];
+  }
+}
+
+// Chunk map of several series (built once per assemble).  Chunks per series c_s = ceil(len_s / R);
+// chunk_first is their exclusive prefix sum (one work-group, carried across blocks of 256).
+__global__ __launch_bounds__(256) void k_chunk_first(const int64_t* __restrict__ offsets, int32_t n_series,
+                                                      int64_t n_pts, int R, int64_t* __restrict__ chunk_first,
+                                                      unsigned long long* __restrict__ status) {
+  __shared__ int64_t sc[256];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    carry = 0;
+    if (offsets[0] != 0 || offsets[n_series] != n_pts) atomicMin(status, 1ull);   // SPINGP_E_INVALID
+  }
+  __syncthreads();
+  for (int64_t base = 0; base < n_series; base += 256) {
+    const int64_t s = base + tid;
+    int64_t c = 0;
+    if (s < n_series) {
+      const int64_t len = offsets[s + 1] - offsets[s];
+      if (len < 0) atomicMin(status, 1ull);            // decreasing offsets
+      c = len > 0 ? (len + R - 1) / R : 0;
+    }
+    sc[tid] = c;
+    __syncthreads();
+    for (int d = 1; d < 256; d *= 2) {                 // inclusive scan
+      const int64_t v = tid >= d ? sc[tid - d] : 0;
+      __syncthreads();
+      sc[tid] += v;
+      __syncthreads();
+    }
+    if (s < n_series) chunk_first[s] = carry + sc[tid] - c;
+    __syncthreads();
+    if (tid == 255) carry += sc[255];
+    __syncthreads();
+  }
+  if (tid == 0) chunk_first[n_series] = carry;
+}
+
+// Device-side validation of several series, one thread per chunk slot: finite t and y, t
+// non-decreasing inside each series.  key = (index << 4) | code, minimised over offending points.
+template <int R>
+__global__ void k_validate_chunks(const double* __restrict__ t, const double* __restrict__ y, int64_t n_pts,
+                                  const double* __restrict__ hyper, SeriesMap sm,
+                                  unsigned long long* __restrict__ key) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < sm.n_series) {
+    for (int k = 0; k < 3; ++k) {
+      const double h = hyper[3 * c + k];
+      if (!(isfinite(h) && h > 0.0)) atomicMin(key, 5ull);              // SPINGP_E_HYPER
+    }
+  }
+  if (c >= sm.slots) return;
+  const Lane<2> ln = lane_of<2, R, true>(c, n_pts, hyper, sm);
+  for (int k = 0; k < ln.len; ++k) {
+    const int64_t n = ln.start + k;
+    unsigned long long code = 0;
+    if (!isfinite(t[n]) || !isfinite(y[n])) code = 4;                      // SPINGP_E_NONFINITE
+    else if (n + 1 < ln.s_end && t[n + 1] < t[n]) code = 3;               // SPINGP_E_UNSORTED
+    if (code) {
+      atomicMin(key, ((unsigned long long)(n + 1) << 4) | code);
+      return;
+    }
+  }
+}
+
+// chunk_series: -1 everywhere, then the series of every chunk.
+__global__ void k_chunk_fill(int32_t* __restrict__ chunk_series, int64_t slots) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < slots) chunk_series[i] = -1;
+}
+__global__ void k_chunk_map(const int64_t* __restrict__ chunk_first, int32_t n_series, int64_t slots,
+                            int32_t* __restrict__ chunk_series) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_series) return;
+  const int64_t c1 = chunk_first[s + 1] < slots ? chunk_first[s + 1] : slots;
+  for (int64_t c = chunk_first[s]; c < c1; ++c) chunk_series[c] = (int32_t)s;
 }
 
 }  // namespace spg

@@ -111,13 +111,17 @@ def spingp_destroy(h):
 
 def spingp_assemble(h, t, y, hyper, offsets=None, n_series=1):
     n = t.numel()
+    lib = load_library()
     off = None
     if offsets is not None:
-        if offsets.dtype != torch.int64 or not offsets.is_cuda:
-            raise ValueError("offsets must be an int64 tensor on the GPU")
+        if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+            raise ValueError("offsets must be a contiguous int64 tensor on the GPU")
+        if offsets.numel() != int(n_series) + 1:
+            raise ValueError(f"offsets must have n_series + 1 = {int(n_series) + 1} entries")
         off = ctypes.c_void_p(offsets.data_ptr())
-    _check(load_library().spingp_assemble(h, _dev(t, "t"), _dev(y, "y", n), off, int(n_series), int(n),
-                                          _dev(hyper, "hyper"), 0), "spingp_assemble")
+    nh = lib.spingp_n_hyper(h) * int(n_series)
+    _check(lib.spingp_assemble(h, _dev(t, "t"), _dev(y, "y", n), off, int(n_series), int(n),
+                               _dev(hyper, "hyper", nh), 0), "spingp_assemble")
 
 
 def spingp_factor(h):
@@ -149,7 +153,7 @@ def spingp_status(h):
 
 
 N_KERNELS = 5
-KERNEL_NAMES = ("validate", "fwd_fold_tree", "top_tree", "bwd_elim_adjoint", "finalize")
+KERNEL_NAMES = ("validate", "fwd_fold_tree", "top_tree", "bwd_elim_adjoint", "series_reduce")
 
 
 def spingp_profile(h, enable):

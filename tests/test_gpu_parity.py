@@ -7,7 +7,7 @@ CPU tests pin against the dense GP, mpmath fixtures and the Kalman filter.
 import numpy as np
 import pytest
 
-from gpu_util import check_grad, check_logml, check_mean_var, to_dev
+from gpu_util import check_grad, compare_series, to_dev
 from oracle import native
 from workloads import make_config
 
@@ -66,41 +66,8 @@ def _reference_spread(w):
 
 
 def _compare(w, got, blocks=True, widen=1.0):
-    """Element-wise comparison; `widen` multiplies the mean/variance/block bars (1 = the 1e-9 bars)."""
     t, y, hyp = w.series(0)
-    ref = native.btd_factored(w.terms, hyp, t, y, want_blocks=blocks)
-    gref = native.tangent_grad(w.terms, hyp, t, y)
-    assert got["status"] == 0
-    check_logml(got["logml"], ref["logml"])
-    check_logml(got["logml2"], ref["logml"])
-    check_logml(got["datafit"], ref["datafit"], tol=1e-8)
-    assert abs(got["logdet"] - ref["logdet"]) <= 1e-8 * max(1.0, abs(ref["logdet"]))
-    tol = 1e-9 * widen
-    sc_m = np.abs(ref["f_mean"]) + np.sqrt(ref["f_var"])
-    assert np.max(np.abs(got["f_mean"] - ref["f_mean"]) / sc_m) <= tol
-    assert np.max(np.abs(got["f_var"] - ref["f_var"]) / ref["f_var"]) <= tol
-    if widen == 1.0:
-        check_mean_var(got["f_mean"], got["f_var"], ref["f_mean"], ref["f_var"])
-    check_grad(got["grad"], gref["grad"])
-    if blocks:
-        b = ref["z_mean"].shape[1]
-        zs = np.sqrt(np.maximum(np.einsum("nii->ni", ref["S_diag"]), 0.0))
-        ez = np.abs(got["z_mean"].T - ref["z_mean"]) / (np.abs(ref["z_mean"]) + zs)
-        assert ez.max() <= tol, f"z_mean {ez.max():.3e} at {np.unravel_index(ez.argmax(), ez.shape)}"
-        iu = np.triu_indices(b)
-        Sd_ref = ref["S_diag"][:, iu[0], iu[1]].T
-        scale = np.sqrt(np.abs(np.einsum("nii->ni", ref["S_diag"])))     # sqrt(S_ii)
-        sc = (scale[:, iu[0]] * scale[:, iu[1]]).T
-        es = np.abs(got["S_diag"] - Sd_ref) / sc
-        assert es.max() <= tol, f"S_diag {es.max():.3e}"
-        n = t.shape[0]
-        if n > 1:
-            Ss_ref = ref["S_sub"].reshape(n - 1, b * b).T
-            rows = np.repeat(np.arange(b), b)
-            cols = np.tile(np.arange(b), b)
-            sc2 = scale[1:, rows].T * scale[:-1, cols].T
-            eb = np.abs(got["S_sub"][:, : n - 1] - Ss_ref) / sc2
-            assert eb.max() <= tol, f"S_sub {eb.max():.3e}"
+    compare_series(w.terms, t, y, hyp, got, blocks=blocks, widen=widen)
 
 
 def test_config1_matern32_n1000(lib):

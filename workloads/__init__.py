@@ -9,6 +9,7 @@ from .generate import (  # noqa: F401
     KIND_MATERN52,
     KIND_PERIODIC,
     Workload,
+    make_batch,
     make_config,
     make_series,
     n_hyper,

@@ -230,18 +230,137 @@ def make_config(k: int, n: int | None = None, n_series: int | None = None,
             lens = np.minimum(lens, max_len)
         ells = np.exp(rng.uniform(np.log(0.5), np.log(20.0), S))
         noises = rng.uniform(0.01, 0.5, S)
-        children = np.random.SeedSequence(4).spawn(S)
-        ts, ys = [], []
-        hyper = np.zeros((S, 3))
+        hyper = np.stack([ells, np.ones(S), noises], axis=1)
+        w = make_batch(lens, hyper, [(KIND_MATERN52, 0)], seed=4)
+        w.name = "batched_matern52_%dseries" % S
+        w.notes["lengths"] = "log-U[64,16384]"
+        return w
+    raise ValueError("config must be 1..5")
+
+
+def _recurrence_last_component(A, w, x0):
+    """x_0 = x0, x_{k+1} = A_k x_k + w_k (A: [n-1, d, d], w: [n-1, d]); returns x_k[d-1] for all
+    k, with about sqrt(n) blocks of sqrt(n) steps, vectorised over the blocks."""
+    n = A.shape[0] + 1
+    d = x0.shape[0]
+    block = max(16, int(np.sqrt(n)) + 1)
+    nb = (n + block - 1) // block
+    Ap = np.broadcast_to(np.eye(d), (nb * block, d, d)).copy()
+    Ap[: n - 1] = A
+    wp = np.zeros((nb * block, d))
+    wp[: n - 1] = w
+    Ap = Ap.reshape(nb, block, d, d)
+    wp = wp.reshape(nb, block, d)
+    state = np.zeros((nb, d))
+    phi = np.broadcast_to(np.eye(d), (nb, d, d)).copy()
+    local_last = np.zeros((nb, block))
+    for j in range(block):
+        local_last[:, j] = state[:, d - 1]
+        state = np.einsum("bij,bj->bi", Ap[:, j], state) + wp[:, j]
+        phi = Ap[:, j] @ phi
+    X = np.zeros((nb, d))
+    X[0] = x0
+    for b in range(nb - 1):
+        X[b + 1] = phi[b] @ X[b] + state[b]
+    out = np.zeros((nb, block))
+    yv = X
+    for j in range(block):
+        out[:, j] = yv[:, d - 1] + local_last[:, j]
+        yv = np.einsum("bij,bj->bi", Ap[:, j], yv)
+    return out.reshape(-1)[:n]
+
+
+def _psd_factor_apply(Q, xi):
+    """W xi for W W^T = Q (batched, PSD up to rounding): an LDL^T factorisation with pivots below
+    1e-14 of the diagonal scale treated as zero (their column is dropped), so near-singular Q
+    from tiny gaps is handled; W = L sqrt(D)."""
+    n, d, _ = Q.shape
+    Lm = np.zeros((n, d, d))
+    D = np.zeros((n, d))
+    scale = np.max(np.abs(np.einsum("kii->ki", Q)), axis=1)
+    for j in range(d):
+        Dj = Q[:, j, j] - np.einsum("kc,kc->k", Lm[:, j, :j] ** 2, D[:, :j])
+        ok = Dj > 1e-14 * scale
+        D[:, j] = np.where(ok, Dj, 0.0)
+        Lm[:, j, j] = 1.0
+        safe = np.where(ok, Dj, 1.0)
+        for r in range(j + 1, d):
+            num = Q[:, r, j] - np.einsum("kc,kc,kc->k", Lm[:, r, :j], Lm[:, j, :j], D[:, :j])
+            Lm[:, r, j] = np.where(ok, num / safe, 0.0)
+    return np.einsum("kij,kj->ki", Lm, np.sqrt(D) * xi)
+
+
+def _matern_batch(ts, kind, hyper, draws):
+    """Prior sample paths of independent Matern series, concatenated, in one recurrence: the
+    step out of a series' last point has A = 0 and carries the next series' initial state.
+    `draws[i]` = (standard normal of the initial state, standard normals of the transition noise)."""
+    order = _MATERN_ORDER[kind]
+    lens = np.array([t.shape[0] for t in ts], dtype=np.int64)
+    nz = np.nonzero(lens)[0]
+    n = int(lens.sum())
+    A = np.zeros((max(n - 1, 0), order, order))
+    w = np.zeros((max(n - 1, 0), order))
+    x0_first = None
+    pos = 0
+    for k, i in enumerate(nz):
+        L = int(lens[i])
+        lam = np.sqrt(2.0 * _MATERN_NU[kind]) / hyper[i, 0]
+        P = _cascade_stationary_cov(order, lam)
+        P *= hyper[i, 1] / P[order - 1, order - 1]
+        x0 = np.linalg.cholesky(P) @ draws[i][0]
+        if k == 0:
+            x0_first = x0
+        else:
+            w[pos - 1] = x0          # boundary step: A = 0, noise = next initial state
+        if L > 1:
+            dt = np.diff(ts[i])
+            Ai = _cascade_transition(order, lam, dt)
+            Q = P[None] - Ai @ P[None] @ np.swapaxes(Ai, -1, -2)
+            A[pos: pos + L - 1] = Ai
+            w[pos: pos + L - 1] = _psd_factor_apply(Q, draws[i][1])
+        pos += L
+    if n == 0:
+        return np.zeros(0)
+    return _recurrence_last_component(A, w, x0_first)
+
+
+def make_batch(lens, hyper, terms, seed) -> Workload:
+    """Independent series of the given lengths (zero allowed) and hyperparameter rows, one child
+    stream per series: times are cumulative Exp(1) gaps, y a prior sample plus noise."""
+    lens = np.asarray(lens, dtype=np.int64)
+    hyper = np.asarray(hyper, dtype=np.float64).reshape(lens.shape[0], -1)
+    S = lens.shape[0]
+    children = np.random.SeedSequence(seed).spawn(S)
+    ts, ys = [], []
+    if len(terms) == 1 and terms[0][0] in _MATERN_ORDER:
+        # one Matern term: the same draws per series as make_series, one vectorised recurrence
+        # (the transition noise uses an LDL^T square root of Q_n instead of eigh: same law)
+        order = _MATERN_ORDER[terms[0][0]]
+        draws, eps = [], []
+        for i in range(S):
+            r = np.random.default_rng(children[i])
+            n = int(lens[i])
+            ts.append(np.cumsum(r.exponential(1.0, n)))
+            if n > 0:
+                draws.append((r.standard_normal(order), r.standard_normal((n - 1, order))))
+                eps.append(r.standard_normal(n))
+            else:
+                draws.append(None)
+                eps.append(np.zeros(0))
+        f = _matern_batch(ts, terms[0][0], hyper, draws)
+        pos = 0
+        for i in range(S):
+            n = int(lens[i])
+            ys.append(f[pos: pos + n] + np.sqrt(hyper[i, 2]) * eps[i])
+            pos += n
+    else:
         for i in range(S):
             r = np.random.default_rng(children[i])
             t = np.cumsum(r.exponential(1.0, int(lens[i])))
-            hyper[i] = (ells[i], 1.0, noises[i])
             ts.append(t)
-            ys.append(make_series(t, [(KIND_MATERN52, 0)], hyper[i], r))
-        offsets = np.zeros(S + 1, dtype=np.int64)
-        offsets[1:] = np.cumsum(lens)
-        return Workload(name="batched_matern52_%dseries" % S, terms=[(KIND_MATERN52, 0)],
-                        t=np.concatenate(ts), y=np.concatenate(ys), offsets=offsets, hyper=hyper,
-                        notes={"grid": "cumsum Exp(1) per series", "lengths": "log-U[64,16384]"})
-    raise ValueError("config must be 1..5")
+            ys.append(make_series(t, terms, hyper[i], r) if lens[i] > 0 else np.zeros(0))
+    offsets = np.zeros(S + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(lens)
+    return Workload(name="batch_%dseries_seed%d" % (S, seed), terms=list(terms),
+                    t=np.concatenate(ts), y=np.concatenate(ys), offsets=offsets, hyper=hyper.copy(),
+                    notes={"grid": "cumsum Exp(1) per series"})
