@@ -65,8 +65,9 @@ typedef struct {
 /*
  * Create a handle for a model given as a sum of terms (host array of n_terms entries) and the
  * largest problem it will see.  `stream` is a hipStream_t (NULL = the default stream).
- * Supported models: a single Matern-3/2 (b = 2) or Matern-5/2 (b = 3) term, one series.
- * Allocates all device workspace; returns SPINGP_E_UNSUPPORTED for other models.
+ * Supported models: a single Matern-3/2 (b = 2) or Matern-5/2 (b = 3) term; any number of
+ * series up to max_series.  Allocates all device workspace (sized for every compiled tile shape,
+ * see spingp_tile_shape); returns SPINGP_E_UNSUPPORTED for other models.
  */
 int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,
                   int32_t max_series, void* stream);
@@ -78,14 +79,32 @@ int spingp_destroy(spingp_handle h);
 int spingp_state_dim(spingp_handle h);
 int spingp_n_hyper(spingp_handle h);
 
+/* Device bytes of workspace the handle holds (allocated by spingp_create), -1 for NULL. */
+int64_t spingp_workspace_bytes(spingp_handle h);
+
+/* Flags of spingp_assemble. */
+#define SPINGP_FLAG_GRAPH 1u     /* spingp_logml_grad replays a HIP graph of its launches */
+#define SPINGP_FLAG_AUTOTUNE 2u  /* choose the tile shape from the process-wide tuning cache */
+
 /*
  * Assemble: bind the inputs and build the factored block-tridiagonal precision (Theorem 1
- * with G^T Sigma^-1 G = I (x) h h^T / s2, Sec. 2.2).  t, y: [n_points]; offsets: NULL or
- * [n_series + 1] int64 with offsets[0] = 0, offsets[n_series] = n_points; hyper:
- * [n_series x n_hyper].  The blocks (A_n, Q_n, J, eta_n) are recomputed from t, y and hyper
- * inside the kernels that use them, so this call only validates and records the inputs;
- * device-side validation results are read with spingp_status.  flags: reserved, pass 0.
- * Invalidates any earlier factorisation.
+ * with G^T Sigma^-1 G = I (x) h h^T / s2, Sec. 2.2).  t, y: [n_points] (n_points >= 1);
+ * offsets: [n_series + 1] int64 device array with offsets[0] = 0, non-decreasing,
+ * offsets[n_series] = n_points (required when n_series > 1, ignored for one series; empty
+ * series are allowed); hyper: [n_series x n_hyper].  Time must be non-decreasing inside each
+ * series and may restart between series.  The blocks (A_n, Q_n, J, eta_n) are recomputed from
+ * t, y and hyper inside the kernels that use them, so this call only validates the inputs and,
+ * for several series, builds the map from chunks of R nodes to series; device-side validation
+ * results (bad offsets report SPINGP_E_INVALID) are read with spingp_status.
+ * flags: 0 or a combination of
+ *   SPINGP_FLAG_GRAPH: the first spingp_logml_grad call, and any call with other output
+ *     pointers, captures its launch sequence into a HIP graph on a private non-blocking stream
+ *     (created at the first capture) and instantiates it; calls replay it on the handle's
+ *     stream (hyperparameters are read from device memory, so new values need no new capture).
+ *   SPINGP_FLAG_AUTOTUNE: use the tile shape the process-wide cache holds for this problem
+ *     class (b, one or several series, ceil log2 n_points, ceil log2 n_series); on a miss run
+ *     spingp_tune(h, 3) here, which synchronises the stream.
+ * Invalidates any earlier factorisation and captured graph.
  */
 int spingp_assemble(spingp_handle h, const double* t, const double* y, const int64_t* offsets, int32_t n_series,
                     int64_t n_points, const double* hyper, uint32_t flags);
@@ -100,7 +119,8 @@ int spingp_factor(spingp_handle h);
 /*
  * Log marginal likelihood (eq. ml2 via the determinant lemma eq. det_1) of the factored
  * problem.  logml: [n_series]; datafit: NULL or [n_series] = y^T K_y^-1 y; logdet: NULL or
- * [n_series] = log det K_y.  Needs factor.
+ * [n_series] = log det K_y.  An empty series has all three 0.  Needs factor.  One series reads
+ * the root of the reduction; several series run an elimination sweep over every chunk.
  */
 int spingp_logml(spingp_handle h, double* logml, double* datafit, double* logdet);
 
@@ -114,19 +134,36 @@ int spingp_solve(spingp_handle h, double* f_mean, double* z_mean);
  * Selected inverse (subproblems 2 and 4: the block-tridiagonal part of the inverse precision,
  * Sec. 3.1): f_var: NULL or [n_points] = Var[f(t_n) | y] (latent, eq. k3, no noise);
  * S_diag: NULL or [b(b+1)/2 x n_points] = Cov(z_n | y); S_sub: NULL or [b*b x n_points], entry n
- * = Cov(z_{n+1}, z_n | y) for n < n_points - 1 (entry n_points - 1 is left untouched).
- * Needs factor.
+ * = Cov(z_{n+1}, z_n | y) for n < n_points - 1 inside one series (the entry at the last node of
+ * every series is left untouched).  Needs factor.
  */
 int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, double* S_sub);
 
 /*
  * Log marginal likelihood and its gradient (Sec. 2.4) with respect to the raw hyperparameters
- * of the hyperparameter row: grad: [n_series x n_hyper], logml: [n_series].  Always runs the
- * forward reduction itself (it reads the hyperparameters from device memory, so an optimiser may
- * update them between calls without a new assemble), then the adjoint sweep; leaves the handle
- * factored.  Needs assemble.
+ * of the hyperparameter row: grad: [n_series x n_hyper], logml: [n_series] (an empty series
+ * gets 0 and a zero gradient).  Always runs the forward reduction itself (it reads the
+ * hyperparameters from device memory, so an optimiser may update them between calls without a
+ * new assemble), then the adjoint sweep; leaves the handle factored.  Replays a HIP graph when
+ * assembled with SPINGP_FLAG_GRAPH.  Needs assemble.
  */
 int spingp_logml_grad(spingp_handle h, double* logml, double* grad);
+
+/*
+ * Tile shapes (R nodes folded per lane, L lanes per work-group) compiled into the library;
+ * shape 0 is the default.  Results agree across shapes up to rounding.
+ */
+int spingp_tile_count(void);
+int spingp_tile_shape(int32_t index, int32_t* R, int32_t* L);
+/* Current shape of the handle; selecting one re-validates and re-maps the bound inputs. */
+int spingp_get_tile(spingp_handle h, int32_t* index);
+int spingp_set_tile(spingp_handle h, int32_t index);
+/*
+ * Autotuner: time spingp_logml_grad `reps` times on the assembled problem for every tile shape
+ * (HIP events on the handle's stream; synchronises), keep the fastest for this handle and
+ * record it in the process-wide cache used by SPINGP_FLAG_AUTOTUNE.  Needs assemble.
+ */
+int spingp_tune(spingp_handle h, int32_t reps);
 
 /*
  * Synchronise the handle's stream and report the first device-detected data error since the
@@ -139,12 +176,12 @@ int spingp_status(spingp_handle h, int64_t* first_bad);
  * Diagnostics: per-kernel timing with HIP events recorded on the handle's stream around every
  * launch the library makes.  spingp_profile(h, 1) creates the events and starts recording,
  * spingp_profile(h, 0) stops and releases them.  spingp_profile_read synchronises and returns,
- * per kernel id (0 validate, 1 forward fold + work-group tree, 2 top-level tree and
- * down-sweeps, 3 work-group down-sweep + chunk elimination + adjoint (+ gradient sum),
- * 4 reserved), the total milliseconds and launch counts since the last read (host arrays of
- * SPINGP_N_KERNELS).
+ * per kernel id (0 validation and chunk map, 1 forward fold + work-group tree, 2 top-level
+ * tree, 3 top-level path walk + work-group down-sweep + chunk elimination + adjoint (+ gradient
+ * sum), 4 per-series sums, 5 a whole graph replay of spingp_logml_grad), the total
+ * milliseconds and launch counts since the last read (host arrays of SPINGP_N_KERNELS).
  */
-#define SPINGP_N_KERNELS 5
+#define SPINGP_N_KERNELS 6
 int spingp_profile(spingp_handle h, int enable);
 int spingp_profile_read(spingp_handle h, double* total_ms, int64_t* launches);
 

@@ -15,9 +15,15 @@ from .spingp import (  # noqa: F401
     spingp_create,
     spingp_destroy,
     spingp_factor,
+    spingp_get_tile,
     spingp_logml,
     spingp_logml_grad,
     spingp_selinv,
+    spingp_set_tile,
     spingp_solve,
     spingp_status,
+    spingp_tile_count,
+    spingp_tile_shape,
+    spingp_tune,
+    spingp_workspace_bytes,
 )

@@ -4,6 +4,7 @@
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -11,11 +12,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspingp.so")
+# The C-ABI unit, then one object per compiled tile shape (R points per lane, L lanes per
+# work-group); the list must match spg::tile_ops() in spingp_api.hip.
 SOURCES = ["spingp_api.hip"]
-HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp"]
+TILES = [(8, 128), (4, 128), (8, 64), (4, 64)]
+HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp", "spingp_host.hpp", "spingp_series.hpp"]
 
 HIPCC_FLAGS = [
-    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
+    "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
     # packed fp32 arithmetic stays off; all arithmetic here is fp64 anyway
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
@@ -29,16 +33,39 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def _compile(args):
+    cmd, out = args
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    return out, res.returncode, res.stdout + res.stderr
+
+
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    inc = ["-I", os.path.join(os.path.dirname(HERE), "include")]
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    jobs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        jobs.append(([hipcc()] + HIPCC_FLAGS + inc + ["-c", os.path.join(CSRC, src), "-o", obj], obj))
+    for r, l in TILES:
+        obj = os.path.join(objdir, f"spingp_tile_R{r}_L{l}.o")
+        jobs.append(([hipcc()] + HIPCC_FLAGS + inc + [f"-DSPG_TILE_R={r}", f"-DSPG_TILE_L={l}", "-c",
+                                                       os.path.join(CSRC, "spingp_tile.hip"), "-o", obj], obj))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(_compile, jobs))
+    for out, rc, log in results:
+        if rc != 0:
+            sys.stderr.write(log)
+            raise RuntimeError(f"hipcc failed building {os.path.basename(out)}")
+        if verbose:
+            sys.stderr.write(log)
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(os.path.dirname(HERE), "include"), "-o", tmp] + srcs
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + [o for o, _, _ in results]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libspingp.so")
-    if verbose:
-        sys.stderr.write(res.stderr)
+        raise RuntimeError("linking libspingp.so failed")
     os.replace(tmp, LIB)
     return LIB
 

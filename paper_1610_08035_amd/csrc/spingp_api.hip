@@ -4,15 +4,17 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 
 #include "../../include/spingp.h"
-#include "spingp_kernels.hpp"
+#include "spingp_host.hpp"
+#include "spingp_series.hpp"
 
 namespace {
 
-constexpr int kR = 8;        // points folded sequentially per lane
-constexpr int kL = 128;      // lanes (chunks) per work-group
 constexpr int kT = 256;      // threads of the element-wise helper kernels
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -53,13 +55,31 @@ __global__ void k_copy_scalars(const double* __restrict__ scal, int64_t n_pts, d
 
 }  // namespace
 
+namespace spg {
+const TileOps* tile_ops_R8_L128();
+const TileOps* tile_ops_R4_L128();
+const TileOps* tile_ops_R8_L64();
+const TileOps* tile_ops_R4_L64();
+// The first entry is the default shape.
+const TileOps* tile_ops(int i) {
+  switch (i) {
+    case 0: return tile_ops_R8_L128();
+    case 1: return tile_ops_R4_L128();
+    case 2: return tile_ops_R8_L64();
+    case 3: return tile_ops_R4_L64();
+    default: return nullptr;
+  }
+}
+}  // namespace spg
+
 struct spingp_ctx {
   int b = 0;
   int n_hyper = 0;
   int64_t max_points = 0;
   int32_t max_series = 0;
   hipStream_t stream = nullptr;
-  // workspace
+  int64_t ws_bytes = 0;
+  // workspace (sized for the largest tile requirement)
   double* lane = nullptr;          // work-group trees of the forward kernel (2L slots each)
   double* top = nullptr;           // top-level tree over the work-group aggregates
   unsigned int* top_cnt = nullptr; // arrival counters of the top-level bands
@@ -71,7 +91,10 @@ struct spingp_ctx {
   int32_t* chunk_series = nullptr; // several series: series of every chunk slot
   int64_t* chunk_first = nullptr;  // several series: first chunk of every series
   unsigned long long* key = nullptr;
-  int64_t lane_ld = 0, G_max = 0, slots_max = 0;
+  double* tune_out = nullptr;      // logML and gradient written while tuning
+  int64_t lane_ld = 0;
+  // tile shape
+  int tile = 0;
   // bound inputs
   const double* t = nullptr;
   const double* y = nullptr;
@@ -80,9 +103,14 @@ struct spingp_ctx {
   int64_t n_points = 0;
   int32_t n_series = 0;
   bool batched = false;
-  int64_t G = 0;
   bool assembled = false;
   bool factored = false;
+  // graph replay of spingp_logml_grad
+  bool use_graph = false;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const double* g_logml = nullptr;
+  const double* g_grad = nullptr;
   // profiling (optional)
   static constexpr int kPool = 64;
   bool prof = false;
@@ -116,15 +144,48 @@ static void prof_end(spingp_ctx* h, int kid) {
   h->prof_kid[h->prof_n] = kid;
   h->prof_n += 1;
 }
+static void prof_mark(void* arg, int kid, int end) {
+  spingp_ctx* h = (spingp_ctx*)arg;
+  if (end) prof_end(h, kid);
+  else prof_begin(h);
+}
 
 static int hip_ok(hipError_t e) { return e == hipSuccess ? SPINGP_OK : SPINGP_E_HIP; }
 
-// Work-groups of the forward and reverse kernels for n points in s series: one lane per chunk
-// of R consecutive nodes of one series; with several series every series starts a new chunk,
-// so there are at most ceil(n / R) + s chunks (the unused slots at the end are padding).
-static int64_t groups_for(int64_t n, int64_t s, bool batched) {
-  const int64_t chunks = ceil_div(n, kR) + (batched ? s : 0);
-  return ceil_div(chunks, kL);
+static const spg::TileOps* ops(const spingp_ctx* h) { return spg::tile_ops(h->tile); }
+
+static spg::LaunchCtx launch_ctx(spingp_ctx* h, bool timed = true) {
+  spg::LaunchCtx c;
+  c.b = h->b;
+  c.stream = h->stream;
+  c.t = h->t;
+  c.y = h->y;
+  c.hyper = h->hyper;
+  c.offsets = h->offsets;
+  c.n_points = h->n_points;
+  c.n_series = h->n_series;
+  c.batched = h->batched;
+  c.lane = h->lane;
+  c.lane_ld = h->lane_ld;
+  c.top = h->top;
+  c.top_ld = h->top_ld;
+  c.top_cnt = h->top_cnt;
+  c.done = h->done;
+  c.scal = h->scal;
+  c.part = h->part;
+  c.part_ld = h->part_ld;
+  c.chunk_series = h->chunk_series;
+  c.chunk_first = h->chunk_first;
+  c.key = h->key;
+  c.mark = (timed && h->prof) ? prof_mark : nullptr;
+  c.mark_arg = h;
+  return c;
+}
+
+static void drop_graph(spingp_ctx* h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+  h->g_logml = h->g_grad = nullptr;
 }
 
 extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,
@@ -136,9 +197,24 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   if (terms[0].kind == SPINGP_MATERN32) b = 2;
   else if (terms[0].kind == SPINGP_MATERN52) b = 3;
   else return SPINGP_E_UNSUPPORTED;
-  // grid sizes are 32-bit: at most 2^31 - 1 work-groups of the largest launch
-  if (max_points > (int64_t(1) << 40) || groups_for(max_points, max_series, max_series > 1) >= (int64_t(1) << 31))
-    return SPINGP_E_UNSUPPORTED;
+  if (max_points > (int64_t(1) << 40)) return SPINGP_E_UNSUPPORTED;
+  // workspace for the most demanding tile shape
+  const bool multi = max_series > 1;
+  int64_t G_max = 0, lane_ld = 0;
+  for (int i = 0; i < spg::kNumTiles; ++i) {
+    const spg::TileOps* T = spg::tile_ops(i);
+    const int64_t G = T->groups(max_points, max_series, multi);
+    if (G > G_max) G_max = G;
+    if (G * 2 * T->L > lane_ld) lane_ld = G * 2 * T->L;
+  }
+  // grid sizes are 32-bit
+  if (G_max >= (int64_t(1) << 31)) return SPINGP_E_UNSUPPORTED;
+  int64_t slots_max = 0;
+  for (int i = 0; i < spg::kNumTiles; ++i) {
+    const spg::TileOps* T = spg::tile_ops(i);
+    const int64_t sl = T->groups(max_points, max_series, multi) * T->L;
+    if (sl > slots_max) slots_max = sl;
+  }
   spingp_ctx* h = new (std::nothrow) spingp_ctx();
   if (!h) return SPINGP_E_NOMEM;
   h->b = b;
@@ -147,34 +223,34 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   h->max_series = max_series;
   h->stream = (hipStream_t)stream;
   const int NF = (b == 2) ? spg::ElemLayout<2>::kFields : spg::ElemLayout<3>::kFields;
-  h->G_max = groups_for(max_points, max_series, max_series > 1);
-  h->slots_max = h->G_max * kL;
-  h->lane_ld = h->G_max * 2 * kL;
-  int64_t ltop = 32;
-  while (ltop < h->G_max) ltop *= 32;
-  h->top_ld = 2 * ltop;
-  h->top_cnt_n = 0;
-  for (int64_t n = h->G_max; ; n = ceil_div(n, 32)) {
-    h->top_cnt_n += ceil_div(n, 32);
-    if (n <= 32) break;
-  }
-  h->part_ld = max_series > 1 ? h->slots_max : h->G_max;
-  const int64_t part_n = max_series > 1 ? 5 * h->slots_max : 3 * h->G_max;
+  h->lane_ld = lane_ld;
+  spg::top_sizes(G_max, h->top_ld, h->top_cnt_n);
+  h->part_ld = multi ? slots_max : G_max;
+  const int64_t part_n = multi ? 5 * slots_max : 3 * G_max;
+  struct Req {
+    void** p;
+    int64_t bytes;
+  } reqs[] = {
+      {(void**)&h->lane, (int64_t)sizeof(double) * NF * h->lane_ld},
+      {(void**)&h->top, (int64_t)sizeof(double) * NF * h->top_ld},
+      {(void**)&h->top_cnt, (int64_t)sizeof(unsigned int) * h->top_cnt_n},
+      {(void**)&h->scal, (int64_t)sizeof(double) * 8},
+      {(void**)&h->part, (int64_t)sizeof(double) * part_n},
+      {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
+      {(void**)&h->done, (int64_t)sizeof(unsigned int)},
+      {(void**)&h->tune_out, (int64_t)sizeof(double) * 4 * max_series},
+      {(void**)&h->chunk_series, multi ? (int64_t)sizeof(int32_t) * slots_max : 0},
+      {(void**)&h->chunk_first, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
+  };
   bool ok = true;
-  ok = ok && hipMalloc(&h->lane, sizeof(double) * NF * h->lane_ld) == hipSuccess;
-  ok = ok && hipMalloc(&h->top, sizeof(double) * NF * h->top_ld) == hipSuccess;
-  ok = ok && hipMalloc(&h->top_cnt, sizeof(unsigned int) * h->top_cnt_n) == hipSuccess;
+  for (auto& r : reqs) {
+    if (!ok || r.bytes == 0) continue;
+    ok = hipMalloc(r.p, r.bytes) == hipSuccess;
+    h->ws_bytes += r.bytes;
+  }
   ok = ok && hipMemset(h->top_cnt, 0, sizeof(unsigned int) * h->top_cnt_n) == hipSuccess;
-  ok = ok && hipMalloc(&h->scal, sizeof(double) * 8) == hipSuccess;
-  ok = ok && hipMalloc(&h->part, sizeof(double) * part_n) == hipSuccess;
-  ok = ok && hipMalloc(&h->key, sizeof(unsigned long long)) == hipSuccess;
-  ok = ok && hipMalloc(&h->done, sizeof(unsigned int)) == hipSuccess;
   ok = ok && hipMemset(h->done, 0, sizeof(unsigned int)) == hipSuccess;
   ok = ok && hipMemset(h->key, 0xff, sizeof(unsigned long long)) == hipSuccess;
-  if (max_series > 1) {
-    ok = ok && hipMalloc(&h->chunk_series, sizeof(int32_t) * h->slots_max) == hipSuccess;
-    ok = ok && hipMalloc(&h->chunk_first, sizeof(int64_t) * ((int64_t)max_series + 1)) == hipSuccess;
-  }
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
     spingp_destroy(h);
@@ -220,6 +296,8 @@ extern "C" int spingp_destroy(spingp_handle h) {
   if (!h) return SPINGP_E_INVALID;
   (void)spingp_profile(h, 0);
   if (h->stream || h->lane) (void)hipStreamSynchronize(h->stream);
+  drop_graph(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   (void)hipFree(h->lane);
   (void)hipFree(h->top);
   (void)hipFree(h->top_cnt);
@@ -227,6 +305,7 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)hipFree(h->part);
   (void)hipFree(h->key);
   (void)hipFree(h->done);
+  (void)hipFree(h->tune_out);
   (void)hipFree(h->chunk_series);
   (void)hipFree(h->chunk_first);
   delete h;
@@ -235,28 +314,120 @@ extern "C" int spingp_destroy(spingp_handle h) {
 
 extern "C" int spingp_state_dim(spingp_handle h) { return h ? h->b : -1; }
 extern "C" int spingp_n_hyper(spingp_handle h) { return h ? h->n_hyper : -1; }
+extern "C" int64_t spingp_workspace_bytes(spingp_handle h) { return h ? h->ws_bytes : -1; }
 
-static spg::SeriesMap make_map(const spingp_ctx* h) {
-  spg::SeriesMap sm;
-  memset(&sm, 0, sizeof(sm));
-  sm.n_series = h->n_series;
-  if (h->batched) {
-    sm.offsets = h->offsets;
-    sm.chunk_series = h->chunk_series;
-    sm.chunk_first = h->chunk_first;
-    sm.slots = h->G * kL;
+// Validation and (several series) chunk map of the bound inputs for the current tile shape.
+static int bind(spingp_ctx* h) {
+  drop_graph(h);
+  h->factored = false;
+  const spg::TileOps* T = ops(h);
+  hipLaunchKernelGGL(k_fill_key, dim3(1), dim3(1), 0, h->stream, h->key);
+  prof_begin(h);
+  if (!h->batched) {
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)ceil_div(h->n_points, kT)), dim3(kT), 0, h->stream, h->t, h->y,
+                       h->n_points, h->hyper, h->n_hyper, h->key);
+  } else {
+    const int64_t slots = T->groups(h->n_points, h->n_series, true) * T->L;
+    hipLaunchKernelGGL(spg::k_chunk_first, dim3(1), dim3(256), 0, h->stream, h->offsets, h->n_series, h->n_points,
+                       T->R, h->chunk_first, h->key);
+    hipLaunchKernelGGL(spg::k_chunk_fill, dim3((unsigned)ceil_div(slots, kT)), dim3(kT), 0, h->stream,
+                       h->chunk_series, slots);
+    hipLaunchKernelGGL(spg::k_chunk_map, dim3((unsigned)ceil_div(h->n_series, kT)), dim3(kT), 0, h->stream,
+                       h->chunk_first, h->n_series, slots, h->chunk_series);
+    if (T->map(launch_ctx(h, false)) != hipSuccess) return SPINGP_E_HIP;
   }
-  return sm;
+  prof_end(h, spg::kKidValidate);
+  return hip_ok(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------- tuning cache
+namespace {
+using TuneKey = std::tuple<int, bool, int, int>;   // b, several series, ceil log2 N, ceil log2 S
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_cache;
+
+int ceil_log2(int64_t x) {
+  int k = 0;
+  while ((int64_t(1) << k) < x) ++k;
+  return k;
+}
+TuneKey tune_key(const spingp_ctx* h) {
+  return TuneKey(h->b, h->batched, ceil_log2(h->n_points), ceil_log2(h->n_series));
+}
+}  // namespace
+
+static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed);
+
+extern "C" int spingp_tune(spingp_handle h, int32_t reps) {
+  if (!h || reps < 1) return SPINGP_E_INVALID;
+  if (!h->assembled) return SPINGP_E_ORDER;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return SPINGP_E_HIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SPINGP_E_HIP;
+  }
+  int best = -1, rc = SPINGP_OK;
+  float best_ms = 0.f;
+  for (int i = 0; i < spg::kNumTiles && rc == SPINGP_OK; ++i) {
+    h->tile = i;
+    rc = bind(h);
+    if (rc) break;
+    rc = run_logml_grad(h, h->tune_out, h->tune_out + h->max_series, false);   // warm-up
+    if (rc) break;
+    (void)hipEventRecord(e0, h->stream);
+    for (int r = 0; r < reps && rc == SPINGP_OK; ++r)
+      rc = run_logml_grad(h, h->tune_out, h->tune_out + h->max_series, false);
+    (void)hipEventRecord(e1, h->stream);
+    float ms = 0.f;
+    if (rc == SPINGP_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = SPINGP_E_HIP;
+    if (rc == SPINGP_OK && (best < 0 || ms < best_ms)) {
+      best = i;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->tile = best < 0 ? 0 : best;
+  const int rc2 = bind(h);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[tune_key(h)] = h->tile;
+  return SPINGP_OK;
+}
+
+extern "C" int spingp_tile_count(void) { return spg::kNumTiles; }
+
+extern "C" int spingp_tile_shape(int32_t i, int32_t* R, int32_t* L) {
+  const spg::TileOps* T = spg::tile_ops(i);
+  if (!T || !R || !L) return SPINGP_E_INVALID;
+  *R = T->R;
+  *L = T->L;
+  return SPINGP_OK;
+}
+
+extern "C" int spingp_get_tile(spingp_handle h, int32_t* index) {
+  if (!h || !index) return SPINGP_E_INVALID;
+  *index = h->tile;
+  return SPINGP_OK;
+}
+
+extern "C" int spingp_set_tile(spingp_handle h, int32_t index) {
+  if (!h || !spg::tile_ops(index)) return SPINGP_E_INVALID;
+  h->tile = index;
+  return h->assembled ? bind(h) : SPINGP_OK;
 }
 
 extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y, const int64_t* offsets,
                                int32_t n_series, int64_t n_points, const double* hyper, uint32_t flags) {
-  if (!h || !t || !y || !hyper || flags != 0) return SPINGP_E_INVALID;
+  if (!h || !t || !y || !hyper) return SPINGP_E_INVALID;
+  if (flags & ~(uint32_t)(SPINGP_FLAG_GRAPH | SPINGP_FLAG_AUTOTUNE)) return SPINGP_E_INVALID;
   if (n_series < 1 || n_series > h->max_series) return SPINGP_E_INVALID;
   if (n_points < 1 || n_points > h->max_points) return SPINGP_E_INVALID;
   if (n_series > 1 && !offsets) return SPINGP_E_INVALID;
   h->assembled = false;
-  h->factored = false;
   h->t = t;
   h->y = y;
   h->hyper = hyper;
@@ -265,102 +436,49 @@ extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y
   h->n_series = n_series;
   // one series is the whole array (offsets, if given, are not read)
   h->batched = n_series > 1;
-  h->G = groups_for(n_points, n_series, h->batched);
-  hipLaunchKernelGGL(k_fill_key, dim3(1), dim3(1), 0, h->stream, h->key);
-  prof_begin(h);
-  if (!h->batched) {
-    hipLaunchKernelGGL(k_validate, dim3((unsigned)ceil_div(n_points, kT)), dim3(kT), 0, h->stream, t, y, n_points,
-                       hyper, h->n_hyper, h->key);
-  } else {
-    const int64_t slots = h->G * kL;
-    hipLaunchKernelGGL(spg::k_chunk_first, dim3(1), dim3(256), 0, h->stream, offsets, n_series, n_points, kR,
-                       h->chunk_first, h->key);
-    hipLaunchKernelGGL(spg::k_chunk_fill, dim3((unsigned)ceil_div(slots, kT)), dim3(kT), 0, h->stream,
-                       h->chunk_series, slots);
-    hipLaunchKernelGGL(spg::k_chunk_map, dim3((unsigned)ceil_div(n_series, kT)), dim3(kT), 0, h->stream,
-                       h->chunk_first, n_series, slots, h->chunk_series);
-    hipLaunchKernelGGL(spg::k_validate_chunks<kR>, dim3((unsigned)ceil_div(slots, kT)), dim3(kT), 0, h->stream, t,
-                       y, n_points, hyper, make_map(h), h->key);
+  h->use_graph = (flags & SPINGP_FLAG_GRAPH) != 0;
+  bool tune = false;
+  if (flags & SPINGP_FLAG_AUTOTUNE) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(tune_key(h));
+    if (it != g_tune_cache.end()) h->tile = it->second;
+    else tune = true;
   }
-  prof_end(h, 0);
-  const int rc = hip_ok(hipGetLastError());
-  h->assembled = rc == SPINGP_OK;
+  int rc = bind(h);
+  if (rc) return rc;
+  h->assembled = true;
+  if (tune) {
+    // a miss of the tuning cache: only if the inputs are valid (tuning synchronises anyway)
+    int64_t bad = -1;
+    rc = spingp_status(h, &bad);
+    if (rc == SPINGP_OK) rc = spingp_tune(h, 3);
+    else if (rc != SPINGP_E_HIP) rc = SPINGP_OK;   // a data error: reported by spingp_status
+  }
   return rc;
-}
-
-static spg::TopTree make_top(spingp_ctx* h) {
-  spg::TopTree T;
-  memset(&T, 0, sizeof(T));
-  T.elems = h->top;
-  T.ld = h->top_ld;
-  T.G = h->G;
-  T.cnt = h->top_cnt;
-  int nb = 1;
-  int64_t ltop = 32;
-  while (ltop < h->G) {
-    ltop *= 32;
-    ++nb;
-  }
-  T.Ltop = ltop;
-  T.n_bands = nb;
-  int64_t off = 0, n = h->G;
-  for (int b = 0; b < nb; ++b) {
-    T.cnt_off[b] = off;
-    off += ceil_div(n, 32);
-    n = ceil_div(n, 32);
-  }
-  return T;
-}
-
-template <int B, bool BATCHED>
-static int launch_factor(spingp_ctx* h) {
-  const spg::TopTree top = make_top(h);
-  const spg::SeriesMap sm = make_map(h);
-  prof_begin(h);
-  hipLaunchKernelGGL((spg::k_fwd<B, kR, kL, BATCHED>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t, h->y,
-                     h->n_points, h->hyper, sm, h->lane, h->lane_ld, top, h->key);
-  prof_end(h, 1);
-  prof_begin(h);
-  hipLaunchKernelGGL((spg::k_top_bands<B, BATCHED>), dim3((unsigned)ceil_div(h->G, 32)), dim3(64), 0, h->stream,
-                     h->hyper, sm, top, h->scal);
-  prof_end(h, 2);
-  return hip_ok(hipGetLastError());
-}
-
-static int do_factor(spingp_ctx* h) {
-  if (h->b == 2) return h->batched ? launch_factor<2, true>(h) : launch_factor<2, false>(h);
-  return h->batched ? launch_factor<3, true>(h) : launch_factor<3, false>(h);
 }
 
 extern "C" int spingp_factor(spingp_handle h) {
   if (!h) return SPINGP_E_INVALID;
   if (!h->assembled) return SPINGP_E_ORDER;
-  const int rc = do_factor(h);
+  const int rc = hip_ok(ops(h)->factor(launch_ctx(h)));
   h->factored = rc == SPINGP_OK;
   return rc;
 }
 
-template <int B, int MODE, bool BATCHED>
-static int launch_bwd(spingp_ctx* h, const spg::BwdOut& o) {
-  prof_begin(h);
-  hipLaunchKernelGGL((spg::k_bwd<B, kR, kL, MODE, BATCHED>), dim3((unsigned)h->G), dim3(kL), 0, h->stream, h->t,
-                     h->y, h->n_points, h->hyper, make_map(h), h->lane, h->lane_ld, make_top(h), o);
-  prof_end(h, 3);
-  return hip_ok(hipGetLastError());
-}
-
-template <int MODE>
-static int run_bwd(spingp_ctx* h, const spg::BwdOut& o) {
-  if (h->b == 2) return h->batched ? launch_bwd<2, MODE, true>(h, o) : launch_bwd<2, MODE, false>(h, o);
-  return h->batched ? launch_bwd<3, MODE, true>(h, o) : launch_bwd<3, MODE, false>(h, o);
+static int run_bwd(spingp_ctx* h, int mode, const spg::BwdOut& o, bool timed = true) {
+  return hip_ok(ops(h)->bwd(launch_ctx(h, timed), mode, o));
 }
 
 // several series: per-series fixed-order sums of the reverse kernel's per-chunk partials
-static int series_reduce(spingp_ctx* h, double* logml, double* datafit, double* logdet, double* grad) {
-  prof_begin(h);
-  hipLaunchKernelGGL(spg::k_series_reduce, dim3((unsigned)h->n_series), dim3(64), 0, h->stream, make_map(h),
-                     h->part, h->part_ld, h->n_points, logml, datafit, logdet, grad);
-  prof_end(h, 4);
+static int series_reduce(spingp_ctx* h, double* logml, double* datafit, double* logdet, double* grad,
+                         bool timed = true) {
+  const spg::TileOps* T = ops(h);
+  const spg::SeriesMap sm =
+      spg::make_map(launch_ctx(h), T->groups(h->n_points, h->n_series, true) * T->L);
+  if (timed) prof_begin(h);
+  hipLaunchKernelGGL(spg::k_series_reduce, dim3((unsigned)h->n_series), dim3(64), 0, h->stream, sm, h->part,
+                     h->part_ld, h->n_points, logml, datafit, logdet, grad);
+  if (timed) prof_end(h, spg::kKidReduce);
   return hip_ok(hipGetLastError());
 }
 
@@ -384,7 +502,7 @@ extern "C" int spingp_logml(spingp_handle h, double* logml, double* datafit, dou
     return hip_ok(hipGetLastError());
   }
   // several series: the per-series terms come from an elimination sweep over every chunk
-  const int rc = run_bwd<spg::kWantLogml>(h, make_out(h));
+  const int rc = run_bwd(h, spg::kWantLogml, make_out(h));
   if (rc) return rc;
   return series_reduce(h, logml, datafit, logdet, nullptr);
 }
@@ -396,7 +514,7 @@ extern "C" int spingp_solve(spingp_handle h, double* f_mean, double* z_mean) {
   spg::BwdOut o = make_out(h);
   o.f_mean = f_mean;
   o.z_mean = z_mean;
-  return run_bwd<spg::kWantMean>(h, o);
+  return run_bwd(h, spg::kWantMean, o);
 }
 
 extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, double* S_sub) {
@@ -407,24 +525,75 @@ extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, dou
   o.f_var = f_var;
   o.S_diag = S_diag;
   o.S_sub = S_sub;
-  if (S_sub) return run_bwd<spg::kWantVar | spg::kWantSub>(h, o);
-  return run_bwd<spg::kWantVar>(h, o);
+  return run_bwd(h, S_sub ? (spg::kWantVar | spg::kWantSub) : spg::kWantVar, o);
 }
 
-extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
-  if (!h || !logml || !grad) return SPINGP_E_INVALID;
-  if (!h->assembled) return SPINGP_E_ORDER;
-  // the forward pass always runs: hyperparameters live in device memory and may have changed
-  int rc = spingp_factor(h);
+// forward pass + adjoint sweep (+ per-series sums) on h->stream
+static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed) {
+  int rc = hip_ok(ops(h)->factor(launch_ctx(h, timed)));
   if (rc) return rc;
   spg::BwdOut o = make_out(h);
   if (!h->batched) {
     o.logml = logml;
     o.grad = grad;
   }
-  rc = run_bwd<spg::kWantGrad>(h, o);
+  rc = run_bwd(h, spg::kWantGrad, o, timed);
   if (rc || !h->batched) return rc;
-  return series_reduce(h, logml, nullptr, nullptr, grad);
+  return series_reduce(h, logml, nullptr, nullptr, grad, timed);
+}
+
+// Capture the launch sequence of spingp_logml_grad for these output pointers on the private
+// capture stream and instantiate it.
+static int capture_logml_grad(spingp_ctx* h, double* logml, double* grad) {
+  drop_graph(h);
+  if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
+    h->cap = nullptr;
+    return SPINGP_E_HIP;
+  }
+  hipStream_t user = h->stream;
+  h->stream = h->cap;
+  if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    h->stream = user;
+    return SPINGP_E_HIP;
+  }
+  const int rc = run_logml_grad(h, logml, grad, false);
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h->cap, &g);
+  h->stream = user;
+  if (rc || ec != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc ? rc : SPINGP_E_HIP;
+  }
+  const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    h->gexec = nullptr;
+    return SPINGP_E_HIP;
+  }
+  h->g_logml = logml;
+  h->g_grad = grad;
+  return SPINGP_OK;
+}
+
+extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
+  if (!h || !logml || !grad) return SPINGP_E_INVALID;
+  if (!h->assembled) return SPINGP_E_ORDER;
+  // the forward pass always runs: hyperparameters live in device memory and may have changed
+  h->factored = false;
+  int rc;
+  if (h->use_graph) {
+    if (!h->gexec || h->g_logml != logml || h->g_grad != grad) {
+      rc = capture_logml_grad(h, logml, grad);
+      if (rc) return rc;
+    }
+    prof_begin(h);
+    rc = hip_ok(hipGraphLaunch(h->gexec, h->stream));
+    prof_end(h, spg::kKidGraph);
+  } else {
+    rc = run_logml_grad(h, logml, grad, true);
+  }
+  h->factored = rc == SPINGP_OK;
+  return rc;
 }
 
 extern "C" int spingp_status(spingp_handle h, int64_t* first_bad) {

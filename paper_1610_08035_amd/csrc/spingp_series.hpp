@@ -1,0 +1,95 @@
+// Kernels of the batched layout that do not depend on the tile shape: the chunk map built at
+// assemble time and the per-series sums of the reverse kernel's partials.  Included by the C-ABI
+// translation unit only.
+#pragma once
+
+#include "spingp_kernels.hpp"
+
+namespace spg {
+
+// Fixed-order per-series sum of the per-chunk partials: one 64-lane work-group per series; lane i
+// adds chunks first + i, first + i + 64, ... in order, then a fixed tree over the lanes.  Writes
+// logml[s] (eq. ml2), and datafit[s] = y^T K_y^-1 y, logdet[s] = log det K_y, grad[s][0..2] where
+// not null.  An empty series gets logml 0 and a zero gradient.
+__global__ __launch_bounds__(64) void k_series_reduce(SeriesMap sm, const double* __restrict__ part,
+                                                       int64_t part_ld, int64_t n_pts, double* __restrict__ logml,
+                                                       double* __restrict__ datafit, double* __restrict__ logdet,
+                                                       double* __restrict__ grad) {
+  __shared__ double red[5][64];
+  const int tid = threadIdx.x;
+  const int64_t s = blockIdx.x;
+  const int64_t c0 = sm.chunk_first[s];
+  const int64_t c1 = sm.chunk_first[s + 1] < sm.slots ? sm.chunk_first[s + 1] : sm.slots;
+  const int nf = grad ? 5 : 2;
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = c0 + tid; c < c1; c += 64) {
+    for (int f = 0; f < nf; ++f) acc[f] += part[f * part_ld + c];
+  }
+  for (int f = 0; f < 5; ++f) red[f][tid] = acc[f];
+  __syncthreads();
+  for (int stride = 32; stride > 0; stride /= 2) {
+    if (tid < stride) for (int f = 0; f < 5; ++f) red[f][tid] += red[f][tid + stride];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int64_t ob = sm.offsets[s], oe = sm.offsets[s + 1];
+    const double ns = (oe > ob && ob >= 0 && oe <= n_pts) ? (double)(oe - ob) : 0.0;
+    const double fit = red[0][0], ld = red[1][0];
+    if (logml) logml[s] = -0.5 * fit - 0.5 * ld - 0.5 * ns * kLog2Pi;
+    if (datafit) datafit[s] = fit;
+    if (logdet) logdet[s] = ld;
+    if (grad) for (int f = 0; f < 3; ++f) grad[s * 3 + f] = red[f + 2][0];
+  }
+}
+
+// Chunk map of several series (built once per assemble).  Chunks per series c_s = ceil(len_s / R);
+// chunk_first is their exclusive prefix sum (one work-group, carried across blocks of 256).
+__global__ __launch_bounds__(256) void k_chunk_first(const int64_t* __restrict__ offsets, int32_t n_series,
+                                                      int64_t n_pts, int R, int64_t* __restrict__ chunk_first,
+                                                      unsigned long long* __restrict__ status) {
+  __shared__ int64_t sc[256];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    carry = 0;
+    if (offsets[0] != 0 || offsets[n_series] != n_pts) atomicMin(status, 1ull);   // SPINGP_E_INVALID
+  }
+  __syncthreads();
+  for (int64_t base = 0; base < n_series; base += 256) {
+    const int64_t s = base + tid;
+    int64_t c = 0;
+    if (s < n_series) {
+      const int64_t len = offsets[s + 1] - offsets[s];
+      if (len < 0) atomicMin(status, 1ull);            // decreasing offsets
+      c = len > 0 ? (len + R - 1) / R : 0;
+    }
+    sc[tid] = c;
+    __syncthreads();
+    for (int d = 1; d < 256; d *= 2) {                 // inclusive scan
+      const int64_t v = tid >= d ? sc[tid - d] : 0;
+      __syncthreads();
+      sc[tid] += v;
+      __syncthreads();
+    }
+    if (s < n_series) chunk_first[s] = carry + sc[tid] - c;
+    __syncthreads();
+    if (tid == 255) carry += sc[255];
+    __syncthreads();
+  }
+  if (tid == 0) chunk_first[n_series] = carry;
+}
+
+// chunk_series: -1 everywhere, then the series of every chunk.
+__global__ void k_chunk_fill(int32_t* __restrict__ chunk_series, int64_t slots) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < slots) chunk_series[i] = -1;
+}
+__global__ void k_chunk_map(const int64_t* __restrict__ chunk_first, int32_t n_series, int64_t slots,
+                            int32_t* __restrict__ chunk_series) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_series) return;
+  const int64_t c1 = chunk_first[s + 1] < slots ? chunk_first[s + 1] : slots;
+  for (int64_t c = chunk_first[s]; c < c1; ++c) chunk_series[c] = (int32_t)s;
+}
+
+}  // namespace spg

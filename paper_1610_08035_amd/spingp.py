@@ -64,9 +64,17 @@ def load_library():
     lib.spingp_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     lib.spingp_strerror.argtypes = [ctypes.c_int]
     lib.spingp_strerror.restype = ctypes.c_char_p
+    lib.spingp_workspace_bytes.argtypes = [vp]
+    lib.spingp_workspace_bytes.restype = i64
+    lib.spingp_tile_count.argtypes = []
+    lib.spingp_tile_shape.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.spingp_get_tile.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.spingp_set_tile.argtypes = [vp, i32]
+    lib.spingp_tune.argtypes = [vp, i32]
     for name in ("spingp_create", "spingp_destroy", "spingp_state_dim", "spingp_n_hyper", "spingp_assemble",
                  "spingp_factor", "spingp_logml", "spingp_solve", "spingp_selinv", "spingp_logml_grad",
-                 "spingp_status", "spingp_profile", "spingp_profile_read"):
+                 "spingp_status", "spingp_profile", "spingp_profile_read", "spingp_tile_count",
+                 "spingp_tile_shape", "spingp_get_tile", "spingp_set_tile", "spingp_tune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -109,7 +117,11 @@ def spingp_destroy(h):
     _check(load_library().spingp_destroy(h), "spingp_destroy")
 
 
-def spingp_assemble(h, t, y, hyper, offsets=None, n_series=1):
+FLAG_GRAPH = 1
+FLAG_AUTOTUNE = 2
+
+
+def spingp_assemble(h, t, y, hyper, offsets=None, n_series=1, flags=0):
     n = t.numel()
     lib = load_library()
     off = None
@@ -121,7 +133,7 @@ def spingp_assemble(h, t, y, hyper, offsets=None, n_series=1):
         off = ctypes.c_void_p(offsets.data_ptr())
     nh = lib.spingp_n_hyper(h) * int(n_series)
     _check(lib.spingp_assemble(h, _dev(t, "t"), _dev(y, "y", n), off, int(n_series), int(n),
-                               _dev(hyper, "hyper", nh), 0), "spingp_assemble")
+                               _dev(hyper, "hyper", nh), int(flags)), "spingp_assemble")
 
 
 def spingp_factor(h):
@@ -152,8 +164,36 @@ def spingp_status(h):
     return rc, bad.value
 
 
-N_KERNELS = 5
-KERNEL_NAMES = ("validate", "fwd_fold_tree", "top_tree", "bwd_elim_adjoint", "series_reduce")
+N_KERNELS = 6
+KERNEL_NAMES = ("validate", "fwd_fold_tree", "top_tree", "bwd_elim_adjoint", "series_reduce", "graph")
+
+
+def spingp_workspace_bytes(h):
+    return int(load_library().spingp_workspace_bytes(h))
+
+
+def spingp_tile_count():
+    return int(load_library().spingp_tile_count())
+
+
+def spingp_tile_shape(i):
+    r, l = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().spingp_tile_shape(int(i), ctypes.byref(r), ctypes.byref(l)), "spingp_tile_shape")
+    return r.value, l.value
+
+
+def spingp_get_tile(h):
+    i = ctypes.c_int32()
+    _check(load_library().spingp_get_tile(h, ctypes.byref(i)), "spingp_get_tile")
+    return i.value
+
+
+def spingp_set_tile(h, i):
+    _check(load_library().spingp_set_tile(h, int(i)), "spingp_set_tile")
+
+
+def spingp_tune(h, reps=3):
+    _check(load_library().spingp_tune(h, int(reps)), "spingp_tune")
 
 
 def spingp_profile(h, enable):
@@ -192,9 +232,10 @@ class Handle:
         except Exception:
             pass
 
-    def assemble(self, t, y, hyper, offsets=None):
+    def assemble(self, t, y, hyper, offsets=None, graph=False, autotune=False):
         n_series = 1 if offsets is None else offsets.numel() - 1
-        spingp_assemble(self._h, t, y, hyper, offsets, n_series)
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_AUTOTUNE if autotune else 0)
+        spingp_assemble(self._h, t, y, hyper, offsets, n_series, flags)
         self.n = t.numel()
         self.n_series = n_series
         self._keep = (t, y, hyper, offsets)   # keep the bound buffers alive
@@ -240,3 +281,18 @@ class Handle:
 
     def status(self):
         return spingp_status(self._h)
+
+    @property
+    def tile(self):
+        return spingp_get_tile(self._h)
+
+    @tile.setter
+    def tile(self, i):
+        spingp_set_tile(self._h, i)
+
+    def tune(self, reps=3):
+        spingp_tune(self._h, reps)
+        return self.tile
+
+    def workspace_bytes(self):
+        return spingp_workspace_bytes(self._h)
