@@ -30,6 +30,24 @@ FLOPS_PER_POINT = {
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes on
+# this workload, scaled by a 256 MiB copy (FETCH x 2.0, WRITE x 1.0); valid only for the kernel
+# sources they were taken on (sha256 over csrc/, see kernel_source_sha), else reported as null.
+TRAFFIC = {"kernel": "bwd_elim_adjoint", "bytes": (42692.1 * 2.0 + 6606.2) * 1024.0,
+           "source_sha": "abd5d7c2a74e31f6d67acf94b487bd0aa2b20c757006925f5eb064d42486af52"}
+
+
+def kernel_source_sha():
+    import hashlib
+    d = os.path.join(ROOT, "paper_1610_08035_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
 
 def cpu_baseline(w, budget_s=10.0):
     """The C oracle (sequential elimination + tangent-linear gradient), timed on the host.
@@ -105,6 +123,41 @@ def batched_report(spg, steps, warmup):
             "speedup": el_s / el_b}
 
 
+def large_report(spg, steps, warmup):
+    """The large single series (Matern-5/2, N = 2^24, Exp(1) gaps): logML + gradient throughput
+    and the device memory the call holds (inputs, library workspace, outputs) next to what
+    storing every reduction level would take (two elements of 33 doubles per node at b = 3)."""
+    import torch
+    from workloads import make_config
+    w = make_config(5)
+    n = w.n_points
+    dev = torch.device("cuda:0")
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    td, yd = torch.as_tensor(w.t, device=dev), torch.as_tensor(w.y, device=dev)
+    hd = torch.as_tensor(w.hyper.reshape(-1), device=dev)
+    h = spg.Handle(w.terms, n)
+    h.assemble(td, yd, hd, graph=True)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(1, 3, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        spg.spingp_logml_grad(h._h, ll, g)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    if h.status()[0] != 0:
+        raise RuntimeError("large workload failed validation")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        spg.spingp_logml_grad(h._h, ll, g)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    ws = h.workspace_bytes()
+    h.close()
+    return {"workload": "matern52_n16777216_exp1gaps_logml_grad", "n_points": n, "points_per_s": n / el,
+            "ms_per_step": 1e3 * el, "steps": steps, "device_bytes_in_use": used, "workspace_bytes": ws,
+            "input_bytes": 16 * n, "every_level_stored_bytes": 2 * 33 * 8 * n}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +165,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-series batched report")
+    ap.add_argument("--no-large", action="store_true", help="skip the N = 2^24 report")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM counters)")
     args = ap.parse_args()
@@ -172,6 +226,9 @@ def main():
     per_kernel = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
     dom = max(FLOPS_PER_POINT, key=lambda k: per_kernel[k])
     achieved = FLOPS_PER_POINT[dom] * n / (per_kernel[dom] * 1e-3) / 1e12
+    traffic = None
+    if TRAFFIC["kernel"] == dom and TRAFFIC["source_sha"] == kernel_source_sha():
+        traffic = TRAFFIC["bytes"]
     out = {
         "metric": "time points/sec, logML+grad, Matern-5/2 N=2^20 FP64; % HBM roofline",
         "value": value,
@@ -188,7 +245,7 @@ def main():
         "config": {"workload": "matern52_n1048576_exp1gaps_logml_grad", "n_points": n, "state_dim": 3,
                    "n_hyper": 3, "hyper": [float(v) for v in hyp]},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_point": FLOPS_PER_POINT[dom]},
         "kernel_ms": {k: round(v, 5) for k, v in per_kernel.items()},
         "logml": float(ll.item()),
@@ -196,6 +253,8 @@ def main():
     h.close()
     if not args.no_batched:
         out["batched"] = batched_report(spg, args.steps, args.warmup)
+    if not args.no_large:
+        out["large"] = large_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -109,57 +109,11 @@ def _matern_prior_path(t: np.ndarray, kind: int, ell: float, var: float,
                        rng: np.random.Generator) -> np.ndarray:
     """One sample path of a Matern GP at sorted times t (exact in distribution)."""
     order = _MATERN_ORDER[kind]
-    lam = np.sqrt(2.0 * _MATERN_NU[kind]) / ell
-    P = _cascade_stationary_cov(order, lam)
-    P *= var / P[order - 1, order - 1]
     n = t.shape[0]
-    # (iii) initial state
-    x0 = np.linalg.cholesky(P) @ rng.standard_normal(order)
-    # (iv) transition noise, drawn in one piece so the blocking never changes the stream
+    # (iii) initial state, (iv) transition noise, drawn in one piece
+    z0 = rng.standard_normal(order)
     xi = rng.standard_normal((max(n - 1, 0), order))
-    if n == 1:
-        return np.array([x0[order - 1]])
-    dt = np.diff(t)
-
-    # noise_n = sqrt(Qc_n) xi_n with Qc_n = P - A P A^T, eigenvalues clipped at 0
-    def noise(idx):
-        A = _cascade_transition(order, lam, dt[idx])
-        Q = P[None] - A @ P[None] @ np.swapaxes(A, -1, -2)
-        Q = 0.5 * (Q + np.swapaxes(Q, -1, -2))
-        w, V = np.linalg.eigh(Q)
-        w = np.sqrt(np.clip(w, 0.0, None))
-        return A, np.einsum("kij,kj->ki", V * w[:, None, :], xi[idx])
-
-    # blocked exact linear recurrence x_{n+1} = A_n x_n + w_n (about sqrt(n) blocks of sqrt(n))
-    block = max(16, int(np.sqrt(n)) + 1)
-    nb = (n + block - 1) // block
-    local = np.zeros((nb, block, order))
-    ell_state = np.zeros((nb, order))
-    phi = np.broadcast_to(np.eye(order), (nb, order, order)).copy()
-    starts = np.arange(nb) * block
-    for j in range(block):
-        local[:, j] = ell_state
-        idx = starts + j
-        ok = idx < n - 1
-        if not ok.any():
-            continue
-        A, w = noise(idx[ok])
-        ell_state[ok] = np.einsum("kij,kj->ki", A, ell_state[ok]) + w
-        phi[ok] = A @ phi[ok]
-    X = np.zeros((nb, order))
-    X[0] = x0
-    for k in range(nb - 1):
-        X[k + 1] = phi[k] @ X[k] + ell_state[k]
-    out = np.zeros((nb, block))
-    phi = np.broadcast_to(np.eye(order), (nb, order, order)).copy()
-    for j in range(block):
-        idx = starts + j
-        out[:, j] = (phi[:, order - 1, :] * X).sum(-1) + local[:, j, order - 1]
-        ok = idx < n - 1
-        if ok.any():
-            A = _cascade_transition(order, lam, dt[idx[ok]])
-            phi[ok] = A @ phi[ok]
-    return out.reshape(-1)[:n]
+    return _matern_batch([t], kind, np.array([[ell, var, 0.0]]), [(z0, xi)])
 
 
 def _periodic_prior_path(t, harmonics, ell, var, period, rng):
@@ -312,12 +266,14 @@ def _matern_batch(ts, kind, hyper, draws):
             x0_first = x0
         else:
             w[pos - 1] = x0          # boundary step: A = 0, noise = next initial state
-        if L > 1:
-            dt = np.diff(ts[i])
-            Ai = _cascade_transition(order, lam, dt)
+        dt = np.diff(ts[i])
+        for a in range(0, L - 1, 1 << 20):          # slices bound the temporary memory
+            e = min(L - 1, a + (1 << 20))
+            Ai = _cascade_transition(order, lam, dt[a:e])
+            # Q_n = P - A P A^T (PSD up to rounding; the factor drops non-positive pivots)
             Q = P[None] - Ai @ P[None] @ np.swapaxes(Ai, -1, -2)
-            A[pos: pos + L - 1] = Ai
-            w[pos: pos + L - 1] = _psd_factor_apply(Q, draws[i][1])
+            A[pos + a: pos + e] = Ai
+            w[pos + a: pos + e] = _psd_factor_apply(Q, draws[i][1][a:e])
         pos += L
     if n == 0:
         return np.zeros(0)
@@ -334,7 +290,6 @@ def make_batch(lens, hyper, terms, seed) -> Workload:
     ts, ys = [], []
     if len(terms) == 1 and terms[0][0] in _MATERN_ORDER:
         # one Matern term: the same draws per series as make_series, one vectorised recurrence
-        # (the transition noise uses an LDL^T square root of Q_n instead of eigh: same law)
         order = _MATERN_ORDER[terms[0][0]]
         draws, eps = [], []
         for i in range(S):
