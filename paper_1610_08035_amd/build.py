@@ -14,9 +14,9 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspingp.so")
 # The C-ABI unit, then one object per compiled tile shape (R points per lane, L lanes per
 # work-group); the list must match spg::tile_ops() in spingp_api.hip.
-SOURCES = ["spingp_api.hip"]
+SOURCES = ["spingp_api.hip", "spingp_wide.hip"]
 TILES = [(8, 128), (4, 128), (8, 64), (4, 64)]
-HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp", "spingp_host.hpp", "spingp_series.hpp"]
+HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp", "spingp_host.hpp", "spingp_series.hpp", "spingp_wide.hpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

@@ -95,6 +95,10 @@ struct spingp_ctx {
   int64_t lane_ld = 0;
   // tile shape
   int tile = 0;
+  // wide-state path (b = 10)
+  bool wide = false;
+  bool wide_down = false;          // down-sweep messages match the current factorisation
+  spg::wide::WideCtx wplan;
   // bound inputs
   const double* t = nullptr;
   const double* y = nullptr;
@@ -182,22 +186,86 @@ static spg::LaunchCtx launch_ctx(spingp_ctx* h, bool timed = true) {
   return c;
 }
 
+static spg::wide::WideCtx wide_ctx(spingp_ctx* h, bool timed = true) {
+  spg::wide::WideCtx c = h->wplan;
+  c.stream = h->stream;
+  c.t = h->t;
+  c.y = h->y;
+  c.hyper = h->hyper;
+  c.n_points = h->n_points;
+  c.scal = h->scal;
+  c.mark = (timed && h->prof) ? prof_mark : nullptr;
+  c.mark_arg = h;
+  return c;
+}
+
 static void drop_graph(spingp_ctx* h) {
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   h->gexec = nullptr;
   h->g_logml = h->g_grad = nullptr;
 }
 
+// The wide-state model: one series, all tree levels and their messages stored item-major.
+static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_series, void* stream) {
+  if (max_series != 1) return SPINGP_E_UNSUPPORTED;
+  if (max_points > (int64_t(1) << 31)) return SPINGP_E_UNSUPPORTED;
+  spingp_ctx* h = new (std::nothrow) spingp_ctx();
+  if (!h) return SPINGP_E_NOMEM;
+  h->wide = true;
+  h->b = spg::wide::kStateDim;
+  h->n_hyper = spg::wide::kHyper;
+  h->max_points = max_points;
+  h->max_series = 1;
+  h->stream = (hipStream_t)stream;
+  spg::wide::WideCtx& w = h->wplan;
+  memset(&w, 0, sizeof(w));
+  spg::wide::plan_levels(max_points, w);
+  int64_t items = 0;
+  for (int k = 0; k < w.n_levels; ++k) items += w.n[k];
+  struct Req {
+    void** p;
+    int64_t bytes;
+  } reqs[] = {
+      {(void**)&w.elems, (int64_t)sizeof(double) * items * spg::wide::elem_stride()},
+      {(void**)&w.msgs, (int64_t)sizeof(double) * items * spg::wide::msg_stride()},
+      {(void**)&w.cst, (int64_t)sizeof(double) * spg::wide::const_size()},
+      {(void**)&w.part, (int64_t)sizeof(double) * w.node_grid * spg::wide::part_stride()},
+      {(void**)&h->scal, (int64_t)sizeof(double) * 8},
+      {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
+  };
+  bool ok = true;
+  for (auto& r : reqs) {
+    if (!ok) break;
+    ok = hipMalloc(r.p, r.bytes) == hipSuccess;
+    h->ws_bytes += r.bytes;
+  }
+  ok = ok && hipMemset(h->key, 0xff, sizeof(unsigned long long)) == hipSuccess;
+  ok = ok && hipDeviceSynchronize() == hipSuccess;
+  if (!ok) {
+    spingp_destroy(h);
+    return SPINGP_E_NOMEM;
+  }
+  *out = h;
+  return SPINGP_OK;
+}
+
 extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,
                              int32_t max_series, void* stream) {
   if (!out || !terms || n_terms < 1 || max_points < 1 || max_series < 1) return SPINGP_E_INVALID;
   *out = nullptr;
-  if (n_terms != 1) return SPINGP_E_UNSUPPORTED;
   int b;
-  if (terms[0].kind == SPINGP_MATERN32) b = 2;
-  else if (terms[0].kind == SPINGP_MATERN52) b = 3;
-  else return SPINGP_E_UNSUPPORTED;
+  bool wide = false;
+  if (n_terms == 1 && terms[0].kind == SPINGP_MATERN32) b = 2;
+  else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN52) b = 3;
+  else if (n_terms == 2 && terms[0].kind == SPINGP_MATERN32 && terms[1].kind == SPINGP_PERIODIC &&
+           terms[1].harmonics == 3) {
+    b = spg::wide::kStateDim;
+    wide = true;
+  } else {
+    return SPINGP_E_UNSUPPORTED;
+  }
   if (max_points > (int64_t(1) << 40)) return SPINGP_E_UNSUPPORTED;
+  if (wide) return create_wide(out, max_points, max_series, stream);
   // workspace for the most demanding tile shape
   const bool multi = max_series > 1;
   int64_t G_max = 0, lane_ld = 0;
@@ -308,6 +376,10 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)hipFree(h->tune_out);
   (void)hipFree(h->chunk_series);
   (void)hipFree(h->chunk_first);
+  (void)hipFree(h->wplan.elems);
+  (void)hipFree(h->wplan.msgs);
+  (void)hipFree(h->wplan.cst);
+  (void)hipFree(h->wplan.part);
   delete h;
   return SPINGP_OK;
 }
@@ -320,6 +392,7 @@ extern "C" int64_t spingp_workspace_bytes(spingp_handle h) { return h ? h->ws_by
 static int bind(spingp_ctx* h) {
   drop_graph(h);
   h->factored = false;
+  h->wide_down = false;
   const spg::TileOps* T = ops(h);
   hipLaunchKernelGGL(k_fill_key, dim3(1), dim3(1), 0, h->stream, h->key);
   prof_begin(h);
@@ -361,6 +434,7 @@ static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed
 extern "C" int spingp_tune(spingp_handle h, int32_t reps) {
   if (!h || reps < 1) return SPINGP_E_INVALID;
   if (!h->assembled) return SPINGP_E_ORDER;
+  if (h->wide) return SPINGP_OK;   // one schedule only
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return SPINGP_E_HIP;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -416,6 +490,7 @@ extern "C" int spingp_get_tile(spingp_handle h, int32_t* index) {
 
 extern "C" int spingp_set_tile(spingp_handle h, int32_t index) {
   if (!h || !spg::tile_ops(index)) return SPINGP_E_INVALID;
+  if (h->wide && index != 0) return SPINGP_E_UNSUPPORTED;
   h->tile = index;
   return h->assembled ? bind(h) : SPINGP_OK;
 }
@@ -428,6 +503,10 @@ extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y
   if (n_points < 1 || n_points > h->max_points) return SPINGP_E_INVALID;
   if (n_series > 1 && !offsets) return SPINGP_E_INVALID;
   h->assembled = false;
+  if (h->wide) {
+    memset(&h->wplan.n, 0, sizeof(h->wplan.n));
+    spg::wide::plan_levels(n_points, h->wplan);
+  }
   h->t = t;
   h->y = y;
   h->hyper = hyper;
@@ -438,7 +517,7 @@ extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y
   h->batched = n_series > 1;
   h->use_graph = (flags & SPINGP_FLAG_GRAPH) != 0;
   bool tune = false;
-  if (flags & SPINGP_FLAG_AUTOTUNE) {
+  if ((flags & SPINGP_FLAG_AUTOTUNE) && !h->wide) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(tune_key(h));
     if (it != g_tune_cache.end()) h->tile = it->second;
@@ -457,12 +536,30 @@ extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y
   return rc;
 }
 
+static int do_factor(spingp_ctx* h, bool timed) {
+  h->wide_down = false;
+  if (h->wide) return hip_ok(spg::wide::factor(wide_ctx(h, timed)));
+  return hip_ok(ops(h)->factor(launch_ctx(h, timed)));
+}
+
 extern "C" int spingp_factor(spingp_handle h) {
   if (!h) return SPINGP_E_INVALID;
   if (!h->assembled) return SPINGP_E_ORDER;
-  const int rc = hip_ok(ops(h)->factor(launch_ctx(h)));
+  const int rc = do_factor(h, true);
   h->factored = rc == SPINGP_OK;
   return rc;
+}
+
+// wide path: down-sweep once per factorisation, then the node step
+static int wide_node(spingp_ctx* h, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
+                     double* S_sub, bool timed = true) {
+  const spg::wide::WideCtx c = wide_ctx(h, timed);
+  if (!h->wide_down) {
+    const int rc = hip_ok(spg::wide::down(c));
+    if (rc) return rc;
+    h->wide_down = true;
+  }
+  return hip_ok(spg::wide::node(c, mode, f_mean, f_var, z_mean, S_diag, S_sub));
 }
 
 static int run_bwd(spingp_ctx* h, int mode, const spg::BwdOut& o, bool timed = true) {
@@ -511,6 +608,7 @@ extern "C" int spingp_solve(spingp_handle h, double* f_mean, double* z_mean) {
   if (!h) return SPINGP_E_INVALID;
   if (!h->factored) return SPINGP_E_ORDER;
   if (!f_mean && !z_mean) return SPINGP_OK;
+  if (h->wide) return wide_node(h, spg::kWantMean, f_mean, nullptr, z_mean, nullptr, nullptr);
   spg::BwdOut o = make_out(h);
   o.f_mean = f_mean;
   o.z_mean = z_mean;
@@ -521,6 +619,9 @@ extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, dou
   if (!h) return SPINGP_E_INVALID;
   if (!h->factored) return SPINGP_E_ORDER;
   if (!f_var && !S_diag && !S_sub) return SPINGP_OK;
+  if (h->wide)
+    return wide_node(h, S_sub ? (spg::kWantVar | spg::kWantSub) : spg::kWantVar, nullptr, f_var, nullptr, S_diag,
+                     S_sub);
   spg::BwdOut o = make_out(h);
   o.f_var = f_var;
   o.S_diag = S_diag;
@@ -530,8 +631,13 @@ extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, dou
 
 // forward pass + adjoint sweep (+ per-series sums) on h->stream
 static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed) {
-  int rc = hip_ok(ops(h)->factor(launch_ctx(h, timed)));
+  int rc = do_factor(h, timed);
   if (rc) return rc;
+  if (h->wide) {
+    rc = wide_node(h, spg::kWantGrad, nullptr, nullptr, nullptr, nullptr, nullptr, timed);
+    if (rc) return rc;
+    return hip_ok(spg::wide::finish(wide_ctx(h, timed), logml, grad));
+  }
   spg::BwdOut o = make_out(h);
   if (!h->batched) {
     o.logml = logml;

@@ -110,4 +110,40 @@ inline SeriesMap make_map(const LaunchCtx& c, int64_t slots) {
 constexpr int kNumTiles = 4;
 const TileOps* tile_ops(int i);
 
+// Wide-state path (Matern-3/2 + periodic with 3 harmonics, b = 10, one series): level-by-level
+// reduction with one wavefront per element operation (spingp_wide.hip).
+namespace wide {
+constexpr int kMaxLevels = 64;
+struct WideCtx {
+  hipStream_t stream;
+  const double* t;
+  const double* y;
+  const double* hyper;
+  int64_t n_points;
+  double* elems;      // all tree levels, item-major
+  double* msgs;       // messages of all levels, item-major
+  double* cst;        // model constants of the current hyperparameters
+  double* part;       // per-work-group gradient partials of the node step
+  double* scal;       // log-likelihood terms at the root
+  int n_levels;       // level 0 = the N leaves, level n_levels - 1 = the root
+  int64_t n[kMaxLevels];
+  int64_t off[kMaxLevels];
+  int node_grid;      // work-groups of the node step (rows of part)
+  void (*mark)(void* arg, int kid, int end);
+  void* mark_arg;
+};
+constexpr int kStateDim = 10;
+constexpr int kHyper = 6;
+int64_t elem_stride();     // doubles per stored element
+int64_t msg_stride();      // doubles per stored message
+int64_t const_size();      // doubles of the model constants
+int64_t part_stride();     // doubles per work-group partial
+void plan_levels(int64_t n, WideCtx& c);
+hipError_t factor(const WideCtx& c);                       // setup, leaves, up-sweep, root
+hipError_t down(const WideCtx& c);                         // down-sweep of all levels
+hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
+                double* S_sub);                            // node step (kWant* bits)
+hipError_t finish(const WideCtx& c, double* logml, double* grad);   // gradient sum
+}  // namespace wide
+
 }  // namespace spg

@@ -1,0 +1,104 @@
+// Launch sequence of the wide-state path (see spingp_wide.hpp).
+#include "spingp_host.hpp"
+#include "spingp_wide.hpp"
+
+namespace spg {
+namespace wide {
+namespace {
+
+using Model = SumM32Periodic<3>;
+static_assert(Model::B == kStateDim, "state dimension of the wide model");
+static_assert(Model::NH == kHyper, "hyperparameters of the wide model");
+constexpr int kGridCap = 4096;
+
+inline void mark(const WideCtx& c, int kid, int end) {
+  if (c.mark) c.mark(c.mark_arg, kid, end);
+}
+inline unsigned grid_for(int64_t items) { return (unsigned)(items < kGridCap ? items : kGridCap); }
+
+}  // namespace
+
+int64_t elem_stride() { return Lay<Model::B>::kEs; }
+int64_t msg_stride() { return Lay<Model::B>::kMs; }
+int64_t const_size() { return Model::kConst; }
+int64_t part_stride() { return Model::B * Model::B + 3; }
+
+void plan_levels(int64_t n, WideCtx& c) {
+  int k = 0;
+  int64_t off = 0;
+  for (int64_t m = n;; m = (m + 1) / 2) {
+    c.n[k] = m;
+    c.off[k] = off;
+    off += m;
+    ++k;
+    if (m == 1 || k == kMaxLevels) break;
+  }
+  c.n_levels = k;
+  c.node_grid = (int)(n < 2048 ? n : 2048);
+}
+
+hipError_t factor(const WideCtx& c) {
+  constexpr int B = Model::B;
+  mark(c, kKidFwd, 0);
+  hipLaunchKernelGGL(k_wide_setup<Model>, dim3(1), dim3(kW), 0, c.stream, c.hyper, c.cst);
+  hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points)), dim3(kW), 0, c.stream, c.t, c.y, c.n_points,
+                     c.cst, c.elems);
+  for (int k = 1; k < c.n_levels; ++k)
+    hipLaunchKernelGGL(k_wide_up<B>, dim3(grid_for(c.n[k])), dim3(kW), 0, c.stream, c.elems, c.off[k - 1],
+                       c.n[k - 1], c.off[k], c.n[k]);
+  mark(c, kKidFwd, 1);
+  mark(c, kKidTop, 0);
+  hipLaunchKernelGGL(k_wide_root<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, c.elems, c.off[c.n_levels - 1],
+                     c.msgs, c.scal);
+  mark(c, kKidTop, 1);
+  return hipGetLastError();
+}
+
+hipError_t down(const WideCtx& c) {
+  constexpr int B = Model::B;
+  mark(c, kKidBwd, 0);
+  for (int k = c.n_levels - 1; k >= 1; --k)
+    hipLaunchKernelGGL(k_wide_down<B>, dim3(grid_for(c.n[k - 1])), dim3(kW), 0, c.stream, c.elems, c.msgs,
+                       c.off[k], c.off[k - 1], c.n[k - 1]);
+  mark(c, kKidBwd, 1);
+  return hipGetLastError();
+}
+
+template <int MODE>
+static void launch_node(const WideCtx& c, const WideOut& o) {
+  hipLaunchKernelGGL((k_wide_node<Model, MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.t, c.y,
+                     c.n_points, c.cst, c.elems, c.msgs, o);
+}
+
+hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
+                double* S_sub) {
+  WideOut o;
+  o.f_mean = f_mean;
+  o.f_var = f_var;
+  o.z_mean = z_mean;
+  o.S_diag = S_diag;
+  o.S_sub = S_sub;
+  o.ld = c.n_points;
+  o.part = c.part;
+  mark(c, kKidBwd, 0);
+  switch (mode) {
+    case kWantGrad: launch_node<kWantGrad>(c, o); break;
+    case kWantMean: launch_node<kWantMean>(c, o); break;
+    case kWantVar: launch_node<kWantVar>(c, o); break;
+    case kWantVar | kWantSub: launch_node<kWantVar | kWantSub>(c, o); break;
+    default: return hipErrorInvalidValue;
+  }
+  mark(c, kKidBwd, 1);
+  return hipGetLastError();
+}
+
+hipError_t finish(const WideCtx& c, double* logml, double* grad) {
+  mark(c, kKidReduce, 0);
+  hipLaunchKernelGGL(k_wide_final<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, c.part, c.node_grid, c.scal, logml,
+                     grad);
+  mark(c, kKidReduce, 1);
+  return hipGetLastError();
+}
+
+}  // namespace wide
+}  // namespace spg

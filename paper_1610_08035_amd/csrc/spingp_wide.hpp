@@ -1,0 +1,907 @@
+// Wide-state path (b = 10: Matern-3/2 plus a periodic term with 3 harmonics, Sec. 2.1 and the
+// periodic state-space form of the appendix) for one series.
+//
+// The per-lane kernels keep a whole chain element in registers; at b = 10 an element has 322
+// doubles, so here one wavefront (a "team" of 64 lanes, one work-group) works on one element
+// operation at a time with its 10 x 10 blocks staged in LDS, every lane owning one or two
+// matrix entries.  The cyclic reduction runs level by level over all N nodes (one node per
+// leaf), one launch per level:
+//   up-sweep   level k element i = E(k-1, 2i) (x) E(k-1, 2i+1)      (odd-even reduction)
+//   down-sweep messages of level k-1 from those of level k: the predicted state (m, P)
+//              entering an element's left node (prefix) and the information (J, eta) that
+//              all later data put on its right node (suffix)
+//   node step  with the exact predicted state at node n and the exact information on node
+//              n+1, the filtered state, the smoothed moments and the derivatives of the log
+//              marginal likelihood with respect to the edge n -> n+1 are all local:
+//                lam = Gam^T eta' - W m',  Lam = 1/2 (lam lam^T - W)   (dL/dm', dL/dP')
+//                mu = m+ + P+ A^T lam,  S = P+ - P+ A^T W A P+,  S_sub = (I - P' W) A P+
+//                A_bar = lam m+^T + 2 Lam A (P+ - P0),  P0_bar += Lam - A^T Lam A
+//              and the noise variance by the posterior expectation of d log N(y; h z, s2).
+//
+// State basis.  The model's natural state is block diagonal (Matern block, then one rotation
+// block per harmonic) with observation vector h = (1, 0, 1, 0, ...).  The kernels run in the
+// basis z' = T z with T = I except row 0 = h^T, where the observation is e_0 (so the node
+// information is rank one in entry (0, 0)); A' = T A T^-1, Q' = T Q T^T, P0' = T P0 T^T.
+// State outputs are mapped back with T^-1, gradients with T^T (.) T^-T.
+#pragma once
+#include "spingp_device.hpp"
+
+namespace spg {
+namespace wide {
+
+constexpr int kW = 64;  // lanes per team (one wavefront, one work-group)
+
+SPG_DEV void tsync() { __syncthreads(); }
+
+// ---------------------------------------------------------------------------- layouts
+template <int B>
+struct Lay {
+  static constexpr int BB = B * B;
+  // element (item-major in global memory, same order in LDS): A, b, Q, J, eta, cf, cl
+  static constexpr int kA = 0, kb = BB, kQ = BB + B, kJ = 2 * BB + B, keta = 3 * BB + B;
+  static constexpr int kcf = 3 * BB + 2 * B, kcl = kcf + 1;
+  static constexpr int kE = kcl + 1;
+  static constexpr int kEs = (kE + 7) / 8 * 8;        // item stride (64-byte multiple)
+  // message: m, P (prefix) and J, eta (suffix)
+  static constexpr int km = 0, kP = B, kMJ = B + BB, kMeta = 2 * BB + B;
+  static constexpr int kM = 2 * BB + 2 * B;
+  static constexpr int kMs = (kM + 7) / 8 * 8;
+  // scratch of one element operation: 8 matrices and 10 vectors
+  static constexpr int kTmp = 8 * BB + 10 * B;
+};
+
+// ---------------------------------------------------------------------------- team algebra
+// Row-major B x B matrices in LDS.  Outputs never alias inputs.  Every call ends with a
+// barrier, so its result is visible to the whole team.
+template <int B>
+SPG_DEV void t_copy(const double* __restrict__ X, double* __restrict__ Y, int n) {
+  for (int e = threadIdx.x; e < n; e += kW) Y[e] = X[e];
+  tsync();
+}
+template <int B>
+SPG_DEV void t_mm(const double* X, const double* Y, double* Z) {        // Z = X Y
+  for (int e = threadIdx.x; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double s = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[i * B + k], Y[k * B + j], s);
+    Z[e] = s;
+  }
+  tsync();
+}
+template <int B>
+SPG_DEV void t_mtm(const double* X, const double* Y, double* Z) {       // Z = X^T Y
+  for (int e = threadIdx.x; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double s = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[k * B + i], Y[k * B + j], s);
+    Z[e] = s;
+  }
+  tsync();
+}
+template <int B>
+SPG_DEV void t_mmt(const double* X, const double* Y, double* Z) {       // Z = X Y^T
+  for (int e = threadIdx.x; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double s = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[i * B + k], Y[j * B + k], s);
+    Z[e] = s;
+  }
+  tsync();
+}
+template <int B>
+SPG_DEV void t_mv(const double* X, const double* v, double* w) {        // w = X v
+  if (threadIdx.x < B) {
+    const int i = threadIdx.x;
+    double s = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[i * B + k], v[k], s);
+    w[i] = s;
+  }
+  tsync();
+}
+template <int B>
+SPG_DEV void t_mtv(const double* X, const double* v, double* w) {       // w = X^T v
+  if (threadIdx.x < B) {
+    const int i = threadIdx.x;
+    double s = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[k * B + i], v[k], s);
+    w[i] = s;
+  }
+  tsync();
+}
+template <int B>
+SPG_DEV void t_sym(double* X) {                                          // X = (X + X^T) / 2
+  for (int e = threadIdx.x; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    if (i < j) {
+      const double a = 0.5 * (X[i * B + j] + X[j * B + i]);
+      X[i * B + j] = a;
+      X[j * B + i] = a;
+    }
+  }
+  tsync();
+}
+template <int B>
+SPG_DEV void t_add_eye(double* X) {
+  if (threadIdx.x < B) X[threadIdx.x * (B + 1)] += 1.0;
+  tsync();
+}
+// Every lane returns the same value (broadcast reads, fixed order).
+template <int B>
+SPG_DEV double t_dot(const double* a, const double* b) {
+  double s = 0.0;
+  SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(a[k], b[k], s);
+  return s;
+}
+
+// G = M^-1 by Gauss-Jordan with partial pivoting (M is overwritten); returns log |det M|.
+// The pivot search is done redundantly by every lane, so the pivot row is uniform.
+template <int B>
+SPG_DEV double t_inv_logdet(double* M, double* G, double* fcol) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < B * B; e += kW) G[e] = (e / B == e % B) ? 1.0 : 0.0;
+  tsync();
+  double ld = 0.0;
+  for (int c = 0; c < B; ++c) {
+    int p = c;
+    double best = fabs(M[c * B + c]);
+    for (int r = c + 1; r < B; ++r) {
+      const double v = fabs(M[r * B + c]);
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    tsync();
+    if (p != c) {
+      if (tid < B) {
+        const double x = M[c * B + tid];
+        M[c * B + tid] = M[p * B + tid];
+        M[p * B + tid] = x;
+      } else if (tid < 2 * B) {
+        const int k = tid - B;
+        const double x = G[c * B + k];
+        G[c * B + k] = G[p * B + k];
+        G[p * B + k] = x;
+      }
+      tsync();
+    }
+    const double piv = M[c * B + c];
+    ld += log(fabs(piv));
+    const double ip = 1.0 / piv;
+    if (tid < B) fcol[tid] = M[tid * B + c];
+    tsync();
+    if (tid < B) M[c * B + tid] *= ip;
+    else if (tid < 2 * B) G[c * B + tid - B] *= ip;
+    tsync();
+    for (int e = tid; e < 2 * B * B; e += kW) {
+      const int mat = e / (B * B), f = e - mat * B * B;
+      const int r = f / B, k = f - r * B;
+      if (r == c) continue;
+      double* X = mat ? G : M;
+      X[r * B + k] = fma(-fcol[r], X[c * B + k], X[r * B + k]);
+    }
+    tsync();
+  }
+  return ld;
+}
+
+// ---------------------------------------------------------------------------- element ops
+// R = E1 (x) E2 (join at the shared node; see spingp_device.hpp).
+template <int B>
+SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tmp) {
+  using Y = Lay<B>;
+  constexpr int BB = B * B;
+  double *M = tmp, *G = M + BB, *Pp = G + BB, *W = Pp + BB, *GA = W + BB, *T = GA + BB, *WA = T + BB,
+         *AWA = WA + BB;
+  double* v = AWA + BB;
+  double *Gb = v, *Ppe = v + B, *g = v + 2 * B, *Gte = v + 3 * B, *Wb = v + 4 * B, *r = v + 5 * B, *Ag = v + 6 * B,
+         *Ar = v + 7 * B, *fcol = v + 8 * B;
+  const int tid = threadIdx.x;
+  t_mm<B>(E1 + Y::kQ, E2 + Y::kJ, M);
+  t_add_eye<B>(M);
+  const double ld = t_inv_logdet<B>(M, G, fcol);
+  t_mm<B>(G, E1 + Y::kQ, Pp);
+  t_sym<B>(Pp);
+  t_mm<B>(E2 + Y::kJ, G, W);
+  t_sym<B>(W);
+  t_mm<B>(G, E1 + Y::kA, GA);
+  if (tid < B) {
+    const int i = tid;
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      s1 = fma(G[i * B + k], E1[Y::kb + k], s1);
+      s2 = fma(Pp[i * B + k], E2[Y::keta + k], s2);
+      s3 = fma(G[k * B + i], E2[Y::keta + k], s3);
+      s4 = fma(W[i * B + k], E1[Y::kb + k], s4);
+    }
+    Gb[i] = s1;
+    Ppe[i] = s2;
+    Gte[i] = s3;
+    Wb[i] = s4;
+    g[i] = s1 + s2;
+    r[i] = s3 - s4;
+  }
+  tsync();
+  const double cf = -0.5 * t_dot<B>(E1 + Y::kb, Wb) + t_dot<B>(E2 + Y::keta, Gb) + 0.5 * t_dot<B>(E2 + Y::keta, Ppe);
+  t_mm<B>(E2 + Y::kA, GA, R + Y::kA);
+  t_mv<B>(E2 + Y::kA, g, Ag);
+  t_mm<B>(E2 + Y::kA, Pp, T);
+  t_mmt<B>(T, E2 + Y::kA, R + Y::kQ);
+  t_mm<B>(W, E1 + Y::kA, WA);
+  t_mtm<B>(E1 + Y::kA, WA, AWA);
+  t_mtv<B>(E1 + Y::kA, r, Ar);
+  for (int e = tid; e < BB; e += kW) {
+    R[Y::kQ + e] += E2[Y::kQ + e];
+    R[Y::kJ + e] = E1[Y::kJ + e] + AWA[e];
+  }
+  if (tid < B) {
+    R[Y::kb + tid] = Ag[tid] + E2[Y::kb + tid];
+    R[Y::keta + tid] = E1[Y::keta + tid] + Ar[tid];
+  }
+  if (tid == 0) {
+    R[Y::kcf] = E1[Y::kcf] + E2[Y::kcf] + cf;
+    R[Y::kcl] = E1[Y::kcl] + E2[Y::kcl] - 0.5 * ld;
+  }
+  tsync();
+  t_sym<B>(R + Y::kQ);
+  t_sym<B>(R + Y::kJ);
+}
+
+// Prefix: the predicted state N(m, P) at E's left node pushed through E -> (mo, Po); returns
+// the log-normaliser increments in dcf, dcl (uniform over the team).
+template <int B>
+SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double* mo, double* Po, double* tmp,
+                      double& dcf, double& dcl) {
+  using Y = Lay<B>;
+  constexpr int BB = B * B;
+  double *M = tmp, *G = M + BB, *Pp = G + BB, *W = Pp + BB, *T = W + BB;
+  double* v = tmp + 8 * BB;
+  double *Gm = v, *Ppe = v + B, *g = v + 2 * B, *Wm = v + 3 * B, *Ag = v + 4 * B, *fcol = v + 8 * B;
+  const int tid = threadIdx.x;
+  t_mm<B>(P, E + Y::kJ, M);
+  t_add_eye<B>(M);
+  const double ld = t_inv_logdet<B>(M, G, fcol);
+  t_mm<B>(G, P, Pp);
+  t_sym<B>(Pp);
+  t_mm<B>(E + Y::kJ, G, W);
+  t_sym<B>(W);
+  if (tid < B) {
+    const int i = tid;
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      s1 = fma(G[i * B + k], m[k], s1);
+      s2 = fma(Pp[i * B + k], E[Y::keta + k], s2);
+      s3 = fma(W[i * B + k], m[k], s3);
+    }
+    Gm[i] = s1;
+    Ppe[i] = s2;
+    Wm[i] = s3;
+    g[i] = s1 + s2;
+  }
+  tsync();
+  dcf = -0.5 * t_dot<B>(m, Wm) + t_dot<B>(E + Y::keta, Gm) + 0.5 * t_dot<B>(E + Y::keta, Ppe) + E[Y::kcf];
+  dcl = -0.5 * ld + E[Y::kcl];
+  t_mv<B>(E + Y::kA, g, Ag);
+  t_mm<B>(E + Y::kA, Pp, T);
+  t_mmt<B>(T, E + Y::kA, Po);
+  for (int e = tid; e < BB; e += kW) Po[e] += E[Y::kQ + e];
+  if (tid < B) mo[tid] = Ag[tid] + E[Y::kb + tid];
+  tsync();
+  t_sym<B>(Po);
+}
+
+// Suffix: information (Jb, etab) on E's right node pulled back to its left node -> (Jo, etao).
+template <int B>
+SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, double* Jo, double* etao, double* tmp) {
+  using Y = Lay<B>;
+  constexpr int BB = B * B;
+  double *M = tmp, *G = M + BB, *W = G + BB, *WA = W + BB, *AWA = WA + BB;
+  double* v = tmp + 8 * BB;
+  double *r = v, *Ar = v + B, *fcol = v + 8 * B;
+  const int tid = threadIdx.x;
+  t_mm<B>(E + Y::kQ, Jb, M);
+  t_add_eye<B>(M);
+  (void)t_inv_logdet<B>(M, G, fcol);
+  t_mm<B>(Jb, G, W);
+  t_sym<B>(W);
+  if (tid < B) {
+    const int i = tid;
+    double s1 = 0.0, s2 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      s1 = fma(G[k * B + i], etab[k], s1);
+      s2 = fma(W[i * B + k], E[Y::kb + k], s2);
+    }
+    r[i] = s1 - s2;
+  }
+  tsync();
+  t_mm<B>(W, E + Y::kA, WA);
+  t_mtm<B>(E + Y::kA, WA, AWA);
+  t_mtv<B>(E + Y::kA, r, Ar);
+  for (int e = tid; e < BB; e += kW) Jo[e] = E[Y::kJ + e] + AWA[e];
+  if (tid < B) etao[tid] = E[Y::keta + tid] + Ar[tid];
+  tsync();
+  t_sym<B>(Jo);
+}
+
+// ---------------------------------------------------------------------------- the model
+// Matern-3/2 (state 0..1) + periodic with NJ harmonics (states 2 + 2j, 3 + 2j for j = 0..NJ).
+// Hyperparameter row: (l_M, var_M, l_P, var_P, period, s2).  The periodic term is the
+// truncated cosine series of the periodic kernel with weights
+//   q_j^2 = var_P c_j exp(-x) I_j(x),  x = 1 / l_P^2,  c_0 = 1, c_j = 2,
+// its harmonic j is a rotation by j w dt (w = 2 pi / period) with Q = 0.
+template <int NJ>
+struct SumM32Periodic {
+  static constexpr int B = 2 + 2 * (NJ + 1);
+  static constexpr int NH = 6;
+  // constants shared by all kernels of one call, computed by k_wide_setup into global memory:
+  // scalars, q_j^2, dq_j^2/dx, P0' = T P0 T^T
+  static constexpr int kLamM = 0, kVarM = 1, kEllP = 2, kVarP = 3, kPer = 4, kS2 = 5, kW0 = 6, kX = 7;
+  static constexpr int kQ2 = 8, kDQ2 = kQ2 + NJ + 1, kP0 = kDQ2 + NJ + 1;
+  static constexpr int kConst = kP0 + B * B;
+
+  SPG_DEV static bool observed(int k) { return k == 0 || (k >= 2 && (k & 1) == 0); }
+  // T (row 0 = h^T, identity below) and T^-1 (row 0 = (1, -h_1, ..., -h_{B-1}), identity below)
+  SPG_DEV static double T_at(int i, int j) { return i == 0 ? (observed(j) ? 1.0 : 0.0) : (i == j ? 1.0 : 0.0); }
+  SPG_DEV static double Ti_at(int i, int j) {
+    if (i == 0) return j == 0 ? 1.0 : (observed(j) ? -1.0 : 0.0);
+    return i == j ? 1.0 : 0.0;
+  }
+  // entry (i, j) of the original-basis transition, its derivatives with respect to lam_M and
+  // the period, and of Q (Matern block only; the rotation blocks have Q = 0)
+  SPG_DEV static void edge_entry(const double* c, double dt, int i, int j, double& a, double& q, double& da_lam,
+                                 double& da_per) {
+    a = q = da_lam = da_per = 0.0;
+    if (i < 2 && j < 2) {
+      const double lam = c[kLamM], var = c[kVarM];
+      const double x = lam * dt, e = exp(-lam * dt);
+      const double A2[2][2] = {{e * (1.0 + x), e * dt}, {-e * lam * x, e * (1.0 - x)}};
+      const double P2[2] = {var, var * lam * lam};
+      a = A2[i][j];
+      q = (i == j ? P2[i] : 0.0) - (A2[i][0] * P2[0] * A2[j][0] + A2[i][1] * P2[1] * A2[j][1]);
+      const double D2[2][2] = {{-dt * x, -dt * dt}, {x * (x - 2.0), dt * (x - 2.0)}};
+      da_lam = e * D2[i][j];
+    } else if (i >= 2 && j >= 2 && ((i - 2) >> 1) == ((j - 2) >> 1)) {
+      const int h = (i - 2) >> 1;
+      const int ri = (i - 2) & 1, rj = (j - 2) & 1;
+      const double th = (double)h * c[kW0] * dt;
+      double sn, cs;
+      sincos(th, &sn, &cs);
+      // [[cos, -sin], [sin, cos]] and its derivative in theta, times d theta / d period
+      const double R[2][2] = {{cs, -sn}, {sn, cs}};
+      const double dR[2][2] = {{-sn, -cs}, {cs, -sn}};
+      a = R[ri][rj];
+      da_per = dR[ri][rj] * (-th / c[kPer]);
+    }
+  }
+  // diagonal of the original-basis P0 and its derivatives: d/dlam_M, d/dvar_M, d/dl_P, d/dvar_P
+  SPG_DEV static void p0_diag(const double* c, int k, double& p, double& dlam, double& dvarm, double& dellp,
+                              double& dvarp) {
+    p = dlam = dvarm = dellp = dvarp = 0.0;
+    if (k == 0) {
+      p = c[kVarM];
+      dvarm = 1.0;
+    } else if (k == 1) {
+      p = c[kVarM] * c[kLamM] * c[kLamM];
+      dlam = 2.0 * c[kVarM] * c[kLamM];
+      dvarm = c[kLamM] * c[kLamM];
+    } else {
+      const int h = (k - 2) >> 1;
+      const double ell = c[kEllP];
+      p = c[kQ2 + h];
+      dellp = c[kDQ2 + h] * (-2.0 / (ell * ell * ell));
+      dvarp = c[kQ2 + h] / c[kVarP];
+    }
+  }
+};
+
+// exp(-x) I_j(x) by its power series, summed in log space (no overflow for large x).
+SPG_DEV double bessel_ive(int j, double x) {
+  if (j < 0) j = -j;
+  if (!(x > 0.0)) return j == 0 ? 1.0 : 0.0;
+  const double lh = log(0.5 * x);
+  double lt = j * lh - lgamma(j + 1.0) - x;
+  double s = 0.0;
+  for (int k = 0; k < 200000; ++k) {
+    const double tk = exp(lt);
+    s += tk;
+    if (k > 0.5 * x + 8.0 && tk <= 1e-18 * s) break;
+    lt += 2.0 * lh - log((double)(k + 1)) - log((double)(k + 1 + j));
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------- kernels
+// Model constants from the hyperparameter row (one work-group).
+template <class M>
+__global__ __launch_bounds__(kW) void k_wide_setup(const double* __restrict__ hyper, double* __restrict__ cst) {
+  constexpr int B = M::B;
+  __shared__ double c[M::kConst];
+  __shared__ double P0[B * B], X[B * B];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    c[M::kLamM] = 1.7320508075688772935 / hyper[0];
+    c[M::kVarM] = hyper[1];
+    c[M::kEllP] = hyper[2];
+    c[M::kVarP] = hyper[3];
+    c[M::kPer] = hyper[4];
+    c[M::kS2] = hyper[5];
+    c[M::kW0] = 6.283185307179586477 / hyper[4];
+    c[M::kX] = 1.0 / (hyper[2] * hyper[2]);
+  }
+  tsync();
+  // q_j^2 and dq_j^2 / dx, with d(e^-x I_j)/dx = (I_{j-1} + I_{j+1}) e^-x / 2 - e^-x I_j
+  const int NJ = B / 2 - 2;
+  if (tid <= NJ) {
+    const double x = c[M::kX], cj = tid == 0 ? 1.0 : 2.0;
+    const double i0 = bessel_ive(tid, x), im = bessel_ive(tid - 1, x), ip = bessel_ive(tid + 1, x);
+    c[M::kQ2 + tid] = c[M::kVarP] * cj * i0;
+    c[M::kDQ2 + tid] = c[M::kVarP] * cj * (0.5 * (im + ip) - i0);
+  }
+  tsync();
+  for (int e = tid; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double p = 0.0, d0, d1, d2, d3;
+    if (i == j) M::p0_diag(c, i, p, d0, d1, d2, d3);
+    P0[e] = p;
+  }
+  tsync();
+  // P0' = T P0 T^T
+  for (int e = tid; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double s = 0.0;
+    for (int k = 0; k < B; ++k) s = fma(M::T_at(i, k), P0[k * B + j], s);
+    X[e] = s;
+  }
+  tsync();
+  for (int e = tid; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double s = 0.0;
+    for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::T_at(j, k), s);
+    c[M::kP0 + e] = s;
+  }
+  tsync();
+  for (int e = tid; e < M::kConst; e += kW) cst[e] = c[e];
+}
+
+// Leaf n: node n's information and the edge n -> n+1 (A = 0, Q = 0 after the last node).
+template <class M>
+__global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, const double* __restrict__ y,
+                                                  int64_t n_pts, const double* __restrict__ cst,
+                                                  double* __restrict__ elems) {
+  constexpr int B = M::B, BB = B * B;
+  using Y = Lay<B>;
+  __shared__ double c[M::kConst];
+  __shared__ double Ao[BB], Qo[BB], X[BB], E[Y::kEs];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
+  tsync();
+  const double s2 = c[M::kS2];
+  for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
+    const bool edge = n + 1 < n_pts;
+    const double dt = edge ? t[n + 1] - t[n] : 0.0;
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      double a = 0.0, q = 0.0, d0, d1;
+      if (edge) M::edge_entry(c, dt, i, j, a, q, d0, d1);
+      Ao[e] = a;
+      Qo[e] = q;
+    }
+    tsync();
+    // A' = T A T^-1 and Q' = T Q T^T, with the constant T applied entry by entry
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      double s = 0.0;
+      for (int k = 0; k < B; ++k) s = fma(M::T_at(i, k), Ao[k * B + j], s);
+      X[e] = s;
+    }
+    tsync();
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      double s = 0.0;
+      for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::Ti_at(k, j), s);
+      E[Y::kA + e] = s;
+    }
+    tsync();
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      double s = 0.0;
+      for (int k = 0; k < B; ++k) s = fma(M::T_at(i, k), Qo[k * B + j], s);
+      X[e] = s;
+    }
+    tsync();
+    const double yn = y[n];
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      double s = 0.0;
+      for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::T_at(j, k), s);
+      E[Y::kQ + e] = s;
+      E[Y::kJ + e] = (e == 0) ? 1.0 / s2 : 0.0;
+    }
+    if (tid < B) {
+      E[Y::kb + tid] = 0.0;
+      E[Y::keta + tid] = tid == 0 ? yn / s2 : 0.0;
+    }
+    if (tid == 0) {
+      E[Y::kcf] = -0.5 * yn * yn / s2;
+      E[Y::kcl] = -0.5 * (kLog2Pi + log(s2));
+    }
+    tsync();
+    t_sym<B>(E + Y::kQ);
+    double* out = elems + n * Y::kEs;
+    for (int e = tid; e < Y::kEs; e += kW) out[e] = e < Y::kE ? E[e] : 0.0;
+    tsync();
+  }
+}
+
+// Up-sweep: level k (n_cur elements at off_cur) from level k - 1 (n_prev at off_prev).
+template <int B>
+__global__ __launch_bounds__(kW) void k_wide_up(double* __restrict__ elems, int64_t off_prev, int64_t n_prev,
+                                                int64_t off_cur, int64_t n_cur) {
+  using Y = Lay<B>;
+  __shared__ double E1[Y::kEs], E2[Y::kEs], R[Y::kEs], tmp[Y::kTmp];
+  const int tid = threadIdx.x;
+  for (int64_t i = blockIdx.x; i < n_cur; i += gridDim.x) {
+    const double* a = elems + (off_prev + 2 * i) * Y::kEs;
+    double* out = elems + (off_cur + i) * Y::kEs;
+    if (2 * i + 1 >= n_prev) {                 // unpaired tail: passes through
+      for (int e = tid; e < Y::kEs; e += kW) out[e] = a[e];
+      continue;
+    }
+    const double* b = a + Y::kEs;
+    for (int e = tid; e < Y::kEs; e += kW) {
+      E1[e] = a[e];
+      E2[e] = b[e];
+    }
+    tsync();
+    t_combine<B>(E1, E2, R, tmp);
+    for (int e = tid; e < Y::kEs; e += kW) out[e] = e < Y::kE ? R[e] : 0.0;
+    tsync();
+  }
+}
+
+// Root: messages of the root element (prefix = the prior N(0, P0'), suffix = nothing) and the
+// log marginal likelihood (the prior pushed through the whole chain).
+template <class M>
+__global__ __launch_bounds__(kW) void k_wide_root(const double* __restrict__ cst, const double* __restrict__ elems,
+                                                  int64_t off_root, double* __restrict__ msgs,
+                                                  double* __restrict__ scal) {
+  constexpr int B = M::B, BB = B * B;
+  using Y = Lay<B>;
+  __shared__ double E[Y::kEs], m0[B], P0[BB], mo[B], Po[BB], tmp[Y::kTmp];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[off_root * Y::kEs + e];
+  for (int e = tid; e < BB; e += kW) P0[e] = cst[M::kP0 + e];
+  if (tid < B) m0[tid] = 0.0;
+  tsync();
+  double* msg = msgs + off_root * Y::kMs;
+  for (int e = tid; e < Y::kMs; e += kW) {
+    double v = 0.0;
+    if (e >= Y::kP && e < Y::kP + BB) v = P0[e - Y::kP];
+    msg[e] = v;
+  }
+  double dcf, dcl;
+  t_prefix<B>(m0, P0, E, mo, Po, tmp, dcf, dcl);
+  if (tid == 0) {
+    scal[0] = dcf + dcl;
+    scal[1] = dcf;
+    scal[2] = dcl;
+  }
+}
+
+// Down-sweep: messages of level k - 1 (n_child at off_child) from level k (at off_par).
+template <int B>
+__global__ __launch_bounds__(kW) void k_wide_down(const double* __restrict__ elems, double* __restrict__ msgs,
+                                                  int64_t off_par, int64_t off_child, int64_t n_child) {
+  using Y = Lay<B>;
+  constexpr int BB = B * B;
+  __shared__ double par[Y::kMs], E[Y::kEs], out[Y::kMs], tmp[Y::kTmp];
+  const int tid = threadIdx.x;
+  for (int64_t c = blockIdx.x; c < n_child; c += gridDim.x) {
+    const double* pm = msgs + (off_par + (c >> 1)) * Y::kMs;
+    double* om = msgs + (off_child + c) * Y::kMs;
+    const bool left = (c & 1) == 0;
+    if (left && c + 1 >= n_child) {            // unpaired tail: same messages as its parent
+      for (int e = tid; e < Y::kMs; e += kW) om[e] = pm[e];
+      continue;
+    }
+    const double* sib = elems + (off_child + (left ? c + 1 : c - 1)) * Y::kEs;
+    for (int e = tid; e < Y::kMs; e += kW) par[e] = pm[e];
+    for (int e = tid; e < Y::kEs; e += kW) E[e] = sib[e];
+    tsync();
+    if (left) {
+      // prefix unchanged; suffix pulled back through the right sibling
+      for (int e = tid; e < B + BB; e += kW) out[e] = par[e];
+      t_suffix<B>(E, par + Y::kMJ, par + Y::kMeta, out + Y::kMJ, out + Y::kMeta, tmp);
+    } else {
+      // prefix pushed through the left sibling; suffix unchanged
+      for (int e = tid; e < B + BB; e += kW) out[Y::kMJ + e] = par[Y::kMJ + e];
+      double dcf, dcl;
+      t_prefix<B>(par + Y::km, par + Y::kP, E, out + Y::km, out + Y::kP, tmp, dcf, dcl);
+    }
+    for (int e = tid; e < Y::kMs; e += kW) om[e] = e < Y::kM ? out[e] : 0.0;
+    tsync();
+  }
+}
+
+struct WideOut {
+  double* f_mean;
+  double* f_var;
+  double* z_mean;
+  double* S_diag;
+  double* S_sub;
+  int64_t ld;
+  double* part;      // [gridDim.x][kPart] per-work-group gradient partials
+};
+
+// Node step (see the file comment).  Gradient partials per work-group: P0'_bar (B*B),
+// <A_bar, dA/dlam_M>, <A_bar, dA/dperiod>, d/ds2.
+template <class M, int MODE>
+__global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, const double* __restrict__ y,
+                                                  int64_t n_pts, const double* __restrict__ cst,
+                                                  const double* __restrict__ elems, const double* __restrict__ msgs,
+                                                  WideOut out) {
+  constexpr int B = M::B, BB = B * B;
+  using Y = Lay<B>;
+  constexpr bool kGrad = (MODE & kWantGrad) != 0;
+  constexpr bool kCov = (MODE & (kWantVar | kWantSub)) != 0;
+  constexpr bool kSub = (MODE & kWantSub) != 0;
+  constexpr int kPart = BB + 3;
+  __shared__ double c[M::kConst];
+  __shared__ double E[Y::kEs], G_[Y::kMs];   // leaf element; messages (prefix at n, suffix on n + 1)
+  __shared__ double mp[B], Pp[BB], mn[B], Pn[BB], Mx[BB], Gm[BB], W[BB], lam[B], Lam[BB], X1[BB], X2[BB],
+      X3[BB], mu[B], fcol[B], red[kW], tmp[Y::kTmp];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
+  tsync();
+  const double* P0 = c + M::kP0;
+  const double s2 = c[M::kS2];
+  double acc_p0[2] = {0.0, 0.0}, acc_lam = 0.0, acc_per = 0.0, acc_s2 = 0.0;
+  for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
+    const bool edge = n + 1 < n_pts;
+    for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[n * Y::kEs + e];
+    for (int e = tid; e < Y::kMs; e += kW) G_[e] = msgs[n * Y::kMs + e];
+    tsync();
+    const double* m = G_ + Y::km;
+    const double* P = G_ + Y::kP;
+    const double* A = E + Y::kA;
+    // filtered state at n: K = P e0 / s, v = y - m_0
+    const double yn = y[n];
+    const double s = P[0] + s2, is = 1.0 / s, v = yn - m[0];
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      Pp[e] = P[e] - P[i * B] * P[j * B] * is;
+    }
+    if (tid < B) mp[tid] = m[tid] + P[tid * B] * is * v;
+    tsync();
+    t_sym<B>(Pp);
+    // predicted state at n + 1 and the suffix information on it
+    const double* Js = G_ + Y::kMJ;
+    const double* es = G_ + Y::kMeta;
+    t_mv<B>(A, mp, mn);                 // b = 0 at a leaf
+    t_mm<B>(A, Pp, X1);
+    t_mmt<B>(X1, A, Pn);
+    for (int e = tid; e < BB; e += kW) Pn[e] += E[Y::kQ + e];
+    tsync();
+    t_sym<B>(Pn);
+    // seed at n + 1: Gam = (I + P' J')^-1, W = J' Gam, lam = Gam^T eta' - W m', Lam
+    t_mm<B>(Pn, Js, Mx);
+    t_add_eye<B>(Mx);
+    (void)t_inv_logdet<B>(Mx, Gm, fcol);
+    t_mm<B>(Js, Gm, W);
+    t_sym<B>(W);
+    if (tid < B) {
+      const int i = tid;
+      double s1 = 0.0, s3 = 0.0;
+      for (int k = 0; k < B; ++k) {
+        s1 = fma(Gm[k * B + i], es[k], s1);
+        s3 = fma(W[i * B + k], mn[k], s3);
+      }
+      lam[i] = s1 - s3;
+    }
+    tsync();
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      Lam[e] = 0.5 * (lam[i] * lam[j] - W[e]);
+    }
+    tsync();
+    // smoothed mean mu = m+ + P+ A^T lam
+    t_mtv<B>(A, lam, fcol);
+    if (tid < B) {
+      double sacc = mp[tid];
+      for (int k = 0; k < B; ++k) sacc = fma(Pp[tid * B + k], fcol[k], sacc);
+      mu[tid] = sacc;
+    }
+    tsync();
+    // smoothed covariance S = P+ - (A P+)^T W (A P+)   (X1 = A P+)
+    double S00 = 0.0;
+    if (kCov || kGrad) {
+      t_mm<B>(W, X1, X2);                // W A P+
+      t_mtm<B>(X1, X2, X3);              // (A P+)^T W A P+
+      for (int e = tid; e < BB; e += kW) X3[e] = Pp[e] - X3[e];
+      tsync();
+      t_sym<B>(X3);
+      S00 = X3[0];
+    }
+    if (out.f_mean && tid == 0) out.f_mean[n] = mu[0];
+    if (out.f_var && tid == 0) out.f_var[n] = S00;
+    if (out.z_mean && tid < B) {
+      double z = mu[tid];
+      if (tid == 0) for (int k = 1; k < B; ++k) z = fma(M::Ti_at(0, k), mu[k], z);
+      out.z_mean[tid * out.ld + n] = z;
+    }
+    if (out.S_diag || (kSub && out.S_sub && edge)) {
+      // back to the original basis: S_o = T^-1 S' T^-T, S_sub_o = T^-1 S_sub' T^-T
+      if (out.S_diag) {
+        for (int e = tid; e < BB; e += kW) {
+          const int i = e / B, j = e - i * B;
+          double sacc = 0.0;
+          for (int k = 0; k < B; ++k) sacc = fma(M::Ti_at(i, k), X3[k * B + j], sacc);
+          X2[e] = sacc;
+        }
+        tsync();
+        for (int e = tid; e < BB; e += kW) {
+          const int i = e / B, j = e - i * B;
+          if (j < i) continue;
+          double sacc = 0.0;
+          for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], M::Ti_at(j, k), sacc);
+          const int pk = i * B - i * (i - 1) / 2 + (j - i);     // packed upper, row-major
+          out.S_diag[(int64_t)pk * out.ld + n] = sacc;
+        }
+        tsync();
+      }
+      if (kSub && out.S_sub && edge) {
+        // S_sub' = (I - P' W) A P+ = X1 - Pn (W X1)
+        t_mm<B>(W, X1, X2);
+        t_mm<B>(Pn, X2, Mx);
+        for (int e = tid; e < BB; e += kW) Mx[e] = X1[e] - Mx[e];
+        tsync();
+        for (int e = tid; e < BB; e += kW) {
+          const int i = e / B, j = e - i * B;
+          double sacc = 0.0;
+          for (int k = 0; k < B; ++k) sacc = fma(M::Ti_at(i, k), Mx[k * B + j], sacc);
+          X2[e] = sacc;
+        }
+        tsync();
+        for (int e = tid; e < BB; e += kW) {
+          const int i = e / B, j = e - i * B;
+          double sacc = 0.0;
+          for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], M::Ti_at(j, k), sacc);
+          out.S_sub[(int64_t)e * out.ld + n] = sacc;
+        }
+        tsync();
+      }
+    }
+    if (kGrad) {
+      // noise: E[d/ds2 log N(y; z_0, s2)] = -1/(2 s2) + ((y - mu_0)^2 + S_00) / (2 s2^2)
+      if (tid == 0) {
+        const double r = yn - mu[0];
+        acc_s2 += -0.5 / s2 + 0.5 * (r * r + S00) / (s2 * s2);
+      }
+      if (edge) {
+        // A_bar = lam m+^T + 2 Lam A (P+ - P0)   (Mx = A (P+ - P0))
+        for (int e = tid; e < BB; e += kW) X2[e] = Pp[e] - P0[e];
+        tsync();
+        t_mm<B>(A, X2, Mx);
+        t_mm<B>(Lam, Mx, X2);
+        for (int e = tid; e < BB; e += kW) {
+          const int i = e / B, j = e - i * B;
+          X2[e] = fma(lam[i], mp[j], 2.0 * X2[e]);
+        }
+        tsync();
+        // original basis: A_bar_o = T^T A_bar T^-T, contracted with dA/dlam_M and dA/dperiod
+        for (int e = tid; e < BB; e += kW) {
+          const int i = e / B, j = e - i * B;
+          double sacc = 0.0;
+          for (int k = 0; k < B; ++k) sacc = fma(M::T_at(k, i), X2[k * B + j], sacc);
+          Mx[e] = sacc;
+        }
+        tsync();
+        const double dt = t[n + 1] - t[n];
+        for (int e = tid; e < BB; e += kW) {
+          const int i = e / B, j = e - i * B;
+          double ab = 0.0;
+          for (int k = 0; k < B; ++k) ab = fma(Mx[i * B + k], M::Ti_at(j, k), ab);
+          double a, q, dl, dp;
+          M::edge_entry(c, dt, i, j, a, q, dl, dp);
+          acc_lam = fma(ab, dl, acc_lam);
+          acc_per = fma(ab, dp, acc_per);
+        }
+        // P0_bar += Lam - A^T Lam A
+        t_mm<B>(Lam, A, X2);
+        t_mtm<B>(A, X2, Mx);
+        for (int e = tid, r = 0; e < BB; e += kW, ++r) acc_p0[r] += Lam[e] - Mx[e];
+      }
+      if (n == 0) {
+        // the first state is drawn from N(0, P0'): P0_bar += Lam_0, the seed of the prior
+        // against all the information on node 0 (its own and the suffix pulled back)
+        t_suffix<B>(E, Js, es, X2, mn, tmp);
+        t_mm<B>(P0, X2, Mx);
+        t_add_eye<B>(Mx);
+        (void)t_inv_logdet<B>(Mx, Gm, fcol);
+        t_mm<B>(X2, Gm, W);
+        t_sym<B>(W);
+        t_mtv<B>(Gm, mn, lam);
+        for (int e = tid, r = 0; e < BB; e += kW, ++r) {
+          const int i = e / B, j = e - i * B;
+          acc_p0[r] += 0.5 * (lam[i] * lam[j] - W[e]);
+        }
+      }
+    }
+    tsync();
+  }
+  if (kGrad) {
+    // per-work-group partials: lane-owned entries of P0_bar, then the three sums reduced over
+    // the team in a fixed order
+    double* pw = out.part + (int64_t)blockIdx.x * kPart;
+    for (int e = tid, r = 0; e < BB; e += kW, ++r) pw[e] = acc_p0[r];
+    const double vals[3] = {acc_lam, acc_per, acc_s2};
+    for (int f = 0; f < 3; ++f) {
+      red[tid] = vals[f];
+      tsync();
+      if (tid == 0) {
+        double sacc = 0.0;
+        for (int k = 0; k < kW; ++k) sacc += red[k];
+        pw[BB + f] = sacc;
+      }
+      tsync();
+    }
+  }
+}
+
+// Sum of the per-work-group partials (fixed order) and the gradient with respect to the raw
+// hyperparameters (l_M, var_M, l_P, var_P, period, s2); also copies the log likelihood.
+template <class M>
+__global__ __launch_bounds__(kW) void k_wide_final(const double* __restrict__ cst, const double* __restrict__ part,
+                                                   int n_part, const double* __restrict__ scal,
+                                                   double* __restrict__ logml, double* __restrict__ grad) {
+  constexpr int B = M::B, BB = B * B;
+  constexpr int kPart = BB + 3;
+  __shared__ double c[M::kConst], tot[kPart], X[BB], Pb[BB];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
+  for (int f = tid; f < kPart; f += kW) {
+    double sacc = 0.0;
+    for (int w = 0; w < n_part; ++w) sacc += part[(int64_t)w * kPart + f];
+    tot[f] = sacc;
+  }
+  tsync();
+  // P0_bar in the original basis: T^T P0'_bar T
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double sacc = 0.0;
+    for (int k = 0; k < B; ++k) sacc = fma(M::T_at(k, i), tot[k * B + j], sacc);
+    X[e] = sacc;
+  }
+  tsync();
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double sacc = 0.0;
+    for (int k = 0; k < B; ++k) sacc = fma(X[i * B + k], M::T_at(k, j), sacc);
+    Pb[e] = sacc;
+  }
+  tsync();
+  if (tid == 0) {
+    // P0 is diagonal in the original basis
+    double g_lam = tot[BB + 0], g_varm = 0.0, g_ellp = 0.0, g_varp = 0.0;
+    for (int k = 0; k < B; ++k) {
+      double p, dl, dvm, dep, dvp;
+      M::p0_diag(c, k, p, dl, dvm, dep, dvp);
+      const double pb = Pb[k * B + k];
+      g_lam = fma(pb, dl, g_lam);
+      g_varm = fma(pb, dvm, g_varm);
+      g_ellp = fma(pb, dep, g_ellp);
+      g_varp = fma(pb, dvp, g_varp);
+    }
+    const double ellm = 1.7320508075688772935 / c[M::kLamM];
+    grad[0] = g_lam * (-c[M::kLamM] / ellm);
+    grad[1] = g_varm;
+    grad[2] = g_ellp;
+    grad[3] = g_varp;
+    grad[4] = tot[BB + 1];
+    grad[5] = tot[BB + 2];
+    if (logml) logml[0] = scal[0];
+  }
+}
+
+}  // namespace wide
+}  // namespace spg
