@@ -158,6 +158,50 @@ def large_report(spg, steps, warmup):
             "input_bytes": 16 * n, "every_level_stored_bytes": 2 * 33 * 8 * n}
 
 
+def sum_report(spg, steps, warmup):
+    """Matern-3/2 + periodic with 3 harmonics (b = 10), N = 2^18, t uniform on [0, 1e4]:
+    logML + the six-component gradient through the wide-state path, graph replay."""
+    import torch
+    from paper_1610_08035_amd.spingp import spingp_profile, spingp_profile_read
+    from workloads import make_config
+    w = make_config(3)
+    n = w.n_points
+    dev = torch.device("cuda:0")
+    td, yd = torch.as_tensor(w.t, device=dev), torch.as_tensor(w.y, device=dev)
+    hd = torch.as_tensor(w.hyper.reshape(-1), device=dev)
+    h = spg.Handle(w.terms, n)
+    h.assemble(td, yd, hd)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    g = torch.empty(1, 6, dtype=torch.float64, device=dev)
+    for _ in range(warmup):
+        spg.spingp_logml_grad(h._h, ll, g)
+    torch.cuda.synchronize()
+    if h.status()[0] != 0:
+        raise RuntimeError("sum-kernel workload failed validation")
+    # per-phase times from the library's events (eager launches), then the timed graph replays
+    spingp_profile(h._h, 1)
+    spg.spingp_logml_grad(h._h, ll, g)
+    prof = spingp_profile_read(h._h)
+    spingp_profile(h._h, 0)
+    h.close()
+    h = spg.Handle(w.terms, n)
+    h.assemble(td, yd, hd, graph=True)
+    for _ in range(warmup):
+        spg.spingp_logml_grad(h._h, ll, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        spg.spingp_logml_grad(h._h, ll, g)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    h.close()
+    phases = {"leaves_up_sweep": prof["fwd_fold_tree"][0], "root": prof["top_tree"][0],
+              "down_sweep_node_step": prof["bwd_elim_adjoint"][0], "gradient_sum": prof["series_reduce"][0]}
+    return {"workload": w.name + "_logml_grad", "n_points": n, "state_dim": 10, "n_hyper": 6,
+            "points_per_s": n / el, "ms_per_step": 1e3 * el, "steps": steps, "graph": True,
+            "phase_ms": {k: round(v, 4) for k, v in phases.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +210,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-series batched report")
     ap.add_argument("--no-large", action="store_true", help="skip the N = 2^24 report")
+    ap.add_argument("--no-sum", action="store_true", help="skip the b = 10 sum-kernel report")
+    ap.add_argument("--only", choices=["batched", "large", "sum"], default=None,
+                    help="run one secondary workload alone and print its JSON (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM counters)")
     args = ap.parse_args()
@@ -187,6 +234,10 @@ def main():
     import paper_1610_08035_amd as spg
     from paper_1610_08035_amd.spingp import spingp_profile, spingp_profile_read
     from workloads import make_config
+    if args.only:
+        fn = {"batched": batched_report, "large": large_report, "sum": sum_report}[args.only]
+        print(json.dumps({args.only: fn(spg, args.steps, args.warmup)}), flush=True)
+        return
 
     w = make_config(2)              # Matern-5/2, N = 2^20, Exp(1) gaps, l = 5, var = 2, s2 = 0.05
     n = w.n_points
@@ -255,6 +306,8 @@ def main():
         out["batched"] = batched_report(spg, args.steps, args.warmup)
     if not args.no_large:
         out["large"] = large_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
+    if not args.no_sum:
+        out["sum_kernel"] = sum_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -229,7 +229,7 @@ static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_serie
       {(void**)&w.elems, (int64_t)sizeof(double) * items * spg::wide::elem_stride()},
       {(void**)&w.msgs, (int64_t)sizeof(double) * items * spg::wide::msg_stride()},
       {(void**)&w.cst, (int64_t)sizeof(double) * spg::wide::const_size()},
-      {(void**)&w.part, (int64_t)sizeof(double) * w.node_grid * spg::wide::part_stride()},
+      {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride()},
       {(void**)&h->scal, (int64_t)sizeof(double) * 8},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
   };

@@ -9,12 +9,14 @@ namespace {
 using Model = SumM32Periodic<3>;
 static_assert(Model::B == kStateDim, "state dimension of the wide model");
 static_assert(Model::NH == kHyper, "hyperparameters of the wide model");
-constexpr int kGridCap = 4096;
+// Work-group caps: about what fits on the 256 CUs at once for each kernel's LDS and VGPRs,
+// so that no launch ends with a second, mostly empty round.
+constexpr int kGridUp = 2048, kGridDown = 4096, kGridLeaf = 4096, kGridNode = 1536;
 
 inline void mark(const WideCtx& c, int kid, int end) {
   if (c.mark) c.mark(c.mark_arg, kid, end);
 }
-inline unsigned grid_for(int64_t items) { return (unsigned)(items < kGridCap ? items : kGridCap); }
+inline unsigned grid_for(int64_t items, int cap) { return (unsigned)(items < cap ? items : cap); }
 
 }  // namespace
 
@@ -34,17 +36,17 @@ void plan_levels(int64_t n, WideCtx& c) {
     if (m == 1 || k == kMaxLevels) break;
   }
   c.n_levels = k;
-  c.node_grid = (int)(n < 2048 ? n : 2048);
+  c.node_grid = (int)(n < kGridNode ? n : kGridNode);
 }
 
 hipError_t factor(const WideCtx& c) {
   constexpr int B = Model::B;
   mark(c, kKidFwd, 0);
   hipLaunchKernelGGL(k_wide_setup<Model>, dim3(1), dim3(kW), 0, c.stream, c.hyper, c.cst);
-  hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points)), dim3(kW), 0, c.stream, c.t, c.y, c.n_points,
+  hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points, kGridLeaf)), dim3(kW), 0, c.stream, c.t, c.y, c.n_points,
                      c.cst, c.elems);
   for (int k = 1; k < c.n_levels; ++k)
-    hipLaunchKernelGGL(k_wide_up<B>, dim3(grid_for(c.n[k])), dim3(kW), 0, c.stream, c.elems, c.off[k - 1],
+    hipLaunchKernelGGL(k_wide_up<B>, dim3(grid_for(c.n[k], kGridUp)), dim3(kW), 0, c.stream, c.elems, c.off[k - 1],
                        c.n[k - 1], c.off[k], c.n[k]);
   mark(c, kKidFwd, 1);
   mark(c, kKidTop, 0);
@@ -58,7 +60,7 @@ hipError_t down(const WideCtx& c) {
   constexpr int B = Model::B;
   mark(c, kKidBwd, 0);
   for (int k = c.n_levels - 1; k >= 1; --k)
-    hipLaunchKernelGGL(k_wide_down<B>, dim3(grid_for(c.n[k - 1])), dim3(kW), 0, c.stream, c.elems, c.msgs,
+    hipLaunchKernelGGL(k_wide_down<B>, dim3(grid_for(c.n[k - 1], kGridDown)), dim3(kW), 0, c.stream, c.elems, c.msgs,
                        c.off[k], c.off[k - 1], c.n[k - 1]);
   mark(c, kKidBwd, 1);
   return hipGetLastError();
@@ -94,8 +96,10 @@ hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, doubl
 
 hipError_t finish(const WideCtx& c, double* logml, double* grad) {
   mark(c, kKidReduce, 0);
-  hipLaunchKernelGGL(k_wide_final<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, c.part, c.node_grid, c.scal, logml,
-                     grad);
+  double* tot = c.part + (int64_t)c.node_grid * part_stride();
+  hipLaunchKernelGGL(k_wide_sum<Model>, dim3((unsigned)part_stride()), dim3(kW), 0, c.stream, c.part, c.node_grid,
+                     tot);
+  hipLaunchKernelGGL(k_wide_final<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, tot, c.scal, logml, grad);
   mark(c, kKidReduce, 1);
   return hipGetLastError();
 }

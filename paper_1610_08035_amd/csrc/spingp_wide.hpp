@@ -346,6 +346,20 @@ struct SumM32Periodic {
     if (i == 0) return j == 0 ? 1.0 : (observed(j) ? -1.0 : 0.0);
     return i == j ? 1.0 : 0.0;
   }
+  // entry (i, j) of T^T X T^-T for a row-major X in LDS, from the sparsity of T:
+  // (X T^-T)[k][0] = X[k][0] - sum over observed l >= 1 of X[k][l], (X T^-T)[k][j] = X[k][j]
+  // for j >= 1; (T^T Y)[i][j] = Y[i][j] + [i >= 1 observed] Y[0][j]
+  SPG_DEV static double abar_orig(const double* X, int i, int j) {
+    auto y = [&](int k) {
+      double v = X[k * B + j];
+      if (j == 0)
+        for (int l = 2; l < B; l += 2) v -= X[k * B + l];
+      return v;
+    };
+    double r = y(i);
+    if (i >= 1 && observed(i)) r += y(0);
+    return r;
+  }
   // entry (i, j) of the original-basis transition, its derivatives with respect to lam_M and
   // the period, and of Q (Matern block only; the rotation blocks have Q = 0)
   SPG_DEV static void edge_entry(const double* c, double dt, int i, int j, double& a, double& q, double& da_lam,
@@ -788,19 +802,12 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
           X2[e] = fma(lam[i], mp[j], 2.0 * X2[e]);
         }
         tsync();
-        // original basis: A_bar_o = T^T A_bar T^-T, contracted with dA/dlam_M and dA/dperiod
-        for (int e = tid; e < BB; e += kW) {
-          const int i = e / B, j = e - i * B;
-          double sacc = 0.0;
-          for (int k = 0; k < B; ++k) sacc = fma(M::T_at(k, i), X2[k * B + j], sacc);
-          Mx[e] = sacc;
-        }
-        tsync();
+        // original basis: A_bar_o = T^T A_bar T^-T, needed only on the block-diagonal support
+        // of dA/dlam_M and dA/dperiod (one lane per entry of the 2 x 2 blocks)
         const double dt = t[n + 1] - t[n];
-        for (int e = tid; e < BB; e += kW) {
-          const int i = e / B, j = e - i * B;
-          double ab = 0.0;
-          for (int k = 0; k < B; ++k) ab = fma(Mx[i * B + k], M::Ti_at(j, k), ab);
+        if (tid < 2 * B) {
+          const int blk = tid >> 2, i = 2 * blk + ((tid >> 1) & 1), j = 2 * blk + (tid & 1);
+          const double ab = M::abar_orig(X2, i, j);
           double a, q, dl, dp;
           M::edge_entry(c, dt, i, j, a, q, dl, dp);
           acc_lam = fma(ab, dl, acc_lam);
@@ -848,22 +855,41 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
   }
 }
 
-// Sum of the per-work-group partials (fixed order) and the gradient with respect to the raw
-// hyperparameters (l_M, var_M, l_P, var_P, period, s2); also copies the log likelihood.
+// Sum of the per-work-group partials: work-group f adds field f over all node work-groups
+// (lane-strided, then a fixed tree over the lanes), so the result is independent of timing.
 template <class M>
-__global__ __launch_bounds__(kW) void k_wide_final(const double* __restrict__ cst, const double* __restrict__ part,
-                                                   int n_part, const double* __restrict__ scal,
-                                                   double* __restrict__ logml, double* __restrict__ grad) {
+__global__ __launch_bounds__(kW) void k_wide_sum(const double* __restrict__ part, int n_part,
+                                                 double* __restrict__ tot) {
+  constexpr int kPart = M::B * M::B + 3;
+  __shared__ double red[kW];
+  const int tid = threadIdx.x, f = blockIdx.x;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  int w = tid;
+  for (; w + 3 * kW < n_part; w += 4 * kW) {
+    SPG_UNROLL for (int u = 0; u < 4; ++u) a[u] += part[(int64_t)(w + u * kW) * kPart + f];
+  }
+  for (; w < n_part; w += kW) a[0] += part[(int64_t)w * kPart + f];
+  red[tid] = (a[0] + a[1]) + (a[2] + a[3]);
+  tsync();
+  for (int st = kW / 2; st > 0; st /= 2) {
+    if (tid < st) red[tid] += red[tid + st];
+    tsync();
+  }
+  if (tid == 0) tot[f] = red[0];
+}
+
+// Gradient with respect to the raw hyperparameters (l_M, var_M, l_P, var_P, period, s2) from
+// the summed partials; also copies the log likelihood.
+template <class M>
+__global__ __launch_bounds__(kW) void k_wide_final(const double* __restrict__ cst, const double* __restrict__ totg,
+                                                   const double* __restrict__ scal, double* __restrict__ logml,
+                                                   double* __restrict__ grad) {
   constexpr int B = M::B, BB = B * B;
   constexpr int kPart = BB + 3;
   __shared__ double c[M::kConst], tot[kPart], X[BB], Pb[BB];
   const int tid = threadIdx.x;
   for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
-  for (int f = tid; f < kPart; f += kW) {
-    double sacc = 0.0;
-    for (int w = 0; w < n_part; ++w) sacc += part[(int64_t)w * kPart + f];
-    tot[f] = sacc;
-  }
+  for (int e = tid; e < kPart; e += kW) tot[e] = totg[e];
   tsync();
   // P0_bar in the original basis: T^T P0'_bar T
   for (int e = tid; e < BB; e += kW) {
