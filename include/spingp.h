@@ -177,8 +177,9 @@ int spingp_status(spingp_handle h, int64_t* first_bad);
  * launch the library makes.  spingp_profile(h, 1) creates the events and starts recording,
  * spingp_profile(h, 0) stops and releases them.  spingp_profile_read synchronises and returns,
  * per kernel id (0 validation and chunk map, 1 forward fold + work-group tree, 2 top-level
- * tree, 3 top-level path walk + work-group down-sweep + chunk elimination + adjoint (+ gradient
- * sum), 4 per-series sums, 5 a whole graph replay of spingp_logml_grad), the total
+ * tree, 3 top-level path walk + work-group down-sweep + chunk elimination + adjoint, 4 sums of
+ * the reverse kernel's partials (per series, or over work-groups for one series), 5 a whole
+ * graph replay of spingp_logml_grad), the total
  * milliseconds and launch counts since the last read (host arrays of SPINGP_N_KERNELS).
  */
 #define SPINGP_N_KERNELS 6

@@ -84,7 +84,6 @@ struct spingp_ctx {
   double* top = nullptr;           // top-level tree over the work-group aggregates
   unsigned int* top_cnt = nullptr; // arrival counters of the top-level bands
   int64_t top_ld = 0, top_cnt_n = 0;
-  unsigned int* done = nullptr;    // finished work-groups of the backward kernel
   double* scal = nullptr;          // one series: log-likelihood terms at the root
   double* part = nullptr;          // gradient / log-likelihood partials
   int64_t part_ld = 0;
@@ -174,7 +173,6 @@ static spg::LaunchCtx launch_ctx(spingp_ctx* h, bool timed = true) {
   c.top = h->top;
   c.top_ld = h->top_ld;
   c.top_cnt = h->top_cnt;
-  c.done = h->done;
   c.scal = h->scal;
   c.part = h->part;
   c.part_ld = h->part_ld;
@@ -305,7 +303,6 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
       {(void**)&h->scal, (int64_t)sizeof(double) * 8},
       {(void**)&h->part, (int64_t)sizeof(double) * part_n},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
-      {(void**)&h->done, (int64_t)sizeof(unsigned int)},
       {(void**)&h->tune_out, (int64_t)sizeof(double) * 4 * max_series},
       {(void**)&h->chunk_series, multi ? (int64_t)sizeof(int32_t) * slots_max : 0},
       {(void**)&h->chunk_first, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
@@ -317,7 +314,6 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
     h->ws_bytes += r.bytes;
   }
   ok = ok && hipMemset(h->top_cnt, 0, sizeof(unsigned int) * h->top_cnt_n) == hipSuccess;
-  ok = ok && hipMemset(h->done, 0, sizeof(unsigned int)) == hipSuccess;
   ok = ok && hipMemset(h->key, 0xff, sizeof(unsigned long long)) == hipSuccess;
   ok = ok && hipDeviceSynchronize() == hipSuccess;
   if (!ok) {
@@ -372,7 +368,6 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)hipFree(h->scal);
   (void)hipFree(h->part);
   (void)hipFree(h->key);
-  (void)hipFree(h->done);
   (void)hipFree(h->tune_out);
   (void)hipFree(h->chunk_series);
   (void)hipFree(h->chunk_first);
@@ -585,8 +580,6 @@ static spg::BwdOut make_out(spingp_ctx* h) {
   o.ld = h->n_points;
   o.part = h->part;
   o.part_ld = h->part_ld;
-  o.done = h->done;
-  o.scal = h->scal;
   return o;
 }
 
@@ -638,14 +631,16 @@ static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed
     if (rc) return rc;
     return hip_ok(spg::wide::finish(wide_ctx(h, timed), logml, grad));
   }
-  spg::BwdOut o = make_out(h);
-  if (!h->batched) {
-    o.logml = logml;
-    o.grad = grad;
-  }
-  rc = run_bwd(h, spg::kWantGrad, o, timed);
-  if (rc || !h->batched) return rc;
-  return series_reduce(h, logml, nullptr, nullptr, grad, timed);
+  rc = run_bwd(h, spg::kWantGrad, make_out(h), timed);
+  if (rc) return rc;
+  if (h->batched) return series_reduce(h, logml, nullptr, nullptr, grad, timed);
+  // one series: fixed-order sum of the work-group partials
+  const spg::TileOps* T = ops(h);
+  if (timed) prof_begin(h);
+  hipLaunchKernelGGL(spg::k_grad_finish, dim3(1), dim3(256), 0, h->stream, h->part, h->part_ld,
+                     T->groups(h->n_points, 1, false), h->scal, logml, grad);
+  if (timed) prof_end(h, spg::kKidReduce);
+  return hip_ok(hipGetLastError());
 }
 
 // Capture the launch sequence of spingp_logml_grad for these output pointers on the private

@@ -170,6 +170,53 @@ SPG_DEV double inv_logdet(const double (&Min)[B][B], double (&G)[B][B]) {
   return log(fabs(pivprod));
 }
 
+// a b - c d with one rounding error on each product folded back (Kahan's 2x2 determinant):
+// accurate to a few ulps of the result even when the two products nearly cancel.
+SPG_DEV double diff_of_products(double a, double b, double c, double d) {
+  const double w = c * d;
+  const double e = fma(-c, d, w);
+  const double f = fma(a, b, -w);
+  return f + e;
+}
+
+// b = 2 and b = 3: the inverse through the adjugate, one division and a short dependency
+// chain (the pivoted elimination above needs one division per column in sequence).
+template <>
+SPG_DEV double inv_logdet<2>(const double (&M)[2][2], double (&G)[2][2]) {
+  const double det = diff_of_products(M[0][0], M[1][1], M[0][1], M[1][0]);
+  const double id = 1.0 / det;
+  G[0][0] = M[1][1] * id;
+  G[0][1] = -M[0][1] * id;
+  G[1][0] = -M[1][0] * id;
+  G[1][1] = M[0][0] * id;
+  return log(fabs(det));
+}
+template <>
+SPG_DEV double inv_logdet<3>(const double (&M)[3][3], double (&G)[3][3]) {
+  // cofactor C[i][j]; the inverse is C^T / det
+  const double c00 = diff_of_products(M[1][1], M[2][2], M[1][2], M[2][1]);
+  const double c01 = diff_of_products(M[1][2], M[2][0], M[1][0], M[2][2]);
+  const double c02 = diff_of_products(M[1][0], M[2][1], M[1][1], M[2][0]);
+  const double c10 = diff_of_products(M[0][2], M[2][1], M[0][1], M[2][2]);
+  const double c11 = diff_of_products(M[0][0], M[2][2], M[0][2], M[2][0]);
+  const double c12 = diff_of_products(M[0][1], M[2][0], M[0][0], M[2][1]);
+  const double c20 = diff_of_products(M[0][1], M[1][2], M[0][2], M[1][1]);
+  const double c21 = diff_of_products(M[0][2], M[1][0], M[0][0], M[1][2]);
+  const double c22 = diff_of_products(M[0][0], M[1][1], M[0][1], M[1][0]);
+  const double det = fma(M[0][0], c00, fma(M[0][1], c01, M[0][2] * c02));
+  const double id = 1.0 / det;
+  G[0][0] = c00 * id;
+  G[0][1] = c10 * id;
+  G[0][2] = c20 * id;
+  G[1][0] = c01 * id;
+  G[1][1] = c11 * id;
+  G[1][2] = c21 * id;
+  G[2][0] = c02 * id;
+  G[2][1] = c12 * id;
+  G[2][2] = c22 * id;
+  return log(fabs(det));
+}
+
 // ------------------------------------------------------------------ state-space models
 // Per-series constants.  Matern-nu (nu = 3/2 -> b = 2, nu = 5/2 -> b = 3), observation
 // vector h = e_0.  With lam = sqrt(2 nu) / l and x = lam dt, the transition

@@ -25,7 +25,6 @@ struct LaunchCtx {
   double* top;                   // top-level tree, leading dimension top_ld
   int64_t top_ld;
   unsigned int* top_cnt;
-  unsigned int* done;
   double* scal;
   double* part;
   int64_t part_ld;

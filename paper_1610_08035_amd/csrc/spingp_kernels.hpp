@@ -127,6 +127,38 @@ SPG_DEV bool edge_at(const Lane<B>& ln, const double* __restrict__ t, int64_t n,
   return false;
 }
 
+// A chunk's times (and the next node's) and observations, loaded together at the start so that
+// a lane waits on memory once, not once per node.  Indices are clamped into [0, n_pts); entries
+// past the chunk are never used.
+template <int R>
+struct ChunkData {
+  double t[R + 1];
+  double y[R];
+};
+template <int B, int R>
+SPG_DEV void load_chunk(const Lane<B>& ln, const double* __restrict__ t, const double* __restrict__ y, int64_t n_pts,
+                        ChunkData<R>& cd) {
+  SPG_UNROLL for (int k = 0; k <= R; ++k) {
+    int64_t n = ln.start + k;
+    if (n > n_pts - 1) n = n_pts - 1;
+    cd.t[k] = t[n];
+    if (k < R) cd.y[k] = y[n];
+  }
+}
+// edge_at for node start + k from the loaded times
+template <int B, int R>
+SPG_DEV bool edge_k(const Lane<B>& ln, const ChunkData<R>& cd, int k, double& dt, double& e, double (&A)[B][B]) {
+  if (ln.start + k + 1 < ln.s_end) {
+    dt = cd.t[k + 1] - cd.t[k];
+    Matern<B>::transition(ln.p, dt, e, A);
+    return true;
+  }
+  dt = 0.0;
+  e = 0.0;
+  mat_zero<B>(A);
+  return false;
+}
+
 // Q - P0 after the non-model edge leaving a series: P0(next) - P0, or -P0 after the last series.
 template <int B>
 SPG_DEV void end_edge_D(const Lane<B>& ln, const double (&P0)[B][B], double (&D)[B][B]) {
@@ -143,15 +175,14 @@ SPG_DEV void end_edge_D(const Lane<B>& ln, const double (&P0)[B][B], double (&D)
 // Q of the running element is carried as D = Q - P0 so that Q_n = P0 - A_n P0 A_n^T is never
 // formed: Q_new = A (Q - q q^T/s) A^T + Q_n  <=>  D_new = A (D - q q^T/s) A^T.
 template <int B, int R>
-SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const double* __restrict__ t,
-                        const double* __restrict__ y, Elem<B>& E) {
+SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const ChunkData<R>& cd, Elem<B>& E) {
   const SeriesPar& p = ln.p;
   const double is2 = 1.0 / p.s2;
   double D[B][B];
   {
     // first node: element (A_s, 0, Q_s, J, eta_s) with the node's constants
     double dt, e, A[B][B];
-    const bool ok = edge_at<B>(ln, t, ln.start, dt, e, A);
+    const bool ok = edge_k<B, R>(ln, cd, 0, dt, e, A);
     mat_copy<B>(A, E.A);
     if (ok) {
       double T[B][B];
@@ -161,7 +192,7 @@ SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const doubl
     } else {
       end_edge_D<B>(ln, P0, D);
     }
-    const double y0 = y[ln.start];
+    const double y0 = cd.y[0];
     mat_zero<B>(E.J);
     E.J[0][0] = is2;
     SPG_UNROLL for (int i = 0; i < B; ++i) {
@@ -174,8 +205,7 @@ SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const doubl
   }
   SPG_UNROLL for (int k = 1; k < R; ++k) {
     if (k < ln.len) {
-      const int64_t n = ln.start + k;
-      const double yn = y[n];
+      const double yn = cd.y[k];
       double q[B];
       SPG_UNROLL for (int i = 0; i < B; ++i) q[i] = D[i][0] + P0[i][0];
       const double s = q[0] + p.s2;
@@ -200,7 +230,7 @@ SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const doubl
       E.cl += -0.5 * (kLog2Pi + log(s));
       E.cf += -0.5 * v * vis;
       double dt, e, A[B][B];
-      const bool ok = edge_at<B>(ln, t, n, dt, e, A);
+      const bool ok = edge_k<B, R>(ln, cd, k, dt, e, A);
       if (ok) {
         double T[B][B];
         mm<B>(A, Ap, E.A);
@@ -334,8 +364,13 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
   double P0[B][B];
   Matern<B>::pinf(ln.p, P0);
   Elem<B> E;
-  if (ln.len > 0) fold_chunk<B, R>(ln, P0, t, y, E);
-  else elem_identity<B>(E);
+  if (ln.len > 0) {
+    ChunkData<R> cd;
+    load_chunk<B, R>(ln, t, y, n_pts, cd);
+    fold_chunk<B, R>(ln, P0, cd, E);
+  } else {
+    elem_identity<B>(E);
+  }
   elem_store<B>(tree_elems, tree_ld, gbase + tid, E);
   lds_store<B, L>(pool, tid, E);
   __syncthreads();
@@ -444,10 +479,6 @@ struct BwdOut {
   double* part;     // one series: [3][G] work-group gradient partials; several series: [5][slots]
                     // per-chunk (sum v^2/s, sum log s, d/dlengthscale, d/dvariance, d/dnoise)
   int64_t part_ld;
-  unsigned int* done;        // one series: finished work-groups (the last sums the partials)
-  const double* scal;        // one series: log-likelihood scalars of the forward pass
-  double* logml;             // one series: [1] or null
-  double* grad;              // one series: [3] or null
 };
 
 template <int B, int R, int L, int MODE, bool BATCHED>
@@ -560,6 +591,8 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
   // ---- chunk elimination (natural order) from the exact predicted state at its first node
   const int64_t start = ln.start;
   const int len = ln.len;
+  ChunkData<R> cd;
+  load_chunk<B, R>(ln, t, y, n_pts, cd);
   double sm_[R][B];       // predicted means
   double sD[R][B][B];     // predicted covariances minus P0
   double m[B], D[B][B];
@@ -579,7 +612,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
       double u[B];
       SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = D[i][0] + P0[i][0];
       const double s = u[0] + p.s2, is = 1.0 / s;
-      const double v = y[n] - m[0];
+      const double v = cd.y[k] - m[0];
       if (kLl) {
         fit_chunk = fma(v * v, is, fit_chunk);
         ldet_chunk += log(s);
@@ -590,7 +623,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
         SPG_UNROLL for (int j = 0; j < B; ++j) Dp[i][j] = fma(-u[i] * is, u[j], D[i][j]);
       }
       double A[B][B], dt_, e_;
-      const bool ok = edge_at<B>(ln, t, n, dt_, e_, A);
+      const bool ok = edge_k<B, R>(ln, cd, k, dt_, e_, A);
       if (ok) {
         double T[B][B];
         mv<B>(A, mp, m);
@@ -646,7 +679,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
         double u[B];
         SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = Dk[i][0] + P0[i][0];
         const double s = u[0] + p.s2, is = 1.0 / s;
-        const double v = y[n] - mk[0];
+        const double v = cd.y[k] - mk[0];
         double mp[B], Dp[B][B];
         SPG_UNROLL for (int i = 0; i < B; ++i) {
           mp[i] = fma(u[i] * is, v, mk[i]);
@@ -655,7 +688,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
         // prediction adjoint through edge n (nothing flows through the edge leaving a series)
         double mbp[B], Pbp[B][B], Lhp[B][B];
         double A[B][B], dt, e;
-        const bool edge_ok = edge_at<B>(ln, t, n, dt, e, A);   // recomputed: cheaper than keeping it live
+        const bool edge_ok = edge_k<B, R>(ln, cd, k, dt, e, A);   // recomputed: cheaper than keeping it live
         if (edge_ok) {
           mtv<B>(A, lam, mbp);            // A^T lam'
           if (kGrad) {
@@ -783,7 +816,10 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
     }
     if (kGrad) SPG_UNROLL for (int c = 0; c < 3; ++c) out.part[(int64_t)(c + 2) * out.part_ld + chunk] = gr[c];
   } else if (kGrad) {
-    // ---- one series: fixed-order work-group reduction of the gradient partials (reuses the pool)
+    // ---- one series: fixed-order work-group reduction of the gradient partials (reuses the
+    //      pool); k_grad_finish sums the work-group partials in a fixed order.  No cross-work-
+    //      group signalling here: an agent-scope fence per work-group (an L2 write-back on this
+    //      GPU) costs more than the separate launch.
     __syncthreads();
     SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] = gr[c];
     __syncthreads();
@@ -793,37 +829,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
       }
       __syncthreads();
     }
-    // publish this work-group's partial; the last work-group to finish sums all partials in a
-    // fixed order (independent of which one is last) and resets the counter for the next call
-    __shared__ unsigned int ticket;
-    if (tid == 0) {
-      SPG_UNROLL for (int c = 0; c < 3; ++c) out.part[c * out.part_ld + blockIdx.x] = pool[c * L];
-      __threadfence();
-      ticket = atomicAdd(out.done, 1u);
-    }
-    __syncthreads();
-    if (ticket == gridDim.x - 1) {
-      __threadfence();
-      const int64_t G = gridDim.x;
-      double acc[3] = {0.0, 0.0, 0.0};
-      for (int64_t i = tid; i < G; i += L) {
-        SPG_UNROLL for (int c = 0; c < 3; ++c) acc[c] += out.part[c * out.part_ld + i];
-      }
-      __syncthreads();
-      SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] = acc[c];
-      __syncthreads();
-      SPG_UNROLL for (int stride = L / 2; stride > 0; stride /= 2) {
-        if (tid < stride) {
-          SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] += pool[c * L + tid + stride];
-        }
-        __syncthreads();
-      }
-      if (tid == 0) {
-        if (out.grad) SPG_UNROLL for (int c = 0; c < 3; ++c) out.grad[c] = pool[c * L];
-        if (out.logml) out.logml[0] = out.scal[0];
-        *out.done = 0u;
-      }
-    }
+    if (tid == 0) SPG_UNROLL for (int c = 0; c < 3; ++c) out.part[c * out.part_ld + blockIdx.x] = pool[c * L];
   }
 }
 

@@ -1,11 +1,34 @@
-// Kernels of the batched layout that do not depend on the tile shape: the chunk map built at
-// assemble time and the per-series sums of the reverse kernel's partials.  Included by the C-ABI
-// translation unit only.
+// Kernels that do not depend on the tile shape: the chunk map of several series built at
+// assemble time, and the fixed-order sums of the reverse kernel's partials (per series, or over
+// the work-groups of one series).  Included by the C-ABI translation unit only.
 #pragma once
 
 #include "spingp_kernels.hpp"
 
 namespace spg {
+
+// One series: sum of the G work-group gradient partials in a fixed order (lane-strided, then a
+// fixed tree), and the log likelihood from the root of the reduction.
+__global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ part, int64_t part_ld, int64_t G,
+                                                      const double* __restrict__ scal, double* __restrict__ logml,
+                                                      double* __restrict__ grad) {
+  __shared__ double red[3][256];
+  const int tid = threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = tid; i < G; i += 256) {
+    SPG_UNROLL for (int c = 0; c < 3; ++c) acc[c] += part[c * part_ld + i];
+  }
+  SPG_UNROLL for (int c = 0; c < 3; ++c) red[c][tid] = acc[c];
+  __syncthreads();
+  for (int stride = 128; stride > 0; stride /= 2) {
+    if (tid < stride) SPG_UNROLL for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + stride];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (grad) SPG_UNROLL for (int c = 0; c < 3; ++c) grad[c] = red[c][0];
+    if (logml) logml[0] = scal[0];
+  }
+}
 
 // Fixed-order per-series sum of the per-chunk partials: one 64-lane work-group per series; lane i
 // adds chunks first + i, first + i + 64, ... in order, then a fixed tree over the lanes.  Writes
