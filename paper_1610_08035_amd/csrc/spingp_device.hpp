@@ -39,6 +39,15 @@ namespace spg {
 
 constexpr double kLog2Pi = 1.8378770664093454836;
 
+// Work-group barrier that orders LDS accesses only: global loads and stores issued before it stay
+// in flight (a plain __syncthreads also waits for every outstanding global access of the
+// thread).  For exchanges through LDS; data passed through global memory needs __syncthreads.
+SPG_DEV void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ------------------------------------------------------------------ small dense algebra
 // All matrices are row-major register arrays with compile-time sizes; every loop unrolls.
 template <int B>

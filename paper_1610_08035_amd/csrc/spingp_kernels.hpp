@@ -373,7 +373,7 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
   }
   elem_store<B>(tree_elems, tree_ld, gbase + tid, E);
   lds_store<B, L>(pool, tid, E);
-  __syncthreads();
+  lds_barrier();
   int off = L;   // slot offset of the level being produced
   SPG_UNROLL for (int stride = 1; stride < L; stride *= 2) {
     const int i = tid * 2 * stride;
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
       elem_store<B>(tree_elems, tree_ld, gbase + off + tid, Rr);
     }
     off += L / (2 * stride);
-    __syncthreads();
+    lds_barrier();
   }
   // this work-group's aggregate is leaf blockIdx.x of the top-level tree
   if (tid == 0) {
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyp
       }
       lds_store<B, 32>(pool, tid, Eg);
     }
-    __syncthreads();
+    lds_barrier();
     SPG_UNROLL for (int k = 0; k < 5; ++k) {
       const int stride = 1 << k;
       const int i = tid * 2 * stride;
@@ -444,7 +444,7 @@ __global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyp
         lds_store<B, 32>(pool, i, Rr);
         elem_store<B>(top.elems, top.ld, top_level_off(top, lev0 + k + 1) + (glo >> (k + 1)) + tid, Rr);
       }
-      __syncthreads();
+      lds_barrier();
     }
     if (band > 0 && tid == 0) top.cnt[top.cnt_off[band] + group] = 0u;   // ready for the next call
     group = group >> 5;
@@ -515,7 +515,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
       elem_load<B>(top.elems, top.ld, top_level_off(top, tid) + ((wg >> tid) ^ 1), E);
       lds_store<B, 32>(pool, tid, E);
     }
-    __syncthreads();
+    lds_barrier();
     // message entering this work-group, walked down the top-level tree: the prefix part
     // (predicted state from the first prior) on wave 0, the suffix part (information from the
     // end) on wave 1, one combine per level
@@ -550,11 +550,11 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
         }
       }
     }
-    __syncthreads();
+    lds_barrier();
     int off = 2 * L - 2;   // root slot: the message entering this work-group
     if (tid == 0) lds_store_prefix<B, NS>(pool, off, m_, P_);
     if (tid == L / 2) lds_store_suffix<B, NS>(pool, off, J_, e_);
-    __syncthreads();
+    lds_barrier();
     // ---- work-group down-sweep: thread i < cnt carries the prefix of parent i into its right
     //      child, thread L/2 + i (another wavefront) the suffix of parent i into its left child;
     //      the children's elements come from the tree the forward kernel stored
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
           lds_store_suffix<B, NS>(pool, noff + 2 * i, Jo, eo);
         }
       }
-      __syncthreads();
+      lds_barrier();
       off = noff;
     }
   }
@@ -820,14 +820,14 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
     //      pool); k_grad_finish sums the work-group partials in a fixed order.  No cross-work-
     //      group signalling here: an agent-scope fence per work-group (an L2 write-back on this
     //      GPU) costs more than the separate launch.
-    __syncthreads();
+    lds_barrier();
     SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] = gr[c];
-    __syncthreads();
+    lds_barrier();
     SPG_UNROLL for (int stride = L / 2; stride > 0; stride /= 2) {
       if (tid < stride) {
         SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] += pool[c * L + tid + stride];
       }
-      __syncthreads();
+      lds_barrier();
     }
     if (tid == 0) SPG_UNROLL for (int c = 0; c < 3; ++c) out.part[c * out.part_ld + blockIdx.x] = pool[c * L];
   }

@@ -31,7 +31,7 @@ namespace wide {
 
 constexpr int kW = 64;  // lanes per team (one wavefront, one work-group)
 
-SPG_DEV void tsync() { __syncthreads(); }
+SPG_DEV void tsync() { lds_barrier(); }   // teams exchange data through LDS only
 
 // ---------------------------------------------------------------------------- layouts
 template <int B>
