@@ -679,7 +679,9 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
         double u[B];
         SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = Dk[i][0] + P0[i][0];
         const double s = u[0] + p.s2, is = 1.0 / s;
-        const double v = cd.y[k] - mk[0];
+        // t and y re-read here (cache-resident) rather than kept live across the sweep: the
+        // registers are worth more than the loads
+        const double v = y[n] - mk[0];
         double mp[B], Dp[B][B];
         SPG_UNROLL for (int i = 0; i < B; ++i) {
           mp[i] = fma(u[i] * is, v, mk[i]);
@@ -688,7 +690,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
         // prediction adjoint through edge n (nothing flows through the edge leaving a series)
         double mbp[B], Pbp[B][B], Lhp[B][B];
         double A[B][B], dt, e;
-        const bool edge_ok = edge_k<B, R>(ln, cd, k, dt, e, A);   // recomputed: cheaper than keeping it live
+        const bool edge_ok = edge_at<B>(ln, t, n, dt, e, A);   // recomputed: cheaper than keeping it live
         if (edge_ok) {
           mtv<B>(A, lam, mbp);            // A^T lam'
           if (kGrad) {
