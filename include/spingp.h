@@ -166,6 +166,22 @@ int spingp_set_tile(spingp_handle h, int32_t index);
 int spingp_tune(spingp_handle h, int32_t reps);
 
 /*
+ * Diagnostics (not part of the hot path, which never forms these blocks): the edge blocks and
+ * the multiplied-out blocks of the posterior precision of every series (Theorem 1, Sec. 2.2):
+ *   A: NULL or [b*b x n_points], entry n = A_n = expm(F (t_{n+1} - t_n)) (row-major; zero at
+ *      the last node of a series);
+ *   Q: NULL or [b(b+1)/2 x n_points] packed upper, Q_n = P0 - A_n P0 A_n^T (zero there too);
+ *   D: NULL or [b(b+1)/2 x n_points] packed upper, diagonal block D_n = J + (P0^-1 at a
+ *      series' first node, else Q_{n-1}^-1) + A_n^T Q_n^-1 A_n (the last term absent at its
+ *      last node), J = h h^T / s2;
+ *   Bsub: NULL or [b*b x n_points], entry n = the block (n+1, n) = -Q_n^-1 A_n.
+ * D and Bsub need Q_n^-1 and lose accuracy as Q_n approaches singularity (near-duplicate
+ * times); Q_n = 0 (duplicate times) gives non-finite values.  Needs assemble.  Matern models
+ * only (SPINGP_E_UNSUPPORTED for the sum kernel).
+ */
+int spingp_blocks(spingp_handle h, double* A, double* Q, double* D, double* Bsub);
+
+/*
  * Synchronise the handle's stream and report the first device-detected data error since the
  * last assemble: returns SPINGP_OK or the error code; *first_bad (host, may be NULL) receives
  * the offending point index (or -1 for a hyperparameter error / no error).

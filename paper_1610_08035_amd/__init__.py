@@ -12,6 +12,7 @@ from .spingp import (  # noqa: F401
     SpinGPError,
     load_library,
     spingp_assemble,
+    spingp_blocks,
     spingp_create,
     spingp_destroy,
     spingp_factor,

@@ -697,6 +697,14 @@ extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
   return rc;
 }
 
+extern "C" int spingp_blocks(spingp_handle h, double* A, double* Q, double* D, double* Bsub) {
+  if (!h) return SPINGP_E_INVALID;
+  if (!h->assembled) return SPINGP_E_ORDER;
+  if (h->wide) return SPINGP_E_UNSUPPORTED;
+  if (!A && !Q && !D && !Bsub) return SPINGP_OK;
+  return hip_ok(ops(h)->blocks(launch_ctx(h), A, Q, D, Bsub));
+}
+
 extern "C" int spingp_status(spingp_handle h, int64_t* first_bad) {
   if (!h) return SPINGP_E_INVALID;
   if (first_bad) *first_bad = -1;

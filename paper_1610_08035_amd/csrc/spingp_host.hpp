@@ -51,6 +51,8 @@ struct TileOps {
   hipError_t (*factor)(const LaunchCtx& c);
   // reverse sweep with the given output selection (kWant* bits)
   hipError_t (*bwd)(const LaunchCtx& c, int mode, const BwdOut& o);
+  // materialised edge and precision blocks (diagnostics)
+  hipError_t (*blocks)(const LaunchCtx& c, double* A, double* Q, double* D, double* Bsub);
 };
 
 // Sizes of the top-level tree over G leaves: slots (2 * 32^bands) and arrival counters.

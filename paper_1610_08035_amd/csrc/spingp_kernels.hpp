@@ -835,6 +835,81 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
   }
 }
 
+// ---------------------------------------------------------------------------- diagnostics
+// Materialised blocks (not used by the hot path, which never forms them).  Per node n of a
+// series [s, e):  A_n = expm(F dt_n) and Q_n = P0 - A_n P0 A_n^T for the edge n -> n+1 (zero at
+// the series' last node), and the multiplied-out blocks of the posterior precision (Theorem 1)
+//   D_n = J + [n = s] P0^-1 + [n > s] Q_{n-1}^-1 + [n < e-1] A_n^T Q_n^-1 A_n,
+//   B_n = K_{n+1,n} = -Q_n^-1 A_n            (zero at the series' last node).
+// They need Q^-1, so they are only meaningful where every Q_n is well conditioned (no
+// duplicate or near-duplicate times).  One lane per chunk, its R nodes in turn.  Layout: A and
+// B_n row-major [B*B][ld], Q and D packed upper [B(B+1)/2][ld]; any output may be null.
+template <int B, int R, bool BATCHED>
+__global__ __launch_bounds__(128) void k_blocks(const double* __restrict__ t, int64_t n_pts,
+                                                const double* __restrict__ hyper, SeriesMap sm, int64_t slots,
+                                                double* __restrict__ Ao, double* __restrict__ Qo,
+                                                double* __restrict__ Do, double* __restrict__ Bo, int64_t ld) {
+  const int64_t chunk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (chunk >= slots) return;
+  const Lane<B> ln = lane_of<B, R, BATCHED>(chunk, n_pts, hyper, sm);
+  if (ln.len == 0) return;
+  double P0[B][B], Pi[B][B];
+  Matern<B>::pinf(ln.p, P0);
+  (void)inv_logdet<B>(P0, Pi);
+  const double is2 = 1.0 / ln.p.s2;
+  // Q^-1 of the edge entering the chunk's first node (if it is not the series' first node)
+  double Qprev_i[B][B];
+  mat_zero<B>(Qprev_i);
+  if (ln.start > ln.s_begin) {
+    double dt, e, A[B][B], T[B][B], Q[B][B];
+    dt = t[ln.start] - t[ln.start - 1];
+    Matern<B>::transition(ln.p, dt, e, A);
+    mm<B>(A, P0, T);
+    mmt_sym<B>(T, A, Q);
+    SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Q[i][j] = P0[i][j] - Q[i][j];
+    (void)inv_logdet<B>(Q, Qprev_i);
+  }
+  SPG_UNROLL for (int k = 0; k < R; ++k) {
+    if (k < ln.len) {
+      const int64_t n = ln.start + k;
+      double A[B][B], Q[B][B], Qi[B][B], D[B][B], Bn[B][B];
+      double dt, e;
+      const bool edge = edge_at<B>(ln, t, n, dt, e, A);
+      if (edge) {
+        double T[B][B];
+        mm<B>(A, P0, T);
+        mmt_sym<B>(T, A, Q);
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Q[i][j] = P0[i][j] - Q[i][j];
+        (void)inv_logdet<B>(Q, Qi);
+        symmetrize<B>(Qi);
+        mm<B>(Qi, A, T);
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Bn[i][j] = -T[i][j];
+        mtm_sym<B>(A, T, D);                  // A^T Q^-1 A
+      } else {
+        mat_zero<B>(Q);
+        mat_zero<B>(Qi);
+        mat_zero<B>(Bn);
+        mat_zero<B>(D);
+      }
+      const bool first = n == ln.s_begin;
+      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
+        D[i][j] += first ? Pi[i][j] : Qprev_i[i][j];
+      D[0][0] += is2;
+      int pk = 0;
+      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j) {
+        if (Qo) Qo[(int64_t)pk * ld + n] = Q[i][j];
+        if (Do) Do[(int64_t)pk * ld + n] = 0.5 * (D[i][j] + D[j][i]);
+        ++pk;
+      }
+      SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) {
+        if (Ao) Ao[(int64_t)(i * B + j) * ld + n] = A[i][j];
+        if (Bo) Bo[(int64_t)(i * B + j) * ld + n] = Bn[i][j];
+      }
+      mat_copy<B>(Qi, Qprev_i);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------- several series
 // Device-side validation of several series, one thread per chunk slot: finite t and y, t
 // non-decreasing inside each series.  key = (index << 4) | code, minimised over offending points.

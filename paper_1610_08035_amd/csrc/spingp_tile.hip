@@ -89,7 +89,21 @@ hipError_t bwd(const LaunchCtx& c, int mode, const BwdOut& o) {
   }
 }
 
-const TileOps kOps = {R, L, groups, map, factor, bwd};
+template <int B, bool BATCHED>
+hipError_t blocks_b(const LaunchCtx& c, double* A, double* Q, double* D, double* Bs) {
+  const int64_t slots = groups(c.n_points, c.n_series, BATCHED) * L;
+  constexpr int T = 128;
+  hipLaunchKernelGGL((k_blocks<B, R, BATCHED>), dim3((unsigned)((slots + T - 1) / T)), dim3(T), 0, c.stream, c.t,
+                     c.n_points, c.hyper, make_map(c, slots), slots, A, Q, D, Bs, c.n_points);
+  return hipGetLastError();
+}
+
+hipError_t blocks(const LaunchCtx& c, double* A, double* Q, double* D, double* Bs) {
+  if (c.b == 2) return c.batched ? blocks_b<2, true>(c, A, Q, D, Bs) : blocks_b<2, false>(c, A, Q, D, Bs);
+  return c.batched ? blocks_b<3, true>(c, A, Q, D, Bs) : blocks_b<3, false>(c, A, Q, D, Bs);
+}
+
+const TileOps kOps = {R, L, groups, map, factor, bwd, blocks};
 
 }  // namespace
 

@@ -71,10 +71,11 @@ def load_library():
     lib.spingp_get_tile.argtypes = [vp, ctypes.POINTER(i32)]
     lib.spingp_set_tile.argtypes = [vp, i32]
     lib.spingp_tune.argtypes = [vp, i32]
+    lib.spingp_blocks.argtypes = [vp, vp, vp, vp, vp]
     for name in ("spingp_create", "spingp_destroy", "spingp_state_dim", "spingp_n_hyper", "spingp_assemble",
                  "spingp_factor", "spingp_logml", "spingp_solve", "spingp_selinv", "spingp_logml_grad",
                  "spingp_status", "spingp_profile", "spingp_profile_read", "spingp_tile_count",
-                 "spingp_tile_shape", "spingp_get_tile", "spingp_set_tile", "spingp_tune"):
+                 "spingp_tile_shape", "spingp_get_tile", "spingp_set_tile", "spingp_tune", "spingp_blocks"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -156,6 +157,11 @@ def spingp_selinv(h, f_var=None, S_diag=None, S_sub=None):
 
 def spingp_logml_grad(h, logml, grad):
     _check(load_library().spingp_logml_grad(h, _dev(logml, "logml"), _dev(grad, "grad")), "spingp_logml_grad")
+
+
+def spingp_blocks(h, A=None, Q=None, D=None, Bsub=None):
+    _check(load_library().spingp_blocks(h, _dev(A, "A"), _dev(Q, "Q"), _dev(D, "D"), _dev(Bsub, "Bsub")),
+           "spingp_blocks")
 
 
 def spingp_status(h):
@@ -296,3 +302,14 @@ class Handle:
 
     def workspace_bytes(self):
         return spingp_workspace_bytes(self._h)
+
+    def blocks(self):
+        """Materialised (A, Q, D, Bsub) SoA blocks (see spingp_blocks)."""
+        dev = self._keep[0].device
+        b, n = self.b, self.n
+        A = torch.zeros(b * b, n, dtype=torch.float64, device=dev)
+        Q = torch.zeros(b * (b + 1) // 2, n, dtype=torch.float64, device=dev)
+        D = torch.zeros_like(Q)
+        Bs = torch.zeros_like(A)
+        spingp_blocks(self._h, A, Q, D, Bs)
+        return A, Q, D, Bs
