@@ -48,6 +48,21 @@ def gp_dense(model: SumModel, t, y, want_grad: bool = True) -> dict:
     return out
 
 
+def gp_predict_dense(model: SumModel, t, y, t_star) -> dict:
+    """Latent predictive mean and variance at new times t* (eq. mean4-mean6, eq. k3 at t*):
+    m* = K(t*, t) K_y^-1 y,   v* = k(0) - diag(K(t*, t) K_y^-1 K(t, t*))."""
+    t = np.asarray(t, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    ts = np.asarray(t_star, dtype=np.float64)
+    n = t.shape[0]
+    Ky = model.kernel(t[:, None] - t[None, :]) + model.noise * np.eye(n)
+    Ks = model.kernel(ts[:, None] - t[None, :])
+    L = scipy.linalg.cholesky(Ky, lower=True)
+    alpha = scipy.linalg.cho_solve((L, True), y)
+    V = scipy.linalg.solve_triangular(L, Ks.T, lower=True)
+    return {"f_mean": Ks @ alpha, "f_var": model.kernel(np.zeros(1))[0] - np.sum(V * V, axis=0)}
+
+
 def stacked_prior_cov(model: SumModel, t) -> np.ndarray:
     """Prior covariance of the stacked states [z_0; ...; z_{N-1}] (N b x N b)."""
     t = np.asarray(t, dtype=np.float64)

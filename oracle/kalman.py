@@ -44,6 +44,11 @@ def kf_rts(model: SumModel, t, y) -> dict:
             P = A[i - 1] @ P @ A[i - 1].T + model.Q(t[i] - t[i - 1])
             P = 0.5 * (P + P.T)
         mp_[i], Pp[i] = m, P
+        if np.isnan(y[i]):
+            # no observation at this time (a prediction point): the filtered state is the
+            # predicted one and the point adds nothing to the likelihood
+            mf[i], Pf[i] = m, P
+            continue
         u = P @ h
         s = float(h @ u) + s2
         v = y[i] - float(h @ m)
@@ -65,8 +70,9 @@ def kf_rts(model: SumModel, t, y) -> dict:
         Si = Pf[i] + G @ (S[i + 1] - Pp[i + 1]) @ G.T
         S[i] = 0.5 * (Si + Si.T)
         Ssub[i] = S[i + 1] @ G.T
+    n_obs = int(np.count_nonzero(~np.isnan(y)))
     return {
-        "logml": -0.5 * datafit - 0.5 * logdet - 0.5 * n * np.log(2.0 * np.pi),
+        "logml": -0.5 * datafit - 0.5 * logdet - 0.5 * n_obs * np.log(2.0 * np.pi),
         "datafit": datafit, "logdet": logdet,
         "m_pred": mp_, "P_pred": Pp, "m_filt": mf, "P_filt": Pf,
         "z_mean": mu, "S_diag": S, "S_sub": Ssub,
