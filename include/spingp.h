@@ -166,6 +166,21 @@ int spingp_set_tile(spingp_handle h, int32_t index);
 int spingp_tune(spingp_handle h, int32_t reps);
 
 /*
+ * Prediction at new times (eq. mean4-mean6 and the variance of eq. k3 at t*): the latent
+ * predictive mean f_mean[j] = E[f(t*_j) | y] and variance f_var[j] = Var[f(t*_j) | y] (no noise
+ * term) of a one-series handle.  t_star: [n_star] device array, finite and non-decreasing
+ * (violations are reported by spingp_status with the index in t_star; results are then
+ * unspecified); f_mean, f_var: NULL or [n_star].  The prediction times are merged into the
+ * chain as nodes without an observation and the whole reduction runs on the merged chain, so
+ * n_points + n_star must not exceed the handle's max_points (SPINGP_E_INVALID).  Uses the
+ * hyperparameters in device memory at the time of the call.  Overwrites the handle's
+ * factorisation: call spingp_factor again before spingp_logml, spingp_solve or spingp_selinv
+ * (spingp_logml_grad refactors by itself).  Needs assemble.  Several series:
+ * SPINGP_E_UNSUPPORTED.
+ */
+int spingp_predict(spingp_handle h, const double* t_star, int64_t n_star, double* f_mean, double* f_var);
+
+/*
  * Diagnostics (not part of the hot path, which never forms these blocks): the edge blocks and
  * the multiplied-out blocks of the posterior precision of every series (Theorem 1, Sec. 2.2):
  *   A: NULL or [b*b x n_points], entry n = A_n = expm(F (t_{n+1} - t_n)) (row-major; zero at

@@ -19,6 +19,7 @@ from .spingp import (  # noqa: F401
     spingp_get_tile,
     spingp_logml,
     spingp_logml_grad,
+    spingp_predict,
     spingp_selinv,
     spingp_set_tile,
     spingp_solve,

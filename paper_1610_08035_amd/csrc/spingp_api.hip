@@ -91,6 +91,7 @@ struct spingp_ctx {
   int64_t* chunk_first = nullptr;  // several series: first chunk of every series
   unsigned long long* key = nullptr;
   double* tune_out = nullptr;      // logML and gradient written while tuning
+  double* pred = nullptr;          // one series: merged times, observations, mean, variance
   int64_t lane_ld = 0;
   // tile shape
   int tile = 0;
@@ -230,6 +231,7 @@ static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_serie
       {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride()},
       {(void**)&h->scal, (int64_t)sizeof(double) * 8},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
+      {(void**)&h->pred, (int64_t)sizeof(double) * 4 * max_points},
   };
   bool ok = true;
   for (auto& r : reqs) {
@@ -304,6 +306,7 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
       {(void**)&h->part, (int64_t)sizeof(double) * part_n},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
       {(void**)&h->tune_out, (int64_t)sizeof(double) * 4 * max_series},
+      {(void**)&h->pred, multi ? 0 : (int64_t)sizeof(double) * 4 * max_points},
       {(void**)&h->chunk_series, multi ? (int64_t)sizeof(int32_t) * slots_max : 0},
       {(void**)&h->chunk_first, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
   };
@@ -369,6 +372,7 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)hipFree(h->part);
   (void)hipFree(h->key);
   (void)hipFree(h->tune_out);
+  (void)hipFree(h->pred);
   (void)hipFree(h->chunk_series);
   (void)hipFree(h->chunk_first);
   (void)hipFree(h->wplan.elems);
@@ -695,6 +699,56 @@ extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
   }
   h->factored = rc == SPINGP_OK;
   return rc;
+}
+
+extern "C" int spingp_predict(spingp_handle h, const double* t_star, int64_t n_star, double* f_mean,
+                              double* f_var) {
+  if (!h || !t_star || n_star < 1) return SPINGP_E_INVALID;
+  if (!h->assembled) return SPINGP_E_ORDER;
+  if (h->batched || !h->pred) return SPINGP_E_UNSUPPORTED;
+  if (h->n_points + n_star > h->max_points) return SPINGP_E_INVALID;
+  if (!f_mean && !f_var) return SPINGP_OK;
+  const int64_t n = h->n_points, m = n_star, nm = n + m;
+  double* tm = h->pred;
+  double* ym = tm + h->max_points;
+  double* fm = ym + h->max_points;
+  double* fv = fm + h->max_points;
+  drop_graph(h);                     // the shared workspace is about to hold the merged problem
+  h->factored = false;
+  h->wide_down = false;
+  hipLaunchKernelGGL(spg::k_validate_star, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, t_star, m,
+                     h->key);
+  hipLaunchKernelGGL(spg::k_merge, dim3((unsigned)ceil_div(nm, kT)), dim3(kT), 0, h->stream, h->t, h->y, n, t_star,
+                     m, tm, ym);
+  int rc;
+  if (h->wide) {
+    spg::wide::WideCtx c = wide_ctx(h);
+    memset(&c.n, 0, sizeof(c.n));
+    spg::wide::plan_levels(nm, c);
+    c.t = tm;
+    c.y = ym;
+    c.n_points = nm;
+    rc = hip_ok(spg::wide::factor(c));
+    if (!rc) rc = hip_ok(spg::wide::down(c));
+    if (!rc) rc = hip_ok(spg::wide::node(c, spg::kWantVar, fm, fv, nullptr, nullptr, nullptr));
+  } else {
+    spg::LaunchCtx c = launch_ctx(h);
+    c.t = tm;
+    c.y = ym;
+    c.n_points = nm;
+    rc = hip_ok(ops(h)->factor(c));
+    if (!rc) {
+      spg::BwdOut o = make_out(h);
+      o.ld = nm;
+      o.f_mean = fm;
+      o.f_var = fv;
+      rc = hip_ok(ops(h)->bwd(c, spg::kWantVar, o));
+    }
+  }
+  if (rc) return rc;
+  hipLaunchKernelGGL(spg::k_gather, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, h->t, n, t_star, m, fm,
+                     fv, f_mean, f_var);
+  return hip_ok(hipGetLastError());
 }
 
 extern "C" int spingp_blocks(spingp_handle h, double* A, double* Q, double* D, double* Bsub) {

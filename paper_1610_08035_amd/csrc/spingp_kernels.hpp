@@ -192,27 +192,31 @@ SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const Chunk
     } else {
       end_edge_D<B>(ln, P0, D);
     }
+    // a NaN observation marks a node without one (a prediction time merged into the chain):
+    // no information, no likelihood term
     const double y0 = cd.y[0];
+    const bool o0 = y0 == y0;
     mat_zero<B>(E.J);
-    E.J[0][0] = is2;
+    E.J[0][0] = o0 ? is2 : 0.0;
     SPG_UNROLL for (int i = 0; i < B; ++i) {
       E.b[i] = 0.0;
       E.eta[i] = 0.0;
     }
-    E.eta[0] = y0 * is2;
-    E.cf = -0.5 * y0 * y0 * is2;
-    E.cl = -0.5 * (kLog2Pi + log(p.s2));
+    E.eta[0] = o0 ? y0 * is2 : 0.0;
+    E.cf = o0 ? -0.5 * y0 * y0 * is2 : 0.0;
+    E.cl = o0 ? -0.5 * (kLog2Pi + log(p.s2)) : 0.0;
   }
   SPG_UNROLL for (int k = 1; k < R; ++k) {
     if (k < ln.len) {
       const double yn = cd.y[k];
+      const bool obs = yn == yn;
       double q[B];
       SPG_UNROLL for (int i = 0; i < B; ++i) q[i] = D[i][0] + P0[i][0];
       const double s = q[0] + p.s2;
-      const double is = 1.0 / s;
+      const double is = obs ? 1.0 / s : 0.0;        // no observation: zero gain
       double a[B];
       SPG_UNROLL for (int i = 0; i < B; ++i) a[i] = E.A[0][i];
-      const double v = yn - E.b[0];
+      const double v = obs ? yn - E.b[0] : 0.0;
       const double vis = v * is;
       double Ap[B][B], bp[B], Dp[B][B];
       SPG_UNROLL for (int i = 0; i < B; ++i) {
@@ -227,7 +231,7 @@ SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const Chunk
         Dp[i][j] = Dp[j][i];
         E.J[i][j] = E.J[j][i];
       }
-      E.cl += -0.5 * (kLog2Pi + log(s));
+      if (obs) E.cl += -0.5 * (kLog2Pi + log(s));
       E.cf += -0.5 * v * vis;
       double dt, e, A[B][B];
       const bool ok = edge_k<B, R>(ln, cd, k, dt, e, A);
@@ -611,9 +615,11 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
       }
       double u[B];
       SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = D[i][0] + P0[i][0];
-      const double s = u[0] + p.s2, is = 1.0 / s;
-      const double v = cd.y[k] - m[0];
-      if (kLl) {
+      const double yk = cd.y[k];
+      const bool obs = yk == yk;                    // NaN: a node without observation
+      const double s = u[0] + p.s2, is = obs ? 1.0 / s : 0.0;
+      const double v = obs ? yk - m[0] : 0.0;
+      if (kLl && obs) {
         fit_chunk = fma(v * v, is, fit_chunk);
         ldet_chunk += log(s);
       }
@@ -678,10 +684,12 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
         }
         double u[B];
         SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = Dk[i][0] + P0[i][0];
-        const double s = u[0] + p.s2, is = 1.0 / s;
+        const double yk = y[n];
+        const bool obs = yk == yk;
+        const double s = u[0] + p.s2, is = obs ? 1.0 / s : 0.0;
         // t and y re-read here (cache-resident) rather than kept live across the sweep: the
         // registers are worth more than the loads
-        const double v = y[n] - mk[0];
+        const double v = obs ? yk - mk[0] : 0.0;
         double mp[B], Dp[B][B];
         SPG_UNROLL for (int i = 0; i < B; ++i) {
           mp[i] = fma(u[i] * is, v, mk[i]);

@@ -115,4 +115,65 @@ __global__ void k_chunk_map(const int64_t* __restrict__ chunk_first, int32_t n_s
   for (int64_t c = chunk_first[s]; c < c1; ++c) chunk_series[c] = (int32_t)s;
 }
 
+// ---------------------------------------------------------------------------- prediction
+// Prediction times t* are merged into the chain as nodes without an observation (NaN in the
+// merged y).  Order: a training point precedes a prediction time equal to it.  With both
+// arrays sorted the merged positions are a permutation of [0, n + m); with t* unsorted (an
+// error reported through the status word) they stay inside [0, n + m).
+SPG_DEV int64_t count_less(const double* __restrict__ a, int64_t n, double x) {
+  int64_t lo = 0, hi = n;           // first index with a[i] >= x
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+SPG_DEV int64_t count_not_greater(const double* __restrict__ a, int64_t n, double x) {
+  int64_t lo = 0, hi = n;           // first index with a[i] > x
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_merge(const double* __restrict__ t, const double* __restrict__ y, int64_t n,
+                        const double* __restrict__ ts, int64_t m, double* __restrict__ tm,
+                        double* __restrict__ ym) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) {
+    const int64_t pos = idx + count_less(ts, m, t[idx]);
+    tm[pos] = t[idx];
+    ym[pos] = y[idx];
+  } else if (idx < n + m) {
+    const int64_t j = idx - n;
+    const int64_t pos = j + count_not_greater(t, n, ts[j]);
+    tm[pos] = ts[j];
+    ym[pos] = __builtin_nan("");
+  }
+}
+
+// Prediction times must be finite and non-decreasing: key = (index << 4) | code as elsewhere,
+// the index counted in t*.
+__global__ void k_validate_star(const double* __restrict__ ts, int64_t m, unsigned long long* __restrict__ key) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  unsigned long long code = 0;
+  if (!isfinite(ts[j])) code = 4;                       // SPINGP_E_NONFINITE
+  else if (j + 1 < m && ts[j + 1] < ts[j]) code = 3;    // SPINGP_E_UNSORTED
+  if (code) atomicMin(key, ((unsigned long long)(j + 1) << 4) | code);
+}
+
+__global__ void k_gather(const double* __restrict__ t, int64_t n, const double* __restrict__ ts, int64_t m,
+                         const double* __restrict__ fm, const double* __restrict__ fv, double* __restrict__ f_mean,
+                         double* __restrict__ f_var) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int64_t pos = j + count_not_greater(t, n, ts[j]);
+  if (f_mean) f_mean[j] = fm[pos];
+  if (f_var) f_var[j] = fv[pos];
+}
+
 }  // namespace spg

@@ -523,21 +523,23 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
       X[e] = s;
     }
     tsync();
+    // a NaN observation marks a node without one (a prediction time): no information
     const double yn = y[n];
+    const bool obs = yn == yn;
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
       double s = 0.0;
       for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::T_at(j, k), s);
       E[Y::kQ + e] = s;
-      E[Y::kJ + e] = (e == 0) ? 1.0 / s2 : 0.0;
+      E[Y::kJ + e] = (e == 0 && obs) ? 1.0 / s2 : 0.0;
     }
     if (tid < B) {
       E[Y::kb + tid] = 0.0;
-      E[Y::keta + tid] = tid == 0 ? yn / s2 : 0.0;
+      E[Y::keta + tid] = (tid == 0 && obs) ? yn / s2 : 0.0;
     }
     if (tid == 0) {
-      E[Y::kcf] = -0.5 * yn * yn / s2;
-      E[Y::kcl] = -0.5 * (kLog2Pi + log(s2));
+      E[Y::kcf] = obs ? -0.5 * yn * yn / s2 : 0.0;
+      E[Y::kcl] = obs ? -0.5 * (kLog2Pi + log(s2)) : 0.0;
     }
     tsync();
     t_sym<B>(E + Y::kQ);
@@ -680,7 +682,8 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
     const double* A = E + Y::kA;
     // filtered state at n: K = P e0 / s, v = y - m_0
     const double yn = y[n];
-    const double s = P[0] + s2, is = 1.0 / s, v = yn - m[0];
+    const bool obs = yn == yn;                 // NaN: a node without observation (zero gain)
+    const double s = P[0] + s2, is = obs ? 1.0 / s : 0.0, v = obs ? yn - m[0] : 0.0;
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
       Pp[e] = P[e] - P[i * B] * P[j * B] * is;
@@ -787,7 +790,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
     }
     if (kGrad) {
       // noise: E[d/ds2 log N(y; z_0, s2)] = -1/(2 s2) + ((y - mu_0)^2 + S_00) / (2 s2^2)
-      if (tid == 0) {
+      if (tid == 0 && obs) {
         const double r = yn - mu[0];
         acc_s2 += -0.5 / s2 + 0.5 * (r * r + S00) / (s2 * s2);
       }

@@ -72,10 +72,11 @@ def load_library():
     lib.spingp_set_tile.argtypes = [vp, i32]
     lib.spingp_tune.argtypes = [vp, i32]
     lib.spingp_blocks.argtypes = [vp, vp, vp, vp, vp]
+    lib.spingp_predict.argtypes = [vp, vp, i64, vp, vp]
     for name in ("spingp_create", "spingp_destroy", "spingp_state_dim", "spingp_n_hyper", "spingp_assemble",
                  "spingp_factor", "spingp_logml", "spingp_solve", "spingp_selinv", "spingp_logml_grad",
                  "spingp_status", "spingp_profile", "spingp_profile_read", "spingp_tile_count",
-                 "spingp_tile_shape", "spingp_get_tile", "spingp_set_tile", "spingp_tune", "spingp_blocks"):
+                 "spingp_tile_shape", "spingp_get_tile", "spingp_set_tile", "spingp_tune", "spingp_blocks", "spingp_predict"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -157,6 +158,12 @@ def spingp_selinv(h, f_var=None, S_diag=None, S_sub=None):
 
 def spingp_logml_grad(h, logml, grad):
     _check(load_library().spingp_logml_grad(h, _dev(logml, "logml"), _dev(grad, "grad")), "spingp_logml_grad")
+
+
+def spingp_predict(h, t_star, f_mean=None, f_var=None):
+    m = t_star.numel()
+    _check(load_library().spingp_predict(h, _dev(t_star, "t_star"), int(m), _dev(f_mean, "f_mean", m),
+                                         _dev(f_var, "f_var", m)), "spingp_predict")
 
 
 def spingp_blocks(h, A=None, Q=None, D=None, Bsub=None):
@@ -302,6 +309,13 @@ class Handle:
 
     def workspace_bytes(self):
         return spingp_workspace_bytes(self._h)
+
+    def predict(self, t_star):
+        """Latent predictive mean and variance at the (sorted) times t_star."""
+        fm = torch.empty_like(t_star)
+        fv = torch.empty_like(t_star)
+        spingp_predict(self._h, t_star, fm, fv)
+        return fm, fv
 
     def blocks(self):
         """Materialised (A, Q, D, Bsub) SoA blocks (see spingp_blocks)."""
