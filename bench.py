@@ -203,6 +203,36 @@ def sum_report(spg, steps, warmup):
             "phase_ms": {k: round(v, 4) for k, v in phases.items()}}
 
 
+def predict_report(spg, steps, warmup):
+    """Prediction at 2^16 new times (uniform over the data range) from the N = 2^20 Matern-5/2
+    series: latent mean and variance through the merged chain (eager launches)."""
+    import torch
+    from workloads import make_config
+    w = make_config(2)
+    t, y, hyp = w.series(0)
+    dev = torch.device("cuda:0")
+    m = 1 << 16
+    ts = torch.as_tensor(np.sort(np.random.default_rng(7).uniform(t[0], t[-1], m)), device=dev)
+    td, yd, hd = (torch.as_tensor(a, device=dev) for a in (t, y, hyp))
+    h = spg.Handle(w.terms, t.shape[0] + m)
+    h.assemble(td, yd, hd)
+    fm = torch.empty(m, dtype=torch.float64, device=dev)
+    fv = torch.empty_like(fm)
+    for _ in range(warmup):
+        spg.spingp_predict(h._h, ts, fm, fv)
+    torch.cuda.synchronize()
+    if h.status()[0] != 0:
+        raise RuntimeError("prediction workload failed validation")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        spg.spingp_predict(h._h, ts, fm, fv)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    h.close()
+    return {"workload": "matern52_n1048576_predict_65536", "n_train": int(t.shape[0]), "n_star": m,
+            "ms_per_call": 1e3 * el, "merged_points_per_s": (t.shape[0] + m) / el, "steps": steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,9 +242,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-series batched report")
     ap.add_argument("--no-large", action="store_true", help="skip the N = 2^24 report")
     ap.add_argument("--no-sum", action="store_true", help="skip the b = 10 sum-kernel report")
+    ap.add_argument("--no-predict", action="store_true", help="skip the prediction report")
     ap.add_argument("--tile", type=int, default=None,
                     help="headline tile shape index instead of the autotuner's choice (counter runs)")
-    ap.add_argument("--only", choices=["batched", "large", "sum"], default=None,
+    ap.add_argument("--only", choices=["batched", "large", "sum", "predict"], default=None,
                     help="run one secondary workload alone and print its JSON (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM counters)")
@@ -238,7 +269,8 @@ def main():
     from paper_1610_08035_amd.spingp import spingp_profile, spingp_profile_read
     from workloads import make_config
     if args.only:
-        fn = {"batched": batched_report, "large": large_report, "sum": sum_report}[args.only]
+        fn = {"batched": batched_report, "large": large_report, "sum": sum_report,
+              "predict": predict_report}[args.only]
         print(json.dumps({args.only: fn(spg, args.steps, args.warmup)}), flush=True)
         return
 
@@ -328,6 +360,8 @@ def main():
         out["large"] = large_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_sum:
         out["sum_kernel"] = sum_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
+    if not args.no_predict:
+        out["predict"] = predict_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
