@@ -220,3 +220,19 @@ def test_batched_host_errors(lib):
     with pytest.raises(lib.SpinGPError):   # several series need offsets
         lib.spingp_assemble(h._h, to_dev(w.t), to_dev(w.y), to_dev(w.hyper.reshape(-1)), None, 4)
     h.close()
+
+
+def test_autograd_batched(lib):
+    """The autograd function over a batch: per-series logML, gradient of a weighted sum."""
+    from paper_1610_08035_amd.autograd import logml
+    w = make_config(4, n_series=10, max_len=600)
+    hy = to_dev(w.hyper).requires_grad_(True)
+    ll = logml(to_dev(w.t), to_dev(w.y), hy, w.terms, to_dev(w.offsets, torch.int64))
+    wts = torch.arange(1, 11, dtype=torch.float64, device="cuda:0")
+    (wts * ll).sum().backward()
+    g = hy.grad.cpu().numpy()
+    for s in range(w.n_series):
+        t, y, hyp = w.series(s)
+        r = native.tangent_grad(w.terms, hyp, t, y)
+        check_logml(ll[s].item(), r["logml"])
+        check_grad(g[s] / (s + 1), r["grad"])

@@ -128,3 +128,15 @@ def test_sum_kernel_host_errors(lib):
     h.assemble(to_dev(w.t), to_dev(w.y), to_dev(hy))
     assert h.status()[0] == 5
     h.close()
+
+
+def test_sum_kernel_autograd(lib):
+    from paper_1610_08035_amd.autograd import logml
+    w = make_config(3, n=5000)
+    t, y, hyp = w.series(0)
+    hy = to_dev(hyp).requires_grad_(True)
+    ll = logml(to_dev(t), to_dev(y), hy, w.terms)
+    ll.sum().backward()
+    r = native.tangent_grad(w.terms, hyp, t, y)
+    assert abs(ll.item() - r["logml"]) <= 1e-8 * abs(r["logml"])
+    check_grad(hy.grad.cpu().numpy(), r["grad"])
