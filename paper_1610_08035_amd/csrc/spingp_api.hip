@@ -57,16 +57,15 @@ __global__ void k_copy_scalars(const double* __restrict__ scal, int64_t n_pts, d
 
 namespace spg {
 const TileOps* tile_ops_R8_L128();
-const TileOps* tile_ops_R4_L128();
 const TileOps* tile_ops_R8_L64();
-const TileOps* tile_ops_R4_L64();
-// The first entry is the default shape.
+const TileOps* tile_ops_R8_L256();
+// The first entry is the default shape.  All keep R = 8 (two tree elements per 8 points): a
+// smaller R doubles the stored trees and was never the fastest.
 const TileOps* tile_ops(int i) {
   switch (i) {
     case 0: return tile_ops_R8_L128();
-    case 1: return tile_ops_R4_L128();
-    case 2: return tile_ops_R8_L64();
-    case 3: return tile_ops_R4_L64();
+    case 1: return tile_ops_R8_L64();
+    case 2: return tile_ops_R8_L256();
     default: return nullptr;
   }
 }
