@@ -168,17 +168,23 @@ int spingp_tune(spingp_handle h, int32_t reps);
 /*
  * Prediction at new times (eq. mean4-mean6 and the variance of eq. k3 at t*): the latent
  * predictive mean f_mean[j] = E[f(t*_j) | y] and variance f_var[j] = Var[f(t*_j) | y] (no noise
- * term) of a one-series handle.  t_star: [n_star] device array, finite and non-decreasing
- * (violations are reported by spingp_status with the index in t_star; results are then
- * unspecified); f_mean, f_var: NULL or [n_star].  The prediction times are merged into the
- * chain as nodes without an observation and the whole reduction runs on the merged chain, so
- * n_points + n_star must not exceed the handle's max_points (SPINGP_E_INVALID).  Uses the
- * hyperparameters in device memory at the time of the call.  Overwrites the handle's
+ * term).  t_star: [n_star] device array, finite; f_mean, f_var: NULL or [n_star].
+ * One series (offsets_star NULL): t_star non-decreasing.  Several series: offsets_star is an
+ * [n_series + 1] device int64 array, offsets_star[0] = 0, non-decreasing, offsets_star[n_series]
+ * = n_star; times [offsets_star[s], offsets_star[s+1]) belong to series s, with its
+ * hyperparameters, and are non-decreasing within it; a series may get none.  The call re-runs
+ * the assemble-time checks of the bound inputs and checks t_star: spingp_status then reports
+ * these (for t_star: code 1 for the offsets, 3 or 4 with the index in t_star); results are then
+ * unspecified.  The prediction times are merged into the chain as nodes without an
+ * observation (after training points at equal times) and the whole reduction runs on the merged
+ * chain, so n_points + n_star must not exceed the handle's max_points (SPINGP_E_INVALID).  Uses
+ * the hyperparameters in device memory at the time of the call.  Overwrites the handle's
  * factorisation: call spingp_factor again before spingp_logml, spingp_solve or spingp_selinv
- * (spingp_logml_grad refactors by itself).  Needs assemble.  Several series:
- * SPINGP_E_UNSUPPORTED.
+ * (spingp_logml_grad refactors by itself).  Needs assemble; a batched handle needs offsets_star
+ * (SPINGP_E_INVALID without).
  */
-int spingp_predict(spingp_handle h, const double* t_star, int64_t n_star, double* f_mean, double* f_var);
+int spingp_predict(spingp_handle h, const double* t_star, const int64_t* offsets_star, int64_t n_star,
+                   double* f_mean, double* f_var);
 
 /*
  * Diagnostics (not part of the hot path, which never forms these blocks): the edge blocks and

@@ -90,7 +90,8 @@ struct spingp_ctx {
   int64_t* chunk_first = nullptr;  // several series: first chunk of every series
   unsigned long long* key = nullptr;
   double* tune_out = nullptr;      // logML and gradient written while tuning
-  double* pred = nullptr;          // one series: merged times, observations, mean, variance
+  double* pred = nullptr;          // prediction: merged times, observations, mean, variance
+  int64_t* pred_off = nullptr;     // prediction, several series: merged offsets
   int64_t lane_ld = 0;
   // tile shape
   int tile = 0;
@@ -305,7 +306,8 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
       {(void**)&h->part, (int64_t)sizeof(double) * part_n},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
       {(void**)&h->tune_out, (int64_t)sizeof(double) * 4 * max_series},
-      {(void**)&h->pred, multi ? 0 : (int64_t)sizeof(double) * 4 * max_points},
+      {(void**)&h->pred, (int64_t)sizeof(double) * 4 * max_points},
+      {(void**)&h->pred_off, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
       {(void**)&h->chunk_series, multi ? (int64_t)sizeof(int32_t) * slots_max : 0},
       {(void**)&h->chunk_first, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
   };
@@ -372,6 +374,7 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)hipFree(h->key);
   (void)hipFree(h->tune_out);
   (void)hipFree(h->pred);
+  (void)hipFree(h->pred_off);
   (void)hipFree(h->chunk_series);
   (void)hipFree(h->chunk_first);
   (void)hipFree(h->wplan.elems);
@@ -387,6 +390,18 @@ extern "C" int spingp_n_hyper(spingp_handle h) { return h ? h->n_hyper : -1; }
 extern "C" int64_t spingp_workspace_bytes(spingp_handle h) { return h ? h->ws_bytes : -1; }
 
 // Validation and (several series) chunk map of the bound inputs for the current tile shape.
+// Chunk -> series map of a concatenated batch with the given offsets and total length.
+static void map_chunks(spingp_ctx* h, const int64_t* offsets, int64_t n_points) {
+  const spg::TileOps* T = ops(h);
+  const int64_t slots = T->groups(n_points, h->n_series, true) * T->L;
+  hipLaunchKernelGGL(spg::k_chunk_first, dim3(1), dim3(256), 0, h->stream, offsets, h->n_series, n_points, T->R,
+                     h->chunk_first, h->key);
+  hipLaunchKernelGGL(spg::k_chunk_fill, dim3((unsigned)ceil_div(slots, kT)), dim3(kT), 0, h->stream,
+                     h->chunk_series, slots);
+  hipLaunchKernelGGL(spg::k_chunk_map, dim3((unsigned)ceil_div(h->n_series, kT)), dim3(kT), 0, h->stream,
+                     h->chunk_first, h->n_series, slots, h->chunk_series);
+}
+
 static int bind(spingp_ctx* h) {
   drop_graph(h);
   h->factored = false;
@@ -398,13 +413,7 @@ static int bind(spingp_ctx* h) {
     hipLaunchKernelGGL(k_validate, dim3((unsigned)ceil_div(h->n_points, kT)), dim3(kT), 0, h->stream, h->t, h->y,
                        h->n_points, h->hyper, h->n_hyper, h->key);
   } else {
-    const int64_t slots = T->groups(h->n_points, h->n_series, true) * T->L;
-    hipLaunchKernelGGL(spg::k_chunk_first, dim3(1), dim3(256), 0, h->stream, h->offsets, h->n_series, h->n_points,
-                       T->R, h->chunk_first, h->key);
-    hipLaunchKernelGGL(spg::k_chunk_fill, dim3((unsigned)ceil_div(slots, kT)), dim3(kT), 0, h->stream,
-                       h->chunk_series, slots);
-    hipLaunchKernelGGL(spg::k_chunk_map, dim3((unsigned)ceil_div(h->n_series, kT)), dim3(kT), 0, h->stream,
-                       h->chunk_first, h->n_series, slots, h->chunk_series);
+    map_chunks(h, h->offsets, h->n_points);
     if (T->map(launch_ctx(h, false)) != hipSuccess) return SPINGP_E_HIP;
   }
   prof_end(h, spg::kKidValidate);
@@ -700,53 +709,89 @@ extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
   return rc;
 }
 
-extern "C" int spingp_predict(spingp_handle h, const double* t_star, int64_t n_star, double* f_mean,
-                              double* f_var) {
+extern "C" int spingp_predict(spingp_handle h, const double* t_star, const int64_t* offsets_star, int64_t n_star,
+                              double* f_mean, double* f_var) {
   if (!h || !t_star || n_star < 1) return SPINGP_E_INVALID;
   if (!h->assembled) return SPINGP_E_ORDER;
-  if (h->batched || !h->pred) return SPINGP_E_UNSUPPORTED;
+  if (!h->pred || (h->batched && !h->pred_off)) return SPINGP_E_UNSUPPORTED;
+  if (h->batched && !offsets_star) return SPINGP_E_INVALID;
   if (h->n_points + n_star > h->max_points) return SPINGP_E_INVALID;
   if (!f_mean && !f_var) return SPINGP_OK;
   const int64_t n = h->n_points, m = n_star, nm = n + m;
+  const int32_t S = h->n_series;
   double* tm = h->pred;
   double* ym = tm + h->max_points;
   double* fm = ym + h->max_points;
   double* fv = fm + h->max_points;
-  drop_graph(h);                     // the shared workspace is about to hold the merged problem
-  h->factored = false;
-  h->wide_down = false;
-  hipLaunchKernelGGL(spg::k_validate_star, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, t_star, m,
-                     h->key);
-  hipLaunchKernelGGL(spg::k_merge, dim3((unsigned)ceil_div(nm, kT)), dim3(kT), 0, h->stream, h->t, h->y, n, t_star,
-                     m, tm, ym);
-  int rc;
-  if (h->wide) {
-    spg::wide::WideCtx c = wide_ctx(h);
-    memset(&c.n, 0, sizeof(c.n));
-    spg::wide::plan_levels(nm, c);
-    c.t = tm;
-    c.y = ym;
-    c.n_points = nm;
-    rc = hip_ok(spg::wide::factor(c));
-    if (!rc) rc = hip_ok(spg::wide::down(c));
-    if (!rc) rc = hip_ok(spg::wide::node(c, spg::kWantVar, fm, fv, nullptr, nullptr, nullptr));
-  } else {
-    spg::LaunchCtx c = launch_ctx(h);
-    c.t = tm;
-    c.y = ym;
-    c.n_points = nm;
-    rc = hip_ok(ops(h)->factor(c));
-    if (!rc) {
-      spg::BwdOut o = make_out(h);
-      o.ld = nm;
-      o.f_mean = fm;
-      o.f_var = fv;
-      rc = hip_ok(ops(h)->bwd(c, spg::kWantVar, o));
+  // fresh status word and checks of the bound inputs, as at assemble; the shared workspace is
+  // about to hold the merged problem
+  int rc = bind(h);
+  if (rc) return rc;
+  if (!h->batched) {
+    hipLaunchKernelGGL(spg::k_validate_star, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, t_star, m,
+                       h->key);
+    hipLaunchKernelGGL(spg::k_merge, dim3((unsigned)ceil_div(nm, kT)), dim3(kT), 0, h->stream, h->t, h->y, n,
+                       t_star, m, tm, ym);
+    if (h->wide) {
+      spg::wide::WideCtx c = wide_ctx(h);
+      memset(&c.n, 0, sizeof(c.n));
+      spg::wide::plan_levels(nm, c);
+      c.t = tm;
+      c.y = ym;
+      c.n_points = nm;
+      rc = hip_ok(spg::wide::factor(c));
+      if (!rc) rc = hip_ok(spg::wide::down(c));
+      if (!rc) rc = hip_ok(spg::wide::node(c, spg::kWantVar, fm, fv, nullptr, nullptr, nullptr));
+    } else {
+      spg::LaunchCtx c = launch_ctx(h);
+      c.t = tm;
+      c.y = ym;
+      c.n_points = nm;
+      rc = hip_ok(ops(h)->factor(c));
+      if (!rc) {
+        spg::BwdOut o = make_out(h);
+        o.ld = nm;
+        o.f_mean = fm;
+        o.f_var = fv;
+        rc = hip_ok(ops(h)->bwd(c, spg::kWantVar, o));
+      }
     }
+    if (rc) return rc;
+    hipLaunchKernelGGL(spg::k_gather, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, h->t, n, t_star, m,
+                       fm, fv, f_mean, f_var);
+    return hip_ok(hipGetLastError());
+  }
+  // several series: merge series by series, map the merged chunks, run the batched path on the
+  // merged chain, gather, then restore the chunk map of the bound batch
+  const spg::TileOps* T = ops(h);
+  const int64_t nv = m > S ? m : S;
+  hipLaunchKernelGGL(spg::k_validate_star_batch, dim3((unsigned)ceil_div(nv, kT)), dim3(kT), 0, h->stream, t_star,
+                     offsets_star, S, m, h->key);
+  hipLaunchKernelGGL(spg::k_merged_offsets, dim3((unsigned)ceil_div((int64_t)S + 1, kT)), dim3(kT), 0, h->stream,
+                     h->offsets, offsets_star, S, h->pred_off);
+  hipLaunchKernelGGL(spg::k_merge_batch, dim3((unsigned)ceil_div(nm, kT)), dim3(kT), 0, h->stream, h->t, h->y,
+                     h->offsets, S, n, t_star, offsets_star, m, tm, ym);
+  map_chunks(h, h->pred_off, nm);
+  spg::LaunchCtx c = launch_ctx(h);
+  c.t = tm;
+  c.y = ym;
+  c.offsets = h->pred_off;
+  c.n_points = nm;
+  rc = hip_ok(T->factor(c));
+  if (!rc) {
+    spg::BwdOut o = make_out(h);
+    o.ld = nm;
+    o.f_mean = fm;
+    o.f_var = fv;
+    rc = hip_ok(T->bwd(c, spg::kWantVar, o));
   }
   if (rc) return rc;
-  hipLaunchKernelGGL(spg::k_gather, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, h->t, n, t_star, m, fm,
-                     fv, f_mean, f_var);
+  hipLaunchKernelGGL(spg::k_gather_batch, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, h->t,
+                     h->offsets, S, n, t_star, offsets_star, m, fm, fv, f_mean, f_var);
+  rc = hip_ok(hipGetLastError());
+  if (rc) return rc;
+  // the bound batch's chunk map again; the status word keeps what the checks above found
+  map_chunks(h, h->offsets, h->n_points);
   return hip_ok(hipGetLastError());
 }
 

@@ -166,6 +166,95 @@ __global__ void k_validate_star(const double* __restrict__ ts, int64_t m, unsign
   if (code) atomicMin(key, ((unsigned long long)(j + 1) << 4) | code);
 }
 
+// Several series: series s holds training points [off[s], off[s+1]) and prediction times
+// [os[s], os[s+1]); both merge into [mo[s], mo[s+1]) with mo = off + os.  Indices are clamped so
+// that offsets reported invalid by the status word never reach outside the arrays.
+SPG_DEV int32_t series_of(const int64_t* __restrict__ off, int32_t S, int64_t i) {
+  int32_t lo = 0, hi = S - 1;       // the last s with off[s] <= i
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+SPG_DEV void clamp_range(const int64_t* __restrict__ off, int32_t s, int64_t n, int64_t& a, int64_t& e) {
+  a = off[s];
+  e = off[s + 1];
+  a = a < 0 ? 0 : (a > n ? n : a);
+  e = e < a ? a : (e > n ? n : e);
+}
+
+__global__ void k_merged_offsets(const int64_t* __restrict__ off, const int64_t* __restrict__ os, int32_t S,
+                                 int64_t* __restrict__ mo) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s <= S) mo[s] = off[s] + os[s];
+}
+
+SPG_DEV int64_t merged_pos_train(const double* __restrict__ t, const int64_t* __restrict__ off,
+                                 const double* __restrict__ ts, const int64_t* __restrict__ os, int32_t S,
+                                 int64_t n, int64_t m, int64_t i) {
+  const int32_t s = series_of(off, S, i);
+  int64_t a, e, as, es;
+  clamp_range(off, s, n, a, e);
+  clamp_range(os, s, m, as, es);
+  int64_t pos = a + as + (i - a) + count_less(ts + as, es - as, t[i]);
+  return pos < 0 ? 0 : (pos > n + m - 1 ? n + m - 1 : pos);
+}
+SPG_DEV int64_t merged_pos_star(const double* __restrict__ t, const int64_t* __restrict__ off,
+                                const double* __restrict__ ts, const int64_t* __restrict__ os, int32_t S,
+                                int64_t n, int64_t m, int64_t j) {
+  const int32_t s = series_of(os, S, j);
+  int64_t a, e, as, es;
+  clamp_range(off, s, n, a, e);
+  clamp_range(os, s, m, as, es);
+  int64_t pos = a + as + (j - as) + count_not_greater(t + a, e - a, ts[j]);
+  return pos < 0 ? 0 : (pos > n + m - 1 ? n + m - 1 : pos);
+}
+
+__global__ void k_merge_batch(const double* __restrict__ t, const double* __restrict__ y,
+                              const int64_t* __restrict__ off, int32_t S, int64_t n, const double* __restrict__ ts,
+                              const int64_t* __restrict__ os, int64_t m, double* __restrict__ tm,
+                              double* __restrict__ ym) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) {
+    const int64_t pos = merged_pos_train(t, off, ts, os, S, n, m, idx);
+    tm[pos] = t[idx];
+    ym[pos] = y[idx];
+  } else if (idx < n + m) {
+    const int64_t j = idx - n;
+    const int64_t pos = merged_pos_star(t, off, ts, os, S, n, m, j);
+    tm[pos] = ts[j];
+    ym[pos] = __builtin_nan("");
+  }
+}
+
+// Prediction times of several series: finite, non-decreasing inside each series (they may
+// restart between series); offsets_star[0] = 0, non-decreasing, offsets_star[S] = m.
+__global__ void k_validate_star_batch(const double* __restrict__ ts, const int64_t* __restrict__ os, int32_t S,
+                                      int64_t m, unsigned long long* __restrict__ key) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0 && (os[0] != 0 || os[S] != m)) atomicMin(key, 1ull);           // SPINGP_E_INVALID
+  if (j < S && os[j + 1] < os[j]) atomicMin(key, 1ull);
+  if (j >= m) return;
+  const int32_t s = series_of(os, S, j);
+  unsigned long long code = 0;
+  if (!isfinite(ts[j])) code = 4;                                          // SPINGP_E_NONFINITE
+  else if (j + 1 < m && j + 1 < os[s + 1] && ts[j + 1] < ts[j]) code = 3;   // SPINGP_E_UNSORTED
+  if (code) atomicMin(key, ((unsigned long long)(j + 1) << 4) | code);
+}
+
+__global__ void k_gather_batch(const double* __restrict__ t, const int64_t* __restrict__ off, int32_t S, int64_t n,
+                               const double* __restrict__ ts, const int64_t* __restrict__ os, int64_t m,
+                               const double* __restrict__ fm, const double* __restrict__ fv,
+                               double* __restrict__ f_mean, double* __restrict__ f_var) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const int64_t pos = merged_pos_star(t, off, ts, os, S, n, m, j);
+  if (f_mean) f_mean[j] = fm[pos];
+  if (f_var) f_var[j] = fv[pos];
+}
+
 __global__ void k_gather(const double* __restrict__ t, int64_t n, const double* __restrict__ ts, int64_t m,
                          const double* __restrict__ fm, const double* __restrict__ fv, double* __restrict__ f_mean,
                          double* __restrict__ f_var) {

@@ -72,7 +72,7 @@ def load_library():
     lib.spingp_set_tile.argtypes = [vp, i32]
     lib.spingp_tune.argtypes = [vp, i32]
     lib.spingp_blocks.argtypes = [vp, vp, vp, vp, vp]
-    lib.spingp_predict.argtypes = [vp, vp, i64, vp, vp]
+    lib.spingp_predict.argtypes = [vp, vp, vp, i64, vp, vp]
     for name in ("spingp_create", "spingp_destroy", "spingp_state_dim", "spingp_n_hyper", "spingp_assemble",
                  "spingp_factor", "spingp_logml", "spingp_solve", "spingp_selinv", "spingp_logml_grad",
                  "spingp_status", "spingp_profile", "spingp_profile_read", "spingp_tile_count",
@@ -160,9 +160,14 @@ def spingp_logml_grad(h, logml, grad):
     _check(load_library().spingp_logml_grad(h, _dev(logml, "logml"), _dev(grad, "grad")), "spingp_logml_grad")
 
 
-def spingp_predict(h, t_star, f_mean=None, f_var=None):
+def spingp_predict(h, t_star, f_mean=None, f_var=None, offsets_star=None):
     m = t_star.numel()
-    _check(load_library().spingp_predict(h, _dev(t_star, "t_star"), int(m), _dev(f_mean, "f_mean", m),
+    off = None
+    if offsets_star is not None:
+        if offsets_star.dtype != torch.int64 or not offsets_star.is_cuda or not offsets_star.is_contiguous():
+            raise ValueError("offsets_star must be a contiguous int64 tensor on the GPU")
+        off = ctypes.c_void_p(offsets_star.data_ptr())
+    _check(load_library().spingp_predict(h, _dev(t_star, "t_star"), off, int(m), _dev(f_mean, "f_mean", m),
                                          _dev(f_var, "f_var", m)), "spingp_predict")
 
 
@@ -310,11 +315,14 @@ class Handle:
     def workspace_bytes(self):
         return spingp_workspace_bytes(self._h)
 
-    def predict(self, t_star):
-        """Latent predictive mean and variance at the (sorted) times t_star."""
+    def predict(self, t_star, offsets_star=None):
+        """Latent predictive mean and variance at the times t_star (sorted within each series;
+        offsets_star [n_series + 1] splits them by series on a batched handle)."""
+        if offsets_star is not None and offsets_star.numel() != self.n_series + 1:
+            raise ValueError(f"offsets_star must have n_series + 1 = {self.n_series + 1} entries")
         fm = torch.empty_like(t_star)
         fv = torch.empty_like(t_star)
-        spingp_predict(self._h, t_star, fm, fv)
+        spingp_predict(self._h, t_star, fm, fv, offsets_star)
         return fm, fv
 
     def blocks(self):

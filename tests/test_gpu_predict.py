@@ -7,7 +7,7 @@ import pytest
 from gpu_util import TOL_MEAN, TOL_VAR, to_dev
 from oracle import dense, kalman, native
 from oracle.ssm import model_for
-from workloads import KIND_MATERN32, KIND_MATERN52, KIND_PERIODIC, make_config
+from workloads import KIND_MATERN32, KIND_MATERN52, KIND_PERIODIC, make_batch, make_config
 
 pytestmark = pytest.mark.gpu
 
@@ -119,8 +119,117 @@ def test_predict_errors(lib):
     assert h.status() == (3, 19)                             # unsorted prediction times
     h.close()
     wb = make_config(4, n_series=3, max_len=50)
-    hb = lib.Handle(wb.terms, 1000, max_series=3)
+    hb = lib.Handle(wb.terms, wb.n_points + 20, max_series=3)
     hb.assemble(to_dev(wb.t), to_dev(wb.y), to_dev(wb.hyper.reshape(-1)), to_dev(wb.offsets, torch.int64))
+    ts = to_dev(np.linspace(0, 10, 9))
     with pytest.raises(lib.SpinGPError):
-        hb.predict(to_dev(np.linspace(0, 10, 5)))            # several series
+        hb.predict(ts)                                        # several series need offsets_star
+    with pytest.raises(lib.SpinGPError):                      # n_points + n_star > max_points
+        hb.predict(to_dev(np.linspace(0, 10, 21)), to_dev(np.array([0, 21, 21, 21]), torch.int64))
+    # times restart at a series boundary: not an error
+    hb.predict(to_dev(np.r_[np.linspace(0, 10, 5), np.linspace(0, 1, 4)]), to_dev(np.array([0, 5, 5, 9]), torch.int64))
+    assert hb.status() == (0, -1)
+    hb.predict(ts, to_dev(np.array([0, 4, 4, 8]), torch.int64))
+    assert hb.status()[0] == 1                                # offsets_star does not end at n_star
+    hb.predict(ts, to_dev(np.array([0, 6, 4, 9]), torch.int64))
+    assert hb.status()[0] == 1                                # decreasing offsets_star
+    tb = np.linspace(0, 10, 9)
+    tb[6] = tb[5] - 1.0
+    hb.predict(to_dev(tb), to_dev(np.array([0, 2, 5, 9]), torch.int64))
+    assert hb.status() == (3, 5)                              # unsorted inside series 2
+    tb = np.linspace(0, 10, 9)
+    tb[1] = np.inf
+    hb.predict(to_dev(tb), to_dev(np.array([0, 2, 5, 9]), torch.int64))
+    assert hb.status() == (4, 1)
     hb.close()
+
+
+def _merged_reference(terms, hyp, t, y, ts):
+    """Kalman/RTS oracle with the prediction times merged as unobserved nodes (training points
+    first at equal times); returns the mean and variance at the prediction times."""
+    tm = np.concatenate([t, ts])
+    ym = np.concatenate([y, np.full(ts.shape[0], np.nan)])
+    order = np.lexsort((np.concatenate([np.zeros(t.shape[0]), np.ones(ts.shape[0])]), tm))
+    pos = np.empty(tm.shape[0], np.int64)
+    pos[order] = np.arange(tm.shape[0])
+    k = kalman.kf_rts(model_for(terms, hyp), tm[order], ym[order])
+    return k["f_mean"][pos[t.shape[0]:]], k["f_var"][pos[t.shape[0]:]]
+
+
+@pytest.mark.parametrize("kind", [KIND_MATERN32, KIND_MATERN52])
+def test_predict_batched_against_kalman(lib, kind):
+    """Several series, each with its own hyperparameters and prediction times: series without
+    training points (prior), series without prediction times, lengths around the chunk and
+    work-group sizes, ties with training times; then logML and gradient of the bound batch."""
+    lens = [0, 5, 300, 1, 0, 1025, 64, 2000, 8, 9]
+    n_pred = [3, 0, 50, 4, 0, 100, 1, 333, 8, 0]
+    S = len(lens)
+    rng = np.random.default_rng(21)
+    hyper = np.stack([np.exp(rng.uniform(np.log(0.5), np.log(20.0), S)),
+                      np.exp(rng.uniform(np.log(0.5), np.log(3.0), S)),
+                      np.exp(rng.uniform(np.log(1e-3), np.log(0.3), S))], axis=1)
+    w = make_batch(lens, hyper, [(kind, 0)], seed=22)
+    ts_parts = []
+    for s in range(S):
+        t, _, _ = w.series(s)
+        lo, hi = (t[0] - 3.0, t[-1] + 3.0) if t.shape[0] else (0.0, 10.0)
+        x = rng.uniform(lo, hi, n_pred[s])
+        if t.shape[0] and n_pred[s] > 2:
+            x[:2] = t[[0, t.shape[0] // 2]]                    # ties with training times
+        ts_parts.append(np.sort(x))
+    ts = np.concatenate(ts_parts)
+    os_ = np.concatenate([[0], np.cumsum(n_pred)]).astype(np.int64)
+    h = lib.Handle(w.terms, w.n_points + ts.shape[0], max_series=S)
+    h.assemble(to_dev(w.t), to_dev(w.y), to_dev(w.hyper.reshape(-1)), to_dev(w.offsets, torch.int64))
+    fm, fv = h.predict(to_dev(ts), to_dev(os_, torch.int64))
+    assert h.status() == (0, -1)
+    fm, fv = fm.cpu().numpy(), fv.cpu().numpy()
+    for s in range(S):
+        if n_pred[s] == 0:
+            continue
+        t, y, hyp = w.series(s)
+        rm, rv = _merged_reference(w.terms, hyp, t, y, ts_parts[s])
+        a, e = int(os_[s]), int(os_[s + 1])
+        try:
+            _check(fm[a:e], fv[a:e], rm, rv)
+        except AssertionError as err:
+            raise AssertionError(f"series {s}: {err}") from None
+        if t.shape[0] == 0:                                   # no data: the prior
+            assert np.max(np.abs(fm[a:e])) == 0.0
+            assert np.allclose(fv[a:e], hyp[1], rtol=1e-12)
+    # the bound batch is intact: logML and gradient of every series
+    ll, g = h.logml_grad()
+    assert h.status() == (0, -1)
+    ll, g = ll.cpu().numpy(), g.cpu().numpy()
+    for s in range(S):
+        t, y, hyp = w.series(s)
+        if t.shape[0] == 0:
+            assert ll[s] == 0.0 and not np.any(g[s])
+            continue
+        r = native.tangent_grad(w.terms, hyp, t, y)
+        assert abs(ll[s] - r["logml"]) <= 1e-8 * abs(r["logml"]), f"series {s}"
+    h.close()
+
+
+def test_predict_batched_matches_one_series_handles(lib):
+    """Each series of a batched prediction equals the one-series prediction of that series."""
+    w = make_config(4, n_series=5, max_len=2500)
+    rng = np.random.default_rng(23)
+    parts = [np.sort(rng.uniform(-1.0, 60.0, int(k))) for k in rng.integers(1, 400, w.n_series)]
+    ts = np.concatenate(parts)
+    os_ = np.concatenate([[0], np.cumsum([p.shape[0] for p in parts])]).astype(np.int64)
+    h = lib.Handle(w.terms, w.n_points + ts.shape[0], max_series=w.n_series)
+    h.assemble(to_dev(w.t), to_dev(w.y), to_dev(w.hyper.reshape(-1)), to_dev(w.offsets, torch.int64))
+    fm, fv = h.predict(to_dev(ts), to_dev(os_, torch.int64))
+    fm, fv = fm.cpu().numpy(), fv.cpu().numpy()
+    for s in range(w.n_series):
+        t, y, hyp = w.series(s)
+        h1 = lib.Handle(w.terms, t.shape[0] + parts[s].shape[0])
+        h1.assemble(to_dev(t), to_dev(y), to_dev(hyp))
+        m1, v1 = h1.predict(to_dev(parts[s]))
+        m1, v1 = m1.cpu().numpy(), v1.cpu().numpy()
+        a, e = int(os_[s]), int(os_[s + 1])
+        assert np.max(np.abs(fm[a:e] - m1) / (np.abs(m1) + np.sqrt(v1))) <= 1e-11, f"series {s}"
+        assert np.max(np.abs(fv[a:e] - v1) / v1) <= 1e-11, f"series {s}"
+        h1.close()
+    h.close()
