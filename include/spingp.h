@@ -155,7 +155,12 @@ int spingp_logml_grad(spingp_handle h, double* logml, double* grad);
  */
 int spingp_tile_count(void);
 int spingp_tile_shape(int32_t index, int32_t* R, int32_t* L);
-/* Current shape of the handle; selecting one re-validates and re-maps the bound inputs. */
+/*
+ * Current shape of the handle; selecting one re-validates and re-maps the bound inputs.
+ * Shapes with R < 8 are available only on handles created with max_points <= 2^20 (their
+ * workspace is twice as large); elsewhere spingp_set_tile returns SPINGP_E_UNSUPPORTED and
+ * the autotuner skips them.
+ */
 int spingp_get_tile(spingp_handle h, int32_t* index);
 int spingp_set_tile(spingp_handle h, int32_t index);
 /*

@@ -59,15 +59,26 @@ namespace spg {
 const TileOps* tile_ops_R8_L128();
 const TileOps* tile_ops_R8_L64();
 const TileOps* tile_ops_R8_L256();
-// The first entry is the default shape.  All keep R = 8 (two tree elements per 8 points): a
-// smaller R doubles the stored trees and was never the fastest.
+const TileOps* tile_ops_R4_L128();
+const TileOps* tile_ops_R4_L256();
+// The first entry is the default shape.  R = 8 is fastest from about 2^19 points up; R = 4
+// (twice the lanes, twice the stored trees) hides more latency on smaller problems.
 const TileOps* tile_ops(int i) {
   switch (i) {
     case 0: return tile_ops_R8_L128();
     case 1: return tile_ops_R8_L64();
     case 2: return tile_ops_R8_L256();
+    case 3: return tile_ops_R4_L128();
+    case 4: return tile_ops_R4_L256();
     default: return nullptr;
   }
+}
+// R = 4 shapes double the lane workspace; they are offered only to handles small enough for
+// them to win, so large handles keep the R = 8 footprint.
+constexpr int64_t kSmallTileMaxPoints = int64_t(1) << 20;
+bool tile_fits(int i, int64_t max_points) {
+  const TileOps* T = tile_ops(i);
+  return T && (T->R >= 8 || max_points <= kSmallTileMaxPoints);
 }
 }  // namespace spg
 
@@ -266,10 +277,11 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   }
   if (max_points > (int64_t(1) << 40)) return SPINGP_E_UNSUPPORTED;
   if (wide) return create_wide(out, max_points, max_series, stream);
-  // workspace for the most demanding tile shape
+  // workspace for the most demanding tile shape the handle may use
   const bool multi = max_series > 1;
   int64_t G_max = 0, lane_ld = 0;
   for (int i = 0; i < spg::kNumTiles; ++i) {
+    if (!spg::tile_fits(i, max_points)) continue;
     const spg::TileOps* T = spg::tile_ops(i);
     const int64_t G = T->groups(max_points, max_series, multi);
     if (G > G_max) G_max = G;
@@ -279,6 +291,7 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   if (G_max >= (int64_t(1) << 31)) return SPINGP_E_UNSUPPORTED;
   int64_t slots_max = 0;
   for (int i = 0; i < spg::kNumTiles; ++i) {
+    if (!spg::tile_fits(i, max_points)) continue;
     const spg::TileOps* T = spg::tile_ops(i);
     const int64_t sl = T->groups(max_points, max_series, multi) * T->L;
     if (sl > slots_max) slots_max = sl;
@@ -451,6 +464,7 @@ extern "C" int spingp_tune(spingp_handle h, int32_t reps) {
   int best = -1, rc = SPINGP_OK;
   float best_ms = 0.f;
   for (int i = 0; i < spg::kNumTiles && rc == SPINGP_OK; ++i) {
+    if (!spg::tile_fits(i, h->max_points)) continue;
     h->tile = i;
     rc = bind(h);
     if (rc) break;
@@ -497,7 +511,7 @@ extern "C" int spingp_get_tile(spingp_handle h, int32_t* index) {
 
 extern "C" int spingp_set_tile(spingp_handle h, int32_t index) {
   if (!h || !spg::tile_ops(index)) return SPINGP_E_INVALID;
-  if (h->wide && index != 0) return SPINGP_E_UNSUPPORTED;
+  if ((h->wide && index != 0) || !spg::tile_fits(index, h->max_points)) return SPINGP_E_UNSUPPORTED;
   h->tile = index;
   return h->assembled ? bind(h) : SPINGP_OK;
 }
@@ -527,7 +541,7 @@ extern "C" int spingp_assemble(spingp_handle h, const double* t, const double* y
   if ((flags & SPINGP_FLAG_AUTOTUNE) && !h->wide) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(tune_key(h));
-    if (it != g_tune_cache.end()) h->tile = it->second;
+    if (it != g_tune_cache.end() && spg::tile_fits(it->second, h->max_points)) h->tile = it->second;
     else tune = true;
   }
   int rc = bind(h);

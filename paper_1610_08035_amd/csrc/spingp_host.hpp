@@ -55,15 +55,28 @@ struct TileOps {
   hipError_t (*blocks)(const LaunchCtx& c, double* A, double* Q, double* D, double* Bsub);
 };
 
-// Sizes of the top-level tree over G leaves: slots (2 * 32^bands) and arrival counters.
+// Shape of the top-level tree over G leaves: n_levels = ceil log2 G (at least 1), bands of 5
+// levels (the last one may be shorter).
+inline int top_levels(int64_t G) {
+  int k = 1;
+  while (((int64_t)1 << k) < G) ++k;
+  return k;
+}
+inline int top_band_levels(int n_levels, int band) {
+  const int r = n_levels - 5 * band;
+  return r < 5 ? r : 5;
+}
+
+// Sizes of the top-level tree over G leaves: slots (2 * Ltop) and arrival counters.
 inline void top_sizes(int64_t G, int64_t& slots, int64_t& counters) {
-  int64_t ltop = 32;
-  while (ltop < G) ltop *= 32;
-  slots = 2 * ltop;
+  const int K = top_levels(G);
+  slots = (int64_t)2 << K;
   counters = 0;
-  for (int64_t n = G;; n = (n + 31) / 32) {
-    counters += (n + 31) / 32;
-    if (n <= 32) break;
+  int64_t n = G;
+  for (int b = 0; 5 * b < K; ++b) {
+    const int bs = top_band_levels(K, b);
+    n = (n + ((int64_t)1 << bs) - 1) >> bs;
+    counters += n;
   }
 }
 
@@ -73,20 +86,16 @@ inline TopTree make_top(const LaunchCtx& c, int64_t G) {
   T.ld = c.top_ld;
   T.G = G;
   T.cnt = c.top_cnt;
-  int nb = 1;
-  int64_t ltop = 32;
-  while (ltop < G) {
-    ltop *= 32;
-    ++nb;
-  }
-  T.Ltop = ltop;
-  T.n_bands = nb;
-  for (int b = 0; b < 7; ++b) T.cnt_off[b] = 0;
+  T.n_levels = top_levels(G);
+  T.Ltop = (int64_t)1 << T.n_levels;
+  T.n_bands = (T.n_levels + 4) / 5;
+  for (int b = 0; b < 8; ++b) T.cnt_off[b] = 0;
   int64_t off = 0, n = G;
-  for (int b = 0; b < nb; ++b) {
+  for (int b = 0; b < T.n_bands; ++b) {
+    const int bs = top_band_levels(T.n_levels, b);
     T.cnt_off[b] = off;
-    off += (n + 31) / 32;
-    n = (n + 31) / 32;
+    n = (n + ((int64_t)1 << bs) - 1) >> bs;   // groups of this band
+    off += n;
   }
   return T;
 }
@@ -108,7 +117,7 @@ inline SeriesMap make_map(const LaunchCtx& c, int64_t slots) {
 }
 
 // Tile shapes compiled into the library, in order of preference when untuned.
-constexpr int kNumTiles = 3;
+constexpr int kNumTiles = 5;
 const TileOps* tile_ops(int i);
 
 // Wide-state path (Matern-3/2 + periodic with 3 harmonics, b = 10, one series): level-by-level

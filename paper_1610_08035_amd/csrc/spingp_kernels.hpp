@@ -329,18 +329,20 @@ SPG_DEV void lds_store_suffix(double* pool, int i, const double (&J)[B][B], cons
 }
 
 // ---------------------------------------------------------------------------- top-level tree
-// The work-group aggregates are the leaves of a complete binary tree with Ltop = 32^n_bands
-// leaves (identity elements pad it), reduced band by band, 5 levels per band, by k_top_bands.
+// The work-group aggregates are the leaves of a complete binary tree with Ltop = 2^n_levels
+// leaves (n_levels = ceil log2 G, at least 1; identity elements pad it), reduced band by band
+// by k_top_bands: every band spans 5 levels except possibly the last, which spans the rest.
 // Level l of the tree starts at slot 2 Ltop - 2 (Ltop >> l); the reverse sweep walks it from
 // the root to its own leaf.
 struct TopTree {
   double* elems;          // field-major elements, leading dimension ld
-  int64_t ld;             // 2 * Ltop slots
+  int64_t ld;             // at least 2 * Ltop slots
   int64_t G;              // real leaves (work-groups of the forward kernel)
-  int64_t Ltop;           // 32^n_bands
-  int n_bands;
+  int64_t Ltop;           // 2^n_levels
+  int n_levels;
+  int n_bands;            // ceil(n_levels / 5)
   unsigned int* cnt;      // arrival counters; band b, group q at cnt[cnt_off[b] + q]
-  int64_t cnt_off[7];
+  int64_t cnt_off[8];
 };
 SPG_DEV int64_t top_level_off(const TopTree& T, int l) { return 2 * T.Ltop - 2 * (T.Ltop >> l); }
 
@@ -400,9 +402,9 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
 }
 
 // ---------------------------------------------------------------------------- kernel: top bands
-// One 64-thread work-group per group of 32 leaves of band 0.  Each reduces its group in LDS and
-// writes every node; then the last work-group of each group of 32 band-0 groups (atomic ticket,
-// no waiting) reduces band 1, and so on.  The work-group that completes the last band holds the
+// One 64-thread work-group per group of (up to) 32 leaves of band 0.  Each reduces its group in
+// LDS and writes every node; then the last work-group of each group of band-0 groups (atomic
+// ticket, no waiting) reduces band 1, and so on.  The work-group that completes the last band holds the
 // root and, for one series, evaluates the log marginal likelihood (the prior N(0, P0) pushed
 // through the whole chain).  Fences here only have to publish the few nodes this kernel writes.
 template <int B, bool BATCHED>
@@ -412,10 +414,13 @@ __global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyp
   __shared__ double pool[NF * 32];
   __shared__ unsigned int s_ticket;
   const int tid = threadIdx.x;
-  int64_t group = blockIdx.x, nb = top.G;
+  int64_t group = blockIdx.x, nb = top.G;   // nb: real nodes at the band's first level
   for (int band = 0; band < top.n_bands; ++band) {
-    const int64_t glo = group << 5;
-    const int real = (int)((nb - glo) < 32 ? (nb - glo) : 32);
+    const int lev0 = 5 * band;
+    const int bs = (top.n_levels - lev0) < 5 ? (top.n_levels - lev0) : 5;
+    const int gsz = 1 << bs;
+    const int64_t glo = group << bs;
+    const int real = (int)((nb - glo) < gsz ? (nb - glo) : gsz);
     if (band > 0) {
       __threadfence();
       __syncthreads();
@@ -424,9 +429,8 @@ __global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyp
       if (s_ticket != (unsigned int)(real - 1)) return;     // not the last of its group
       __threadfence();
     }
-    const int lev0 = 5 * band;
     const int64_t off0 = top_level_off(top, lev0);
-    if (tid < 32) {
+    if (tid < gsz) {
       Elem<B> Eg;
       if (tid < real) {
         elem_load<B>(top.elems, top.ld, off0 + glo + tid, Eg);
@@ -437,10 +441,10 @@ __global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyp
       lds_store<B, 32>(pool, tid, Eg);
     }
     lds_barrier();
-    SPG_UNROLL for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < bs; ++k) {
       const int stride = 1 << k;
       const int i = tid * 2 * stride;
-      if (i < 32) {
+      if (i < gsz) {
         Elem<B> E1, E2, Rr;
         lds_load<B, 32>(pool, i, E1);
         lds_load<B, 32>(pool, i + stride, E2);
@@ -451,8 +455,11 @@ __global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyp
       lds_barrier();
     }
     if (band > 0 && tid == 0) top.cnt[top.cnt_off[band] + group] = 0u;   // ready for the next call
-    group = group >> 5;
-    nb = (nb + 31) >> 5;
+    nb = (nb + gsz - 1) >> bs;
+    if (band + 1 < top.n_bands) {
+      const int bn = (top.n_levels - lev0 - 5) < 5 ? (top.n_levels - lev0 - 5) : 5;
+      group = group >> bn;
+    }
   }
   if (!BATCHED && tid == 0) {
     const SeriesPar p = load_par<B>(hyper);
@@ -511,7 +518,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
   Matern<B>::pinf(p, P0);
   const int64_t wg = blockIdx.x;
   const int64_t gbase = wg * (2 * L);
-  const int nlev = 5 * top.n_bands;
+  const int nlev = top.n_levels;
   {
     // ---- top-level path: child level l = tid holds sibling (wg >> l) ^ 1 of the path node
     if (tid < nlev) {

@@ -179,3 +179,28 @@ def test_graph_replays_match_eager(lib, batched):
     assert torch.equal(ll2, ll) and torch.equal(g2, g)
     eager.close()
     gh.close()
+
+
+def test_small_lane_tiles_only_on_small_handles(lib):
+    """Shapes with R < 8 need twice the lane workspace: a handle above 2^20 points refuses them
+    and its tuner never picks them; a small handle accepts every shape."""
+    small = [i for i in _tiles(lib) if lib.spingp_tile_shape(i)[0] < 8]
+    assert small, "the library compiles R = 4 shapes"
+    w = make_config(2, n=5000)
+    t, y, hyp = (to_dev(a) for a in w.series(0))
+    big = lib.Handle(w.terms, (1 << 20) + 1)
+    for i in small:
+        with pytest.raises(lib.SpinGPError):
+            big.tile = i
+    big.assemble(t, y, hyp)
+    assert lib.spingp_tile_shape(big.tune(reps=1))[0] >= 8
+    ll_big, g_big = [x.cpu().numpy() for x in big.logml_grad()]
+    h = lib.Handle(w.terms, 1 << 20)
+    h.assemble(t, y, hyp)
+    for i in small:
+        h.tile = i
+        ll, g = [x.cpu().numpy() for x in h.logml_grad()]
+        check_logml(ll.item(), ll_big.item(), tol=1e-12)
+        check_grad(g.reshape(-1), g_big.reshape(-1), tol=1e-10)
+    big.close()
+    h.close()
