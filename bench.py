@@ -5,7 +5,7 @@ spingp_assemble, as in a training loop whose optimiser updates the hyperparamete
 memory): chunk fold and work-group trees, top-level tree and down-sweeps, chunk elimination +
 adjoint sweep + gradient sum.  Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -31,11 +31,13 @@ PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flo
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes on
-# this workload, scaled by a 256 MiB copy (FETCH x 2.0, WRITE x 1.0); valid only for the tile
-# shape and the kernel sources they were taken on (sha256 over csrc/, see kernel_source_sha),
-# else reported as null.
-TRAFFIC = {"kernel": "bwd_elim_adjoint", "tile": (8, 128), "bytes": (42100.6 * 2.0 + 4192.0) * 1024.0,
-           "source_sha": "70f95540da10c400b631ce430ab100b163ca0dd454a9df02daf5c999668dc8d0"}
+# this workload, per tile shape (R, L), scaled by a 256 MiB copy (FETCH x 2.0, WRITE x 1.0);
+# valid only for the kernel sources they were taken on (sha256 over csrc/, see
+# kernel_source_sha), else reported as null.
+TRAFFIC = {"kernel": "bwd_elim_adjoint",
+           "bytes": {(8, 128): (44164.9 * 2.0 + 6240.2) * 1024.0,
+                     (8, 256): (44523.9 * 2.0 + 6192.0) * 1024.0},
+           "source_sha": "44d4d843a8150ac0655184d505341dd33dd976079d3ded79825c793439046027"}
 
 
 def kernel_source_sha():
@@ -71,8 +73,9 @@ def cpu_baseline(w, budget_s=10.0):
 
 def batched_report(spg, steps, warmup):
     """4096 independent Matern-5/2 series (lengths log-uniform in [64, 16384]) in one batched
-    call (autotuned tile shape, HIP-graph replay) against one single-series call per series on
-    pre-assembled handles, same GPU, same inputs resident in device memory."""
+    call (autotuned tile shape, eager launches on a side stream) against one single-series call
+    per series on pre-assembled handles, same GPU, same stream, same inputs resident in device
+    memory."""
     import torch
     from workloads import make_config
     w = make_config(4)
@@ -81,8 +84,10 @@ def batched_report(spg, steps, warmup):
     hd = torch.as_tensor(w.hyper.reshape(-1), device=dev)
     od = torch.as_tensor(w.offsets, device=dev)
     S, n = w.n_series, w.n_points
-    h = spg.Handle(w.terms, n, S)
-    h.assemble(td, yd, hd, od, graph=True, autotune=True)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    h = spg.Handle(w.terms, n, S, stream=side)
+    h.assemble(td, yd, hd, od, autotune=True)
     ll = torch.empty(S, dtype=torch.float64, device=dev)
     g = torch.empty(S, 3, dtype=torch.float64, device=dev)
     for _ in range(warmup):
@@ -101,7 +106,7 @@ def batched_report(spg, steps, warmup):
     hs, outs = [], []
     for s in range(S):
         a, e = int(w.offsets[s]), int(w.offsets[s + 1])
-        hh = spg.Handle(w.terms, e - a)
+        hh = spg.Handle(w.terms, e - a, stream=side)
         hh.assemble(td[a:e], yd[a:e], hd[3 * s: 3 * s + 3])
         hs.append(hh)
         outs.append((ll[s: s + 1], g[s: s + 1]))
@@ -109,7 +114,7 @@ def batched_report(spg, steps, warmup):
         for hh, (l1, g1) in zip(hs, outs):
             spg.spingp_logml_grad(hh._h, l1, g1)
     torch.cuda.synchronize()
-    ps_steps = max(1, steps // 4)
+    ps_steps = max(1, min(10, steps // 4))
     t0 = time.perf_counter()
     for _ in range(ps_steps):
         for hh, (l1, g1) in zip(hs, outs):
@@ -119,7 +124,7 @@ def batched_report(spg, steps, warmup):
     for hh in hs:
         hh.close()
     return {"workload": w.name, "n_series": S, "n_points": n, "points_per_s": n / el_b, "ms_per_step": 1e3 * el_b,
-            "tile": {"R": R, "L": L}, "graph": True, "steps": steps,
+            "tile": {"R": R, "L": L}, "launch": "eager, side stream", "steps": steps,
             "per_series_launch": {"points_per_s": n / el_s, "ms_per_step": 1e3 * el_s, "steps": ps_steps},
             "speedup": el_s / el_b}
 
@@ -137,8 +142,9 @@ def large_report(spg, steps, warmup):
     free0 = torch.cuda.mem_get_info()[0]
     td, yd = torch.as_tensor(w.t, device=dev), torch.as_tensor(w.y, device=dev)
     hd = torch.as_tensor(w.hyper.reshape(-1), device=dev)
-    h = spg.Handle(w.terms, n)
-    h.assemble(td, yd, hd, graph=True)
+    torch.cuda.synchronize()
+    h = spg.Handle(w.terms, n, stream=torch.cuda.Stream())
+    h.assemble(td, yd, hd, autotune=True)
     ll = torch.empty(1, dtype=torch.float64, device=dev)
     g = torch.empty(1, 3, dtype=torch.float64, device=dev)
     for _ in range(warmup):
@@ -153,15 +159,18 @@ def large_report(spg, steps, warmup):
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
     ws = h.workspace_bytes()
+    R, L = spg.spingp_tile_shape(h.tile)
     h.close()
     return {"workload": "matern52_n16777216_exp1gaps_logml_grad", "n_points": n, "points_per_s": n / el,
+            "tile": {"R": R, "L": L}, "launch": "eager, side stream",
             "ms_per_step": 1e3 * el, "steps": steps, "device_bytes_in_use": used, "workspace_bytes": ws,
             "input_bytes": 16 * n, "every_level_stored_bytes": 2 * 33 * 8 * n}
 
 
 def sum_report(spg, steps, warmup):
     """Matern-3/2 + periodic with 3 harmonics (b = 10), N = 2^18, t uniform on [0, 1e4]:
-    logML + the six-component gradient through the wide-state path, graph replay."""
+    logML + the six-component gradient through the wide-state path (eager launches on a side
+    stream; graph replay measures the same here)."""
     import torch
     from paper_1610_08035_amd.spingp import spingp_profile, spingp_profile_read
     from workloads import make_config
@@ -170,7 +179,9 @@ def sum_report(spg, steps, warmup):
     dev = torch.device("cuda:0")
     td, yd = torch.as_tensor(w.t, device=dev), torch.as_tensor(w.y, device=dev)
     hd = torch.as_tensor(w.hyper.reshape(-1), device=dev)
-    h = spg.Handle(w.terms, n)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    h = spg.Handle(w.terms, n, stream=side)
     h.assemble(td, yd, hd)
     ll = torch.empty(1, dtype=torch.float64, device=dev)
     g = torch.empty(1, 6, dtype=torch.float64, device=dev)
@@ -179,16 +190,11 @@ def sum_report(spg, steps, warmup):
     torch.cuda.synchronize()
     if h.status()[0] != 0:
         raise RuntimeError("sum-kernel workload failed validation")
-    # per-phase times from the library's events (eager launches), then the timed graph replays
+    # per-phase times from the library's events, then the timed steps without them
     spingp_profile(h._h, 1)
     spg.spingp_logml_grad(h._h, ll, g)
     prof = spingp_profile_read(h._h)
     spingp_profile(h._h, 0)
-    h.close()
-    h = spg.Handle(w.terms, n)
-    h.assemble(td, yd, hd, graph=True)
-    for _ in range(warmup):
-        spg.spingp_logml_grad(h._h, ll, g)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -199,7 +205,7 @@ def sum_report(spg, steps, warmup):
     phases = {"leaves_up_sweep": prof["fwd_fold_tree"][0], "root": prof["top_tree"][0],
               "down_sweep_node_step": prof["bwd_elim_adjoint"][0], "gradient_sum": prof["series_reduce"][0]}
     return {"workload": w.name + "_logml_grad", "n_points": n, "state_dim": 10, "n_hyper": 6,
-            "points_per_s": n / el, "ms_per_step": 1e3 * el, "steps": steps, "graph": True,
+            "points_per_s": n / el, "ms_per_step": 1e3 * el, "steps": steps, "launch": "eager, side stream",
             "phase_ms": {k: round(v, 4) for k, v in phases.items()}}
 
 
@@ -214,7 +220,8 @@ def predict_report(spg, steps, warmup):
     m = 1 << 16
     ts = torch.as_tensor(np.sort(np.random.default_rng(7).uniform(t[0], t[-1], m)), device=dev)
     td, yd, hd = (torch.as_tensor(a, device=dev) for a in (t, y, hyp))
-    h = spg.Handle(w.terms, t.shape[0] + m)
+    torch.cuda.synchronize()
+    h = spg.Handle(w.terms, t.shape[0] + m, stream=torch.cuda.Stream())
     h.assemble(td, yd, hd)
     fm = torch.empty(m, dtype=torch.float64, device=dev)
     fv = torch.empty_like(fm)
@@ -236,8 +243,8 @@ def predict_report(spg, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-series batched report")
     ap.add_argument("--no-large", action="store_true", help="skip the N = 2^24 report")
@@ -281,28 +288,28 @@ def main():
     td = torch.as_tensor(t, device=dev)
     yd = torch.as_tensor(y, device=dev)
     hd = torch.as_tensor(hyp, device=dev)
-    h = spg.Handle(w.terms, n)
+    torch.cuda.synchronize()
+    # All launches go to a side stream of default priority: back-to-back eager launches there
+    # keep the GPU busy (the host enqueues a step in about 12 us, the GPU runs it in about
+    # 100 us), while a graph replay or the legacy default stream adds a gap of several us per
+    # step.  The graph replay is timed as well and reported beside the main number.
+    side = torch.cuda.Stream()
     ll = torch.empty(1, dtype=torch.float64, device=dev)
     g = torch.empty(1, 3, dtype=torch.float64, device=dev)
-
-    # kernel times come from a profiled eager pass; the timed steps replay the captured graph
-    # the tile shape comes from the library's autotuner (timed at assemble on this problem)
-    hg = spg.Handle(w.terms, n)
+    hs = spg.Handle(w.terms, n, stream=side)
     if args.tile is None:
-        hg.assemble(td, yd, hd, graph=True, autotune=True)
+        hs.assemble(td, yd, hd, autotune=True)   # tile shape timed by the library's autotuner
     else:
-        hg.tile = args.tile
-        hg.assemble(td, yd, hd, graph=True)
-    h.tile = hg.tile
-    spg.spingp_assemble(h._h, td, yd, hd)
+        hs.tile = args.tile
+        hs.assemble(td, yd, hd)
 
     def step():
-        spg.spingp_logml_grad(hg._h, ll, g)
+        spg.spingp_logml_grad(hs._h, ll, g)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    rc, bad = h.status()
+    rc, bad = hs.status()
     if rc != 0:
         raise RuntimeError(f"device status {rc} at {bad}")
 
@@ -312,7 +319,23 @@ def main():
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # per-kernel averages: the same steps through eager launches with HIP events around each
+    # the same steps as HIP-graph replays (same stream, same tile)
+    hg = spg.Handle(w.terms, n, stream=side)
+    hg.tile = hs.tile
+    hg.assemble(td, yd, hd, graph=True)
+    for _ in range(args.warmup):
+        spg.spingp_logml_grad(hg._h, ll, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        spg.spingp_logml_grad(hg._h, ll, g)
+    torch.cuda.synchronize()
+    el_graph = (time.perf_counter() - t0) / args.steps
+    hg.close()
+    # per-kernel averages: the same steps with HIP events around each kernel on the side stream
+    h = spg.Handle(w.terms, n, stream=side)
+    h.tile = hs.tile
+    h.assemble(td, yd, hd)
     for _ in range(2):
         spg.spingp_logml_grad(h._h, ll, g)
     spingp_profile(h._h, 1)
@@ -320,7 +343,9 @@ def main():
         spg.spingp_logml_grad(h._h, ll, g)
     prof = spingp_profile_read(h._h)
     spingp_profile(h._h, 0)
-    hg.close()
+    spg.spingp_logml_grad(hs._h, ll, g)
+    torch.cuda.synchronize()
+    hs.close()
 
     ms_step = 1e3 * elapsed / args.steps
     value = n * args.steps / elapsed
@@ -328,9 +353,8 @@ def main():
     dom = max(FLOPS_PER_POINT, key=lambda k: per_kernel[k])
     achieved = FLOPS_PER_POINT[dom] * n / (per_kernel[dom] * 1e-3) / 1e12
     traffic = None
-    if (TRAFFIC["kernel"] == dom and TRAFFIC["source_sha"] == kernel_source_sha()
-            and tuple(spg.spingp_tile_shape(h.tile)) == TRAFFIC["tile"]):
-        traffic = TRAFFIC["bytes"]
+    if TRAFFIC["kernel"] == dom and TRAFFIC["source_sha"] == kernel_source_sha():
+        traffic = TRAFFIC["bytes"].get(tuple(spg.spingp_tile_shape(h.tile)))
     out = {
         "metric": "time points/sec, logML+grad, Matern-5/2 N=2^20 FP64; % HBM roofline",
         "value": value,
@@ -345,8 +369,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded GP prior sample + noise, Exp(1) gaps)",
         "config": {"workload": "matern52_n1048576_exp1gaps_logml_grad", "n_points": n, "state_dim": 3,
-                   "n_hyper": 3, "hyper": [float(v) for v in hyp], "graph": True,
-                   "tile": dict(zip(("R", "L"), spg.spingp_tile_shape(h.tile)))},
+                   "n_hyper": 3, "hyper": [float(v) for v in hyp], "launch": "eager, side stream",
+                   "tile": dict(zip(("R", "L"), spg.spingp_tile_shape(h.tile))),
+                   "cache": "inputs and workspace (about 80 MB) stay resident in the 256 MB MALL between steps"},
+        "graph_replay": {"ms_per_step": 1e3 * el_graph, "points_per_s": n / el_graph},
         "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                      "flops_per_point": FLOPS_PER_POINT[dom]},
