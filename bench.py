@@ -240,6 +240,32 @@ def predict_report(spg, steps, warmup):
             "ms_per_call": 1e3 * el, "merged_points_per_s": (t.shape[0] + m) / el, "steps": steps}
 
 
+def fit_report(spg):
+    """Maximum-marginal-likelihood fit of the N = 2^20 Matern-5/2 series by scaled conjugate
+    gradients from a start away from the generating hyperparameters (l = 5, var = 2,
+    s2 = 0.05): evaluations, wall time, time per evaluation (one logML + gradient call plus
+    the host round trip of five numbers)."""
+    import torch
+    from paper_1610_08035_amd.optimize import fit
+    from workloads import make_config
+    w = make_config(2)
+    t, y, hyp = w.series(0)
+    dev = torch.device("cuda:0")
+    td, yd = torch.as_tensor(t, device=dev), torch.as_tensor(y, device=dev)
+    h = spg.Handle(w.terms, t.shape[0], stream=torch.cuda.Stream())
+    hyper0 = [2.0, 1.0, 0.2]
+    fit(td, yd, w.terms, hyper0, max_iter=3, handle=h)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = fit(td, yd, w.terms, hyper0, handle=h)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h.close()
+    return {"workload": "matern52_n1048576_fit_scg", "start": hyper0, "hyper": [float(v) for v in res.hyper[0]],
+            "logml": float(res.logml[0]), "converged": res.converged, "iterations": res.n_iter,
+            "evaluations": res.n_eval, "seconds": el, "ms_per_evaluation": 1e3 * el / res.n_eval}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,9 +276,10 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the N = 2^24 report")
     ap.add_argument("--no-sum", action="store_true", help="skip the b = 10 sum-kernel report")
     ap.add_argument("--no-predict", action="store_true", help="skip the prediction report")
+    ap.add_argument("--no-fit", action="store_true", help="skip the hyperparameter-fit report")
     ap.add_argument("--tile", type=int, default=None,
                     help="headline tile shape index instead of the autotuner's choice (counter runs)")
-    ap.add_argument("--only", choices=["batched", "large", "sum", "predict"], default=None,
+    ap.add_argument("--only", choices=["batched", "large", "sum", "predict", "fit"], default=None,
                     help="run one secondary workload alone and print its JSON (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM counters)")
@@ -276,6 +303,9 @@ def main():
     from paper_1610_08035_amd.spingp import spingp_profile, spingp_profile_read
     from workloads import make_config
     if args.only:
+        if args.only == "fit":
+            print(json.dumps({"fit": fit_report(spg)}), flush=True)
+            return
         fn = {"batched": batched_report, "large": large_report, "sum": sum_report,
               "predict": predict_report}[args.only]
         print(json.dumps({args.only: fn(spg, args.steps, args.warmup)}), flush=True)
@@ -388,6 +418,8 @@ def main():
         out["sum_kernel"] = sum_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_predict:
         out["predict"] = predict_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
+    if not args.no_fit:
+        out["fit"] = fit_report(spg)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -2,7 +2,8 @@
 
 The computation lives in the gfx950 library ``libspingp.so`` behind the C ABI of
 ``include/spingp.h``; ``spingp`` is its thin Python binding and ``autograd`` wraps the log
-marginal likelihood and its hand-written gradient as a torch.autograd.Function.
+marginal likelihood and its hand-written gradient as a torch.autograd.Function;
+``optimize`` fits hyperparameters by maximum marginal likelihood.
 """
 from .spingp import (  # noqa: F401
     MATERN32,
@@ -29,3 +30,4 @@ from .spingp import (  # noqa: F401
     spingp_tune,
     spingp_workspace_bytes,
 )
+from .optimize import FitResult, fit, scg  # noqa: F401,E402

@@ -231,6 +231,7 @@ class Handle:
 
     def __init__(self, terms, max_points, max_series=1, stream=None):
         self.terms = [tuple(x) for x in terms]
+        self.stream = stream            # None: torch's current stream at creation
         self._h = spingp_create(self.terms, max_points, max_series, stream)
         lib = load_library()
         self.b = lib.spingp_state_dim(self._h)
