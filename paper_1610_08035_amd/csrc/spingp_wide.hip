@@ -9,9 +9,10 @@ namespace {
 using Model = SumM32Periodic<3>;
 static_assert(Model::B == kStateDim, "state dimension of the wide model");
 static_assert(Model::NH == kHyper, "hyperparameters of the wide model");
-// Work-group caps: about what fits on the 256 CUs at once for each kernel's LDS and VGPRs,
-// so that no launch ends with a second, mostly empty round.
-constexpr int kGridUp = 2048, kGridDown = 4096, kGridLeaf = 4096, kGridNode = 1536;
+// Work-group caps: what fits on the 256 CUs at once for each kernel's LDS (up 15 KB: 10 per
+// CU, down 13 KB: 11, node 21 KB: 7), so that every team stays resident and loops over its
+// items instead of a launch ending with a second, partly empty round.
+constexpr int kGridUp = 2560, kGridDown = 2816, kGridLeaf = 4096, kGridNode = 1792;
 
 inline void mark(const WideCtx& c, int kid, int end) {
   if (c.mark) c.mark(c.mark_arg, kid, end);

@@ -133,118 +133,167 @@ SPG_DEV double t_dot(const double* a, const double* b) {
   return s;
 }
 
-// G = M^-1 by Gauss-Jordan with partial pivoting (M is overwritten); returns log |det M|.
-// The pivot search is done redundantly by every lane, so the pivot row is uniform.
+// Value of x in lane `lane` (uniform) for every lane of the wavefront.
+SPG_DEV double lane_bcast(double x, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// G = M^-1 by Gauss-Jordan with partial pivoting; returns log |det M| (the same in every lane).
+// Lane r < B keeps row r of [M | G] in registers; the pivot search reads the candidates of the
+// other lanes and the pivot row is broadcast lane to lane, so no column step goes through LDS.
+// Lanes r >= B shadow row B - 1 and write nothing.  M itself is left unchanged.
 template <int B>
-SPG_DEV double t_inv_logdet(double* M, double* G, double* fcol) {
+SPG_DEV double t_inv_logdet(double* M, double* G, double* /*unused*/) {
   const int tid = threadIdx.x;
-  for (int e = tid; e < B * B; e += kW) G[e] = (e / B == e % B) ? 1.0 : 0.0;
-  tsync();
-  double ld = 0.0;
-  for (int c = 0; c < B; ++c) {
+  const int r = tid < B ? tid : B - 1;
+  double a[B], g[B];
+  SPG_UNROLL for (int k = 0; k < B; ++k) {
+    a[k] = M[r * B + k];
+    g[k] = (r == k) ? 1.0 : 0.0;
+  }
+  double mant = 1.0;   // product of the pivots as mantissa and binary exponent: one log at the end
+  int expo = 0;
+  SPG_UNROLL for (int c = 0; c < B; ++c) {
+    // pivot: the first row q >= c with the largest |a[c]|
+    const double mine = fabs(a[c]);
     int p = c;
-    double best = fabs(M[c * B + c]);
-    for (int r = c + 1; r < B; ++r) {
-      const double v = fabs(M[r * B + c]);
+    double best = lane_bcast(mine, c);
+    for (int q = c + 1; q < B; ++q) {
+      const double v = lane_bcast(mine, q);
       if (v > best) {
         best = v;
-        p = r;
+        p = q;
       }
     }
-    tsync();
-    if (p != c) {
-      if (tid < B) {
-        const double x = M[c * B + tid];
-        M[c * B + tid] = M[p * B + tid];
-        M[p * B + tid] = x;
-      } else if (tid < 2 * B) {
-        const int k = tid - B;
-        const double x = G[c * B + k];
-        G[c * B + k] = G[p * B + k];
-        G[p * B + k] = x;
+    if (p != c) {   // uniform: exchange rows c and p
+      SPG_UNROLL for (int k = c; k < B; ++k) {
+        const double xc = lane_bcast(a[k], c), xp = lane_bcast(a[k], p);
+        if (tid == c) a[k] = xp;
+        if (tid == p) a[k] = xc;
       }
-      tsync();
+      SPG_UNROLL for (int k = 0; k < B; ++k) {
+        const double xc = lane_bcast(g[k], c), xp = lane_bcast(g[k], p);
+        if (tid == c) g[k] = xp;
+        if (tid == p) g[k] = xc;
+      }
     }
-    const double piv = M[c * B + c];
-    ld += log(fabs(piv));
+    const double piv = lane_bcast(a[c], c);
+    int e;
+    mant *= frexp(piv, &e);
+    expo += e;
     const double ip = 1.0 / piv;
-    if (tid < B) fcol[tid] = M[tid * B + c];
-    tsync();
-    if (tid < B) M[c * B + tid] *= ip;
-    else if (tid < 2 * B) G[c * B + tid - B] *= ip;
-    tsync();
-    for (int e = tid; e < 2 * B * B; e += kW) {
-      const int mat = e / (B * B), f = e - mat * B * B;
-      const int r = f / B, k = f - r * B;
-      if (r == c) continue;
-      double* X = mat ? G : M;
-      X[r * B + k] = fma(-fcol[r], X[c * B + k], X[r * B + k]);
+    const double f = (tid == c) ? 0.0 : a[c];     // this row's multiplier of the pivot row
+    SPG_UNROLL for (int k = c + 1; k < B; ++k) {
+      const double pk = lane_bcast(a[k], c) * ip;
+      a[k] = (tid == c) ? pk : fma(-f, pk, a[k]);
     }
-    tsync();
+    a[c] = (tid == c) ? 1.0 : 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      const double pk = lane_bcast(g[k], c) * ip;
+      g[k] = (tid == c) ? pk : fma(-f, pk, g[k]);
+    }
   }
-  return ld;
+  if (tid < B) {
+    SPG_UNROLL for (int k = 0; k < B; ++k) G[tid * B + k] = g[k];
+  }
+  tsync();
+  return log(fabs(mant)) + expo * 0.69314718055994530942;
 }
 
 // ---------------------------------------------------------------------------- element ops
+// Entry (i, j) of X Y (TX: X^T, TY: Y^T) for row-major B x B blocks in LDS.
+template <int B, bool TX, bool TY>
+SPG_DEV double mm_entry(const double* X, const double* Y, int i, int j) {
+  double s = 0.0;
+  SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(TX ? X[k * B + i] : X[i * B + k], TY ? Y[j * B + k] : Y[k * B + j], s);
+  return s;
+}
+// Entry (i, j) of the symmetric part (Z + Z^T) / 2 of Z = X Y.
+template <int B, bool TX, bool TY>
+SPG_DEV double mm_sym_entry(const double* X, const double* Y, int i, int j) {
+  return 0.5 * (mm_entry<B, TX, TY>(X, Y, i, j) + mm_entry<B, TX, TY>(X, Y, j, i));
+}
+
+// The element operations below run as a few phases, one barrier each: every lane computes
+// the same entry of all the independent products of a phase (and lanes < B the vectors).
+
 // R = E1 (x) E2 (join at the shared node; see spingp_device.hpp).
 template <int B>
 SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tmp) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
-  double *M = tmp, *G = M + BB, *Pp = G + BB, *W = Pp + BB, *GA = W + BB, *T = GA + BB, *WA = T + BB,
-         *AWA = WA + BB;
-  double* v = AWA + BB;
-  double *Gb = v, *Ppe = v + B, *g = v + 2 * B, *Gte = v + 3 * B, *Wb = v + 4 * B, *r = v + 5 * B, *Ag = v + 6 * B,
-         *Ar = v + 7 * B, *fcol = v + 8 * B;
+  double *M = tmp, *G = M + BB, *Pp = G + BB, *W = Pp + BB, *GA = W + BB, *T = GA + BB, *WA = T + BB;
+  double* v = tmp + 8 * BB;
+  double *Gb = v, *Ppe = v + B, *g = v + 2 * B, *Gte = v + 3 * B, *Wb = v + 4 * B, *r = v + 5 * B;
+  const double *A1 = E1 + Y::kA, *b1 = E1 + Y::kb, *Q1 = E1 + Y::kQ, *J1 = E1 + Y::kJ, *eta1 = E1 + Y::keta;
+  const double *A2 = E2 + Y::kA, *b2 = E2 + Y::kb, *Q2 = E2 + Y::kQ, *J2 = E2 + Y::kJ, *eta2 = E2 + Y::keta;
   const int tid = threadIdx.x;
-  t_mm<B>(E1 + Y::kQ, E2 + Y::kJ, M);
-  t_add_eye<B>(M);
-  const double ld = t_inv_logdet<B>(M, G, fcol);
-  t_mm<B>(G, E1 + Y::kQ, Pp);
-  t_sym<B>(Pp);
-  t_mm<B>(E2 + Y::kJ, G, W);
-  t_sym<B>(W);
-  t_mm<B>(G, E1 + Y::kA, GA);
-  if (tid < B) {
-    const int i = tid;
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) {
-      s1 = fma(G[i * B + k], E1[Y::kb + k], s1);
-      s2 = fma(Pp[i * B + k], E2[Y::keta + k], s2);
-      s3 = fma(G[k * B + i], E2[Y::keta + k], s3);
-      s4 = fma(W[i * B + k], E1[Y::kb + k], s4);
-    }
-    Gb[i] = s1;
-    Ppe[i] = s2;
-    Gte[i] = s3;
-    Wb[i] = s4;
-    g[i] = s1 + s2;
-    r[i] = s3 - s4;
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    M[e] = mm_entry<B, false, false>(Q1, J2, i, j) + (i == j ? 1.0 : 0.0);
   }
   tsync();
-  const double cf = -0.5 * t_dot<B>(E1 + Y::kb, Wb) + t_dot<B>(E2 + Y::keta, Gb) + 0.5 * t_dot<B>(E2 + Y::keta, Ppe);
-  t_mm<B>(E2 + Y::kA, GA, R + Y::kA);
-  t_mv<B>(E2 + Y::kA, g, Ag);
-  t_mm<B>(E2 + Y::kA, Pp, T);
-  t_mmt<B>(T, E2 + Y::kA, R + Y::kQ);
-  t_mm<B>(W, E1 + Y::kA, WA);
-  t_mtm<B>(E1 + Y::kA, WA, AWA);
-  t_mtv<B>(E1 + Y::kA, r, Ar);
+  const double ld = t_inv_logdet<B>(M, G, nullptr);
+  // P+ = G Q1, W = J2 G (both symmetric), G A1; G b1, G^T eta2
   for (int e = tid; e < BB; e += kW) {
-    R[Y::kQ + e] += E2[Y::kQ + e];
-    R[Y::kJ + e] = E1[Y::kJ + e] + AWA[e];
+    const int i = e / B, j = e - i * B;
+    Pp[e] = mm_sym_entry<B, false, false>(G, Q1, i, j);
+    W[e] = mm_sym_entry<B, false, false>(J2, G, i, j);
+    GA[e] = mm_entry<B, false, false>(G, A1, i, j);
   }
   if (tid < B) {
-    R[Y::kb + tid] = Ag[tid] + E2[Y::kb + tid];
-    R[Y::keta + tid] = E1[Y::keta + tid] + Ar[tid];
+    double s1 = 0.0, s3 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      s1 = fma(G[tid * B + k], b1[k], s1);
+      s3 = fma(G[k * B + tid], eta2[k], s3);
+    }
+    Gb[tid] = s1;
+    Gte[tid] = s3;
+  }
+  tsync();
+  // new transition A2 G A1, A2 P+, W A1; P+ eta2, W b1 and the vectors g, r
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    R[Y::kA + e] = mm_entry<B, false, false>(A2, GA, i, j);
+    T[e] = mm_entry<B, false, false>(A2, Pp, i, j);
+    WA[e] = mm_entry<B, false, false>(W, A1, i, j);
+  }
+  if (tid < B) {
+    double s2 = 0.0, s4 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      s2 = fma(Pp[tid * B + k], eta2[k], s2);
+      s4 = fma(W[tid * B + k], b1[k], s4);
+    }
+    Ppe[tid] = s2;
+    Wb[tid] = s4;
+    g[tid] = Gb[tid] + s2;
+    r[tid] = Gte[tid] - s4;
+  }
+  tsync();
+  // new noise A2 P+ A2^T + Q2, information J1 + A1^T W A1 (both symmetric), new offset and eta
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    R[Y::kQ + e] = mm_sym_entry<B, false, true>(T, A2, i, j) + Q2[e];
+    R[Y::kJ + e] = J1[e] + mm_sym_entry<B, true, false>(A1, WA, i, j);
+  }
+  if (tid < B) {
+    double s5 = 0.0, s6 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      s5 = fma(A2[tid * B + k], g[k], s5);
+      s6 = fma(A1[k * B + tid], r[k], s6);
+    }
+    R[Y::kb + tid] = s5 + b2[tid];
+    R[Y::keta + tid] = eta1[tid] + s6;
   }
   if (tid == 0) {
+    const double cf = -0.5 * t_dot<B>(b1, Wb) + t_dot<B>(eta2, Gb) + 0.5 * t_dot<B>(eta2, Ppe);
     R[Y::kcf] = E1[Y::kcf] + E2[Y::kcf] + cf;
     R[Y::kcl] = E1[Y::kcl] + E2[Y::kcl] - 0.5 * ld;
   }
   tsync();
-  t_sym<B>(R + Y::kQ);
-  t_sym<B>(R + Y::kJ);
 }
 
 // Prefix: the predicted state N(m, P) at E's left node pushed through E -> (mo, Po); returns
@@ -256,38 +305,53 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
   constexpr int BB = B * B;
   double *M = tmp, *G = M + BB, *Pp = G + BB, *W = Pp + BB, *T = W + BB;
   double* v = tmp + 8 * BB;
-  double *Gm = v, *Ppe = v + B, *g = v + 2 * B, *Wm = v + 3 * B, *Ag = v + 4 * B, *fcol = v + 8 * B;
+  double *Gm = v, *Ppe = v + B, *g = v + 2 * B, *Wm = v + 3 * B;
+  const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
-  t_mm<B>(P, E + Y::kJ, M);
-  t_add_eye<B>(M);
-  const double ld = t_inv_logdet<B>(M, G, fcol);
-  t_mm<B>(G, P, Pp);
-  t_sym<B>(Pp);
-  t_mm<B>(E + Y::kJ, G, W);
-  t_sym<B>(W);
-  if (tid < B) {
-    const int i = tid;
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) {
-      s1 = fma(G[i * B + k], m[k], s1);
-      s2 = fma(Pp[i * B + k], E[Y::keta + k], s2);
-      s3 = fma(W[i * B + k], m[k], s3);
-    }
-    Gm[i] = s1;
-    Ppe[i] = s2;
-    Wm[i] = s3;
-    g[i] = s1 + s2;
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    M[e] = mm_entry<B, false, false>(P, J, i, j) + (i == j ? 1.0 : 0.0);
   }
   tsync();
-  dcf = -0.5 * t_dot<B>(m, Wm) + t_dot<B>(E + Y::keta, Gm) + 0.5 * t_dot<B>(E + Y::keta, Ppe) + E[Y::kcf];
-  dcl = -0.5 * ld + E[Y::kcl];
-  t_mv<B>(E + Y::kA, g, Ag);
-  t_mm<B>(E + Y::kA, Pp, T);
-  t_mmt<B>(T, E + Y::kA, Po);
-  for (int e = tid; e < BB; e += kW) Po[e] += E[Y::kQ + e];
-  if (tid < B) mo[tid] = Ag[tid] + E[Y::kb + tid];
+  const double ld = t_inv_logdet<B>(M, G, nullptr);
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    Pp[e] = mm_sym_entry<B, false, false>(G, P, i, j);
+    W[e] = mm_sym_entry<B, false, false>(J, G, i, j);
+  }
+  if (tid < B) {
+    double s1 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s1 = fma(G[tid * B + k], m[k], s1);
+    Gm[tid] = s1;
+  }
   tsync();
-  t_sym<B>(Po);
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    T[e] = mm_entry<B, false, false>(A, Pp, i, j);
+  }
+  if (tid < B) {
+    double s2 = 0.0, s3 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      s2 = fma(Pp[tid * B + k], eta[k], s2);
+      s3 = fma(W[tid * B + k], m[k], s3);
+    }
+    Ppe[tid] = s2;
+    Wm[tid] = s3;
+    g[tid] = Gm[tid] + s2;
+  }
+  tsync();
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    Po[e] = mm_sym_entry<B, false, true>(T, A, i, j) + Q[e];
+  }
+  if (tid < B) {
+    double s4 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s4 = fma(A[tid * B + k], g[k], s4);
+    mo[tid] = s4 + bb[tid];
+  }
+  dcf = -0.5 * t_dot<B>(m, Wm) + t_dot<B>(eta, Gm) + 0.5 * t_dot<B>(eta, Ppe) + E[Y::kcf];
+  dcl = -0.5 * ld + E[Y::kcl];
+  tsync();
 }
 
 // Suffix: information (Jb, etab) on E's right node pulled back to its left node -> (Jo, etao).
@@ -295,32 +359,47 @@ template <int B>
 SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, double* Jo, double* etao, double* tmp) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
-  double *M = tmp, *G = M + BB, *W = G + BB, *WA = W + BB, *AWA = WA + BB;
+  double *M = tmp, *G = M + BB, *W = G + BB, *WA = W + BB;
   double* v = tmp + 8 * BB;
-  double *r = v, *Ar = v + B, *fcol = v + 8 * B;
+  double *s1v = v, *r = v + B;
+  const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
-  t_mm<B>(E + Y::kQ, Jb, M);
-  t_add_eye<B>(M);
-  (void)t_inv_logdet<B>(M, G, fcol);
-  t_mm<B>(Jb, G, W);
-  t_sym<B>(W);
-  if (tid < B) {
-    const int i = tid;
-    double s1 = 0.0, s2 = 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) {
-      s1 = fma(G[k * B + i], etab[k], s1);
-      s2 = fma(W[i * B + k], E[Y::kb + k], s2);
-    }
-    r[i] = s1 - s2;
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    M[e] = mm_entry<B, false, false>(Q, Jb, i, j) + (i == j ? 1.0 : 0.0);
   }
   tsync();
-  t_mm<B>(W, E + Y::kA, WA);
-  t_mtm<B>(E + Y::kA, WA, AWA);
-  t_mtv<B>(E + Y::kA, r, Ar);
-  for (int e = tid; e < BB; e += kW) Jo[e] = E[Y::kJ + e] + AWA[e];
-  if (tid < B) etao[tid] = E[Y::keta + tid] + Ar[tid];
+  (void)t_inv_logdet<B>(M, G, nullptr);
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    W[e] = mm_sym_entry<B, false, false>(Jb, G, i, j);
+  }
+  if (tid < B) {
+    double s1 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s1 = fma(G[k * B + tid], etab[k], s1);
+    s1v[tid] = s1;
+  }
   tsync();
-  t_sym<B>(Jo);
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    WA[e] = mm_entry<B, false, false>(W, A, i, j);
+  }
+  if (tid < B) {
+    double s2 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s2 = fma(W[tid * B + k], bb[k], s2);
+    r[tid] = s1v[tid] - s2;
+  }
+  tsync();
+  for (int e = tid; e < BB; e += kW) {
+    const int i = e / B, j = e - i * B;
+    Jo[e] = J[e] + mm_sym_entry<B, true, false>(A, WA, i, j);
+  }
+  if (tid < B) {
+    double s3 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) s3 = fma(A[k * B + tid], r[k], s3);
+    etao[tid] = eta[tid] + s3;
+  }
+  tsync();
 }
 
 // ---------------------------------------------------------------------------- the model
