@@ -240,6 +240,46 @@ def predict_report(spg, steps, warmup):
             "ms_per_call": 1e3 * el, "merged_points_per_s": (t.shape[0] + m) / el, "steps": steps}
 
 
+def bsweep_report(spg, steps, warmup):
+    """Block size sweep in the manner of the paper's time-versus-b experiment: logML + gradient
+    per call for Matern nu = 1/2 .. 7/2 (b = 1 .. 4) and the b = 10 sum kernel, at N = 1000
+    and at N = 2^20 (2^18 for b = 10), eager launches on a side stream."""
+    import torch
+    from workloads import (KIND_MATERN12, KIND_MATERN32, KIND_MATERN52, KIND_MATERN72, make_batch,
+                           make_config)
+    dev = torch.device("cuda:0")
+    side = torch.cuda.Stream()
+    rows = []
+    cases = [(1, [(KIND_MATERN12, 0)]), (2, [(KIND_MATERN32, 0)]), (3, [(KIND_MATERN52, 0)]),
+             (4, [(KIND_MATERN72, 0)]), (10, None)]
+    for b, terms in cases:
+        for n in (1000, (1 << 18) if b == 10 else (1 << 20)):
+            if terms is None:
+                w = make_config(3, n=n)
+            else:
+                w = make_batch([n], np.array([[5.0, 2.0, 0.05]]), terms, seed=b)
+            t, y, hyp = w.series(0)
+            td, yd, hd = (torch.as_tensor(a, device=dev) for a in (t, y, hyp))
+            torch.cuda.synchronize()
+            h = spg.Handle(w.terms, n, stream=side)
+            h.assemble(td, yd, hd, autotune=b <= 4)
+            ll = torch.empty(1, dtype=torch.float64, device=dev)
+            g = torch.empty(1, h.n_hyper, dtype=torch.float64, device=dev)
+            for _ in range(warmup):
+                spg.spingp_logml_grad(h._h, ll, g)
+            torch.cuda.synchronize()
+            k = steps if n <= (1 << 18) or b < 10 else max(2, steps // 4)
+            t0 = time.perf_counter()
+            for _ in range(k):
+                spg.spingp_logml_grad(h._h, ll, g)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / k
+            rows.append({"b": b, "n_points": n, "ms_per_call": 1e3 * el, "points_per_s": n / el,
+                         "tile": dict(zip(("R", "L"), spg.spingp_tile_shape(h.tile))) if b <= 4 else "wide"})
+            h.close()
+    return rows
+
+
 def fit_report(spg):
     """Maximum-marginal-likelihood fit of the N = 2^20 Matern-5/2 series by scaled conjugate
     gradients from a start away from the generating hyperparameters (l = 5, var = 2,
@@ -277,9 +317,10 @@ def main():
     ap.add_argument("--no-sum", action="store_true", help="skip the b = 10 sum-kernel report")
     ap.add_argument("--no-predict", action="store_true", help="skip the prediction report")
     ap.add_argument("--no-fit", action="store_true", help="skip the hyperparameter-fit report")
+    ap.add_argument("--no-bsweep", action="store_true", help="skip the block-size sweep")
     ap.add_argument("--tile", type=int, default=None,
                     help="headline tile shape index instead of the autotuner's choice (counter runs)")
-    ap.add_argument("--only", choices=["batched", "large", "sum", "predict", "fit"], default=None,
+    ap.add_argument("--only", choices=["batched", "large", "sum", "predict", "fit", "bsweep"], default=None,
                     help="run one secondary workload alone and print its JSON (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM counters)")
@@ -307,7 +348,7 @@ def main():
             print(json.dumps({"fit": fit_report(spg)}), flush=True)
             return
         fn = {"batched": batched_report, "large": large_report, "sum": sum_report,
-              "predict": predict_report}[args.only]
+              "predict": predict_report, "bsweep": bsweep_report}[args.only]
         print(json.dumps({args.only: fn(spg, args.steps, args.warmup)}), flush=True)
         return
 
@@ -420,6 +461,8 @@ def main():
         out["predict"] = predict_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_fit:
         out["fit"] = fit_report(spg)
+    if not args.no_bsweep:
+        out["bsweep"] = bsweep_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -54,7 +54,13 @@ typedef enum {
   SPINGP_E_UNSUPPORTED = 8  /* model or size the library does not implement */
 } spingp_status_t;
 
-typedef enum { SPINGP_MATERN32 = 1, SPINGP_MATERN52 = 2, SPINGP_PERIODIC = 3 } spingp_kind_t;
+typedef enum {
+  SPINGP_MATERN32 = 1,  /* Matern nu = 3/2, state (f, f'), b = 2 */
+  SPINGP_MATERN52 = 2,  /* Matern nu = 5/2, b = 3 */
+  SPINGP_PERIODIC = 3,  /* periodic, `harmonics` cosine terms, b = 2 (harmonics + 1) */
+  SPINGP_MATERN12 = 4,  /* Matern nu = 1/2 (exponential kernel), b = 1 */
+  SPINGP_MATERN72 = 5   /* Matern nu = 7/2, b = 4 */
+} spingp_kind_t;
 
 /* One additive covariance term; `harmonics` is used by periodic terms only. */
 typedef struct {
@@ -65,8 +71,10 @@ typedef struct {
 /*
  * Create a handle for a model given as a sum of terms (host array of n_terms entries) and the
  * largest problem it will see.  `stream` is a hipStream_t (NULL = the default stream).
- * Supported models: a single Matern-3/2 (b = 2) or Matern-5/2 (b = 3) term; any number of
- * series up to max_series.  Allocates all device workspace (sized for every compiled tile shape,
+ * Supported models: a single Matern term, nu = 1/2, 3/2, 5/2 or 7/2 (b = 1 to 4; hyperparameter
+ * row (lengthscale, signal variance, noise variance), lam = sqrt(2 nu) / lengthscale), any
+ * number of series up to max_series; Matern-3/2 + periodic with 3 harmonics (b = 10, one
+ * series).  Allocates all device workspace (sized for every compiled tile shape,
  * see spingp_tile_shape); returns SPINGP_E_UNSUPPORTED for other models.
  */
 int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,

@@ -133,11 +133,12 @@ static int model_init(model_t* m, int n_terms, const int* kinds, const int* harm
     m->harm[i] = harm[i];
     m->off[i] = b;
     m->pidx[i] = p;
-    if (kinds[i] == 1 || kinds[i] == 2) {
-      m->dim[i] = kinds[i] == 1 ? 2 : 3;
+    if (kinds[i] == 1 || kinds[i] == 2 || kinds[i] == 4 || kinds[i] == 5) {
+      /* Matern nu = dim - 1/2: kinds 4, 1, 2, 5 are nu = 1/2, 3/2, 5/2, 7/2 */
+      m->dim[i] = kinds[i] == 4 ? 1 : kinds[i] == 1 ? 2 : kinds[i] == 2 ? 3 : 4;
       m->ell[i] = hyper[p];
       m->var[i] = hyper[p + 1];
-      m->lam[i] = sqrt(kinds[i] == 1 ? 3.0 : 5.0) / m->ell[i];
+      m->lam[i] = sqrt(2.0 * m->dim[i] - 1.0) / m->ell[i];
       p += 2;
     } else if (kinds[i] == 3) {
       m->dim[i] = 2 * (harm[i] + 1);
@@ -164,7 +165,28 @@ static int model_init(model_t* m, int n_terms, const int* kinds, const int* harm
   for (int i = 0; i < n_terms; ++i) {
     int o = m->off[i];
     int pi = m->pidx[i];
-    if (m->kind[i] == 1) {
+    if (m->kind[i] == 4) {
+      m->P[o * b + o] = m->var[i];
+      m->dP[pi + 1][o * b + o] = 1.0;
+      m->h[o] = 1.0;
+    } else if (m->kind[i] == 5) {
+      /* entry (r, c) = (-1)^c times the (r + c)-th derivative of k at 0; those are
+         -v l^2/5 (second), v l^4/5 (fourth), -v l^6 (sixth) */
+      double l = m->lam[i], v = m->var[i], dl = -l / m->ell[i];
+      double l2 = l * l, l4 = l2 * l2;
+      double Pm[16] = {1.0, 0.0, -l2 / 5.0, 0.0, 0.0, l2 / 5.0, 0.0, -l4 / 5.0,
+                       -l2 / 5.0, 0.0, l4 / 5.0, 0.0, 0.0, -l4 / 5.0, 0.0, l4 * l2};
+      double dPm[16] = {0.0, 0.0, -2.0 * l / 5.0, 0.0, 0.0, 2.0 * l / 5.0, 0.0, -4.0 * l2 * l / 5.0,
+                        -2.0 * l / 5.0, 0.0, 4.0 * l2 * l / 5.0, 0.0, 0.0, -4.0 * l2 * l / 5.0, 0.0,
+                        6.0 * l4 * l};
+      for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+          m->P[(o + r) * b + o + c] = v * Pm[r * 4 + c];
+          m->dP[pi][(o + r) * b + o + c] = v * dPm[r * 4 + c] * dl;
+          m->dP[pi + 1][(o + r) * b + o + c] = Pm[r * 4 + c];
+        }
+      m->h[o] = 1.0;
+    } else if (m->kind[i] == 1) {
       double l = m->lam[i], v = m->var[i], dl = -l / m->ell[i];
       m->P[o * b + o] = v;
       m->P[(o + 1) * b + o + 1] = v * l * l;
@@ -206,33 +228,44 @@ static void model_A(const model_t* m, double dt, double* A, double (*dA)[MAXB * 
     for (int k = 0; k < m->n_kernel_params; ++k) memset(dA[k], 0, sizeof(double) * b * b);
   for (int i = 0; i < m->n_parts; ++i) {
     int o = m->off[i], pi = m->pidx[i];
-    if (m->kind[i] == 1 || m->kind[i] == 2) {
+    if (m->kind[i] != 3) {
+      /* Matern: F is the companion matrix of (s + l)^d; N = F + l I is nilpotent (N^d = 0) and
+         A = e^{-l dt} (I + N dt + N^2 dt^2/2 + N^3 dt^3/6); dN/dl = dF/dl + I */
       int d = m->dim[i];
       double l = m->lam[i];
-      double N[9] = {0}, Nd[9] = {0};
-      if (d == 2) {
-        double n2[4] = {l, 1.0, -l * l, -l}, nd2[4] = {1.0, 0.0, -2.0 * l, -1.0};
-        memcpy(N, n2, sizeof(n2));
-        memcpy(Nd, nd2, sizeof(nd2));
-      } else {
-        double n3[9] = {l, 1.0, 0.0, 0.0, l, 1.0, -l * l * l, -3.0 * l * l, -2.0 * l};
-        double nd3[9] = {1.0, 0.0, 0.0, 0.0, 1.0, 0.0, -3.0 * l * l, -6.0 * l, -2.0};
-        memcpy(N, n3, sizeof(n3));
-        memcpy(Nd, nd3, sizeof(nd3));
+      double N[16] = {0}, Nd[16] = {0};
+      for (int r = 0; r + 1 < d; ++r) {
+        N[r * d + r] = l;
+        N[r * d + r + 1] = 1.0;
+        Nd[r * d + r] = 1.0;
       }
-      double N2[9], NdN[9], NNd[9];
+      for (int c = 0; c < d; ++c) {
+        /* last row of F: -C(d, c) l^(d - c) */
+        double binom = 1.0;
+        for (int q = 0; q < c; ++q) binom = binom * (d - q) / (q + 1);
+        N[(d - 1) * d + c] = -binom * pow(l, d - c);
+        Nd[(d - 1) * d + c] = -binom * (d - c) * pow(l, d - c - 1);
+      }
+      N[(d - 1) * d + d - 1] += l;
+      Nd[(d - 1) * d + d - 1] += 1.0;
+      double N2[16], N3[16], NdN[16], NNd[16], T1[16], T2[16], T3[16];
       mm(d, N, N, N2);
+      mm(d, N2, N, N3);
       mm(d, Nd, N, NdN);
       mm(d, N, Nd, NNd);
+      mm(d, Nd, N2, T1);    /* Nd N^2 */
+      mm(d, N, NdN, T2);    /* N Nd N */
+      mm(d, N2, Nd, T3);    /* N^2 Nd */
       double e = exp(-l * dt);
       double dl = -l / m->ell[i];
       for (int r = 0; r < d; ++r)
         for (int c = 0; c < d; ++c) {
-          double poly = (r == c ? 1.0 : 0.0) + N[r * d + c] * dt + (d == 3 ? 0.5 * N2[r * d + c] * dt * dt : 0.0);
+          int q = r * d + c;
+          double poly = (r == c ? 1.0 : 0.0) + N[q] * dt + 0.5 * N2[q] * dt * dt + N3[q] * dt * dt * dt / 6.0;
           double a = e * poly;
           A[(o + r) * b + o + c] = a;
           if (dA) {
-            double dpoly = Nd[r * d + c] * dt + (d == 3 ? 0.5 * (NdN[r * d + c] + NNd[r * d + c]) * dt * dt : 0.0);
+            double dpoly = Nd[q] * dt + 0.5 * (NdN[q] + NNd[q]) * dt * dt + (T1[q] + T2[q] + T3[q]) * dt * dt * dt / 6.0;
             dA[pi][(o + r) * b + o + c] = (-dt * a + e * dpoly) * dl;
           }
         }

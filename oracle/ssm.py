@@ -31,36 +31,39 @@ import numpy as np
 import scipy.linalg
 import scipy.special
 
-MATERN32, MATERN52, PERIODIC = 1, 2, 3
+MATERN32, MATERN52, PERIODIC, MATERN12, MATERN72 = 1, 2, 3, 4, 5
+_MATERN_B = {MATERN12: 1, MATERN32: 2, MATERN52: 3, MATERN72: 4}
 
 
 class Matern:
-    """Matern-nu, nu in {3/2, 5/2}; hyperparameters (lengthscale, variance)."""
+    """Matern-nu, nu in {1/2, 3/2, 5/2, 7/2} (b = nu + 1/2); hyperparameters (lengthscale,
+    variance).  F is the companion matrix of (s + lam)^b, lam = sqrt(2 nu) / lengthscale."""
 
     n_params = 2
 
     def __init__(self, kind: int, lengthscale: float, variance: float):
-        if kind not in (MATERN32, MATERN52):
-            raise ValueError("Matern kind must be 1 (nu=3/2) or 2 (nu=5/2)")
+        if kind not in _MATERN_B:
+            raise ValueError("Matern kind must be 4 (nu=1/2), 1 (3/2), 2 (5/2) or 5 (7/2)")
         self.kind = kind
         self.ell = float(lengthscale)
         self.var = float(variance)
-        self.b = 2 if kind == MATERN32 else 3
-        nu = 1.5 if kind == MATERN32 else 2.5
+        self.b = _MATERN_B[kind]
+        nu = self.b - 0.5
         self.lam = np.sqrt(2.0 * nu) / self.ell
 
     # --- SDE ---------------------------------------------------------------
     def F(self):
-        l = self.lam
-        if self.kind == MATERN32:
-            return np.array([[0.0, 1.0], [-l * l, -2.0 * l]])
-        return np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [-l ** 3, -3.0 * l * l, -3.0 * l]])
+        # companion matrix: last row -binom(b, k) lam^(b-k), k = 0..b-1
+        b, l = self.b, self.lam
+        F = np.diag(np.ones(b - 1), 1)
+        F[b - 1, :] = [-scipy.special.comb(b, k, exact=True) * l ** (b - k) for k in range(b)]
+        return F
 
     def dF_dlam(self):
-        l = self.lam
-        if self.kind == MATERN32:
-            return np.array([[0.0, 0.0], [-2.0 * l, -2.0]])
-        return np.array([[0.0, 0.0, 0.0], [0.0, 0.0, 0.0], [-3.0 * l * l, -6.0 * l, -3.0]])
+        b, l = self.b, self.lam
+        F = np.zeros((b, b))
+        F[b - 1, :] = [-scipy.special.comb(b, k, exact=True) * (b - k) * l ** (b - k - 1) for k in range(b)]
+        return F
 
     def H(self):
         h = np.zeros(self.b)
@@ -69,19 +72,33 @@ class Matern:
 
     def Pinf(self):
         l, v = self.lam, self.var
+        if self.kind == MATERN12:
+            return np.array([[v]])
         if self.kind == MATERN32:
             return v * np.diag([1.0, l * l])
-        return v * np.array([[1.0, 0.0, -l * l / 3.0],
-                             [0.0, l * l / 3.0, 0.0],
-                             [-l * l / 3.0, 0.0, l ** 4]])
+        if self.kind == MATERN52:
+            return v * np.array([[1.0, 0.0, -l * l / 3.0],
+                                 [0.0, l * l / 3.0, 0.0],
+                                 [-l * l / 3.0, 0.0, l ** 4]])
+        return v * np.array([[1.0, 0.0, -l ** 2 / 5.0, 0.0],
+                             [0.0, l ** 2 / 5.0, 0.0, -l ** 4 / 5.0],
+                             [-l ** 2 / 5.0, 0.0, l ** 4 / 5.0, 0.0],
+                             [0.0, -l ** 4 / 5.0, 0.0, l ** 6]])
 
     def dPinf_dlam(self):
         l, v = self.lam, self.var
+        if self.kind == MATERN12:
+            return np.zeros((1, 1))
         if self.kind == MATERN32:
             return v * np.diag([0.0, 2.0 * l])
-        return v * np.array([[0.0, 0.0, -2.0 * l / 3.0],
-                             [0.0, 2.0 * l / 3.0, 0.0],
-                             [-2.0 * l / 3.0, 0.0, 4.0 * l ** 3]])
+        if self.kind == MATERN52:
+            return v * np.array([[0.0, 0.0, -2.0 * l / 3.0],
+                                 [0.0, 2.0 * l / 3.0, 0.0],
+                                 [-2.0 * l / 3.0, 0.0, 4.0 * l ** 3]])
+        return v * np.array([[0.0, 0.0, -2.0 * l / 5.0, 0.0],
+                             [0.0, 2.0 * l / 5.0, 0.0, -4.0 * l ** 3 / 5.0],
+                             [-2.0 * l / 5.0, 0.0, 4.0 * l ** 3 / 5.0, 0.0],
+                             [0.0, -4.0 * l ** 3 / 5.0, 0.0, 6.0 * l ** 5]])
 
     # derivatives with respect to the raw hyperparameters (lengthscale, variance)
     def dF(self):
@@ -95,19 +112,28 @@ class Matern:
     # --- covariance function --------------------------------------------------
     def kernel(self, tau):
         r = np.abs(tau) * self.lam
+        if self.kind == MATERN12:
+            return self.var * np.exp(-r)
         if self.kind == MATERN32:
             return self.var * (1.0 + r) * np.exp(-r)
-        return self.var * (1.0 + r + r * r / 3.0) * np.exp(-r)
+        if self.kind == MATERN52:
+            return self.var * (1.0 + r + r * r / 3.0) * np.exp(-r)
+        return self.var * (1.0 + r + 2.0 * r * r / 5.0 + r ** 3 / 15.0) * np.exp(-r)
 
     def dkernel(self, tau):
         """[dk/dlengthscale, dk/dvariance] of the closed-form kernel."""
         tau = np.abs(tau)
         l = self.lam
         e = np.exp(-l * tau)
-        if self.kind == MATERN32:
+        r = l * tau
+        if self.kind == MATERN12:
+            dk_dlam = -self.var * tau * e
+        elif self.kind == MATERN32:
             dk_dlam = -self.var * l * tau * tau * e
-        else:
+        elif self.kind == MATERN52:
             dk_dlam = -self.var * (l * tau * tau / 3.0) * (1.0 + l * tau) * e
+        else:
+            dk_dlam = -self.var * tau * (r / 15.0) * (3.0 + 3.0 * r + r * r) * e
         return [dk_dlam * (-l / self.ell), self.kernel(tau) / self.var]
 
 
@@ -192,7 +218,7 @@ class SumModel:
         self.parts = []
         p = 0
         for kind, harm in terms:
-            if kind in (MATERN32, MATERN52):
+            if kind in _MATERN_B:
                 self.parts.append(Matern(kind, hyper_row[p], hyper_row[p + 1]))
                 p += 2
             elif kind == PERIODIC:

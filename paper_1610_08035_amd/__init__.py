@@ -6,8 +6,10 @@ marginal likelihood and its hand-written gradient as a torch.autograd.Function;
 ``optimize`` fits hyperparameters by maximum marginal likelihood.
 """
 from .spingp import (  # noqa: F401
+    MATERN12,
     MATERN32,
     MATERN52,
+    MATERN72,
     PERIODIC,
     Handle,
     SpinGPError,

@@ -266,8 +266,10 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   *out = nullptr;
   int b;
   bool wide = false;
-  if (n_terms == 1 && terms[0].kind == SPINGP_MATERN32) b = 2;
+  if (n_terms == 1 && terms[0].kind == SPINGP_MATERN12) b = 1;
+  else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN32) b = 2;
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN52) b = 3;
+  else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN72) b = 4;
   else if (n_terms == 2 && terms[0].kind == SPINGP_MATERN32 && terms[1].kind == SPINGP_PERIODIC &&
            terms[1].harmonics == 3) {
     b = spg::wide::kStateDim;
@@ -303,7 +305,10 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   h->max_points = max_points;
   h->max_series = max_series;
   h->stream = (hipStream_t)stream;
-  const int NF = (b == 2) ? spg::ElemLayout<2>::kFields : spg::ElemLayout<3>::kFields;
+  const int NF = b == 1 ? spg::ElemLayout<1>::kFields
+                 : b == 2 ? spg::ElemLayout<2>::kFields
+                 : b == 3 ? spg::ElemLayout<3>::kFields
+                          : spg::ElemLayout<4>::kFields;
   h->lane_ld = lane_ld;
   spg::top_sizes(G_max, h->top_ld, h->top_cnt_n);
   h->part_ld = multi ? slots_max : G_max;

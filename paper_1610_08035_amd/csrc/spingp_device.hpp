@@ -188,6 +188,12 @@ SPG_DEV double diff_of_products(double a, double b, double c, double d) {
   return f + e;
 }
 
+template <>
+SPG_DEV double inv_logdet<1>(const double (&M)[1][1], double (&G)[1][1]) {
+  G[0][0] = 1.0 / M[0][0];
+  return log(fabs(M[0][0]));
+}
+
 // b = 2 and b = 3: the inverse through the adjugate, one division and a short dependency
 // chain (the pivoted elimination above needs one division per column in sequence).
 template <>
@@ -240,6 +246,22 @@ struct SeriesPar {
 
 template <int B>
 struct Matern;
+
+// Matern-1/2 (b = 1, lam = 1 / l): the Ornstein-Uhlenbeck state, A = e^{-lam dt}.
+template <>
+struct Matern<1> {
+  static constexpr int B = 1;
+  SPG_DEV static void pinf(const SeriesPar& p, double (&P)[1][1]) { P[0][0] = p.var; }
+  SPG_DEV static void dpinf_dlam(const SeriesPar&, double (&P)[1][1]) { P[0][0] = 0.0; }
+  SPG_DEV static void transition(const SeriesPar& p, double dt, double& e, double (&A)[1][1]) {
+    e = exp(-p.lam * dt);
+    A[0][0] = e;
+  }
+  SPG_DEV static void transition_e(const SeriesPar&, double, double e, double (&A)[1][1]) { A[0][0] = e; }
+  SPG_DEV static double dA_dlam_dot(const SeriesPar&, double dt, double e, const double (&Ab)[1][1]) {
+    return -dt * e * Ab[0][0];
+  }
+};
 
 template <>
 struct Matern<2> {
@@ -321,6 +343,82 @@ struct Matern<3> {
     s = fma(Ab[2][0], l * x * (3.0 * x - 0.5 * x2 - 3.0), s);
     s = fma(Ab[2][1], x * (6.0 * x - x2 - 6.0), s);
     s = fma(Ab[2][2], dt * (-3.0 + 3.0 * x - 0.5 * x2), s);
+    return e * s;
+  }
+};
+
+// Matern-7/2 (b = 4, lam = sqrt(7) / l): the state holds f and its first three derivatives, F
+// is the companion matrix of (s + lam)^4.  N = F + lam I is nilpotent (N^4 = 0), so
+// A = e^{-lam dt} (I + N dt + N^2 dt^2 / 2 + N^3 dt^3 / 6); the entries below are that sum
+// multiplied out in x = lam dt.  P0 holds the derivatives of k at 0: entry (i, j) is
+// (-1)^j k^(i+j)(0), with k''(0) = -var lam^2 / 5, k''''(0) = var lam^4 / 5,
+// k^(6)(0) = -var lam^6.
+template <>
+struct Matern<4> {
+  static constexpr int B = 4;
+  SPG_DEV static void pinf(const SeriesPar& p, double (&P)[4][4]) {
+    const double v = p.var, l2 = p.lam * p.lam, l4 = l2 * l2;
+    SPG_UNROLL for (int i = 0; i < 4; ++i) SPG_UNROLL for (int j = 0; j < 4; ++j) P[i][j] = 0.0;
+    P[0][0] = v;
+    P[0][2] = P[2][0] = -v * l2 * 0.2;
+    P[1][1] = v * l2 * 0.2;
+    P[1][3] = P[3][1] = -v * l4 * 0.2;
+    P[2][2] = v * l4 * 0.2;
+    P[3][3] = v * l4 * l2;
+  }
+  SPG_DEV static void dpinf_dlam(const SeriesPar& p, double (&P)[4][4]) {
+    const double v = p.var, l = p.lam, l3 = l * l * l;
+    SPG_UNROLL for (int i = 0; i < 4; ++i) SPG_UNROLL for (int j = 0; j < 4; ++j) P[i][j] = 0.0;
+    P[0][2] = P[2][0] = -v * l * 0.4;
+    P[1][1] = v * l * 0.4;
+    P[1][3] = P[3][1] = -v * l3 * 0.8;
+    P[2][2] = v * l3 * 0.8;
+    P[3][3] = 6.0 * v * l3 * l * l;
+  }
+  SPG_DEV static void transition(const SeriesPar& p, double dt, double& e, double (&A)[4][4]) {
+    e = exp(-p.lam * dt);
+    transition_e(p, dt, e, A);
+  }
+  SPG_DEV static void transition_e(const SeriesPar& p, double dt, double e, double (&A)[4][4]) {
+    const double l = p.lam, x = l * dt, x2 = x * x, x3 = x2 * x, l2 = l * l;
+    const double c6 = e * (1.0 / 6.0), c2 = 0.5 * e;
+    A[0][0] = c6 * (x3 + 3.0 * x2 + 6.0 * x + 6.0);
+    A[0][1] = c2 * dt * (x2 + 2.0 * x + 2.0);
+    A[0][2] = c2 * dt * dt * (x + 1.0);
+    A[0][3] = c6 * dt * dt * dt;
+    A[1][0] = -c6 * l * x3;
+    A[1][1] = -c2 * (x3 - x2 - 2.0 * x - 2.0);
+    A[1][2] = -c2 * dt * (x2 - 2.0 * x - 2.0);
+    A[1][3] = -c6 * dt * dt * (x - 3.0);
+    A[2][0] = c6 * l2 * x2 * (x - 3.0);
+    A[2][1] = c2 * l * x2 * (x - 4.0);
+    A[2][2] = c2 * (x - 1.0) * (x2 - 4.0 * x - 2.0);
+    A[2][3] = c6 * dt * (x2 - 6.0 * x + 6.0);
+    A[3][0] = -c6 * l2 * l * x * (x2 - 6.0 * x + 6.0);
+    A[3][1] = -c2 * l2 * x * (x2 - 7.0 * x + 8.0);
+    A[3][2] = -c2 * l * x * (x - 6.0) * (x - 2.0);
+    A[3][3] = -c6 * (x3 - 9.0 * x2 + 18.0 * x - 6.0);
+  }
+  // <Abar, dA/dlam> at fixed dt
+  SPG_DEV static double dA_dlam_dot(const SeriesPar& p, double dt, double e, const double (&Ab)[4][4]) {
+    const double l = p.lam, x = l * dt, x2 = x * x, x3 = x2 * x;
+    const double u = x - 4.0, w = (x - 6.0) * (x - 2.0), z = x3 - 12.0 * x2 + 36.0 * x - 24.0;
+    double s = Ab[0][0] * (-dt * x3 * (1.0 / 6.0));
+    s = fma(Ab[0][1], -0.5 * dt * dt * x2, s);
+    s = fma(Ab[0][2], -0.5 * dt * dt * dt * x, s);
+    s = fma(Ab[0][3], -dt * dt * dt * dt * (1.0 / 6.0), s);
+    s = fma(Ab[1][0], x3 * u * (1.0 / 6.0), s);
+    s = fma(Ab[1][1], 0.5 * dt * x2 * u, s);
+    s = fma(Ab[1][2], 0.5 * dt * dt * x * u, s);
+    s = fma(Ab[1][3], dt * dt * dt * u * (1.0 / 6.0), s);
+    s = fma(Ab[2][0], -l * x2 * w * (1.0 / 6.0), s);
+    s = fma(Ab[2][1], -0.5 * x2 * w, s);
+    s = fma(Ab[2][2], -0.5 * dt * x * w, s);
+    s = fma(Ab[2][3], -dt * dt * w * (1.0 / 6.0), s);
+    s = fma(Ab[3][0], l * l * x * z * (1.0 / 6.0), s);
+    s = fma(Ab[3][1], 0.5 * l * x * z, s);
+    s = fma(Ab[3][2], 0.5 * x * z, s);
+    s = fma(Ab[3][3], dt * z * (1.0 / 6.0), s);
     return e * s;
   }
 };

@@ -26,7 +26,9 @@ SPG_DEV SeriesPar load_par(const double* hyper) {
   p.ell = hyper[0];
   p.var = hyper[1];
   p.s2 = hyper[2];
-  p.lam = (B == 2 ? 1.7320508075688772935 : 2.2360679774997896964) / p.ell;
+  // lam = sqrt(2 nu) / l with nu = B - 1/2
+  p.lam = (B == 1 ? 1.0 : B == 2 ? 1.7320508075688772935 : B == 3 ? 2.2360679774997896964 : 2.6457513110645905905) /
+          p.ell;
   return p;
 }
 

@@ -55,8 +55,13 @@ hipError_t factor_b(const LaunchCtx& c) {
 }
 
 hipError_t factor(const LaunchCtx& c) {
-  if (c.b == 2) return c.batched ? factor_b<2, true>(c) : factor_b<2, false>(c);
-  return c.batched ? factor_b<3, true>(c) : factor_b<3, false>(c);
+  switch (c.b) {
+    case 1: return c.batched ? factor_b<1, true>(c) : factor_b<1, false>(c);
+    case 2: return c.batched ? factor_b<2, true>(c) : factor_b<2, false>(c);
+    case 3: return c.batched ? factor_b<3, true>(c) : factor_b<3, false>(c);
+    case 4: return c.batched ? factor_b<4, true>(c) : factor_b<4, false>(c);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int B, int MODE, bool BATCHED>
@@ -71,8 +76,13 @@ hipError_t bwd_b(const LaunchCtx& c, const BwdOut& o) {
 
 template <int MODE>
 hipError_t bwd_m(const LaunchCtx& c, const BwdOut& o) {
-  if (c.b == 2) return c.batched ? bwd_b<2, MODE, true>(c, o) : bwd_b<2, MODE, false>(c, o);
-  return c.batched ? bwd_b<3, MODE, true>(c, o) : bwd_b<3, MODE, false>(c, o);
+  switch (c.b) {
+    case 1: return c.batched ? bwd_b<1, MODE, true>(c, o) : bwd_b<1, MODE, false>(c, o);
+    case 2: return c.batched ? bwd_b<2, MODE, true>(c, o) : bwd_b<2, MODE, false>(c, o);
+    case 3: return c.batched ? bwd_b<3, MODE, true>(c, o) : bwd_b<3, MODE, false>(c, o);
+    case 4: return c.batched ? bwd_b<4, MODE, true>(c, o) : bwd_b<4, MODE, false>(c, o);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t bwd(const LaunchCtx& c, int mode, const BwdOut& o) {
@@ -84,7 +94,13 @@ hipError_t bwd(const LaunchCtx& c, int mode, const BwdOut& o) {
     case kWantLogml:
       // the per-chunk log-likelihood partials exist for several series only
       if (!c.batched) return hipErrorInvalidValue;
-      return c.b == 2 ? bwd_b<2, kWantLogml, true>(c, o) : bwd_b<3, kWantLogml, true>(c, o);
+      switch (c.b) {
+        case 1: return bwd_b<1, kWantLogml, true>(c, o);
+        case 2: return bwd_b<2, kWantLogml, true>(c, o);
+        case 3: return bwd_b<3, kWantLogml, true>(c, o);
+        case 4: return bwd_b<4, kWantLogml, true>(c, o);
+        default: return hipErrorInvalidValue;
+      }
     default: return hipErrorInvalidValue;
   }
 }
@@ -99,8 +115,13 @@ hipError_t blocks_b(const LaunchCtx& c, double* A, double* Q, double* D, double*
 }
 
 hipError_t blocks(const LaunchCtx& c, double* A, double* Q, double* D, double* Bs) {
-  if (c.b == 2) return c.batched ? blocks_b<2, true>(c, A, Q, D, Bs) : blocks_b<2, false>(c, A, Q, D, Bs);
-  return c.batched ? blocks_b<3, true>(c, A, Q, D, Bs) : blocks_b<3, false>(c, A, Q, D, Bs);
+  switch (c.b) {
+    case 1: return c.batched ? blocks_b<1, true>(c, A, Q, D, Bs) : blocks_b<1, false>(c, A, Q, D, Bs);
+    case 2: return c.batched ? blocks_b<2, true>(c, A, Q, D, Bs) : blocks_b<2, false>(c, A, Q, D, Bs);
+    case 3: return c.batched ? blocks_b<3, true>(c, A, Q, D, Bs) : blocks_b<3, false>(c, A, Q, D, Bs);
+    case 4: return c.batched ? blocks_b<4, true>(c, A, Q, D, Bs) : blocks_b<4, false>(c, A, Q, D, Bs);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 const TileOps kOps = {R, L, groups, map, factor, bwd, blocks};

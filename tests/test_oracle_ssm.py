@@ -4,7 +4,7 @@ import pytest
 import scipy.linalg
 
 from oracle import native
-from oracle.ssm import MATERN32, MATERN52, PERIODIC, Matern, Periodic, model_for
+from oracle.ssm import MATERN12, MATERN32, MATERN52, MATERN72, PERIODIC, Matern, Periodic, model_for
 
 MODELS = [
     ([(MATERN32, 0)], [1.0, 1.0, 0.1]),
@@ -15,6 +15,9 @@ MODELS = [
     ([(PERIODIC, 2)], [0.6, 1.7, 3.0, 0.1]),
     ([(MATERN32, 0), (PERIODIC, 3)], [50.0, 1.0, 1.0, 1.0, 24.0, 0.1]),
     ([(MATERN52, 0), (MATERN32, 0)], [3.0, 1.2, 0.8, 0.5, 0.3]),
+    ([(MATERN12, 0)], [1.5, 0.8, 0.1]),
+    ([(MATERN72, 0)], [4.0, 1.5, 0.05]),
+    ([(MATERN72, 0)], [0.6, 0.9, 0.2]),
 ]
 TAUS = np.array([0.0, 1e-9, 1e-4, 0.01, 0.3, 1.0, 2.7, 10.0, 55.0])
 
@@ -34,12 +37,18 @@ def test_matern_kernel_values_closed_form():
     assert Matern(MATERN32, 1.0, 1.0).kernel(1.0) == pytest.approx((1 + np.sqrt(3)) * np.exp(-np.sqrt(3)), rel=1e-15)
     assert Matern(MATERN52, 1.0, 1.0).kernel(1.0) == pytest.approx(
         (1 + np.sqrt(5) + 5.0 / 3.0) * np.exp(-np.sqrt(5)), rel=1e-15)
+    # nu = 1/2: the exponential kernel; nu = 7/2: (1 + r + 2 r^2/5 + r^3/15) e^-r, r = sqrt7 tau / l
+    assert Matern(MATERN12, 1.0, 1.0).kernel(1.0) == pytest.approx(np.exp(-1.0), rel=1e-15)
+    r7 = np.sqrt(7.0)
+    assert Matern(MATERN72, 1.0, 1.0).kernel(1.0) == pytest.approx(
+        (1 + r7 + 2.0 * 7.0 / 5.0 + 7.0 * r7 / 15.0) * np.exp(-r7), rel=1e-15)
     # paper eq. ss_matern: P0 = diag(1, 3/l^2) for unit variance
     assert np.allclose(Matern(MATERN32, 2.0, 1.0).Pinf(), np.diag([1.0, 3.0 / 4.0]), rtol=0, atol=1e-15)
 
 
 @pytest.mark.parametrize("kind,ell,var", [(MATERN32, 1.0, 1.0), (MATERN32, 0.4, 3.0), (MATERN52, 5.0, 2.0),
-                                          (MATERN52, 0.5, 0.7)])
+                                          (MATERN52, 0.5, 0.7), (MATERN12, 0.8, 1.3), (MATERN72, 3.0, 1.1),
+                                          (MATERN72, 0.45, 0.6)])
 def test_matern_lyapunov(kind, ell, var):
     """Stationary covariance solves F P0 + P0 F^T + L q L^T = 0 with L = e_b: only the last entry is nonzero."""
     m = Matern(kind, ell, var)
@@ -47,10 +56,11 @@ def test_matern_lyapunov(kind, ell, var):
     b = m.b
     mask = np.ones((b, b), bool)
     mask[b - 1, b - 1] = False
-    assert np.abs(R[mask]).max() <= 1e-13 * np.abs(R).max()
+    if mask.any():
+        assert np.abs(R[mask]).max() <= 1e-13 * np.abs(R).max()
     assert R[b - 1, b - 1] < 0
     # q matches the Matern spectral density at 0: var * 2 sqrt(pi) Gamma(nu+1/2)/Gamma(nu) (2 nu)^nu / l^(2 nu)
-    nu = 1.5 if kind == MATERN32 else 2.5
+    nu = m.b - 0.5
     from scipy.special import gamma
     q = var * 2.0 * np.sqrt(np.pi) * gamma(nu + 0.5) / gamma(nu) * (2 * nu) ** nu / ell ** (2 * nu)
     assert -R[b - 1, b - 1] == pytest.approx(q, rel=1e-12)

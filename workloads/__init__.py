@@ -5,8 +5,10 @@ inference arithmetic (no precision blocks, no reduction, no likelihood); both
 the oracle and the device path receive its arrays as plain inputs.
 """
 from .generate import (  # noqa: F401
+    KIND_MATERN12,
     KIND_MATERN32,
     KIND_MATERN52,
+    KIND_MATERN72,
     KIND_PERIODIC,
     Workload,
     make_batch,

@@ -27,9 +27,11 @@ import scipy.special
 KIND_MATERN32 = 1
 KIND_MATERN52 = 2
 KIND_PERIODIC = 3
+KIND_MATERN12 = 4
+KIND_MATERN72 = 5
 
-_MATERN_ORDER = {KIND_MATERN32: 2, KIND_MATERN52: 3}
-_MATERN_NU = {KIND_MATERN32: 1.5, KIND_MATERN52: 2.5}
+_MATERN_ORDER = {KIND_MATERN12: 1, KIND_MATERN32: 2, KIND_MATERN52: 3, KIND_MATERN72: 4}
+_MATERN_NU = {KIND_MATERN12: 0.5, KIND_MATERN32: 1.5, KIND_MATERN52: 2.5, KIND_MATERN72: 3.5}
 
 
 def state_dim(terms) -> int:
