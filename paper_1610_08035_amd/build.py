@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libspingp.so")
 # The C-ABI unit, then one object per compiled tile shape (R points per lane, L lanes per
 # work-group); the list must match spg::tile_ops() in spingp_api.hip.
 SOURCES = ["spingp_api.hip", "spingp_wide.hip"]
-TILES = [(8, 128), (8, 64), (8, 256), (4, 128), (4, 256)]
+TILES = [(8, 128), (8, 64), (8, 256), (4, 128), (4, 256), (16, 128)]
 HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp", "spingp_host.hpp", "spingp_series.hpp", "spingp_wide.hpp"]
 
 HIPCC_FLAGS = [

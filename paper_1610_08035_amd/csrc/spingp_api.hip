@@ -61,8 +61,10 @@ const TileOps* tile_ops_R8_L64();
 const TileOps* tile_ops_R8_L256();
 const TileOps* tile_ops_R4_L128();
 const TileOps* tile_ops_R4_L256();
-// The first entry is the default shape.  R = 8 is fastest from about 2^19 points up; R = 4
-// (twice the lanes, twice the stored trees) hides more latency on smaller problems.
+const TileOps* tile_ops_R16_L128();
+// The first entry is the default shape.  R = 8 is fastest around 2^20 points; R = 4 (twice the
+// lanes, twice the stored trees) hides more latency on smaller problems; R = 16 (half the
+// tree work, a longer per-lane fold) pays off from about 2^23 points and on large batches.
 const TileOps* tile_ops(int i) {
   switch (i) {
     case 0: return tile_ops_R8_L128();
@@ -70,6 +72,7 @@ const TileOps* tile_ops(int i) {
     case 2: return tile_ops_R8_L256();
     case 3: return tile_ops_R4_L128();
     case 4: return tile_ops_R4_L256();
+    case 5: return tile_ops_R16_L128();
     default: return nullptr;
   }
 }

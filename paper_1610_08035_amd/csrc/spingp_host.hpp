@@ -117,7 +117,7 @@ inline SeriesMap make_map(const LaunchCtx& c, int64_t slots) {
 }
 
 // Tile shapes compiled into the library, in order of preference when untuned.
-constexpr int kNumTiles = 5;
+constexpr int kNumTiles = 6;
 const TileOps* tile_ops(int i);
 
 // Wide-state path (Matern-3/2 + periodic with 3 harmonics, b = 10, one series): level-by-level
