@@ -32,7 +32,7 @@
 typedef struct {
   int n_parts;
   int kind[8], harm[8], off[8], dim[8], pidx[8];
-  double ell[8], var[8], period[8], lam[8];
+  double ell[8], var[8], period[8], lam[8], decay[8];
   double q2[8][MAXB], dq2[8][MAXB];
   int b, n_kernel_params;
   double noise;
@@ -140,11 +140,16 @@ static int model_init(model_t* m, int n_terms, const int* kinds, const int* harm
       m->var[i] = hyper[p + 1];
       m->lam[i] = sqrt(2.0 * m->dim[i] - 1.0) / m->ell[i];
       p += 2;
-    } else if (kinds[i] == 3) {
+    } else if (kinds[i] == 3 || kinds[i] == 6) {
+      /* periodic; kind 6 (quasi-periodic) also decays every harmonic by exp(-dt / decay) */
       m->dim[i] = 2 * (harm[i] + 1);
       m->ell[i] = hyper[p];
       m->var[i] = hyper[p + 1];
       m->period[i] = hyper[p + 2];
+      if (kinds[i] == 6) {
+        m->decay[i] = hyper[p + 3];
+        p += 1;
+      }
       double z = 1.0 / (m->ell[i] * m->ell[i]);
       for (int j = 0; j <= harm[i]; ++j) {
         double c = j == 0 ? 1.0 : 2.0;
@@ -228,7 +233,7 @@ static void model_A(const model_t* m, double dt, double* A, double (*dA)[MAXB * 
     for (int k = 0; k < m->n_kernel_params; ++k) memset(dA[k], 0, sizeof(double) * b * b);
   for (int i = 0; i < m->n_parts; ++i) {
     int o = m->off[i], pi = m->pidx[i];
-    if (m->kind[i] != 3) {
+    if (m->kind[i] != 3 && m->kind[i] != 6) {
       /* Matern: F is the companion matrix of (s + l)^d; N = F + l I is nilpotent (N^d = 0) and
          A = e^{-l dt} (I + N dt + N^2 dt^2/2 + N^3 dt^3/6); dN/dl = dF/dl + I */
       int d = m->dim[i];
@@ -271,20 +276,29 @@ static void model_A(const model_t* m, double dt, double* A, double (*dA)[MAXB * 
         }
     } else {
       double w0 = 2.0 * M_PI / m->period[i];
+      int quasi = m->kind[i] == 6;
+      double e = quasi ? exp(-dt / m->decay[i]) : 1.0;
+      double de = quasi ? e * dt / (m->decay[i] * m->decay[i]) : 0.0;   /* d e / d decay */
       for (int j = 0; j <= m->harm[i]; ++j) {
         double ang = j * w0 * dt;
         double c = cos(ang), s = sin(ang);
         int d = o + 2 * j;
-        A[d * b + d] = c;
-        A[d * b + d + 1] = -s;
-        A[(d + 1) * b + d] = s;
-        A[(d + 1) * b + d + 1] = c;
+        A[d * b + d] = e * c;
+        A[d * b + d + 1] = -e * s;
+        A[(d + 1) * b + d] = e * s;
+        A[(d + 1) * b + d + 1] = e * c;
         if (dA) {
           double dang = -ang / m->period[i];
-          dA[pi + 2][d * b + d] = -s * dang;
-          dA[pi + 2][d * b + d + 1] = -c * dang;
-          dA[pi + 2][(d + 1) * b + d] = c * dang;
-          dA[pi + 2][(d + 1) * b + d + 1] = -s * dang;
+          dA[pi + 2][d * b + d] = -e * s * dang;
+          dA[pi + 2][d * b + d + 1] = -e * c * dang;
+          dA[pi + 2][(d + 1) * b + d] = e * c * dang;
+          dA[pi + 2][(d + 1) * b + d + 1] = -e * s * dang;
+          if (quasi) {
+            dA[pi + 3][d * b + d] = de * c;
+            dA[pi + 3][d * b + d + 1] = -de * s;
+            dA[pi + 3][(d + 1) * b + d] = de * s;
+            dA[pi + 3][(d + 1) * b + d + 1] = de * c;
+          }
         }
       }
     }

@@ -31,7 +31,7 @@ import numpy as np
 import scipy.linalg
 import scipy.special
 
-MATERN32, MATERN52, PERIODIC, MATERN12, MATERN72 = 1, 2, 3, 4, 5
+MATERN32, MATERN52, PERIODIC, MATERN12, MATERN72, QUASIPERIODIC = 1, 2, 3, 4, 5, 6
 _MATERN_B = {MATERN12: 1, MATERN32: 2, MATERN52: 3, MATERN72: 4}
 
 
@@ -210,6 +210,43 @@ class Periodic:
         return [self.var * d_ell, self.kernel(tau) / self.var, self.var * d_per]
 
 
+class QuasiPeriodic(Periodic):
+    """Quasi-periodic term: the J-harmonic periodic term times an exponential (Matern-1/2)
+    decay, k(tau) = k_periodic(tau) exp(-|tau| / l_decay); hyperparameters (lengthscale,
+    variance, period, decay lengthscale).  State space: every harmonic block rotates and decays,
+    F_j = [[-lam, -j w0], [j w0, -lam]] with lam = 1 / l_decay; P0 as for the periodic term."""
+
+    n_params = 4
+
+    def __init__(self, harmonics, lengthscale, variance, period, decay):
+        super().__init__(harmonics, lengthscale, variance, period)
+        self.decay = float(decay)
+        self.lam = 1.0 / self.decay
+
+    def F(self):
+        return super().F() - self.lam * np.eye(self.b)
+
+    def dF(self):
+        z = np.zeros((self.b, self.b))
+        return [z, z.copy(), -super().F() / self.period, np.eye(self.b) / self.decay ** 2]
+
+    def dPinf(self):
+        return super().dPinf() + [np.zeros((self.b, self.b))]
+
+    def kernel(self, tau):
+        return super().kernel(tau) * np.exp(-np.abs(tau) / self.decay)
+
+    def kernel_untruncated(self, tau):
+        return super().kernel_untruncated(tau) * np.exp(-np.abs(tau) / self.decay)
+
+    def dkernel(self, tau):
+        tau = np.asarray(tau, dtype=np.float64)
+        e = np.exp(-np.abs(tau) / self.decay)
+        kp = Periodic.kernel(self, tau)
+        d_ell, _, d_per = Periodic.dkernel(self, tau)
+        return [d_ell * e, kp / self.var * e, d_per * e, kp * e * np.abs(tau) / self.decay ** 2]
+
+
 class SumModel:
     """Sum of terms: block-diagonal state space.  Parameters are the terms' in order."""
 
@@ -224,6 +261,10 @@ class SumModel:
             elif kind == PERIODIC:
                 self.parts.append(Periodic(harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2]))
                 p += 3
+            elif kind == QUASIPERIODIC:
+                self.parts.append(QuasiPeriodic(harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2],
+                                                hyper_row[p + 3]))
+                p += 4
             else:
                 raise ValueError(f"unknown kind {kind}")
         self.noise = float(hyper_row[p])

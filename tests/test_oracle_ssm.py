@@ -4,7 +4,8 @@ import pytest
 import scipy.linalg
 
 from oracle import native
-from oracle.ssm import MATERN12, MATERN32, MATERN52, MATERN72, PERIODIC, Matern, Periodic, model_for
+from oracle.ssm import (MATERN12, MATERN32, MATERN52, MATERN72, PERIODIC, QUASIPERIODIC, Matern, Periodic,
+                        model_for)
 
 MODELS = [
     ([(MATERN32, 0)], [1.0, 1.0, 0.1]),
@@ -18,6 +19,8 @@ MODELS = [
     ([(MATERN12, 0)], [1.5, 0.8, 0.1]),
     ([(MATERN72, 0)], [4.0, 1.5, 0.05]),
     ([(MATERN72, 0)], [0.6, 0.9, 0.2]),
+    ([(QUASIPERIODIC, 3)], [1.0, 1.0, 24.0, 50.0, 0.1]),
+    ([(MATERN32, 0), (QUASIPERIODIC, 3)], [50.0, 1.0, 1.2, 0.8, 6.0, 15.0, 0.1]),
 ]
 TAUS = np.array([0.0, 1e-9, 1e-4, 0.01, 0.3, 1.0, 2.7, 10.0, 55.0])
 
@@ -137,3 +140,18 @@ def test_c_closed_forms_match_expm(terms, hyper):
         scale = max(1.0, np.abs(m.F() * dt).max())
         assert np.abs(A[i] - m.A(dt)).max() <= 1e-13 * scale
         assert np.abs(Q[i] - m.Q(dt)).max() <= 1e-13 * scale * np.abs(P).max()
+
+
+def test_quasi_periodic_limits():
+    """The quasi-periodic term is the periodic term times exp(-|tau| / decay): the product
+    form holds at every lag, and a very long decay gives back the periodic logML."""
+    qp = model_for([(QUASIPERIODIC, 3)], [0.9, 1.3, 5.0, 7.0, 0.1])
+    per = model_for([(PERIODIC, 3)], [0.9, 1.3, 5.0, 0.1])
+    for tau in TAUS:
+        assert qp.kernel(tau) == pytest.approx(per.kernel(tau) * np.exp(-tau / 7.0), rel=1e-14, abs=1e-300)
+    rng = np.random.default_rng(3)
+    t = np.sort(rng.uniform(0, 30, 200))
+    y = np.cos(t) + 0.3 * rng.standard_normal(200)
+    far = native.btd_factored([(QUASIPERIODIC, 3)], [0.9, 1.3, 5.0, 1e9, 0.1], t, y, want_blocks=False)
+    ref = native.btd_factored([(PERIODIC, 3)], [0.9, 1.3, 5.0, 0.1], t, y, want_blocks=False)
+    assert abs(far["logml"] - ref["logml"]) <= 1e-6 * abs(ref["logml"])
