@@ -59,7 +59,8 @@ typedef enum {
   SPINGP_MATERN52 = 2,  /* Matern nu = 5/2, b = 3 */
   SPINGP_PERIODIC = 3,  /* periodic, `harmonics` cosine terms, b = 2 (harmonics + 1) */
   SPINGP_MATERN12 = 4,  /* Matern nu = 1/2 (exponential kernel), b = 1 */
-  SPINGP_MATERN72 = 5   /* Matern nu = 7/2, b = 4 */
+  SPINGP_MATERN72 = 5,  /* Matern nu = 7/2, b = 4 */
+  SPINGP_QUASIPERIODIC = 6  /* periodic times exp(-|tau| / decay), b = 2 (harmonics + 1) */
 } spingp_kind_t;
 
 /* One additive covariance term; `harmonics` is used by periodic terms only. */
@@ -73,8 +74,9 @@ typedef struct {
  * largest problem it will see.  `stream` is a hipStream_t (NULL = the default stream).
  * Supported models: a single Matern term, nu = 1/2, 3/2, 5/2 or 7/2 (b = 1 to 4; hyperparameter
  * row (lengthscale, signal variance, noise variance), lam = sqrt(2 nu) / lengthscale), any
- * number of series up to max_series; Matern-3/2 + periodic with 3 harmonics (b = 10, one
- * series).  Allocates all device workspace (sized for every compiled tile shape,
+ * number of series up to max_series; Matern-3/2 + periodic or quasi-periodic with 3 harmonics
+ * (b = 10, one series; hyperparameter row (l_M, var_M, l_P, var_P, period, s2), with the decay
+ * lengthscale before s2 for the quasi-periodic term).  Allocates all device workspace (sized for every compiled tile shape,
  * see spingp_tile_shape); returns SPINGP_E_UNSUPPORTED for other models.
  */
 int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,

@@ -11,6 +11,7 @@ from .spingp import (  # noqa: F401
     MATERN52,
     MATERN72,
     PERIODIC,
+    QUASIPERIODIC,
     Handle,
     SpinGPError,
     load_library,

@@ -219,19 +219,20 @@ static void drop_graph(spingp_ctx* h) {
 }
 
 // The wide-state model: one series, all tree levels and their messages stored item-major.
-static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_series, void* stream) {
+static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_series, void* stream, bool quasi) {
   if (max_series != 1) return SPINGP_E_UNSUPPORTED;
   if (max_points > (int64_t(1) << 31)) return SPINGP_E_UNSUPPORTED;
   spingp_ctx* h = new (std::nothrow) spingp_ctx();
   if (!h) return SPINGP_E_NOMEM;
   h->wide = true;
   h->b = spg::wide::kStateDim;
-  h->n_hyper = spg::wide::kHyper;
+  h->n_hyper = spg::wide::n_hyper(quasi);
   h->max_points = max_points;
   h->max_series = 1;
   h->stream = (hipStream_t)stream;
   spg::wide::WideCtx& w = h->wplan;
   memset(&w, 0, sizeof(w));
+  w.quasi = quasi;
   spg::wide::plan_levels(max_points, w);
   int64_t items = 0;
   for (int k = 0; k < w.n_levels; ++k) items += w.n[k];
@@ -273,7 +274,8 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN32) b = 2;
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN52) b = 3;
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN72) b = 4;
-  else if (n_terms == 2 && terms[0].kind == SPINGP_MATERN32 && terms[1].kind == SPINGP_PERIODIC &&
+  else if (n_terms == 2 && terms[0].kind == SPINGP_MATERN32 &&
+           (terms[1].kind == SPINGP_PERIODIC || terms[1].kind == SPINGP_QUASIPERIODIC) &&
            terms[1].harmonics == 3) {
     b = spg::wide::kStateDim;
     wide = true;
@@ -281,7 +283,7 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
     return SPINGP_E_UNSUPPORTED;
   }
   if (max_points > (int64_t(1) << 40)) return SPINGP_E_UNSUPPORTED;
-  if (wide) return create_wide(out, max_points, max_series, stream);
+  if (wide) return create_wide(out, max_points, max_series, stream, terms[1].kind == SPINGP_QUASIPERIODIC);
   // workspace for the most demanding tile shape the handle may use
   const bool multi = max_series > 1;
   int64_t G_max = 0, lane_ld = 0;

@@ -139,15 +139,16 @@ struct WideCtx {
   int64_t n[kMaxLevels];
   int64_t off[kMaxLevels];
   int node_grid;      // work-groups of the node step (rows of part)
+  bool quasi;         // the periodic term decays (quasi-periodic term, one more hyperparameter)
   void (*mark)(void* arg, int kid, int end);
   void* mark_arg;
 };
 constexpr int kStateDim = 10;
-constexpr int kHyper = 6;
+inline int n_hyper(bool quasi) { return quasi ? 7 : 6; }
 int64_t elem_stride();     // doubles per stored element
 int64_t msg_stride();      // doubles per stored message
 int64_t const_size();      // doubles of the model constants
-int64_t part_stride();     // doubles per work-group partial
+int64_t part_stride();     // doubles per work-group partial (the larger of the two models)
 void plan_levels(int64_t n, WideCtx& c);
 hipError_t factor(const WideCtx& c);                       // setup, leaves, up-sweep, root
 hipError_t down(const WideCtx& c);                         // down-sweep of all levels

@@ -6,9 +6,11 @@ namespace spg {
 namespace wide {
 namespace {
 
-using Model = SumM32Periodic<3>;
-static_assert(Model::B == kStateDim, "state dimension of the wide model");
-static_assert(Model::NH == kHyper, "hyperparameters of the wide model");
+using ModelP = SumM32Periodic<3, false>;   // Matern-3/2 + periodic
+using ModelQ = SumM32Periodic<3, true>;    // Matern-3/2 + quasi-periodic
+static_assert(ModelP::B == kStateDim && ModelQ::B == kStateDim, "state dimension of the wide models");
+static_assert(ModelP::kConst == ModelQ::kConst, "one constant layout");
+static_assert(ModelP::kPart <= ModelQ::kPart, "partial rows sized for the larger model");
 // Work-group caps: what fits on the 256 CUs at once for each kernel's LDS (up 15 KB: 10 per
 // CU, down 13 KB: 11, node 21 KB: 7), so that every team stays resident and loops over its
 // items instead of a launch ending with a second, partly empty round.
@@ -21,10 +23,10 @@ inline unsigned grid_for(int64_t items, int cap) { return (unsigned)(items < cap
 
 }  // namespace
 
-int64_t elem_stride() { return Lay<Model::B>::kEs; }
-int64_t msg_stride() { return Lay<Model::B>::kMs; }
-int64_t const_size() { return Model::kConst; }
-int64_t part_stride() { return Model::B * Model::B + 3; }
+int64_t elem_stride() { return Lay<kStateDim>::kEs; }
+int64_t msg_stride() { return Lay<kStateDim>::kMs; }
+int64_t const_size() { return ModelP::kConst; }
+int64_t part_stride() { return ModelQ::kPart; }
 
 void plan_levels(int64_t n, WideCtx& c) {
   int k = 0;
@@ -40,7 +42,8 @@ void plan_levels(int64_t n, WideCtx& c) {
   c.node_grid = (int)(n < kGridNode ? n : kGridNode);
 }
 
-hipError_t factor(const WideCtx& c) {
+template <class Model>
+hipError_t factor_m(const WideCtx& c) {
   constexpr int B = Model::B;
   mark(c, kKidFwd, 0);
   hipLaunchKernelGGL(k_wide_setup<Model>, dim3(1), dim3(kW), 0, c.stream, c.hyper, c.cst);
@@ -57,8 +60,10 @@ hipError_t factor(const WideCtx& c) {
   return hipGetLastError();
 }
 
+hipError_t factor(const WideCtx& c) { return c.quasi ? factor_m<ModelQ>(c) : factor_m<ModelP>(c); }
+
 hipError_t down(const WideCtx& c) {
-  constexpr int B = Model::B;
+  constexpr int B = kStateDim;
   mark(c, kKidBwd, 0);
   for (int k = c.n_levels - 1; k >= 1; --k)
     hipLaunchKernelGGL(k_wide_down<B>, dim3(grid_for(c.n[k - 1], kGridDown)), dim3(kW), 0, c.stream, c.elems, c.msgs,
@@ -69,8 +74,12 @@ hipError_t down(const WideCtx& c) {
 
 template <int MODE>
 static void launch_node(const WideCtx& c, const WideOut& o) {
-  hipLaunchKernelGGL((k_wide_node<Model, MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.t, c.y,
-                     c.n_points, c.cst, c.elems, c.msgs, o);
+  if (c.quasi)
+    hipLaunchKernelGGL((k_wide_node<ModelQ, MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.t, c.y,
+                       c.n_points, c.cst, c.elems, c.msgs, o);
+  else
+    hipLaunchKernelGGL((k_wide_node<ModelP, MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.t, c.y,
+                       c.n_points, c.cst, c.elems, c.msgs, o);
 }
 
 hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
@@ -95,14 +104,20 @@ hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, doubl
   return hipGetLastError();
 }
 
-hipError_t finish(const WideCtx& c, double* logml, double* grad) {
+template <class Model>
+hipError_t finish_m(const WideCtx& c, double* logml, double* grad) {
   mark(c, kKidReduce, 0);
+  // the totals follow the rows of all node work-groups (rows sized for the larger model)
   double* tot = c.part + (int64_t)c.node_grid * part_stride();
-  hipLaunchKernelGGL(k_wide_sum<Model>, dim3((unsigned)part_stride()), dim3(kW), 0, c.stream, c.part, c.node_grid,
+  hipLaunchKernelGGL(k_wide_sum<Model>, dim3((unsigned)Model::kPart), dim3(kW), 0, c.stream, c.part, c.node_grid,
                      tot);
   hipLaunchKernelGGL(k_wide_final<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, tot, c.scal, logml, grad);
   mark(c, kKidReduce, 1);
   return hipGetLastError();
+}
+
+hipError_t finish(const WideCtx& c, double* logml, double* grad) {
+  return c.quasi ? finish_m<ModelQ>(c, logml, grad) : finish_m<ModelP>(c, logml, grad);
 }
 
 }  // namespace wide

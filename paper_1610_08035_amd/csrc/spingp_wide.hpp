@@ -408,15 +408,35 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
 // truncated cosine series of the periodic kernel with weights
 //   q_j^2 = var_P c_j exp(-x) I_j(x),  x = 1 / l_P^2,  c_0 = 1, c_j = 2,
 // its harmonic j is a rotation by j w dt (w = 2 pi / period) with Q = 0.
-template <int NJ>
+// QUASI: the periodic term times an exponential decay exp(-|tau| / l_D) (the quasi-periodic
+// term); hyperparameter row (l_M, var_M, l_P, var_P, period, l_D, s2); every harmonic block
+// is e^{-dt / l_D} times the rotation and has Q = q_j^2 (1 - e^{-2 dt / l_D}) I.
+template <int NJ, bool QUASI = false>
 struct SumM32Periodic {
   static constexpr int B = 2 + 2 * (NJ + 1);
-  static constexpr int NH = 6;
+  static constexpr int NH = QUASI ? 7 : 6;
+  // scalar gradient sums of the node step: <A_bar, dA/dlam_M>, <A_bar, dA/dperiod>,
+  // [<A_bar, dA/dlam_D>], d/ds2
+  static constexpr int kExtra = QUASI ? 4 : 3;
+  static constexpr int kPart = B * B + kExtra;
   // constants shared by all kernels of one call, computed by k_wide_setup into global memory:
   // scalars, q_j^2, dq_j^2/dx, P0' = T P0 T^T
-  static constexpr int kLamM = 0, kVarM = 1, kEllP = 2, kVarP = 3, kPer = 4, kS2 = 5, kW0 = 6, kX = 7;
-  static constexpr int kQ2 = 8, kDQ2 = kQ2 + NJ + 1, kP0 = kDQ2 + NJ + 1;
+  static constexpr int kLamM = 0, kVarM = 1, kEllP = 2, kVarP = 3, kPer = 4, kS2 = 5, kW0 = 6, kX = 7, kLamD = 8;
+  static constexpr int kQ2 = 9, kDQ2 = kQ2 + NJ + 1, kP0 = kDQ2 + NJ + 1;
   static constexpr int kConst = kP0 + B * B;
+
+  // constants from the hyperparameter row
+  SPG_DEV static void scalars(const double* hyper, double* c) {
+    c[kLamM] = 1.7320508075688772935 / hyper[0];
+    c[kVarM] = hyper[1];
+    c[kEllP] = hyper[2];
+    c[kVarP] = hyper[3];
+    c[kPer] = hyper[4];
+    c[kLamD] = QUASI ? 1.0 / hyper[5] : 0.0;
+    c[kS2] = hyper[NH - 1];
+    c[kW0] = 6.283185307179586477 / hyper[4];
+    c[kX] = 1.0 / (hyper[2] * hyper[2]);
+  }
 
   SPG_DEV static bool observed(int k) { return k == 0 || (k >= 2 && (k & 1) == 0); }
   // T (row 0 = h^T, identity below) and T^-1 (row 0 = (1, -h_1, ..., -h_{B-1}), identity below)
@@ -439,11 +459,11 @@ struct SumM32Periodic {
     if (i >= 1 && observed(i)) r += y(0);
     return r;
   }
-  // entry (i, j) of the original-basis transition, its derivatives with respect to lam_M and
-  // the period, and of Q (Matern block only; the rotation blocks have Q = 0)
+  // entry (i, j) of the original-basis transition, its derivatives with respect to lam_M, the
+  // period and lam_D = 1 / l_D, and of Q
   SPG_DEV static void edge_entry(const double* c, double dt, int i, int j, double& a, double& q, double& da_lam,
-                                 double& da_per) {
-    a = q = da_lam = da_per = 0.0;
+                                 double& da_per, double& da_dec) {
+    a = q = da_lam = da_per = da_dec = 0.0;
     if (i < 2 && j < 2) {
       const double lam = c[kLamM], var = c[kVarM];
       const double x = lam * dt, e = exp(-lam * dt);
@@ -462,8 +482,13 @@ struct SumM32Periodic {
       // [[cos, -sin], [sin, cos]] and its derivative in theta, times d theta / d period
       const double R[2][2] = {{cs, -sn}, {sn, cs}};
       const double dR[2][2] = {{-sn, -cs}, {cs, -sn}};
-      a = R[ri][rj];
-      da_per = dR[ri][rj] * (-th / c[kPer]);
+      const double ed = QUASI ? exp(-c[kLamD] * dt) : 1.0;
+      a = ed * R[ri][rj];
+      da_per = ed * dR[ri][rj] * (-th / c[kPer]);
+      if (QUASI) {
+        da_dec = -dt * a;
+        if (ri == rj) q = c[kQ2 + h] * (1.0 - ed * ed);
+      }
     }
   }
   // diagonal of the original-basis P0 and its derivatives: d/dlam_M, d/dvar_M, d/dl_P, d/dvar_P
@@ -483,6 +508,33 @@ struct SumM32Periodic {
       p = c[kQ2 + h];
       dellp = c[kDQ2 + h] * (-2.0 / (ell * ell * ell));
       dvarp = c[kQ2 + h] / c[kVarP];
+    }
+  }
+  // gradient of the raw hyperparameters from the summed partials: tot[B*B + f] are the scalar
+  // sums, Pb the original-basis P0_bar
+  SPG_DEV static void final_grad(const double* c, const double* tot, const double* Pb, double* grad) {
+    constexpr int BB = B * B;
+    double g_lam = tot[BB + 0], g_varm = 0.0, g_ellp = 0.0, g_varp = 0.0;
+    for (int k = 0; k < B; ++k) {   // P0 is diagonal in the original basis
+      double p, dl, dvm, dep, dvp;
+      p0_diag(c, k, p, dl, dvm, dep, dvp);
+      const double pb = Pb[k * B + k];
+      g_lam = fma(pb, dl, g_lam);
+      g_varm = fma(pb, dvm, g_varm);
+      g_ellp = fma(pb, dep, g_ellp);
+      g_varp = fma(pb, dvp, g_varp);
+    }
+    const double ellm = 1.7320508075688772935 / c[kLamM];
+    grad[0] = g_lam * (-c[kLamM] / ellm);
+    grad[1] = g_varm;
+    grad[2] = g_ellp;
+    grad[3] = g_varp;
+    grad[4] = tot[BB + 1];
+    if (QUASI) {
+      grad[5] = tot[BB + 2] * (-c[kLamD] * c[kLamD]);   // d lam_D / d l_D = -lam_D^2
+      grad[6] = tot[BB + 3];
+    } else {
+      grad[5] = tot[BB + 2];
     }
   }
 };
@@ -511,16 +563,9 @@ __global__ __launch_bounds__(kW) void k_wide_setup(const double* __restrict__ hy
   __shared__ double c[M::kConst];
   __shared__ double P0[B * B], X[B * B];
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    c[M::kLamM] = 1.7320508075688772935 / hyper[0];
-    c[M::kVarM] = hyper[1];
-    c[M::kEllP] = hyper[2];
-    c[M::kVarP] = hyper[3];
-    c[M::kPer] = hyper[4];
-    c[M::kS2] = hyper[5];
-    c[M::kW0] = 6.283185307179586477 / hyper[4];
-    c[M::kX] = 1.0 / (hyper[2] * hyper[2]);
-  }
+  for (int e = tid; e < M::kConst; e += kW) c[e] = 0.0;
+  tsync();
+  if (tid == 0) M::scalars(hyper, c);
   tsync();
   // q_j^2 and dq_j^2 / dx, with d(e^-x I_j)/dx = (I_{j-1} + I_{j+1}) e^-x / 2 - e^-x I_j
   const int NJ = B / 2 - 2;
@@ -574,8 +619,8 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
     const double dt = edge ? t[n + 1] - t[n] : 0.0;
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
-      double a = 0.0, q = 0.0, d0, d1;
-      if (edge) M::edge_entry(c, dt, i, j, a, q, d0, d1);
+      double a = 0.0, q = 0.0, d0, d1, d2;
+      if (edge) M::edge_entry(c, dt, i, j, a, q, d0, d1, d2);
       Ao[e] = a;
       Qo[e] = q;
     }
@@ -740,7 +785,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
   constexpr bool kGrad = (MODE & kWantGrad) != 0;
   constexpr bool kCov = (MODE & (kWantVar | kWantSub)) != 0;
   constexpr bool kSub = (MODE & kWantSub) != 0;
-  constexpr int kPart = BB + 3;
+  constexpr int kPart = M::kPart;
   __shared__ double c[M::kConst];
   __shared__ double E[Y::kEs], G_[Y::kMs];   // leaf element; messages (prefix at n, suffix on n + 1)
   __shared__ double mp[B], Pp[BB], mn[B], Pn[BB], Mx[BB], Gm[BB], W[BB], lam[B], Lam[BB], X1[BB], X2[BB],
@@ -750,7 +795,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
   tsync();
   const double* P0 = c + M::kP0;
   const double s2 = c[M::kS2];
-  double acc_p0[2] = {0.0, 0.0}, acc_lam = 0.0, acc_per = 0.0, acc_s2 = 0.0;
+  double acc_p0[2] = {0.0, 0.0}, acc_lam = 0.0, acc_per = 0.0, acc_dec = 0.0, acc_s2 = 0.0;
   for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
     const bool edge = n + 1 < n_pts;
     for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[n * Y::kEs + e];
@@ -885,15 +930,16 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
         }
         tsync();
         // original basis: A_bar_o = T^T A_bar T^-T, needed only on the block-diagonal support
-        // of dA/dlam_M and dA/dperiod (one lane per entry of the 2 x 2 blocks)
+        // of dA/dlam_M, dA/dperiod and dA/dlam_D (one lane per entry of the 2 x 2 blocks)
         const double dt = t[n + 1] - t[n];
         if (tid < 2 * B) {
           const int blk = tid >> 2, i = 2 * blk + ((tid >> 1) & 1), j = 2 * blk + (tid & 1);
           const double ab = M::abar_orig(X2, i, j);
-          double a, q, dl, dp;
-          M::edge_entry(c, dt, i, j, a, q, dl, dp);
+          double a, q, dl, dp, dd;
+          M::edge_entry(c, dt, i, j, a, q, dl, dp, dd);
           acc_lam = fma(ab, dl, acc_lam);
           acc_per = fma(ab, dp, acc_per);
+          acc_dec = fma(ab, dd, acc_dec);
         }
         // P0_bar += Lam - A^T Lam A
         t_mm<B>(Lam, A, X2);
@@ -923,8 +969,8 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
     // the team in a fixed order
     double* pw = out.part + (int64_t)blockIdx.x * kPart;
     for (int e = tid, r = 0; e < BB; e += kW, ++r) pw[e] = acc_p0[r];
-    const double vals[3] = {acc_lam, acc_per, acc_s2};
-    for (int f = 0; f < 3; ++f) {
+    const double vals[4] = {acc_lam, acc_per, M::kExtra == 4 ? acc_dec : acc_s2, acc_s2};
+    for (int f = 0; f < M::kExtra; ++f) {
       red[tid] = vals[f];
       tsync();
       if (tid == 0) {
@@ -942,7 +988,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
 template <class M>
 __global__ __launch_bounds__(kW) void k_wide_sum(const double* __restrict__ part, int n_part,
                                                  double* __restrict__ tot) {
-  constexpr int kPart = M::B * M::B + 3;
+  constexpr int kPart = M::kPart;
   __shared__ double red[kW];
   const int tid = threadIdx.x, f = blockIdx.x;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -960,14 +1006,14 @@ __global__ __launch_bounds__(kW) void k_wide_sum(const double* __restrict__ part
   if (tid == 0) tot[f] = red[0];
 }
 
-// Gradient with respect to the raw hyperparameters (l_M, var_M, l_P, var_P, period, s2) from
-// the summed partials; also copies the log likelihood.
+// Gradient with respect to the raw hyperparameters (the model's row) from the summed
+// partials; also copies the log likelihood.
 template <class M>
 __global__ __launch_bounds__(kW) void k_wide_final(const double* __restrict__ cst, const double* __restrict__ totg,
                                                    const double* __restrict__ scal, double* __restrict__ logml,
                                                    double* __restrict__ grad) {
   constexpr int B = M::B, BB = B * B;
-  constexpr int kPart = BB + 3;
+  constexpr int kPart = M::kPart;
   __shared__ double c[M::kConst], tot[kPart], X[BB], Pb[BB];
   const int tid = threadIdx.x;
   for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
@@ -989,24 +1035,7 @@ __global__ __launch_bounds__(kW) void k_wide_final(const double* __restrict__ cs
   }
   tsync();
   if (tid == 0) {
-    // P0 is diagonal in the original basis
-    double g_lam = tot[BB + 0], g_varm = 0.0, g_ellp = 0.0, g_varp = 0.0;
-    for (int k = 0; k < B; ++k) {
-      double p, dl, dvm, dep, dvp;
-      M::p0_diag(c, k, p, dl, dvm, dep, dvp);
-      const double pb = Pb[k * B + k];
-      g_lam = fma(pb, dl, g_lam);
-      g_varm = fma(pb, dvm, g_varm);
-      g_ellp = fma(pb, dep, g_ellp);
-      g_varp = fma(pb, dvp, g_varp);
-    }
-    const double ellm = 1.7320508075688772935 / c[M::kLamM];
-    grad[0] = g_lam * (-c[M::kLamM] / ellm);
-    grad[1] = g_varm;
-    grad[2] = g_ellp;
-    grad[3] = g_varp;
-    grad[4] = tot[BB + 1];
-    grad[5] = tot[BB + 2];
+    M::final_grad(c, tot, Pb, grad);
     if (logml) logml[0] = scal[0];
   }
 }

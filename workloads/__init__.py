@@ -10,6 +10,7 @@ from .generate import (  # noqa: F401
     KIND_MATERN52,
     KIND_MATERN72,
     KIND_PERIODIC,
+    KIND_QUASIPERIODIC,
     Workload,
     make_batch,
     make_config,

@@ -29,6 +29,7 @@ KIND_MATERN52 = 2
 KIND_PERIODIC = 3
 KIND_MATERN12 = 4
 KIND_MATERN72 = 5
+KIND_QUASIPERIODIC = 6
 
 _MATERN_ORDER = {KIND_MATERN12: 1, KIND_MATERN32: 2, KIND_MATERN52: 3, KIND_MATERN72: 4}
 _MATERN_NU = {KIND_MATERN12: 0.5, KIND_MATERN32: 1.5, KIND_MATERN52: 2.5, KIND_MATERN72: 3.5}
@@ -40,7 +41,7 @@ def state_dim(terms) -> int:
     for kind, harm in terms:
         if kind in _MATERN_ORDER:
             b += _MATERN_ORDER[kind]
-        elif kind == KIND_PERIODIC:
+        elif kind in (KIND_PERIODIC, KIND_QUASIPERIODIC):
             b += 2 * (harm + 1)
         else:
             raise ValueError(f"unknown term kind {kind}")
@@ -48,10 +49,11 @@ def state_dim(terms) -> int:
 
 
 def n_hyper(terms) -> int:
-    """Hyperparameters per series: (l, var) per Matern, (l, var, period) per periodic, then noise."""
+    """Hyperparameters per series: (l, var) per Matern, (l, var, period) per periodic,
+    (l, var, period, decay) per quasi-periodic, then noise."""
     n = 0
     for kind, _ in terms:
-        n += 3 if kind == KIND_PERIODIC else 2
+        n += {KIND_PERIODIC: 3, KIND_QUASIPERIODIC: 4}.get(kind, 2)
     return n + 1
 
 
@@ -132,6 +134,33 @@ def _periodic_prior_path(t, harmonics, ell, var, period, rng):
     return f
 
 
+def _quasi_periodic_prior_path(t, harmonics, ell, var, period, decay, rng):
+    """Quasi-periodic sample path: every harmonic is a 2-state rotation by j w0 dt that decays
+    by e^{-dt/decay}, with stationary covariance var q_j^2 I (exact in distribution)."""
+    n = t.shape[0]
+    z = 1.0 / (ell * ell)
+    j = np.arange(harmonics + 1)
+    q2 = scipy.special.ive(j, z) * np.where(j == 0, 1.0, 2.0)
+    w0 = 2.0 * np.pi / period
+    dt = np.diff(t)
+    e = np.exp(-dt / decay)
+    f = np.zeros(n)
+    for jj in range(harmonics + 1):
+        s2 = var * q2[jj]
+        x0 = np.sqrt(s2) * rng.standard_normal(2)
+        xi = rng.standard_normal((max(n - 1, 0), 2))
+        if n == 0:
+            continue
+        # state ordered (sin part, cos part): the helper returns the last component
+        c, s = np.cos(jj * w0 * dt), np.sin(jj * w0 * dt)
+        A = np.zeros((n - 1, 2, 2))
+        A[:, 1, 1], A[:, 1, 0] = e * c, -e * s
+        A[:, 0, 1], A[:, 0, 0] = e * s, e * c
+        w = np.sqrt(s2 * np.maximum(1.0 - e * e, 0.0))[:, None] * xi
+        f += _recurrence_last_component(A, w, x0[::-1].copy())
+    return f
+
+
 def make_series(t, terms, hyper_row, rng):
     """Draw y = f + eps at times t for one series with hyperparameter row `hyper_row`."""
     t = np.asarray(t, dtype=np.float64)
@@ -141,6 +170,10 @@ def make_series(t, terms, hyper_row, rng):
         if kind in _MATERN_ORDER:
             f += _matern_prior_path(t, kind, hyper_row[p], hyper_row[p + 1], rng)
             p += 2
+        elif kind == KIND_QUASIPERIODIC:
+            f += _quasi_periodic_prior_path(t, harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2],
+                                            hyper_row[p + 3], rng)
+            p += 4
         else:
             f += _periodic_prior_path(t, harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2], rng)
             p += 3
