@@ -120,3 +120,27 @@ def test_fit_on_a_handle_with_its_own_stream(lib):
     assert res.converged, res.reason
     _check_fit(w.terms, t, y, res.hyper[0], res.logml[0], hyper0)
     h.close()
+
+
+def test_fit_co2_shaped_quasi_periodic(lib):
+    """A stand-in shaped like the paper's CO2 fit (Sec. 4.2; the data set itself is not used):
+    2195 weekly points (time in years), Matern-3/2 + quasi-periodic with a one-year period,
+    seven hyperparameters, fitted by scaled conjugate gradients from a start near the period;
+    the fit must reach the optimum scipy finds on the C oracle from the same start."""
+    from paper_1610_08035_amd.optimize import fit
+    from workloads import KIND_QUASIPERIODIC
+    from workloads.generate import make_series
+    terms = [(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3)]
+    true = np.array([8.0, 4.0, 1.0, 2.0, 1.0, 30.0, 0.1])    # l_M, var_M, l_P, var_P, period, l_D, s2
+    rng = np.random.default_rng(2195)
+    t = np.arange(2195) / 52.0
+    y = make_series(t, terms, true, rng)
+    hyper0 = np.array([5.0, 2.0, 0.8, 1.0, 1.01, 50.0, 0.2])
+    res = fit(to_dev(t), to_dev(y), terms, hyper0, max_iter=2000)
+    assert res.converged, res.reason
+    print(f"\nco2-shaped fit: {res.n_iter} iterations, {res.n_eval} evaluations, {res.hyper[0]}", flush=True)
+    hyp_ref, ll_ref = _oracle_fit(terms, t, y, hyper0)
+    assert abs(res.logml[0] - ll_ref) <= 1e-8 * abs(ll_ref), (res.logml[0], ll_ref)
+    assert np.max(np.abs(np.log(res.hyper[0]) - np.log(hyp_ref))) <= 1e-3, (res.hyper[0], hyp_ref)
+    r = native.tangent_grad(terms, res.hyper[0], t, y)
+    assert np.max(np.abs(r["grad"] * res.hyper[0])) <= 1e-5 * t.shape[0]
