@@ -21,6 +21,7 @@
  * with N = F + lam I nilpotent for Matern, rotations for periodic harmonics,
  * Q[dt] = P0 - A P0 A^T (eq. ss_matern).
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -33,6 +34,7 @@ typedef struct {
   int n_parts;
   int kind[8], harm[8], off[8], dim[8], pidx[8];
   double ell[8], var[8], period[8], lam[8], decay[8];
+  double se_coef[8][MAXB];   /* squared exponential: monic unit-lengthscale coefficients */
   double q2[8][MAXB], dq2[8][MAXB];
   int b, n_kernel_params;
   double noise;
@@ -107,6 +109,109 @@ static int solve(int b, const double* M, double* R, int m, double* logabsdet) {
   return 0;
 }
 
+/* ---------------- squared-exponential approximation ---------------- */
+/* Monic coefficients (s^0 .. s^(n-1)) of prod_k (s - r_k) over the stable roots r_k of
+   sum_{m<=n} (-r^2/2)^m / m! (n even): the truncated exponential's roots u_k found by
+   Durand-Kerner iteration, r_k = the square root of -2 u_k with negative real part. */
+static int se_unit_coeffs(int n, double* coef) {
+  if (n < 2 || n % 2 || n > 16) return -1;
+  double complex c[17], z[16];
+  double fact = 1.0;
+  for (int m = 0; m <= n; ++m) {
+    if (m > 0) fact *= m;
+    c[m] = 1.0 / fact;                         /* u^m coefficient */
+  }
+  for (int m = 0; m <= n; ++m) c[m] /= (1.0 / fact);   /* monic in u */
+  for (int k = 0; k < n; ++k) z[k] = cpow(0.4 + 0.9 * I, k);
+  for (int it = 0; it < 2000; ++it) {
+    double moved = 0.0;
+    for (int k = 0; k < n; ++k) {
+      double complex pv = c[n];
+      for (int m = n - 1; m >= 0; --m) pv = pv * z[k] + c[m];
+      double complex den = 1.0;
+      for (int j = 0; j < n; ++j)
+        if (j != k) den *= (z[k] - z[j]);
+      double complex dz = pv / den;
+      z[k] -= dz;
+      moved = fmax(moved, cabs(dz) / fmax(1.0, cabs(z[k])));
+    }
+    if (moved < 1e-16) break;
+  }
+  double complex poly[17];
+  poly[0] = 1.0;
+  for (int m = 1; m <= n; ++m) poly[m] = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double complex r = csqrt(-2.0 * z[k]);
+    if (creal(r) > 0) r = -r;
+    /* multiply by (s - r): poly holds coefficients of s^0 .. s^k */
+    for (int m = k + 1; m >= 1; --m) poly[m] = poly[m - 1] - r * poly[m];
+    poly[0] = -r * poly[0];
+  }
+  for (int m = 0; m < n; ++m) coef[m] = creal(poly[m]);
+  return 0;
+}
+
+/* exp(X) by scaling and squaring of the Taylor series (b x b). */
+static void expm_taylor(int b, const double* X, double* E) {
+  double nrm = 0.0;
+  for (int i = 0; i < b; ++i) {
+    double r = 0.0;
+    for (int j = 0; j < b; ++j) r += fabs(X[i * b + j]);
+    if (r > nrm) nrm = r;
+  }
+  int sq = 0;
+  while (nrm > 0.25) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  double Y[MAXB * MAXB], T[MAXB * MAXB], U[MAXB * MAXB];
+  double sc = ldexp(1.0, -sq);
+  for (int k = 0; k < b * b; ++k) Y[k] = X[k] * sc;
+  for (int k = 0; k < b * b; ++k) { E[k] = (k / b == k % b) ? 1.0 : 0.0; T[k] = E[k]; }
+  for (int m = 1; m <= 24; ++m) {
+    mm(b, T, Y, U);
+    for (int k = 0; k < b * b; ++k) { T[k] = U[k] / m; E[k] += T[k]; }
+  }
+  for (int q = 0; q < sq; ++q) {
+    mm(b, E, E, U);
+    memcpy(E, U, sizeof(double) * b * b);
+  }
+}
+
+/* Stationary covariance: F P + P F^T + q e_n e_n^T = 0 solved for the n(n+1)/2 entries of the
+   symmetric P (companion F). */
+static int lyap_companion(int n, const double* F, double q, double* P) {
+  int nu = n * (n + 1) / 2;
+  double M[MAXB * MAXB], R[MAXB];
+  if (nu > MAXB) return -1;
+  int idx[16][16];
+  for (int i = 0, k = 0; i < n; ++i)
+    for (int j = i; j < n; ++j, ++k) idx[i][j] = idx[j][i] = k;
+  memset(M, 0, sizeof(M));
+  for (int i = 0; i < n; ++i)
+    for (int j = i; j < n; ++j) {
+      int row = idx[i][j];
+      for (int k = 0; k < n; ++k) {
+        M[row * nu + idx[k][j]] += F[i * n + k];   /* (F P)_ij */
+        M[row * nu + idx[i][k]] += F[j * n + k];   /* (P F^T)_ij */
+      }
+      R[row] = (i == n - 1 && j == n - 1) ? -q : 0.0;
+    }
+  if (solve(nu, M, R, 1, NULL)) return -1;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) P[i * n + j] = R[idx[i][j]];
+  return 0;
+}
+
+/* F of the squared-exponential term at lam = 1 / l. */
+static void se_F(const model_t* m, int i, double* F) {
+  int n = m->dim[i];
+  double l = m->lam[i];
+  memset(F, 0, sizeof(double) * n * n);
+  for (int r = 0; r + 1 < n; ++r) F[r * n + r + 1] = 1.0;
+  for (int c = 0; c < n; ++c) F[(n - 1) * n + c] = -m->se_coef[i][c] * pow(l, n - c);
+}
+
 /* ---------------- model ---------------- */
 /* e^{-z} I_j(z) by its power series, terms summed in log space. */
 static double bessel_ive(int j, double z) {
@@ -140,6 +245,14 @@ static int model_init(model_t* m, int n_terms, const int* kinds, const int* harm
       m->var[i] = hyper[p + 1];
       m->lam[i] = sqrt(2.0 * m->dim[i] - 1.0) / m->ell[i];
       p += 2;
+    } else if (kinds[i] == 7) {
+      /* squared exponential through its spectral approximation of order harm[i] */
+      m->dim[i] = harm[i];
+      m->ell[i] = hyper[p];
+      m->var[i] = hyper[p + 1];
+      m->lam[i] = 1.0 / m->ell[i];
+      if (se_unit_coeffs(harm[i], m->se_coef[i])) return -1;
+      p += 2;
     } else if (kinds[i] == 3 || kinds[i] == 6) {
       /* periodic; kind 6 (quasi-periodic) also decays every harmonic by exp(-dt / decay) */
       m->dim[i] = 2 * (harm[i] + 1);
@@ -170,7 +283,24 @@ static int model_init(model_t* m, int n_terms, const int* kinds, const int* harm
   for (int i = 0; i < n_terms; ++i) {
     int o = m->off[i];
     int pi = m->pidx[i];
-    if (m->kind[i] == 4) {
+    if (m->kind[i] == 7) {
+      /* q = var sqrt(2 pi) n! 2^n lam^(2n - 1); P_rc scales as lam^(r+c) */
+      int n = m->dim[i];
+      double l = m->lam[i], dl = -l / m->ell[i], fact = 1.0;
+      for (int k = 2; k <= n; ++k) fact *= k;
+      double q = m->var[i] * sqrt(2.0 * M_PI) * fact * pow(2.0, n) * pow(l, 2 * n - 1);
+      double F[MAXB * MAXB], Ps[MAXB * MAXB];
+      se_F(m, i, F);
+      if (lyap_companion(n, F, q, Ps)) return -1;
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+          double v = 0.5 * (Ps[r * n + c] + Ps[c * n + r]);
+          m->P[(o + r) * b + o + c] = v;
+          m->dP[pi][(o + r) * b + o + c] = (r + c) * v / l * dl;
+          m->dP[pi + 1][(o + r) * b + o + c] = v / m->var[i];
+        }
+      m->h[o] = 1.0;
+    } else if (m->kind[i] == 4) {
       m->P[o * b + o] = m->var[i];
       m->dP[pi + 1][o * b + o] = 1.0;
       m->h[o] = 1.0;
@@ -233,7 +363,22 @@ static void model_A(const model_t* m, double dt, double* A, double (*dA)[MAXB * 
     for (int k = 0; k < m->n_kernel_params; ++k) memset(dA[k], 0, sizeof(double) * b * b);
   for (int i = 0; i < m->n_parts; ++i) {
     int o = m->off[i], pi = m->pidx[i];
-    if (m->kind[i] != 3 && m->kind[i] != 6) {
+    if (m->kind[i] == 7) {
+      /* A = expm(F dt); with F = lam D C1 D^-1 (D = diag(lam^r)) and x = lam dt,
+         dA/dlam = ((r - c) / lam) A_rc + (dt / lam) (F A)_rc */
+      int n = m->dim[i];
+      double l = m->lam[i], dl = -l / m->ell[i];
+      double F[MAXB * MAXB], X[MAXB * MAXB], E[MAXB * MAXB], FE[MAXB * MAXB];
+      se_F(m, i, F);
+      for (int k = 0; k < n * n; ++k) X[k] = F[k] * dt;
+      expm_taylor(n, X, E);
+      mm(n, F, E, FE);
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+          A[(o + r) * b + o + c] = E[r * n + c];
+          if (dA) dA[pi][(o + r) * b + o + c] = ((r - c) / l * E[r * n + c] + dt / l * FE[r * n + c]) * dl;
+        }
+    } else if (m->kind[i] != 3 && m->kind[i] != 6) {
       /* Matern: F is the companion matrix of (s + l)^d; N = F + l I is nilpotent (N^d = 0) and
          A = e^{-l dt} (I + N dt + N^2 dt^2/2 + N^3 dt^3/6); dN/dl = dF/dl + I */
       int d = m->dim[i];

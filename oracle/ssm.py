@@ -31,7 +31,7 @@ import numpy as np
 import scipy.linalg
 import scipy.special
 
-MATERN32, MATERN52, PERIODIC, MATERN12, MATERN72, QUASIPERIODIC = 1, 2, 3, 4, 5, 6
+MATERN32, MATERN52, PERIODIC, MATERN12, MATERN72, QUASIPERIODIC, SQEXP = 1, 2, 3, 4, 5, 6, 7
 _MATERN_B = {MATERN12: 1, MATERN32: 2, MATERN52: 3, MATERN72: 4}
 
 
@@ -247,6 +247,91 @@ class QuasiPeriodic(Periodic):
         return [d_ell * e, kp / self.var * e, d_per * e, kp * e * np.abs(tau) / self.decay ** 2]
 
 
+class SquaredExponential:
+    """Squared-exponential term var * exp(-tau^2 / (2 l^2)) through a rational approximation of
+    its spectral density S(w) = var sqrt(2 pi) l exp(-l^2 w^2 / 2): the exponential in 1 / S is
+    truncated after `order` + 1 terms (order even, so the polynomial has no real root), and the
+    stable spectral factor gives an SDE of that order in the state (f, f', ...).  With
+    lam = 1 / l the stable roots are lam r_k for fixed r_k, F is the companion matrix of
+    prod (s - lam r_k), the white-noise density is q = var sqrt(2 pi) order! 2^order
+    lam^(2 order - 1), and P0 solves the Lyapunov equation.  The model is the kernel this SDE
+    implies (it equals the squared exponential only as order grows).  Hyperparameters
+    (lengthscale, variance)."""
+
+    n_params = 2
+
+    def __init__(self, order, lengthscale, variance):
+        n = int(order)
+        if n < 2 or n % 2:
+            raise ValueError("the squared-exponential approximation needs an even order >= 2")
+        self.b = n
+        self.ell = float(lengthscale)
+        self.var = float(variance)
+        self.lam = 1.0 / self.ell
+        # roots in u = -r^2 / 2 of the truncated exponential, then the stable square roots
+        u = np.roots([1.0 / float(scipy.special.factorial(k)) for k in range(n, -1, -1)])
+        r = np.sqrt(-2.0 * u.astype(complex))
+        r = np.where(r.real < 0, r, -r)
+        self.unit_coeffs = np.real(np.poly(r))[1:]            # monic, s^(n-1) ... s^0
+        self.kappa = np.sqrt(2.0 * np.pi) * float(scipy.special.factorial(n)) * 2.0 ** n
+
+    def F(self):
+        n, l = self.b, self.lam
+        F = np.diag(np.ones(n - 1), 1)
+        F[n - 1, :] = [-self.unit_coeffs[n - 1 - j] * l ** (n - j) for j in range(n)]
+        return F
+
+    def dF_dlam(self):
+        n, l = self.b, self.lam
+        F = np.zeros((n, n))
+        F[n - 1, :] = [-self.unit_coeffs[n - 1 - j] * (n - j) * l ** (n - j - 1) for j in range(n)]
+        return F
+
+    def H(self):
+        h = np.zeros(self.b)
+        h[0] = 1.0
+        return h
+
+    def Pinf(self):
+        n = self.b
+        q = self.var * self.kappa * self.lam ** (2 * n - 1)
+        W = np.zeros((n, n))
+        W[n - 1, n - 1] = q
+        P = scipy.linalg.solve_continuous_lyapunov(self.F(), -W)
+        return 0.5 * (P + P.T)
+
+    def dF(self):
+        return [self.dF_dlam() * (-self.lam / self.ell), np.zeros((self.b, self.b))]
+
+    def dPinf(self):
+        # P_ij scales as lam^(i+j): dP/dlam = (i + j) P / lam
+        i = np.arange(self.b)
+        P = self.Pinf()
+        dlam = (i[:, None] + i[None, :]) * P / self.lam
+        return [dlam * (-self.lam / self.ell), P / self.var]
+
+    def kernel(self, tau):
+        tau = np.abs(np.asarray(tau, dtype=np.float64))
+        F, P = self.F(), self.Pinf()
+        out = np.array([(scipy.linalg.expm(F * x) @ P)[0, 0] for x in tau.reshape(-1)])
+        return out.reshape(tau.shape)
+
+    def kernel_untruncated(self, tau):
+        return self.var * np.exp(-0.5 * (np.asarray(tau) / self.ell) ** 2)
+
+    def dkernel(self, tau):
+        tau = np.abs(np.asarray(tau, dtype=np.float64))
+        F, P = self.F(), self.Pinf()
+        dF, dP = self.dF(), self.dPinf()
+        d_ell = []
+        for x in tau.reshape(-1):
+            E = scipy.linalg.expm(F * x)
+            dE = scipy.linalg.expm_frechet(F * x, dF[0] * x, compute_expm=False)
+            d_ell.append((dE @ P + E @ dP[0])[0, 0])
+        d_ell = np.array(d_ell).reshape(tau.shape)
+        return [d_ell, self.kernel(tau) / self.var]
+
+
 class SumModel:
     """Sum of terms: block-diagonal state space.  Parameters are the terms' in order."""
 
@@ -261,6 +346,9 @@ class SumModel:
             elif kind == PERIODIC:
                 self.parts.append(Periodic(harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2]))
                 p += 3
+            elif kind == SQEXP:
+                self.parts.append(SquaredExponential(harm, hyper_row[p], hyper_row[p + 1]))
+                p += 2
             elif kind == QUASIPERIODIC:
                 self.parts.append(QuasiPeriodic(harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2],
                                                 hyper_row[p + 3]))

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import btd, dense, kalman, native
-from oracle.ssm import MATERN12, MATERN32, MATERN52, MATERN72, PERIODIC, QUASIPERIODIC, model_for
+from oracle.ssm import MATERN12, MATERN32, MATERN52, MATERN72, PERIODIC, QUASIPERIODIC, SQEXP, model_for
 from workloads import make_config
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "mp_dense_adversarial.json")
@@ -25,6 +25,8 @@ CASES = [
     ("m72", [(MATERN72, 0)], [4.0, 1.5, 0.05]),
     ("m32+per3", [(MATERN32, 0), (PERIODIC, 3)], [50.0, 1.0, 1.0, 1.0, 24.0, 0.1]),
     ("m32+qp3", [(MATERN32, 0), (QUASIPERIODIC, 3)], [50.0, 1.0, 1.2, 0.8, 6.0, 15.0, 0.1]),
+    ("se6", [(SQEXP, 6)], [1.3, 0.7, 0.1]),
+    ("co2", [(MATERN32, 0), (QUASIPERIODIC, 3), (SQEXP, 6)], [50.0, 1.0, 1.2, 0.8, 6.0, 15.0, 2.0, 0.5, 0.1]),
 ]
 
 

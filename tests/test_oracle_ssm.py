@@ -4,8 +4,8 @@ import pytest
 import scipy.linalg
 
 from oracle import native
-from oracle.ssm import (MATERN12, MATERN32, MATERN52, MATERN72, PERIODIC, QUASIPERIODIC, Matern, Periodic,
-                        model_for)
+from oracle.ssm import (MATERN12, MATERN32, MATERN52, MATERN72, PERIODIC, QUASIPERIODIC, SQEXP, Matern, Periodic,
+                        SquaredExponential, model_for)
 
 MODELS = [
     ([(MATERN32, 0)], [1.0, 1.0, 0.1]),
@@ -21,6 +21,8 @@ MODELS = [
     ([(MATERN72, 0)], [0.6, 0.9, 0.2]),
     ([(QUASIPERIODIC, 3)], [1.0, 1.0, 24.0, 50.0, 0.1]),
     ([(MATERN32, 0), (QUASIPERIODIC, 3)], [50.0, 1.0, 1.2, 0.8, 6.0, 15.0, 0.1]),
+    ([(SQEXP, 6)], [1.3, 0.7, 0.1]),
+    ([(MATERN32, 0), (QUASIPERIODIC, 3), (SQEXP, 6)], [50.0, 1.0, 1.2, 0.8, 6.0, 15.0, 2.0, 0.5, 0.1]),
 ]
 TAUS = np.array([0.0, 1e-9, 1e-4, 0.01, 0.3, 1.0, 2.7, 10.0, 55.0])
 
@@ -132,7 +134,10 @@ def test_c_closed_forms_match_expm(terms, hyper):
     m = model_for(terms, hyper)
     t = np.cumsum(np.array([0.0, 0.0, 1e-9, 1e-5, 0.01, 0.4, 1.0, 3.3, 12.0, 60.0, 0.2]))
     A, Q, P, h = native.edges(terms, hyper, t)
-    assert np.allclose(P, m.Pinf(), rtol=1e-14, atol=1e-16)
+    # closed forms agree to rounding; a Lyapunov-solved P0 (squared exponential) to its solve
+    lyap = any(k == SQEXP for k, _ in terms)
+    assert np.allclose(P, m.Pinf(), rtol=1e-12 if lyap else 1e-14,
+                       atol=(1e-15 * np.abs(P).max()) if lyap else 1e-16)
     assert np.array_equal(h, m.H())
     for i in range(t.shape[0] - 1):
         dt = t[i + 1] - t[i]
@@ -155,3 +160,28 @@ def test_quasi_periodic_limits():
     far = native.btd_factored([(QUASIPERIODIC, 3)], [0.9, 1.3, 5.0, 1e9, 0.1], t, y, want_blocks=False)
     ref = native.btd_factored([(PERIODIC, 3)], [0.9, 1.3, 5.0, 0.1], t, y, want_blocks=False)
     assert abs(far["logml"] - ref["logml"]) <= 1e-6 * abs(ref["logml"])
+
+
+@pytest.mark.parametrize("order,err", [(2, 0.15), (4, 0.018), (6, 3.1e-3), (8, 6.5e-4)])
+def test_squared_exponential_approximation_converges(order, err):
+    """The SDE of the truncated spectral density approaches var exp(-tau^2 / 2 l^2): the
+    largest error over the lags shrinks with the order (about 5x per two orders)."""
+    m = SquaredExponential(order, 1.3, 0.7)
+    tau = np.linspace(0.0, 6.0, 61)
+    e = np.abs(m.kernel(tau) - m.kernel_untruncated(tau)).max() / m.var
+    assert e <= err
+
+
+def test_squared_exponential_scaling_in_lengthscale():
+    """P0 entry (i, j) scales as lam^(i+j) (the state holds f and its derivatives), the
+    stable roots as lam: the Lyapunov solutions at two lengthscales agree after rescaling."""
+    a, b = SquaredExponential(6, 1.0, 1.0), SquaredExponential(6, 0.37, 1.0)
+    i = np.arange(6)
+    scale = b.lam ** (i[:, None] + i[None, :])
+    assert np.allclose(b.Pinf() / scale, a.Pinf(), rtol=1e-8, atol=1e-10 * np.abs(a.Pinf()).max())
+    assert np.allclose(np.sort_complex(np.linalg.eigvals(b.F())), np.sort_complex(np.linalg.eigvals(a.F())) * b.lam,
+                       rtol=1e-9)
+    R = a.F() @ a.Pinf() + a.Pinf() @ a.F().T
+    mask = np.ones((6, 6), bool)
+    mask[5, 5] = False
+    assert np.abs(R[mask]).max() <= 1e-10 * np.abs(R).max()
