@@ -242,20 +242,29 @@ def predict_report(spg, steps, warmup):
 
 def bsweep_report(spg, steps, warmup):
     """Block size sweep in the manner of the paper's time-versus-b experiment: logML + gradient
-    per call for Matern nu = 1/2 .. 7/2 (b = 1 .. 4) and the b = 10 sum kernel, at N = 1000
-    and at N = 2^20 (2^18 for b = 10), eager launches on a side stream."""
+    per call for Matern nu = 1/2 .. 7/2 (b = 1 .. 4), the b = 10 sum kernel and the b = 16
+    three-term model of the CO2 fit, at N = 1000 and at N = 2^20 (2^18 for b = 10 and 16),
+    eager launches on a side stream."""
     import torch
-    from workloads import (KIND_MATERN12, KIND_MATERN32, KIND_MATERN52, KIND_MATERN72, make_batch,
-                           make_config)
+    from workloads import (KIND_MATERN12, KIND_MATERN32, KIND_MATERN52, KIND_MATERN72, KIND_QUASIPERIODIC,
+                           KIND_SQEXP, make_batch, make_config)
+    from workloads.generate import Workload, make_series
     dev = torch.device("cuda:0")
     side = torch.cuda.Stream()
     rows = []
     cases = [(1, [(KIND_MATERN12, 0)]), (2, [(KIND_MATERN32, 0)]), (3, [(KIND_MATERN52, 0)]),
-             (4, [(KIND_MATERN72, 0)]), (10, None)]
+             (4, [(KIND_MATERN72, 0)]), (10, None), (16, [(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 6)])]
     for b, terms in cases:
-        for n in (1000, (1 << 18) if b == 10 else (1 << 20)):
+        for n in (1000, (1 << 18) if b >= 10 else (1 << 20)):
             if terms is None:
                 w = make_config(3, n=n)
+            elif b == 16:
+                # weekly-like spacing in years, hyperparameters of the CO2-shaped stand-in
+                rng = np.random.default_rng(16)
+                tt = np.sort(rng.uniform(0.0, n / 52.0, n))
+                hy = np.array([0.8, 0.3, 1.0, 4.0, 1.0, 60.0, 8.0, 20.0, 0.05])
+                w = Workload(name="co2_terms", terms=terms, t=tt, y=make_series(tt, terms, hy, rng),
+                             offsets=np.array([0, n], dtype=np.int64), hyper=hy[None, :].copy())
             else:
                 w = make_batch([n], np.array([[5.0, 2.0, 0.05]]), terms, seed=b)
             t, y, hyp = w.series(0)
@@ -268,7 +277,7 @@ def bsweep_report(spg, steps, warmup):
             for _ in range(warmup):
                 spg.spingp_logml_grad(h._h, ll, g)
             torch.cuda.synchronize()
-            k = steps if n <= (1 << 18) or b < 10 else max(2, steps // 4)
+            k = steps if n <= (1 << 16) or b < 10 else max(2, steps // 4)
             t0 = time.perf_counter()
             for _ in range(k):
                 spg.spingp_logml_grad(h._h, ll, g)
@@ -283,8 +292,9 @@ def bsweep_report(spg, steps, warmup):
 def fit_report(spg):
     """Maximum-marginal-likelihood fits by scaled conjugate gradients: the N = 2^20 Matern-5/2
     series from a start away from the generating hyperparameters (l = 5, var = 2, s2 = 0.05),
-    and a CO2-shaped stand-in (weekly grid, Matern-3/2 + quasi-periodic): evaluations, wall
-    time, time per evaluation (one logML + gradient call plus the host round trip)."""
+    and CO2-shaped stand-ins (weekly grid; Matern-3/2 + quasi-periodic, and the full three-term
+    model with the squared-exponential trend): evaluations, wall time, time per evaluation (one
+    logML + gradient call plus the host round trip)."""
     import torch
     from paper_1610_08035_amd.optimize import fit
     from workloads import make_config
@@ -322,6 +332,25 @@ def fit_report(spg):
     el = time.perf_counter() - t0
     h.close()
     out.append({"workload": "co2_shaped_weekly2195_matern32+quasiperiodic3_fit_scg", "start": hyper0,
+                "hyper": [float(v) for v in res.hyper[0]], "logml": float(res.logml[0]),
+                "converged": res.converged, "iterations": res.n_iter, "evaluations": res.n_eval,
+                "seconds": el, "ms_per_evaluation": 1e3 * el / res.n_eval})
+    # the full three-term model (Matern-3/2 + quasi-periodic + squared-exponential trend, b = 16,
+    # nine hyperparameters), data drawn from (0.8, 0.3, 1, 4, 1, 60, 8, 20, 0.05)
+    from workloads import KIND_SQEXP
+    terms = [(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 6)]
+    y = make_series(t, terms, np.array([0.8, 0.3, 1.0, 4.0, 1.0, 60.0, 8.0, 20.0, 0.05]), np.random.default_rng(2196))
+    yd = torch.as_tensor(y, device=dev)
+    hyper0 = [1.0, 0.5, 0.9, 2.0, 1.005, 40.0, 10.0, 10.0, 0.1]
+    h = spg.Handle(terms, t.shape[0], stream=torch.cuda.Stream())
+    fit(td, yd, terms, hyper0, max_iter=3, handle=h)             # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = fit(td, yd, terms, hyper0, max_iter=3000, handle=h)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h.close()
+    out.append({"workload": "co2_shaped_weekly2195_matern32+quasiperiodic3+sqexp6_fit_scg", "start": hyper0,
                 "hyper": [float(v) for v in res.hyper[0]], "logml": float(res.logml[0]),
                 "converged": res.converged, "iterations": res.n_iter, "evaluations": res.n_eval,
                 "seconds": el, "ms_per_evaluation": 1e3 * el / res.n_eval})

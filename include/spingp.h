@@ -60,10 +60,14 @@ typedef enum {
   SPINGP_PERIODIC = 3,  /* periodic, `harmonics` cosine terms, b = 2 (harmonics + 1) */
   SPINGP_MATERN12 = 4,  /* Matern nu = 1/2 (exponential kernel), b = 1 */
   SPINGP_MATERN72 = 5,  /* Matern nu = 7/2, b = 4 */
-  SPINGP_QUASIPERIODIC = 6  /* periodic times exp(-|tau| / decay), b = 2 (harmonics + 1) */
+  SPINGP_QUASIPERIODIC = 6, /* periodic times exp(-|tau| / decay), b = 2 (harmonics + 1) */
+  SPINGP_SQEXP = 7          /* squared exponential by a spectral approximation of order
+                               `harmonics` (Sec. 2.1: the Taylor-truncated 1 / S; only order 6),
+                               b = harmonics */
 } spingp_kind_t;
 
-/* One additive covariance term; `harmonics` is used by periodic terms only. */
+/* One additive covariance term; `harmonics` is the number of harmonics of periodic terms and
+ * the approximation order of the squared exponential, unused otherwise. */
 typedef struct {
   int32_t kind;
   int32_t harmonics;
@@ -76,8 +80,11 @@ typedef struct {
  * row (lengthscale, signal variance, noise variance), lam = sqrt(2 nu) / lengthscale), any
  * number of series up to max_series; Matern-3/2 + periodic or quasi-periodic with 3 harmonics
  * (b = 10, one series; hyperparameter row (l_M, var_M, l_P, var_P, period, s2), with the decay
- * lengthscale before s2 for the quasi-periodic term).  Allocates all device workspace (sized for every compiled tile shape,
- * see spingp_tile_shape); returns SPINGP_E_UNSUPPORTED for other models.
+ * lengthscale before s2 for the quasi-periodic term); Matern-3/2 + quasi-periodic (3 harmonics)
+ * + squared exponential of order 6, the three-term model of the paper's CO2 fit (Sec. 4.3;
+ * b = 16, one series; row (l_M, var_M, l_P, var_P, period, l_D, l_S, var_S, s2)).  Allocates
+ * all device workspace (sized for every compiled tile shape, see spingp_tile_shape); returns
+ * SPINGP_E_UNSUPPORTED for other models.
  */
 int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,
                   int32_t max_series, void* stream);

@@ -12,6 +12,7 @@ from .spingp import (  # noqa: F401
     MATERN72,
     PERIODIC,
     QUASIPERIODIC,
+    SQEXP,
     Handle,
     SpinGPError,
     load_library,

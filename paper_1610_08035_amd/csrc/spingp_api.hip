@@ -219,20 +219,20 @@ static void drop_graph(spingp_ctx* h) {
 }
 
 // The wide-state model: one series, all tree levels and their messages stored item-major.
-static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_series, void* stream, bool quasi) {
+static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_series, void* stream, int model) {
   if (max_series != 1) return SPINGP_E_UNSUPPORTED;
   if (max_points > (int64_t(1) << 31)) return SPINGP_E_UNSUPPORTED;
   spingp_ctx* h = new (std::nothrow) spingp_ctx();
   if (!h) return SPINGP_E_NOMEM;
   h->wide = true;
-  h->b = spg::wide::kStateDim;
-  h->n_hyper = spg::wide::n_hyper(quasi);
+  h->b = spg::wide::state_dim(model);
+  h->n_hyper = spg::wide::n_hyper(model);
   h->max_points = max_points;
   h->max_series = 1;
   h->stream = (hipStream_t)stream;
   spg::wide::WideCtx& w = h->wplan;
   memset(&w, 0, sizeof(w));
-  w.quasi = quasi;
+  w.model = model;
   spg::wide::plan_levels(max_points, w);
   int64_t items = 0;
   for (int k = 0; k < w.n_levels; ++k) items += w.n[k];
@@ -240,10 +240,10 @@ static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_serie
     void** p;
     int64_t bytes;
   } reqs[] = {
-      {(void**)&w.elems, (int64_t)sizeof(double) * items * spg::wide::elem_stride()},
-      {(void**)&w.msgs, (int64_t)sizeof(double) * items * spg::wide::msg_stride()},
-      {(void**)&w.cst, (int64_t)sizeof(double) * spg::wide::const_size()},
-      {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride()},
+      {(void**)&w.elems, (int64_t)sizeof(double) * items * spg::wide::elem_stride(model)},
+      {(void**)&w.msgs, (int64_t)sizeof(double) * items * spg::wide::msg_stride(model)},
+      {(void**)&w.cst, (int64_t)sizeof(double) * spg::wide::const_size(model)},
+      {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride(model)},
       {(void**)&h->scal, (int64_t)sizeof(double) * 8},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
       {(void**)&h->pred, (int64_t)sizeof(double) * 4 * max_points},
@@ -268,8 +268,9 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
                              int32_t max_series, void* stream) {
   if (!out || !terms || n_terms < 1 || max_points < 1 || max_series < 1) return SPINGP_E_INVALID;
   *out = nullptr;
-  int b;
+  int b = 0;
   bool wide = false;
+  int model = spg::wide::kModelPeriodic;
   if (n_terms == 1 && terms[0].kind == SPINGP_MATERN12) b = 1;
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN32) b = 2;
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN52) b = 3;
@@ -277,13 +278,17 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   else if (n_terms == 2 && terms[0].kind == SPINGP_MATERN32 &&
            (terms[1].kind == SPINGP_PERIODIC || terms[1].kind == SPINGP_QUASIPERIODIC) &&
            terms[1].harmonics == 3) {
-    b = spg::wide::kStateDim;
+    model = terms[1].kind == SPINGP_QUASIPERIODIC ? spg::wide::kModelQuasi : spg::wide::kModelPeriodic;
+    wide = true;
+  } else if (n_terms == 3 && terms[0].kind == SPINGP_MATERN32 && terms[1].kind == SPINGP_QUASIPERIODIC &&
+             terms[1].harmonics == 3 && terms[2].kind == SPINGP_SQEXP && terms[2].harmonics == 6) {
+    model = spg::wide::kModelQuasiSqExp;
     wide = true;
   } else {
     return SPINGP_E_UNSUPPORTED;
   }
   if (max_points > (int64_t(1) << 40)) return SPINGP_E_UNSUPPORTED;
-  if (wide) return create_wide(out, max_points, max_series, stream, terms[1].kind == SPINGP_QUASIPERIODIC);
+  if (wide) return create_wide(out, max_points, max_series, stream, model);
   // workspace for the most demanding tile shape the handle may use
   const bool multi = max_series > 1;
   int64_t G_max = 0, lane_ld = 0;

@@ -120,8 +120,9 @@ inline SeriesMap make_map(const LaunchCtx& c, int64_t slots) {
 constexpr int kNumTiles = 6;
 const TileOps* tile_ops(int i);
 
-// Wide-state path (Matern-3/2 + periodic with 3 harmonics, b = 10, one series): level-by-level
-// reduction with one wavefront per element operation (spingp_wide.hip).
+// Wide-state path (Matern-3/2 + periodic or quasi-periodic with 3 harmonics, b = 10, optionally
+// plus a squared-exponential term of order 6, b = 16; one series): level-by-level reduction with
+// one wavefront per element operation (spingp_wide.hip).
 namespace wide {
 constexpr int kMaxLevels = 64;
 struct WideCtx {
@@ -139,16 +140,19 @@ struct WideCtx {
   int64_t n[kMaxLevels];
   int64_t off[kMaxLevels];
   int node_grid;      // work-groups of the node step (rows of part)
-  bool quasi;         // the periodic term decays (quasi-periodic term, one more hyperparameter)
+  int model;          // kModel* below
   void (*mark)(void* arg, int kid, int end);
   void* mark_arg;
 };
-constexpr int kStateDim = 10;
-inline int n_hyper(bool quasi) { return quasi ? 7 : 6; }
-int64_t elem_stride();     // doubles per stored element
-int64_t msg_stride();      // doubles per stored message
-int64_t const_size();      // doubles of the model constants
-int64_t part_stride();     // doubles per work-group partial (the larger of the two models)
+// Matern-3/2 + periodic (b = 10, 6 hyperparameters), + quasi-periodic (b = 10, 7), + quasi-periodic
+// + squared exponential of order 6 (b = 16, 9)
+constexpr int kModelPeriodic = 0, kModelQuasi = 1, kModelQuasiSqExp = 2;
+int state_dim(int model);
+int n_hyper(int model);
+int64_t elem_stride(int model);    // doubles per stored element
+int64_t msg_stride(int model);     // doubles per stored message
+int64_t const_size(int model);     // doubles of the model constants
+int64_t part_stride(int model);    // doubles per work-group partial
 void plan_levels(int64_t n, WideCtx& c);
 hipError_t factor(const WideCtx& c);                       // setup, leaves, up-sweep, root
 hipError_t down(const WideCtx& c);                         // down-sweep of all levels

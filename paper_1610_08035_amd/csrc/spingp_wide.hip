@@ -6,11 +6,10 @@ namespace spg {
 namespace wide {
 namespace {
 
-using ModelP = SumM32Periodic<3, false>;   // Matern-3/2 + periodic
-using ModelQ = SumM32Periodic<3, true>;    // Matern-3/2 + quasi-periodic
-static_assert(ModelP::B == kStateDim && ModelQ::B == kStateDim, "state dimension of the wide models");
-static_assert(ModelP::kConst == ModelQ::kConst, "one constant layout");
-static_assert(ModelP::kPart <= ModelQ::kPart, "partial rows sized for the larger model");
+using ModelP = SumM32Periodic<3, false>;               // Matern-3/2 + periodic
+using ModelQ = SumM32Periodic<3, true>;                // Matern-3/2 + quasi-periodic
+using ModelS = SumM32Periodic<3, true, kSqExpOrder>;   // ... + squared exponential
+static_assert(ModelP::B == ModelQ::B, "one state dimension for the two b = 10 models");
 // Work-group caps: what fits on the 256 CUs at once for each kernel's LDS (up 15 KB: 10 per
 // CU, down 13 KB: 11, node 21 KB: 7), so that every team stays resident and loops over its
 // items instead of a launch ending with a second, partly empty round.
@@ -23,10 +22,32 @@ inline unsigned grid_for(int64_t items, int cap) { return (unsigned)(items < cap
 
 }  // namespace
 
-int64_t elem_stride() { return Lay<kStateDim>::kEs; }
-int64_t msg_stride() { return Lay<kStateDim>::kMs; }
-int64_t const_size() { return ModelP::kConst; }
-int64_t part_stride() { return ModelQ::kPart; }
+// Calls f with a value of the model's type.
+template <class F>
+auto with_model(int model, F&& f) {
+  if (model == kModelQuasiSqExp) return f(ModelS());
+  if (model == kModelQuasi) return f(ModelQ());
+  return f(ModelP());
+}
+
+int state_dim(int model) {
+  return with_model(model, [](auto m) { return decltype(m)::B; });
+}
+int n_hyper(int model) {
+  return with_model(model, [](auto m) { return decltype(m)::NH; });
+}
+int64_t elem_stride(int model) {
+  return with_model(model, [](auto m) { return (int64_t)Lay<decltype(m)::B>::kEs; });
+}
+int64_t msg_stride(int model) {
+  return with_model(model, [](auto m) { return (int64_t)Lay<decltype(m)::B>::kMs; });
+}
+int64_t const_size(int model) {
+  return with_model(model, [](auto m) { return (int64_t)decltype(m)::kConst; });
+}
+int64_t part_stride(int model) {
+  return with_model(model, [](auto m) { return (int64_t)decltype(m)::kPart; });
+}
 
 void plan_levels(int64_t n, WideCtx& c) {
   int k = 0;
@@ -60,26 +81,34 @@ hipError_t factor_m(const WideCtx& c) {
   return hipGetLastError();
 }
 
-hipError_t factor(const WideCtx& c) { return c.quasi ? factor_m<ModelQ>(c) : factor_m<ModelP>(c); }
+hipError_t factor(const WideCtx& c) {
+  return with_model(c.model, [&](auto m) { return factor_m<decltype(m)>(c); });
+}
 
-hipError_t down(const WideCtx& c) {
-  constexpr int B = kStateDim;
-  mark(c, kKidBwd, 0);
+template <int B>
+static void down_b(const WideCtx& c) {
   for (int k = c.n_levels - 1; k >= 1; --k)
     hipLaunchKernelGGL(k_wide_down<B>, dim3(grid_for(c.n[k - 1], kGridDown)), dim3(kW), 0, c.stream, c.elems, c.msgs,
                        c.off[k], c.off[k - 1], c.n[k - 1]);
+}
+
+hipError_t down(const WideCtx& c) {
+  mark(c, kKidBwd, 0);
+  if (c.model == kModelQuasiSqExp)
+    down_b<ModelS::B>(c);
+  else
+    down_b<ModelP::B>(c);
   mark(c, kKidBwd, 1);
   return hipGetLastError();
 }
 
 template <int MODE>
 static void launch_node(const WideCtx& c, const WideOut& o) {
-  if (c.quasi)
-    hipLaunchKernelGGL((k_wide_node<ModelQ, MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.t, c.y,
-                       c.n_points, c.cst, c.elems, c.msgs, o);
-  else
-    hipLaunchKernelGGL((k_wide_node<ModelP, MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.t, c.y,
-                       c.n_points, c.cst, c.elems, c.msgs, o);
+  with_model(c.model, [&](auto m) {
+    hipLaunchKernelGGL((k_wide_node<decltype(m), MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.t,
+                       c.y, c.n_points, c.cst, c.elems, c.msgs, o);
+    return 0;
+  });
 }
 
 hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
@@ -107,8 +136,8 @@ hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, doubl
 template <class Model>
 hipError_t finish_m(const WideCtx& c, double* logml, double* grad) {
   mark(c, kKidReduce, 0);
-  // the totals follow the rows of all node work-groups (rows sized for the larger model)
-  double* tot = c.part + (int64_t)c.node_grid * part_stride();
+  // the totals follow the rows of all node work-groups
+  double* tot = c.part + (int64_t)c.node_grid * Model::kPart;
   hipLaunchKernelGGL(k_wide_sum<Model>, dim3((unsigned)Model::kPart), dim3(kW), 0, c.stream, c.part, c.node_grid,
                      tot);
   hipLaunchKernelGGL(k_wide_final<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, tot, c.scal, logml, grad);
@@ -117,7 +146,7 @@ hipError_t finish_m(const WideCtx& c, double* logml, double* grad) {
 }
 
 hipError_t finish(const WideCtx& c, double* logml, double* grad) {
-  return c.quasi ? finish_m<ModelQ>(c, logml, grad) : finish_m<ModelP>(c, logml, grad);
+  return with_model(c.model, [&](auto m) { return finish_m<decltype(m)>(c, logml, grad); });
 }
 
 }  // namespace wide

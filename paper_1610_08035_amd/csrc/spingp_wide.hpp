@@ -25,6 +25,7 @@
 // State outputs are mapped back with T^-1, gradients with T^T (.) T^-T.
 #pragma once
 #include "spingp_device.hpp"
+#include "spingp_sqexp_tables.hpp"
 
 namespace spg {
 namespace wide {
@@ -403,27 +404,42 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
 }
 
 // ---------------------------------------------------------------------------- the model
-// Matern-3/2 (state 0..1) + periodic with NJ harmonics (states 2 + 2j, 3 + 2j for j = 0..NJ).
-// Hyperparameter row: (l_M, var_M, l_P, var_P, period, s2).  The periodic term is the
-// truncated cosine series of the periodic kernel with weights
+// Matern-3/2 (state 0..1) + periodic with NJ harmonics (states 2 + 2j, 3 + 2j for j = 0..NJ),
+// optionally followed by a squared-exponential term of order NSE (states kS0 .. B - 1).
+// Hyperparameter row: (l_M, var_M, l_P, var_P, period, [l_D], [l_S, var_S], s2).  The periodic
+// term is the truncated cosine series of the periodic kernel with weights
 //   q_j^2 = var_P c_j exp(-x) I_j(x),  x = 1 / l_P^2,  c_0 = 1, c_j = 2,
 // its harmonic j is a rotation by j w dt (w = 2 pi / period) with Q = 0.
 // QUASI: the periodic term times an exponential decay exp(-|tau| / l_D) (the quasi-periodic
-// term); hyperparameter row (l_M, var_M, l_P, var_P, period, l_D, s2); every harmonic block
-// is e^{-dt / l_D} times the rotation and has Q = q_j^2 (1 - e^{-2 dt / l_D}) I.
-template <int NJ, bool QUASI = false>
+// term); every harmonic block is e^{-dt / l_D} times the rotation and has
+// Q = q_j^2 (1 - e^{-2 dt / l_D}) I.
+// NSE > 0: the squared exponential by its spectral approximation (state f, f', ..., f^(NSE-1),
+// lam_S = 1 / l_S): A_rc = lam_S^(r-c) [expm(C1 lam_S dt)]_rc, expm(C1 x) = 2 Re sum_k Z_k e^{r_k x}
+// over the stable roots with Im r_k > 0, and P0 = var_S lam_S^(r+c) P1 (tables generated from the
+// unit-lengthscale companion matrix C1).  Its block of P0 is dense, and every Q is formed as
+// P0 - A P0 A^T.
+template <int NJ, bool QUASI = false, int NSE = 0>
 struct SumM32Periodic {
-  static constexpr int B = 2 + 2 * (NJ + 1);
-  static constexpr int NH = QUASI ? 7 : 6;
-  // scalar gradient sums of the node step: <A_bar, dA/dlam_M>, <A_bar, dA/dperiod>,
-  // [<A_bar, dA/dlam_D>], d/ds2
-  static constexpr int kExtra = QUASI ? 4 : 3;
+  static constexpr int kNJ = NJ;
+  static constexpr int kS0 = 2 + 2 * (NJ + 1);        // first state of the squared exponential
+  static constexpr int B = kS0 + NSE;
+  static constexpr int NH = 6 + (QUASI ? 1 : 0) + (NSE ? 2 : 0);
+  // derivative channels of the transition: d/dlam_M, d/dperiod, [d/dlam_D], [d/dlam_S]
+  static constexpr int kNA = 2 + (QUASI ? 1 : 0) + (NSE ? 1 : 0);
+  static constexpr int kDec = 2, kDS = QUASI ? 3 : 2;
+  // scalar gradient sums of the node step: <A_bar, dA/dtheta> for the kNA channels, d/ds2
+  static constexpr int kExtra = kNA + 1;
   static constexpr int kPart = B * B + kExtra;
+  static constexpr bool kQFromP0 = NSE > 0;
+  // transition entries whose derivative is nonzero: the 2 x 2 blocks, then the SE block
+  static constexpr int kNS = 2 * kS0 + NSE * NSE;
   // constants shared by all kernels of one call, computed by k_wide_setup into global memory:
-  // scalars, q_j^2, dq_j^2/dx, P0' = T P0 T^T
+  // scalars, lam_S^(r-c), q_j^2, dq_j^2/dx, P0' = T P0 T^T
   static constexpr int kLamM = 0, kVarM = 1, kEllP = 2, kVarP = 3, kPer = 4, kS2 = 5, kW0 = 6, kX = 7, kLamD = 8;
-  static constexpr int kQ2 = 9, kDQ2 = kQ2 + NJ + 1, kP0 = kDQ2 + NJ + 1;
+  static constexpr int kLamS = 9, kVarS = 10, kLPow = 11;
+  static constexpr int kQ2 = kLPow + (NSE ? 2 * NSE - 1 : 0), kDQ2 = kQ2 + NJ + 1, kP0 = kDQ2 + NJ + 1;
   static constexpr int kConst = kP0 + B * B;
+  static_assert(NSE == 0 || NSE == kSqExpOrder, "squared-exponential order of the generated tables");
 
   // constants from the hyperparameter row
   SPG_DEV static void scalars(const double* hyper, double* c) {
@@ -436,9 +452,18 @@ struct SumM32Periodic {
     c[kS2] = hyper[NH - 1];
     c[kW0] = 6.283185307179586477 / hyper[4];
     c[kX] = 1.0 / (hyper[2] * hyper[2]);
+    if (NSE) {
+      const int p = QUASI ? 6 : 5;
+      const double lam = 1.0 / hyper[p];
+      c[kLamS] = lam;
+      c[kVarS] = hyper[p + 1];
+      for (int d = -(NSE - 1); d <= NSE - 1; ++d) c[kLPow + d + NSE - 1] = pow(lam, (double)d);
+    }
   }
 
-  SPG_DEV static bool observed(int k) { return k == 0 || (k >= 2 && (k & 1) == 0); }
+  SPG_DEV static bool observed(int k) {
+    return k == 0 || (k >= 2 && k < kS0 && (k & 1) == 0) || (NSE > 0 && k == kS0);
+  }
   // T (row 0 = h^T, identity below) and T^-1 (row 0 = (1, -h_1, ..., -h_{B-1}), identity below)
   SPG_DEV static double T_at(int i, int j) { return i == 0 ? (observed(j) ? 1.0 : 0.0) : (i == j ? 1.0 : 0.0); }
   SPG_DEV static double Ti_at(int i, int j) {
@@ -452,18 +477,31 @@ struct SumM32Periodic {
     auto y = [&](int k) {
       double v = X[k * B + j];
       if (j == 0)
-        for (int l = 2; l < B; l += 2) v -= X[k * B + l];
+        for (int l = 1; l < B; ++l)
+          if (observed(l)) v -= X[k * B + l];
       return v;
     };
     double r = y(i);
     if (i >= 1 && observed(i)) r += y(0);
     return r;
   }
-  // entry (i, j) of the original-basis transition, its derivatives with respect to lam_M, the
-  // period and lam_D = 1 / l_D, and of Q
-  SPG_DEV static void edge_entry(const double* c, double dt, int i, int j, double& a, double& q, double& da_lam,
-                                 double& da_per, double& da_dec) {
-    a = q = da_lam = da_per = da_dec = 0.0;
+  // support entry s < kNS of the transition derivatives
+  SPG_DEV static void support(int s, int& i, int& j) {
+    if (s < 2 * kS0) {
+      const int blk = s >> 2;
+      i = 2 * blk + ((s >> 1) & 1);
+      j = 2 * blk + (s & 1);
+    } else {
+      const int e = s - 2 * kS0;
+      i = kS0 + e / (NSE ? NSE : 1);
+      j = kS0 + e % (NSE ? NSE : 1);
+    }
+  }
+  // entry (i, j) of the original-basis transition, its derivatives (the kNA channels) and of
+  // the closed-form Q (not used when kQFromP0)
+  SPG_DEV static void edge_entry(const double* c, double dt, int i, int j, double& a, double& q, double* da) {
+    a = q = 0.0;
+    SPG_UNROLL for (int f = 0; f < kNA; ++f) da[f] = 0.0;
     if (i < 2 && j < 2) {
       const double lam = c[kLamM], var = c[kVarM];
       const double x = lam * dt, e = exp(-lam * dt);
@@ -472,8 +510,8 @@ struct SumM32Periodic {
       a = A2[i][j];
       q = (i == j ? P2[i] : 0.0) - (A2[i][0] * P2[0] * A2[j][0] + A2[i][1] * P2[1] * A2[j][1]);
       const double D2[2][2] = {{-dt * x, -dt * dt}, {x * (x - 2.0), dt * (x - 2.0)}};
-      da_lam = e * D2[i][j];
-    } else if (i >= 2 && j >= 2 && ((i - 2) >> 1) == ((j - 2) >> 1)) {
+      da[0] = e * D2[i][j];
+    } else if (i >= 2 && j >= 2 && i < kS0 && j < kS0 && ((i - 2) >> 1) == ((j - 2) >> 1)) {
       const int h = (i - 2) >> 1;
       const int ri = (i - 2) & 1, rj = (j - 2) & 1;
       const double th = (double)h * c[kW0] * dt;
@@ -484,58 +522,80 @@ struct SumM32Periodic {
       const double dR[2][2] = {{-sn, -cs}, {cs, -sn}};
       const double ed = QUASI ? exp(-c[kLamD] * dt) : 1.0;
       a = ed * R[ri][rj];
-      da_per = ed * dR[ri][rj] * (-th / c[kPer]);
+      da[1] = ed * dR[ri][rj] * (-th / c[kPer]);
       if (QUASI) {
-        da_dec = -dt * a;
+        da[kDec] = -dt * a;
         if (ri == rj) q = c[kQ2 + h] * (1.0 - ed * ed);
       }
+    } else if (NSE > 0 && i >= kS0 && j >= kS0) {
+      // A_rc = lam^(r-c) E_rc(lam dt),  dA_rc/dlam = (r-c)/lam A_rc + dt lam^(r-c) (C1 E)_rc
+      const int r = i - kS0, cc = j - kS0;
+      const double lam = c[kLamS], x = lam * dt;
+      double s = 0.0, ds = 0.0;
+      SPG_UNROLL for (int k = 0; k < NSE / 2; ++k) {
+        const double re = kSqExpRootRe[k], im = kSqExpRootIm[k];
+        double sn, cs;
+        sincos(im * x, &sn, &cs);
+        const double m = exp(re * x);
+        const double er = m * cs, ei = m * sn;                  // e^{r_k x}
+        const double zr = kSqExpZRe[(r * NSE + cc) * (NSE / 2) + k], zi = kSqExpZIm[(r * NSE + cc) * (NSE / 2) + k];
+        const double pr = zr * er - zi * ei, pi = zr * ei + zi * er;   // Z e^{r x}
+        s += pr;
+        ds += re * pr - im * pi;                                  // Re(r Z e^{r x})
+      }
+      const double lp = c[kLPow + r - cc + NSE - 1];
+      a = 2.0 * lp * s;
+      da[kDS] = (double)(r - cc) / lam * a + dt * lp * 2.0 * ds;
     }
   }
-  // diagonal of the original-basis P0 and its derivatives: d/dlam_M, d/dvar_M, d/dl_P, d/dvar_P
-  SPG_DEV static void p0_diag(const double* c, int k, double& p, double& dlam, double& dvarm, double& dellp,
-                              double& dvarp) {
-    p = dlam = dvarm = dellp = dvarp = 0.0;
-    if (k == 0) {
-      p = c[kVarM];
-      dvarm = 1.0;
-    } else if (k == 1) {
-      p = c[kVarM] * c[kLamM] * c[kLamM];
-      dlam = 2.0 * c[kVarM] * c[kLamM];
-      dvarm = c[kLamM] * c[kLamM];
-    } else {
-      const int h = (k - 2) >> 1;
-      const double ell = c[kEllP];
-      p = c[kQ2 + h];
-      dellp = c[kDQ2 + h] * (-2.0 / (ell * ell * ell));
-      dvarp = c[kQ2 + h] / c[kVarP];
+  // entry (i, j) of the original-basis P0
+  SPG_DEV static double p0_entry(const double* c, int i, int j) {
+    if (i < kS0 || j < kS0) {
+      if (i != j) return 0.0;
+      if (i == 0) return c[kVarM];
+      if (i == 1) return c[kVarM] * c[kLamM] * c[kLamM];
+      return c[kQ2 + ((i - 2) >> 1)];
     }
+    const int r = i - kS0, cc = j - kS0;
+    return c[kVarS] * pow(c[kLamS], (double)(r + cc)) * kSqExpP1[r * NSE + cc];
   }
   // gradient of the raw hyperparameters from the summed partials: tot[B*B + f] are the scalar
   // sums, Pb the original-basis P0_bar
   SPG_DEV static void final_grad(const double* c, const double* tot, const double* Pb, double* grad) {
     constexpr int BB = B * B;
-    double g_lam = tot[BB + 0], g_varm = 0.0, g_ellp = 0.0, g_varp = 0.0;
-    for (int k = 0; k < B; ++k) {   // P0 is diagonal in the original basis
-      double p, dl, dvm, dep, dvp;
-      p0_diag(c, k, p, dl, dvm, dep, dvp);
+    const double lam = c[kLamM], ell = c[kEllP];
+    // Matern block and harmonics: P0 is diagonal there
+    double g_lam = tot[BB + 0] + Pb[1 * B + 1] * 2.0 * c[kVarM] * lam;
+    const double g_varm = Pb[0] + Pb[1 * B + 1] * lam * lam;
+    double g_ellp = 0.0, g_varp = 0.0;
+    for (int k = 2; k < kS0; ++k) {
+      const int h = (k - 2) >> 1;
       const double pb = Pb[k * B + k];
-      g_lam = fma(pb, dl, g_lam);
-      g_varm = fma(pb, dvm, g_varm);
-      g_ellp = fma(pb, dep, g_ellp);
-      g_varp = fma(pb, dvp, g_varp);
+      g_ellp = fma(pb, c[kDQ2 + h] * (-2.0 / (ell * ell * ell)), g_ellp);
+      g_varp = fma(pb, c[kQ2 + h] / c[kVarP], g_varp);
     }
-    const double ellm = 1.7320508075688772935 / c[kLamM];
-    grad[0] = g_lam * (-c[kLamM] / ellm);
+    const double ellm = 1.7320508075688772935 / lam;
+    grad[0] = g_lam * (-lam / ellm);
     grad[1] = g_varm;
     grad[2] = g_ellp;
     grad[3] = g_varp;
     grad[4] = tot[BB + 1];
-    if (QUASI) {
-      grad[5] = tot[BB + 2] * (-c[kLamD] * c[kLamD]);   // d lam_D / d l_D = -lam_D^2
-      grad[6] = tot[BB + 3];
-    } else {
-      grad[5] = tot[BB + 2];
+    int p = 5;
+    if (QUASI) grad[p++] = tot[BB + kDec] * (-c[kLamD] * c[kLamD]);   // d lam_D / d l_D = -lam_D^2
+    if (NSE) {
+      // P0_ij scales as lam_S^(i+j) and linearly in var_S
+      const double ls = c[kLamS];
+      double g_ls = tot[BB + kDS], g_vs = 0.0;
+      for (int i = kS0; i < B; ++i)
+        for (int j = kS0; j < B; ++j) {
+          const double p0 = p0_entry(c, i, j), pb = Pb[i * B + j];
+          g_ls = fma(pb, (double)(i + j - 2 * kS0) / ls * p0, g_ls);
+          g_vs = fma(pb, p0 / c[kVarS], g_vs);
+        }
+      grad[p++] = g_ls * (-ls * ls);                                    // d lam_S / d l_S
+      grad[p++] = g_vs;
     }
+    grad[p] = tot[BB + kNA];
   }
 };
 
@@ -568,7 +628,7 @@ __global__ __launch_bounds__(kW) void k_wide_setup(const double* __restrict__ hy
   if (tid == 0) M::scalars(hyper, c);
   tsync();
   // q_j^2 and dq_j^2 / dx, with d(e^-x I_j)/dx = (I_{j-1} + I_{j+1}) e^-x / 2 - e^-x I_j
-  const int NJ = B / 2 - 2;
+  constexpr int NJ = M::kNJ;
   if (tid <= NJ) {
     const double x = c[M::kX], cj = tid == 0 ? 1.0 : 2.0;
     const double i0 = bessel_ive(tid, x), im = bessel_ive(tid - 1, x), ip = bessel_ive(tid + 1, x);
@@ -578,9 +638,7 @@ __global__ __launch_bounds__(kW) void k_wide_setup(const double* __restrict__ hy
   tsync();
   for (int e = tid; e < B * B; e += kW) {
     const int i = e / B, j = e - i * B;
-    double p = 0.0, d0, d1, d2, d3;
-    if (i == j) M::p0_diag(c, i, p, d0, d1, d2, d3);
-    P0[e] = p;
+    P0[e] = M::p0_entry(c, i, j);
   }
   tsync();
   // P0' = T P0 T^T
@@ -619,8 +677,8 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
     const double dt = edge ? t[n + 1] - t[n] : 0.0;
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
-      double a = 0.0, q = 0.0, d0, d1, d2;
-      if (edge) M::edge_entry(c, dt, i, j, a, q, d0, d1, d2);
+      double a = 0.0, q = 0.0, da[M::kNA];
+      if (edge) M::edge_entry(c, dt, i, j, a, q, da);
       Ao[e] = a;
       Qo[e] = q;
     }
@@ -640,11 +698,25 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
       E[Y::kA + e] = s;
     }
     tsync();
-    for (int e = tid; e < BB; e += kW) {
-      const int i = e / B, j = e - i * B;
-      double s = 0.0;
-      for (int k = 0; k < B; ++k) s = fma(M::T_at(i, k), Qo[k * B + j], s);
-      X[e] = s;
+    if (M::kQFromP0) {
+      // Q' = P0' - A' P0' A'^T (Q = 0 after the last node)
+      const double* P0 = c + M::kP0;
+      for (int e = tid; e < BB; e += kW) {
+        const int i = e / B, j = e - i * B;
+        Qo[e] = mm_entry<B, false, false>(E + Y::kA, P0, i, j);
+      }
+      tsync();
+      for (int e = tid; e < BB; e += kW) {
+        const int i = e / B, j = e - i * B;
+        X[e] = edge ? P0[e] - mm_entry<B, false, true>(Qo, E + Y::kA, i, j) : 0.0;
+      }
+    } else {
+      for (int e = tid; e < BB; e += kW) {
+        const int i = e / B, j = e - i * B;
+        double s = 0.0;
+        for (int k = 0; k < B; ++k) s = fma(M::T_at(i, k), Qo[k * B + j], s);
+        X[e] = s;
+      }
     }
     tsync();
     // a NaN observation marks a node without one (a prediction time): no information
@@ -653,7 +725,11 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
       double s = 0.0;
-      for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::T_at(j, k), s);
+      if (M::kQFromP0) {
+        s = X[e];
+      } else {
+        for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::T_at(j, k), s);
+      }
       E[Y::kQ + e] = s;
       E[Y::kJ + e] = (e == 0 && obs) ? 1.0 / s2 : 0.0;
     }
@@ -795,7 +871,11 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
   tsync();
   const double* P0 = c + M::kP0;
   const double s2 = c[M::kS2];
-  double acc_p0[2] = {0.0, 0.0}, acc_lam = 0.0, acc_per = 0.0, acc_dec = 0.0, acc_s2 = 0.0;
+  static_assert(M::kNS <= kW, "one lane per support entry of the transition derivatives");
+  constexpr int kRows = (BB + kW - 1) / kW;
+  double acc_p0[kRows], acc_a[M::kNA], acc_s2 = 0.0;
+  SPG_UNROLL for (int r = 0; r < kRows; ++r) acc_p0[r] = 0.0;
+  SPG_UNROLL for (int f = 0; f < M::kNA; ++f) acc_a[f] = 0.0;
   for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
     const bool edge = n + 1 < n_pts;
     for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[n * Y::kEs + e];
@@ -929,17 +1009,16 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
           X2[e] = fma(lam[i], mp[j], 2.0 * X2[e]);
         }
         tsync();
-        // original basis: A_bar_o = T^T A_bar T^-T, needed only on the block-diagonal support
-        // of dA/dlam_M, dA/dperiod and dA/dlam_D (one lane per entry of the 2 x 2 blocks)
+        // original basis: A_bar_o = T^T A_bar T^-T, needed only on the support of the
+        // transition derivatives (one lane per support entry)
         const double dt = t[n + 1] - t[n];
-        if (tid < 2 * B) {
-          const int blk = tid >> 2, i = 2 * blk + ((tid >> 1) & 1), j = 2 * blk + (tid & 1);
+        if (tid < M::kNS) {
+          int i, j;
+          M::support(tid, i, j);
           const double ab = M::abar_orig(X2, i, j);
-          double a, q, dl, dp, dd;
-          M::edge_entry(c, dt, i, j, a, q, dl, dp, dd);
-          acc_lam = fma(ab, dl, acc_lam);
-          acc_per = fma(ab, dp, acc_per);
-          acc_dec = fma(ab, dd, acc_dec);
+          double a, q, da[M::kNA];
+          M::edge_entry(c, dt, i, j, a, q, da);
+          SPG_UNROLL for (int f = 0; f < M::kNA; ++f) acc_a[f] = fma(ab, da[f], acc_a[f]);
         }
         // P0_bar += Lam - A^T Lam A
         t_mm<B>(Lam, A, X2);
@@ -965,13 +1044,15 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
     tsync();
   }
   if (kGrad) {
-    // per-work-group partials: lane-owned entries of P0_bar, then the three sums reduced over
+    // per-work-group partials: lane-owned entries of P0_bar, then the scalar sums reduced over
     // the team in a fixed order
     double* pw = out.part + (int64_t)blockIdx.x * kPart;
     for (int e = tid, r = 0; e < BB; e += kW, ++r) pw[e] = acc_p0[r];
-    const double vals[4] = {acc_lam, acc_per, M::kExtra == 4 ? acc_dec : acc_s2, acc_s2};
     for (int f = 0; f < M::kExtra; ++f) {
-      red[tid] = vals[f];
+      double v = acc_s2;
+      SPG_UNROLL for (int g = 0; g < M::kNA; ++g)
+        if (g == f) v = acc_a[g];
+      red[tid] = v;
       tsync();
       if (tid == 0) {
         double sacc = 0.0;

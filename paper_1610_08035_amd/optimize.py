@@ -1,5 +1,5 @@
 """Hyperparameter fitting: maximise the log marginal likelihood over kernel and noise
-hyperparameters (the paper fits its models by scaled conjugate gradients, Sec. 4.2).
+hyperparameters (the paper fits its models by scaled conjugate gradients, Sec. 4.3).
 
 Each evaluation of logML and its gradient is one ``spingp_logml_grad`` call on a handle whose
 hyperparameter buffer is updated in place (no re-assembly); the optimiser is host logic on a

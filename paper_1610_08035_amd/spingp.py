@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspingp.so")
 
-MATERN32, MATERN52, PERIODIC, MATERN12, MATERN72, QUASIPERIODIC = 1, 2, 3, 4, 5, 6
+MATERN32, MATERN52, PERIODIC, MATERN12, MATERN72, QUASIPERIODIC, SQEXP = 1, 2, 3, 4, 5, 6, 7
 
 ERRORS = {
     0: "ok", 1: "invalid argument", 2: "call order", 3: "unsorted times", 4: "non-finite input",

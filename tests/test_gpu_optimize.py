@@ -123,7 +123,7 @@ def test_fit_on_a_handle_with_its_own_stream(lib):
 
 
 def test_fit_co2_shaped_quasi_periodic(lib):
-    """A stand-in shaped like the paper's CO2 fit (Sec. 4.2; the data set itself is not used):
+    """A stand-in shaped like the paper's CO2 fit (Sec. 4.3; the data set itself is not used):
     2195 weekly points (time in years), Matern-3/2 + quasi-periodic with a one-year period,
     seven hyperparameters, fitted by scaled conjugate gradients from a start near the period;
     the fit must reach the optimum scipy finds on the C oracle from the same start."""
@@ -144,3 +144,36 @@ def test_fit_co2_shaped_quasi_periodic(lib):
     assert np.max(np.abs(np.log(res.hyper[0]) - np.log(hyp_ref))) <= 1e-3, (res.hyper[0], hyp_ref)
     r = native.tangent_grad(terms, res.hyper[0], t, y)
     assert np.max(np.abs(r["grad"] * res.hyper[0])) <= 1e-5 * t.shape[0]
+
+
+def test_fit_co2_shaped_three_terms(lib):
+    """The full three-term model of the paper's CO2 fit (Sec. 4.3): Matern-3/2 + quasi-periodic
+    + squared exponential (long trend), nine hyperparameters, on the 2195-point weekly grid.  The
+    scaled-conjugate-gradient fit on the device must end at a stationary point of the oracle's
+    logML (its own gradient vanishes there) that a further oracle-driven L-BFGS-B run cannot
+    improve beyond rounding."""
+    from paper_1610_08035_amd.optimize import fit
+    from workloads import KIND_QUASIPERIODIC, KIND_SQEXP
+    from workloads.generate import make_series
+    terms = [(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 6)]
+    # l_M, var_M, l_P, var_P, period, l_D, l_S, var_S, s2
+    true = np.array([0.8, 0.3, 1.0, 4.0, 1.0, 60.0, 8.0, 20.0, 0.05])
+    rng = np.random.default_rng(2196)
+    t = np.arange(2195) / 52.0
+    y = make_series(t, terms, true, rng)
+    hyper0 = np.array([1.0, 0.5, 0.9, 2.0, 1.005, 40.0, 10.0, 10.0, 0.1])
+    res = fit(to_dev(t), to_dev(y), terms, hyper0, max_iter=3000)
+    assert res.converged, res.reason
+    print(f"\nthree-term co2-shaped fit: {res.n_iter} iterations, {res.n_eval} evaluations, {res.hyper[0]}",
+          flush=True)
+    r = native.tangent_grad(terms, res.hyper[0], t, y)
+    assert abs(res.logml[0] - r["logml"]) <= 1e-8 * abs(r["logml"]), (res.logml[0], r["logml"])
+    assert np.max(np.abs(r["grad"] * res.hyper[0])) <= 1e-5 * t.shape[0], r["grad"] * res.hyper[0]
+    x0 = np.log(res.hyper[0])
+
+    def fun(x):
+        q = native.tangent_grad(terms, np.exp(x), t, y)
+        return -q["logml"], -q["grad"] * np.exp(x)
+
+    more = minimize(fun, x0, jac=True, method="L-BFGS-B", options={"maxiter": 15, "ftol": 1e-15, "gtol": 1e-12})
+    assert -more.fun <= res.logml[0] + 1e-8 * abs(res.logml[0]), (-more.fun, res.logml[0])

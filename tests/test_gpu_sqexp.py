@@ -1,0 +1,162 @@
+"""GPU parity of the three-term model of the paper's CO2 fit: Matern-3/2 + quasi-periodic
+(3 harmonics) + squared exponential by its spectral approximation of order 6 (b = 16, nine
+hyperparameters: l_M, var_M, l_P, var_P, period, l_D, l_S, var_S, s2), against the C oracle.
+The device forms the squared-exponential transition from spectral projectors of the
+unit-lengthscale companion matrix (tables generated in the package), the oracle from a Taylor
+series of the matrix exponential and a Lyapunov solve of its own: the two share no arithmetic."""
+import numpy as np
+import pytest
+
+from gpu_util import check_grad, check_logml, compare_series, to_dev
+from oracle import kalman, native
+from oracle.ssm import model_for
+from workloads import KIND_MATERN32, KIND_QUASIPERIODIC, KIND_SQEXP
+from workloads.generate import make_series
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TERMS = [(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 6)]
+HYPER = [50.0, 1.0, 1.2, 0.8, 6.0, 15.0, 2.0, 0.5, 0.1]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_08035_amd as spg
+    spg.load_library()
+    return spg
+
+
+def _data(n, hyper, seed, span=None):
+    rng = np.random.default_rng(seed)
+    span = span if span is not None else max(10.0, 0.05 * n)
+    t = np.sort(rng.uniform(0.0, span, n))
+    y = make_series(t, TERMS, hyper, rng)
+    return t, y, np.asarray(hyper, dtype=np.float64)
+
+
+def _run(spg, t, y, hyp, blocks=True):
+    n = t.shape[0]
+    h = spg.Handle(TERMS, n)
+    assert h.b == 16 and h.n_hyper == 9
+    h.assemble(to_dev(t), to_dev(y), to_dev(hyp))
+    h.factor()
+    ll, fit, ld = h.logml(parts=True)
+    fm, zm = h.solve(states=True)
+    if blocks:
+        fv, sd, ss = h.selinv(blocks=True)
+    else:
+        fv = h.selinv()
+    ll2, g = h.logml_grad()
+    out = {"logml": ll.item(), "datafit": fit.item(), "logdet": ld.item(), "f_mean": fm.cpu().numpy(),
+           "z_mean": zm.cpu().numpy(), "f_var": fv.cpu().numpy(), "logml2": ll2.item(),
+           "grad": g.cpu().numpy().reshape(-1), "status": h.status()[0]}
+    if blocks:
+        out["S_diag"] = sd.cpu().numpy()
+        out["S_sub"] = ss.cpu().numpy()
+    h.close()
+    return out
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 64, 65, 1000, 4097])
+def test_sqexp_sum_every_output(lib, n):
+    t, y, hyp = _data(n, HYPER, seed=300 + n)
+    print(f"\nM32 + quasi-periodic + SE6 n={n}", flush=True)
+    compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp))
+
+
+@pytest.mark.parametrize("hyper", [[5.0, 0.5, 0.7, 2.0, 7.0, 3.0, 0.4, 2.0, 0.05],
+                                   [200.0, 2.0, 3.0, 0.5, 50.0, 400.0, 30.0, 1.5, 0.3]])
+def test_sqexp_sum_other_hyperparameters(lib, hyper):
+    t, y, hyp = _data(3000, hyper, seed=17, span=300.0)
+    print(f"\nhyper={hyper}", flush=True)
+    compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp))
+
+
+def test_sqexp_sum_co2_shaped(lib):
+    """Weekly grid of 2195 points in years (the length of the paper's CO2 record), a one-year
+    period, a slowly decaying seasonal term and a long squared-exponential trend."""
+    hyper = [0.5, 0.3, 1.0, 4.0, 1.0, 60.0, 15.0, 100.0, 0.05]
+    rng = np.random.default_rng(18)
+    t = np.arange(2195) / 52.0
+    y = make_series(t, TERMS, hyper, rng)
+    hyp = np.asarray(hyper, dtype=np.float64)
+    compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp))
+
+
+def test_sqexp_sum_large(lib):
+    """2^16 points: many tree levels; logML, the nine-component gradient, means and variances."""
+    t, y, hyp = _data(1 << 16, HYPER, seed=19, span=3000.0)
+    compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp, blocks=False), blocks=False)
+
+
+def test_sqexp_sum_predict(lib):
+    t, y, hyp = _data(2000, HYPER, seed=20, span=100.0)
+    rng = np.random.default_rng(21)
+    ts = np.sort(rng.uniform(-5.0, 110.0, 300))
+    h = lib.Handle(TERMS, t.shape[0] + ts.shape[0])
+    h.assemble(to_dev(t), to_dev(y), to_dev(hyp))
+    fm, fv = h.predict(to_dev(ts))
+    assert h.status()[0] == 0
+    tm = np.concatenate([t, ts])
+    ym = np.concatenate([y, np.full(ts.shape[0], np.nan)])
+    order = np.lexsort((np.concatenate([np.zeros(t.shape[0]), np.ones(ts.shape[0])]), tm))
+    pos = np.empty(tm.shape[0], np.int64)
+    pos[order] = np.arange(tm.shape[0])
+    k = kalman.kf_rts(model_for(TERMS, hyp), tm[order], ym[order])
+    rm, rv = k["f_mean"][pos[t.shape[0]:]], k["f_var"][pos[t.shape[0]:]]
+    fm, fv = fm.cpu().numpy(), fv.cpu().numpy()
+    assert np.max(np.abs(fm - rm) / (np.abs(rm) + np.sqrt(rv))) <= 1e-9
+    assert np.max(np.abs(fv - rv) / rv) <= 1e-9
+    h.close()
+
+
+def test_sqexp_sum_graph_and_autograd(lib):
+    from paper_1610_08035_amd.autograd import logml
+    t, y, hyp = _data(3000, HYPER, seed=22, span=150.0)
+    td, yd = to_dev(t), to_dev(y)
+    hd = to_dev(hyp)
+    eager = lib.Handle(TERMS, t.shape[0])
+    eager.assemble(td, yd, hd)
+    gh = lib.Handle(TERMS, t.shape[0])
+    gh.assemble(td, yd, hd, graph=True)
+    ll = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    g = torch.empty(1, 9, dtype=torch.float64, device="cuda:0")
+    for rep in range(3):
+        if rep == 1:
+            hd.mul_(1.03)
+        lib.spingp_logml_grad(gh._h, ll, g)
+        e_ll, e_g = eager.logml_grad()
+        torch.cuda.synchronize()
+        assert torch.equal(ll, e_ll) and torch.equal(g, e_g), f"replay {rep}"
+    r = native.tangent_grad(TERMS, hd.cpu().numpy(), t, y)
+    check_logml(ll.item(), r["logml"])
+    check_grad(g.cpu().numpy(), r["grad"])
+    eager.close()
+    gh.close()
+    hy = to_dev(hyp).requires_grad_(True)
+    la = logml(td, yd, hy, TERMS)
+    la.sum().backward()
+    r = native.tangent_grad(TERMS, hyp, t, y)
+    check_logml(la.item(), r["logml"])
+    check_grad(hy.grad.cpu().numpy(), r["grad"])
+
+
+def test_sqexp_handle_errors(lib):
+    with pytest.raises(lib.SpinGPError):
+        lib.Handle(TERMS, 100, max_series=2)                                   # one series only
+    with pytest.raises(lib.SpinGPError):
+        lib.Handle([(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 4)], 100)   # order 6 only
+    with pytest.raises(lib.SpinGPError):
+        lib.Handle([(KIND_SQEXP, 6)], 100)                                     # not on its own
+    h = lib.Handle(TERMS, 100)
+    t, y, _ = _data(50, HYPER, seed=23)
+    for k in (6, 7):                                     # SE lengthscale and variance must be > 0
+        hy = np.array(HYPER)
+        hy[k] = 0.0
+        h.assemble(to_dev(t), to_dev(y), to_dev(hy))
+        assert h.status()[0] == 5
+    h.close()

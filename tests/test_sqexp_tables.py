@@ -1,0 +1,87 @@
+"""The squared-exponential constants compiled into the library (csrc/spingp_sqexp_tables.hpp):
+they must reproduce the matrix exponential and the stationary covariance of the unit-lengthscale
+companion matrix, built here from the paper's recipe (Sec. 2.1: the Taylor-truncated inverse
+spectral density, its stable roots) with numpy and scipy, and match what the committed
+generator writes."""
+import math
+import os
+import re
+import sys
+
+import numpy as np
+import scipy.linalg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "paper_1610_08035_amd", "csrc", "spingp_sqexp_tables.hpp")
+
+
+def _read():
+    txt = open(HEADER).read()
+
+    def arr(name):
+        m = re.search(name + r"\[(\d+)\] = \{([^}]*)\}", txt)
+        vals = np.array([float(x) for x in m.group(2).split(",")])
+        assert vals.size == int(m.group(1))
+        return vals
+
+    n = int(re.search(r"kSqExpOrder = (\d+);", txt).group(1))
+    roots = arr("kSqExpRootRe") + 1j * arr("kSqExpRootIm")
+    Z = (arr("kSqExpZRe") + 1j * arr("kSqExpZIm")).reshape(n, n, n // 2)
+    return n, roots, Z, arr("kSqExpP1").reshape(n, n)
+
+
+def _companion(n):
+    # stable roots of sum_m (-r^2 / 2)^m / m!, m = 0..n
+    u = np.roots([1.0 / math.factorial(k) for k in range(n, -1, -1)])
+    r = np.sqrt(-2.0 * u.astype(complex))
+    r = np.where(r.real < 0, r, -r)
+    c = np.real(np.poly(r))
+    C = np.diag(np.ones(n - 1), 1)
+    C[-1, :] = -c[1:][::-1]
+    return C, r
+
+
+def test_roots_are_the_stable_upper_half():
+    n, roots, _, _ = _read()
+    _, r = _companion(n)
+    want = np.sort_complex(r[r.imag > 0])
+    assert np.allclose(np.sort_complex(roots), want, rtol=1e-12, atol=0)
+    assert np.all(roots.real < 0) and np.all(roots.imag > 0)
+
+
+def test_projectors_give_the_matrix_exponential():
+    n, roots, Z, _ = _read()
+    C, _ = _companion(n)
+    for x in (0.0, 1e-4, 0.05, 0.7, 2.5, 9.0):
+        E = 2.0 * np.real(np.einsum("rck,k->rc", Z, np.exp(roots * x)))
+        assert np.abs(E - scipy.linalg.expm(C * x)).max() <= 1e-12 * max(1.0, np.abs(Z).sum(axis=2).max()), x
+    # the projectors sum to the identity and are idempotent
+    full = 2.0 * np.real(Z.sum(axis=2))
+    assert np.abs(full - np.eye(n)).max() <= 1e-12
+    for k in range(n // 2):
+        assert np.abs(Z[:, :, k] @ Z[:, :, k] - Z[:, :, k]).max() <= 1e-9 * np.abs(Z[:, :, k]).max()
+
+
+def test_stationary_covariance():
+    n, _, _, P1 = _read()
+    C, _ = _companion(n)
+    kappa = math.sqrt(2.0 * math.pi) * math.factorial(n) * 2.0 ** n
+    W = np.zeros((n, n))
+    W[-1, -1] = kappa
+    res = C @ P1 + P1 @ C.T + W
+    assert np.abs(res).max() <= 1e-11 * kappa
+    assert np.allclose(P1, P1.T, rtol=1e-15, atol=0)
+    assert np.all(np.linalg.eigvalsh(P1) > 0)
+    # the implied kernel at lag 0 is within 0.3 % of 1 at order 6 (the truncation error)
+    assert abs(P1[0, 0] - 1.0) < 3.1e-3
+
+
+def test_header_matches_the_generator():
+    sys.path.insert(0, os.path.join(ROOT, "paper_1610_08035_amd"))
+    try:
+        from gen_sqexp_tables import tables
+    finally:
+        sys.path.pop(0)
+    n, roots, Z, P1 = _read()
+    r2, Z2, P2 = tables(n)
+    assert np.array_equal(roots, r2) and np.array_equal(Z, Z2) and np.array_equal(P1, P2)

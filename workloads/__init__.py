@@ -11,6 +11,7 @@ from .generate import (  # noqa: F401
     KIND_MATERN72,
     KIND_PERIODIC,
     KIND_QUASIPERIODIC,
+    KIND_SQEXP,
     Workload,
     make_batch,
     make_config,

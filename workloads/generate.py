@@ -30,6 +30,7 @@ KIND_PERIODIC = 3
 KIND_MATERN12 = 4
 KIND_MATERN72 = 5
 KIND_QUASIPERIODIC = 6
+KIND_SQEXP = 7
 
 _MATERN_ORDER = {KIND_MATERN12: 1, KIND_MATERN32: 2, KIND_MATERN52: 3, KIND_MATERN72: 4}
 _MATERN_NU = {KIND_MATERN12: 0.5, KIND_MATERN32: 1.5, KIND_MATERN52: 2.5, KIND_MATERN72: 3.5}
@@ -43,14 +44,16 @@ def state_dim(terms) -> int:
             b += _MATERN_ORDER[kind]
         elif kind in (KIND_PERIODIC, KIND_QUASIPERIODIC):
             b += 2 * (harm + 1)
+        elif kind == KIND_SQEXP:
+            b += harm
         else:
             raise ValueError(f"unknown term kind {kind}")
     return b
 
 
 def n_hyper(terms) -> int:
-    """Hyperparameters per series: (l, var) per Matern, (l, var, period) per periodic,
-    (l, var, period, decay) per quasi-periodic, then noise."""
+    """Hyperparameters per series: (l, var) per Matern and squared exponential, (l, var,
+    period) per periodic, (l, var, period, decay) per quasi-periodic, then noise."""
     n = 0
     for kind, _ in terms:
         n += {KIND_PERIODIC: 3, KIND_QUASIPERIODIC: 4}.get(kind, 2)
@@ -161,6 +164,18 @@ def _quasi_periodic_prior_path(t, harmonics, ell, var, period, decay, rng):
     return f
 
 
+def _sqexp_prior_path(t, ell, var, rng, n_features=256):
+    """Smooth path with (approximately) the squared-exponential covariance var exp(-tau^2 / (2 l^2)),
+    by random Fourier features: frequencies drawn from the kernel's spectral density N(0, 1/l^2),
+    uniform phases, sqrt(2 var / D) sum_d cos(w_d t + phi_d)."""
+    w = rng.standard_normal(n_features) / ell
+    phi = rng.uniform(0.0, 2.0 * np.pi, n_features)
+    f = np.empty(t.shape[0])
+    for s in range(0, t.shape[0], 1 << 15):          # bounded temporaries for long series
+        f[s:s + (1 << 15)] = np.cos(np.outer(t[s:s + (1 << 15)], w) + phi).sum(axis=1)
+    return np.sqrt(2.0 * var / n_features) * f
+
+
 def make_series(t, terms, hyper_row, rng):
     """Draw y = f + eps at times t for one series with hyperparameter row `hyper_row`."""
     t = np.asarray(t, dtype=np.float64)
@@ -174,6 +189,9 @@ def make_series(t, terms, hyper_row, rng):
             f += _quasi_periodic_prior_path(t, harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2],
                                             hyper_row[p + 3], rng)
             p += 4
+        elif kind == KIND_SQEXP:
+            f += _sqexp_prior_path(t, hyper_row[p], hyper_row[p + 1], rng)
+            p += 2
         else:
             f += _periodic_prior_path(t, harm, hyper_row[p], hyper_row[p + 1], hyper_row[p + 2], rng)
             p += 3
