@@ -62,8 +62,9 @@ typedef enum {
   SPINGP_MATERN72 = 5,  /* Matern nu = 7/2, b = 4 */
   SPINGP_QUASIPERIODIC = 6, /* periodic times exp(-|tau| / decay), b = 2 (harmonics + 1) */
   SPINGP_SQEXP = 7          /* squared exponential by a spectral approximation of order
-                               `harmonics` (Sec. 2.1: the Taylor-truncated 1 / S; only order 6),
-                               b = harmonics */
+                               `harmonics` (a state-space form that approximates the kernel,
+                               Sec. 2.2: 1 / S truncated after order + 1 terms of its series;
+                               only order 6), b = harmonics */
 } spingp_kind_t;
 
 /* One additive covariance term; `harmonics` is the number of harmonics of periodic terms and
