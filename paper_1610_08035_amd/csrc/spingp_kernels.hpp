@@ -570,31 +570,35 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
     lds_barrier();
     // ---- work-group down-sweep: thread i < cnt carries the prefix of parent i into its right
     //      child, thread L/2 + i (another wavefront) the suffix of parent i into its left child;
-    //      the children's elements come from the tree the forward kernel stored
+    //      the children's elements come from the tree the forward kernel stored.  Each level's
+    //      sibling element is loaded one level ahead (by the lanes i < 2 cnt that will use it),
+    //      so its global-memory latency overlaps the current level's combine.
+    const bool suf = tid >= L / 2;
+    const int i = suf ? tid - L / 2 : tid;
+    Elem<B> Tc;   // this lane's sibling element of the current level
+    if (i < 1) elem_load<B>(tree_elems, tree_ld, gbase + (off - 2) + 2 * i + (suf ? 1 : 0), Tc);
     SPG_UNROLL for (int cnt = 1; cnt < L; cnt *= 2) {
       const int ncnt = cnt * 2, noff = off - ncnt;
-      const bool suf = tid >= L / 2;
-      const int i = suf ? tid - L / 2 : tid;
+      Elem<B> Tn;
+      if (ncnt < L && i < ncnt)
+        elem_load<B>(tree_elems, tree_ld, gbase + (noff - 2 * ncnt) + 2 * i + (suf ? 1 : 0), Tn);
       if (i < cnt) {
         Msg<B> par;
         lds_load_msg<B, NS>(pool, off + i, par);
         if (!suf) {
-          Elem<B> Tl;
-          elem_load<B>(tree_elems, tree_ld, gbase + noff + 2 * i, Tl);
           double mo[B], Po[B][B], dcf, dcl;
-          prefix_combine<B>(par.m, par.P, Tl, mo, Po, dcf, dcl);
+          prefix_combine<B>(par.m, par.P, Tc, mo, Po, dcf, dcl);
           lds_store_prefix<B, NS>(pool, noff + 2 * i, par.m, par.P);
           lds_store_prefix<B, NS>(pool, noff + 2 * i + 1, mo, Po);
         } else {
-          Elem<B> Tr;
-          elem_load<B>(tree_elems, tree_ld, gbase + noff + 2 * i + 1, Tr);
           double Jo[B][B], eo[B];
-          suffix_combine<B>(Tr, par.J, par.eta, Jo, eo);
+          suffix_combine<B>(Tc, par.J, par.eta, Jo, eo);
           lds_store_suffix<B, NS>(pool, noff + 2 * i + 1, par.J, par.eta);
           lds_store_suffix<B, NS>(pool, noff + 2 * i, Jo, eo);
         }
       }
       lds_barrier();
+      if (ncnt < L) Tc = Tn;
       off = noff;
     }
   }

@@ -10,10 +10,17 @@ using ModelP = SumM32Periodic<3, false>;               // Matern-3/2 + periodic
 using ModelQ = SumM32Periodic<3, true>;                // Matern-3/2 + quasi-periodic
 using ModelS = SumM32Periodic<3, true, kSqExpOrder>;   // ... + squared exponential
 static_assert(ModelP::B == ModelQ::B, "one state dimension for the two b = 10 models");
-// Work-group caps: what fits on the 256 CUs at once for each kernel's LDS (up 15 KB: 10 per
-// CU, down 13 KB: 11, node 21 KB: 7), so that every team stays resident and loops over its
-// items instead of a launch ending with a second, partly empty round.
-constexpr int kGridUp = 2560, kGridDown = 2816, kGridLeaf = 4096, kGridNode = 1792;
+// Work-group caps: what fits on the 256 CUs at once for each kernel's LDS and registers, so
+// that every team stays resident and loops over its items instead of a launch ending with a
+// second, partly empty round.  b = 10: up 15 KB of LDS (10 per CU), down 13 KB (11), node 21
+// KB (7), leaf 16 per CU.  b = 16: up 37 KB and 256 VGPRs (4 per CU), down 33 KB (4), node
+// 50 KB (3), leaf 15 KB (10).
+struct Caps {
+  int up, down, leaf, node;
+};
+constexpr Caps kCaps10 = {2560, 2816, 4096, 1792};
+constexpr Caps kCaps16 = {1024, 1024, 2560, 768};
+inline const Caps& caps(int model) { return model == kModelQuasiSqExp ? kCaps16 : kCaps10; }
 
 inline void mark(const WideCtx& c, int kid, int end) {
   if (c.mark) c.mark(c.mark_arg, kid, end);
@@ -60,7 +67,8 @@ void plan_levels(int64_t n, WideCtx& c) {
     if (m == 1 || k == kMaxLevels) break;
   }
   c.n_levels = k;
-  c.node_grid = (int)(n < kGridNode ? n : kGridNode);
+  const int cap = caps(c.model).node;
+  c.node_grid = (int)(n < cap ? n : cap);
 }
 
 template <class Model>
@@ -68,10 +76,11 @@ hipError_t factor_m(const WideCtx& c) {
   constexpr int B = Model::B;
   mark(c, kKidFwd, 0);
   hipLaunchKernelGGL(k_wide_setup<Model>, dim3(1), dim3(kW), 0, c.stream, c.hyper, c.cst);
-  hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points, kGridLeaf)), dim3(kW), 0, c.stream, c.t, c.y, c.n_points,
+  const Caps& cp = caps(c.model);
+  hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points, cp.leaf)), dim3(kW), 0, c.stream, c.t, c.y, c.n_points,
                      c.cst, c.elems);
   for (int k = 1; k < c.n_levels; ++k)
-    hipLaunchKernelGGL(k_wide_up<B>, dim3(grid_for(c.n[k], kGridUp)), dim3(kW), 0, c.stream, c.elems, c.off[k - 1],
+    hipLaunchKernelGGL(k_wide_up<B>, dim3(grid_for(c.n[k], cp.up)), dim3(kW), 0, c.stream, c.elems, c.off[k - 1],
                        c.n[k - 1], c.off[k], c.n[k]);
   mark(c, kKidFwd, 1);
   mark(c, kKidTop, 0);
@@ -87,8 +96,9 @@ hipError_t factor(const WideCtx& c) {
 
 template <int B>
 static void down_b(const WideCtx& c) {
+  const int cap = caps(c.model).down;
   for (int k = c.n_levels - 1; k >= 1; --k)
-    hipLaunchKernelGGL(k_wide_down<B>, dim3(grid_for(c.n[k - 1], kGridDown)), dim3(kW), 0, c.stream, c.elems, c.msgs,
+    hipLaunchKernelGGL(k_wide_down<B>, dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream, c.elems, c.msgs,
                        c.off[k], c.off[k - 1], c.n[k - 1]);
 }
 
