@@ -414,10 +414,12 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
 // term); every harmonic block is e^{-dt / l_D} times the rotation and has
 // Q = q_j^2 (1 - e^{-2 dt / l_D}) I.
 // NSE > 0: the squared exponential by its spectral approximation (state f, f', ..., f^(NSE-1),
-// lam_S = 1 / l_S): A_rc = lam_S^(r-c) [expm(C1 lam_S dt)]_rc, expm(C1 x) = 2 Re sum_k Z_k e^{r_k x}
-// over the stable roots with Im r_k > 0, and P0 = var_S lam_S^(r+c) P1 (tables generated from the
-// unit-lengthscale companion matrix C1).  Its block of P0 is dense, and every Q is formed as
-// P0 - A P0 A^T.
+// lam_S = 1 / l_S), kept in the scaled state f^(k) / lam_S^k: there the transition is
+// expm(C1 lam_S dt) = 2 Re sum_k Z_k e^{r_k lam_S dt} over the stable roots with Im r_k > 0 and
+// P0 = var_S P1 (tables generated from the unit-lengthscale companion matrix C1), with no powers
+// of lam_S (in the original basis P0 spans lam_S^(2 NSE - 2), which FP64 cannot carry for short
+// lengthscales).  The observation is unchanged (the scale of f is 1); state outputs are scaled
+// back by lam_S^k.  Its block of P0 is dense, and every Q is formed as P0 - A P0 A^T.
 template <int NJ, bool QUASI = false, int NSE = 0>
 struct SumM32Periodic {
   static constexpr int kNJ = NJ;
@@ -434,10 +436,10 @@ struct SumM32Periodic {
   // transition entries whose derivative is nonzero: the 2 x 2 blocks, then the SE block
   static constexpr int kNS = 2 * kS0 + NSE * NSE;
   // constants shared by all kernels of one call, computed by k_wide_setup into global memory:
-  // scalars, lam_S^(r-c), q_j^2, dq_j^2/dx, P0' = T P0 T^T
+  // scalars, lam_S^k, q_j^2, dq_j^2/dx, P0' = T P0 T^T
   static constexpr int kLamM = 0, kVarM = 1, kEllP = 2, kVarP = 3, kPer = 4, kS2 = 5, kW0 = 6, kX = 7, kLamD = 8;
   static constexpr int kLamS = 9, kVarS = 10, kLPow = 11;
-  static constexpr int kQ2 = kLPow + (NSE ? 2 * NSE - 1 : 0), kDQ2 = kQ2 + NJ + 1, kP0 = kDQ2 + NJ + 1;
+  static constexpr int kQ2 = kLPow + NSE, kDQ2 = kQ2 + NJ + 1, kP0 = kDQ2 + NJ + 1;
   static constexpr int kConst = kP0 + B * B;
   static_assert(NSE == 0 || NSE == kSqExpOrder, "squared-exponential order of the generated tables");
 
@@ -457,7 +459,8 @@ struct SumM32Periodic {
       const double lam = 1.0 / hyper[p];
       c[kLamS] = lam;
       c[kVarS] = hyper[p + 1];
-      for (int d = -(NSE - 1); d <= NSE - 1; ++d) c[kLPow + d + NSE - 1] = pow(lam, (double)d);
+      double pw = 1.0;
+      for (int k = 0; k < NSE; ++k, pw *= lam) c[kLPow + k] = pw;
     }
   }
 
@@ -528,7 +531,7 @@ struct SumM32Periodic {
         if (ri == rj) q = c[kQ2 + h] * (1.0 - ed * ed);
       }
     } else if (NSE > 0 && i >= kS0 && j >= kS0) {
-      // A_rc = lam^(r-c) E_rc(lam dt),  dA_rc/dlam = (r-c)/lam A_rc + dt lam^(r-c) (C1 E)_rc
+      // scaled state: A = E(lam dt) = expm(C1 lam dt),  dA/dlam = dt C1 E(lam dt)
       const int r = i - kS0, cc = j - kS0;
       const double lam = c[kLamS], x = lam * dt;
       double s = 0.0, ds = 0.0;
@@ -543,9 +546,8 @@ struct SumM32Periodic {
         s += pr;
         ds += re * pr - im * pi;                                  // Re(r Z e^{r x})
       }
-      const double lp = c[kLPow + r - cc + NSE - 1];
-      a = 2.0 * lp * s;
-      da[kDS] = (double)(r - cc) / lam * a + dt * lp * 2.0 * ds;
+      a = 2.0 * s;
+      da[kDS] = 2.0 * dt * ds;
     }
   }
   // entry (i, j) of the original-basis P0
@@ -556,9 +558,10 @@ struct SumM32Periodic {
       if (i == 1) return c[kVarM] * c[kLamM] * c[kLamM];
       return c[kQ2 + ((i - 2) >> 1)];
     }
-    const int r = i - kS0, cc = j - kS0;
-    return c[kVarS] * pow(c[kLamS], (double)(r + cc)) * kSqExpP1[r * NSE + cc];
+    return c[kVarS] * kSqExpP1[(i - kS0) * NSE + (j - kS0)];
   }
+  // factor from the working state k back to the model's state (lam_S^k on the scaled block)
+  SPG_DEV static double out_scale(const double* c, int k) { return (NSE > 0 && k >= kS0) ? c[kLPow + k - kS0] : 1.0; }
   // gradient of the raw hyperparameters from the summed partials: tot[B*B + f] are the scalar
   // sums, Pb the original-basis P0_bar
   SPG_DEV static void final_grad(const double* c, const double* tot, const double* Pb, double* grad) {
@@ -583,16 +586,12 @@ struct SumM32Periodic {
     int p = 5;
     if (QUASI) grad[p++] = tot[BB + kDec] * (-c[kLamD] * c[kLamD]);   // d lam_D / d l_D = -lam_D^2
     if (NSE) {
-      // P0_ij scales as lam_S^(i+j) and linearly in var_S
+      // in the scaled state P0 = var_S P1 does not depend on lam_S
       const double ls = c[kLamS];
-      double g_ls = tot[BB + kDS], g_vs = 0.0;
+      double g_vs = 0.0;
       for (int i = kS0; i < B; ++i)
-        for (int j = kS0; j < B; ++j) {
-          const double p0 = p0_entry(c, i, j), pb = Pb[i * B + j];
-          g_ls = fma(pb, (double)(i + j - 2 * kS0) / ls * p0, g_ls);
-          g_vs = fma(pb, p0 / c[kVarS], g_vs);
-        }
-      grad[p++] = g_ls * (-ls * ls);                                    // d lam_S / d l_S
+        for (int j = kS0; j < B; ++j) g_vs = fma(Pb[i * B + j], kSqExpP1[(i - kS0) * NSE + (j - kS0)], g_vs);
+      grad[p++] = tot[BB + kDS] * (-ls * ls);                           // d lam_S / d l_S
       grad[p++] = g_vs;
     }
     grad[p] = tot[BB + kNA];
@@ -948,7 +947,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
     if (out.z_mean && tid < B) {
       double z = mu[tid];
       if (tid == 0) for (int k = 1; k < B; ++k) z = fma(M::Ti_at(0, k), mu[k], z);
-      out.z_mean[tid * out.ld + n] = z;
+      out.z_mean[tid * out.ld + n] = z * M::out_scale(c, tid);
     }
     if (out.S_diag || (kSub && out.S_sub && edge)) {
       // back to the original basis: S_o = T^-1 S' T^-T, S_sub_o = T^-1 S_sub' T^-T
@@ -966,7 +965,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
           double sacc = 0.0;
           for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], M::Ti_at(j, k), sacc);
           const int pk = i * B - i * (i - 1) / 2 + (j - i);     // packed upper, row-major
-          out.S_diag[(int64_t)pk * out.ld + n] = sacc;
+          out.S_diag[(int64_t)pk * out.ld + n] = sacc * (M::out_scale(c, i) * M::out_scale(c, j));
         }
         tsync();
       }
@@ -987,7 +986,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
           const int i = e / B, j = e - i * B;
           double sacc = 0.0;
           for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], M::Ti_at(j, k), sacc);
-          out.S_sub[(int64_t)e * out.ld + n] = sacc;
+          out.S_sub[(int64_t)e * out.ld + n] = sacc * (M::out_scale(c, i) * M::out_scale(c, j));
         }
         tsync();
       }

@@ -87,6 +87,49 @@ def test_sqexp_sum_co2_shaped(lib):
     compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp))
 
 
+def test_sqexp_sum_duplicate_times(lib):
+    """Repeated times: the device's squared-exponential transition at dt = 0 is the identity
+    only up to rounding of its projector sum (the oracle's is exact), and Q = P0 - A P0 A^T is
+    then rounding-sized; the outputs must still meet the bars."""
+    t, y, hyp = _data(2000, HYPER, seed=24, span=100.0)
+    t = t.copy()
+    t[500:506] = t[499]
+    t[1500:1502] = t[1499]
+    compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp))
+
+
+def _reference_spread(t, y, hyp):
+    """Largest disagreement, in units of the 1e-9 bars, between two independent FP64 oracles
+    (C block-tridiagonal elimination and the Python Kalman filter + RTS smoother) on the
+    state means, variances and covariance blocks."""
+    c = native.btd_factored(TERMS, hyp, t, y)
+    k = kalman.kf_rts(model_for(TERMS, hyp), t, y)
+    d = np.sqrt(np.maximum(np.einsum("nii->ni", c["S_diag"]), 0.0))
+    ez = np.max(np.abs(k["z_mean"] - c["z_mean"]) / (np.abs(c["z_mean"]) + d))
+    ev = np.max(np.abs(k["f_var"] - c["f_var"]) / c["f_var"])
+    es = np.max(np.abs(k["S_diag"] - c["S_diag"]) / (d[:, :, None] * d[:, None, :]))
+    return max(ez, ev, es) / 1e-9
+
+
+@pytest.mark.parametrize("ell_s", [0.1, 0.2, 5000.0])
+def test_sqexp_sum_extreme_trend_lengthscale(lib, ell_s):
+    """Squared-exponential lengthscales far from the other terms' scales.  Short (lam_S = 5,
+    10): in the model's state (f, f', ..., f^(5)) P0 spans lam_S^10, and two independent FP64
+    oracles already disagree by about lam_S^10 eps (2.5e-9 at lam_S = 5, 2.7e-7 at 10, 0.14 at
+    50); the device keeps that block in the scaled state f^(k) / lam_S^k and is compared with the
+    mean, variance and block bars widened to 4x the oracles' measured spread (logML and gradient
+    bars as elsewhere).  Long (far beyond the span): a nearly constant trend, at the plain bars
+    (the Python oracle's Lyapunov solve breaks down there, lam_S r_k being nearly zero, so only
+    the C oracle is used)."""
+    hyper = list(HYPER)
+    hyper[6] = ell_s
+    t, y, hyp = _data(1500, hyper, seed=25, span=75.0)
+    widen = max(1.0, 4.0 * _reference_spread(t, y, hyp)) if ell_s < 1.0 else 1.0
+    print(f"\nl_S = {ell_s}: bars widened {widen:.3g}x", flush=True)
+    assert widen < 1e4
+    compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp), widen=widen)
+
+
 def test_sqexp_sum_large(lib):
     """2^16 points: many tree levels; logML, the nine-component gradient, means and variances."""
     t, y, hyp = _data(1 << 16, HYPER, seed=19, span=3000.0)
