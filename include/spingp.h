@@ -182,9 +182,10 @@ int spingp_tile_shape(int32_t index, int32_t* R, int32_t* L);
 int spingp_get_tile(spingp_handle h, int32_t* index);
 int spingp_set_tile(spingp_handle h, int32_t index);
 /*
- * Autotuner: time spingp_logml_grad `reps` times on the assembled problem for every tile shape
- * (HIP events on the handle's stream; synchronises), keep the fastest for this handle and
- * record it in the process-wide cache used by SPINGP_FLAG_AUTOTUNE.  Needs assemble.
+ * Autotuner: time spingp_logml_grad `reps` times on the assembled problem for every tile shape,
+ * in two passes over the shapes (HIP events on the handle's stream; synchronises), keep the
+ * shape with the best of its two timings for this handle and record it in the process-wide
+ * cache used by SPINGP_FLAG_AUTOTUNE.  Needs assemble.
  */
 int spingp_tune(spingp_handle h, int32_t reps);
 
