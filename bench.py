@@ -167,29 +167,26 @@ def large_report(spg, steps, warmup):
             "input_bytes": 16 * n, "every_level_stored_bytes": 2 * 33 * 8 * n}
 
 
-def sum_report(spg, steps, warmup):
-    """Matern-3/2 + periodic with 3 harmonics (b = 10), N = 2^18, t uniform on [0, 1e4]:
-    logML + the six-component gradient through the wide-state path (eager launches on a side
-    stream; graph replay measures the same here)."""
+def _wide_report(spg, name, terms, t, y, hyper, steps, warmup):
+    """logML + gradient of one series on the wide-state path (eager launches on a side stream),
+    with the per-phase times from the library's events on one extra call."""
     import torch
     from paper_1610_08035_amd.spingp import spingp_profile, spingp_profile_read
-    from workloads import make_config
-    w = make_config(3)
-    n = w.n_points
+    n = t.shape[0]
     dev = torch.device("cuda:0")
-    td, yd = torch.as_tensor(w.t, device=dev), torch.as_tensor(w.y, device=dev)
-    hd = torch.as_tensor(w.hyper.reshape(-1), device=dev)
+    td, yd = torch.as_tensor(t, device=dev), torch.as_tensor(y, device=dev)
+    hd = torch.as_tensor(np.asarray(hyper, dtype=np.float64).reshape(-1), device=dev)
     torch.cuda.synchronize()
     side = torch.cuda.Stream()
-    h = spg.Handle(w.terms, n, stream=side)
+    h = spg.Handle(terms, n, stream=side)
     h.assemble(td, yd, hd)
     ll = torch.empty(1, dtype=torch.float64, device=dev)
-    g = torch.empty(1, 6, dtype=torch.float64, device=dev)
+    g = torch.empty(1, h.n_hyper, dtype=torch.float64, device=dev)
     for _ in range(warmup):
         spg.spingp_logml_grad(h._h, ll, g)
     torch.cuda.synchronize()
     if h.status()[0] != 0:
-        raise RuntimeError("sum-kernel workload failed validation")
+        raise RuntimeError(f"{name} failed validation")
     # per-phase times from the library's events, then the timed steps without them
     spingp_profile(h._h, 1)
     spg.spingp_logml_grad(h._h, ll, g)
@@ -201,12 +198,38 @@ def sum_report(spg, steps, warmup):
         spg.spingp_logml_grad(h._h, ll, g)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / steps
+    b, nh = h.b, h.n_hyper
     h.close()
     phases = {"leaves_up_sweep": prof["fwd_fold_tree"][0], "root": prof["top_tree"][0],
               "down_sweep_node_step": prof["bwd_elim_adjoint"][0], "gradient_sum": prof["series_reduce"][0]}
-    return {"workload": w.name + "_logml_grad", "n_points": n, "state_dim": 10, "n_hyper": 6,
+    return {"workload": name, "n_points": n, "state_dim": b, "n_hyper": nh,
             "points_per_s": n / el, "ms_per_step": 1e3 * el, "steps": steps, "launch": "eager, side stream",
             "phase_ms": {k: round(v, 4) for k, v in phases.items()}}
+
+
+def sum_report(spg, steps, warmup):
+    """Matern-3/2 + periodic with 3 harmonics (b = 10), N = 2^18, t uniform on [0, 1e4]:
+    logML + the six-component gradient through the wide-state path (eager launches on a side
+    stream; graph replay measures the same here)."""
+    from workloads import make_config
+    w = make_config(3)
+    return _wide_report(spg, w.name + "_logml_grad", w.terms, w.t, w.y, w.hyper[0], steps, warmup)
+
+
+def co2_report(spg, steps, warmup):
+    """The three-term kernel of the CO2 fit: Matern-3/2 + quasi-periodic (3 harmonics) +
+    squared exponential of order 6 (b = 16), N = 2^18 points uniform over 2^18 / 52 years,
+    hyperparameters (0.8, 0.3, 1, 4, 1, 60, 8, 20, 0.05): logML + the nine-component gradient."""
+    from workloads import KIND_MATERN32, KIND_QUASIPERIODIC, KIND_SQEXP
+    from workloads.generate import make_series
+    terms = [(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 6)]
+    n = 1 << 18
+    rng = np.random.default_rng(16)
+    t = np.sort(rng.uniform(0.0, n / 52.0, n))
+    hy = np.array([0.8, 0.3, 1.0, 4.0, 1.0, 60.0, 8.0, 20.0, 0.05])
+    y = make_series(t, terms, hy, rng)
+    return _wide_report(spg, "matern32+quasiperiodic3+sqexp6_n262144_weekly_logml_grad", terms, t, y, hy,
+                        steps, warmup)
 
 
 def predict_report(spg, steps, warmup):
@@ -366,12 +389,13 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 4096-series batched report")
     ap.add_argument("--no-large", action="store_true", help="skip the N = 2^24 report")
     ap.add_argument("--no-sum", action="store_true", help="skip the b = 10 sum-kernel report")
+    ap.add_argument("--no-co2", action="store_true", help="skip the b = 16 three-term (CO2 kernel) report")
     ap.add_argument("--no-predict", action="store_true", help="skip the prediction report")
     ap.add_argument("--no-fit", action="store_true", help="skip the hyperparameter-fit report")
     ap.add_argument("--no-bsweep", action="store_true", help="skip the block-size sweep")
     ap.add_argument("--tile", type=int, default=None,
                     help="headline tile shape index instead of the autotuner's choice (counter runs)")
-    ap.add_argument("--only", choices=["batched", "large", "sum", "predict", "fit", "bsweep"], default=None,
+    ap.add_argument("--only", choices=["batched", "large", "sum", "co2", "predict", "fit", "bsweep"], default=None,
                     help="run one secondary workload alone and print its JSON (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM counters)")
@@ -398,7 +422,7 @@ def main():
         if args.only == "fit":
             print(json.dumps({"fit": fit_report(spg)}), flush=True)
             return
-        fn = {"batched": batched_report, "large": large_report, "sum": sum_report,
+        fn = {"batched": batched_report, "large": large_report, "sum": sum_report, "co2": co2_report,
               "predict": predict_report, "bsweep": bsweep_report}[args.only]
         print(json.dumps({args.only: fn(spg, args.steps, args.warmup)}), flush=True)
         return
@@ -508,6 +532,8 @@ def main():
         out["large"] = large_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_sum:
         out["sum_kernel"] = sum_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
+    if not args.no_co2:
+        out["co2_kernel"] = co2_report(spg, max(2, args.steps // 10), 1)
     if not args.no_predict:
         out["predict"] = predict_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_fit:
