@@ -1,10 +1,13 @@
-// Wide-state path (b = 10: Matern-3/2 plus a periodic term with 3 harmonics, Sec. 2.1 and the
-// periodic state-space form of the appendix) for one series.
+// Wide-state path for one series: Matern-3/2 plus a periodic or quasi-periodic term with 3
+// harmonics (b = 10), optionally plus a squared-exponential term of order 6 (b = 16), the sums
+// of the paper's CO2 kernel (Sec. 4.3) in state-space form (Sec. 2.1; the periodic term by its
+// truncated Bessel-weighted cosine series, the squared exponential by its spectral
+// approximation).
 //
 // The per-lane kernels keep a whole chain element in registers; at b = 10 an element has 322
 // doubles, so here one wavefront (a "team" of 64 lanes, one work-group) works on one element
-// operation at a time with its 10 x 10 blocks staged in LDS, every lane owning one or two
-// matrix entries.  The cyclic reduction runs level by level over all N nodes (one node per
+// operation at a time with its b x b blocks staged in LDS, every lane owning a few matrix
+// entries.  The cyclic reduction runs level by level over all N nodes (one node per
 // leaf), one launch per level:
 //   up-sweep   level k element i = E(k-1, 2i) (x) E(k-1, 2i+1)      (odd-even reduction)
 //   down-sweep messages of level k-1 from those of level k: the predicted state (m, P)

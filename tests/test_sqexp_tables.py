@@ -1,8 +1,9 @@
 """The squared-exponential constants compiled into the library (csrc/spingp_sqexp_tables.hpp):
 they must reproduce the matrix exponential and the stationary covariance of the unit-lengthscale
-companion matrix, built here from the paper's recipe (Sec. 2.1: the Taylor-truncated inverse
-spectral density, its stable roots) with numpy and scipy, and match what the committed
-generator writes."""
+companion matrix, built here with numpy and scipy from the spectral approximation (the inverse
+spectral density truncated after order + 1 terms of its exponential series, its stable roots;
+the paper allows a state-space form that approximates the kernel, Sec. 2.2, and uses the EQ
+kernel in its CO2 model, Sec. 4.3), and match what the committed generator writes."""
 import math
 import os
 import re
