@@ -35,9 +35,9 @@ PEAK_HBM_GBS = 8000.0
 # valid only for the kernel sources they were taken on (sha256 over csrc/, see
 # kernel_source_sha), else reported as null.
 TRAFFIC = {"kernel": "bwd_elim_adjoint",
-           "bytes": {(8, 128): (45004.8 * 2.0 + 8288.2) * 1024.0,
-                     (8, 256): (43861.9 * 2.0 + 8240.0) * 1024.0},
-           "source_sha": "77151ec50de4e7798e3f850f920f8f82332fd39bf4e6e86290f8eecb42cbdef2"}
+           "bytes": {(8, 128): (44892.0 * 2.0 + 8288.2) * 1024.0,
+                     (8, 256): (42814.0 * 2.0 + 8240.0) * 1024.0},
+           "source_sha": "44ef3c297408e102ac7e843d3448085f1b4b9126c30424004ffa9d1682504cda"}
 
 
 def kernel_source_sha():
