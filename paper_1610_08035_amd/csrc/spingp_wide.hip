@@ -79,9 +79,15 @@ hipError_t factor_m(const WideCtx& c) {
   const Caps& cp = caps(c.model);
   hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points, cp.leaf)), dim3(kW), 0, c.stream, c.t, c.y, c.n_points,
                      c.cst, c.elems);
-  for (int k = 1; k < c.n_levels; ++k)
-    hipLaunchKernelGGL(k_wide_up<B>, dim3(grid_for(c.n[k], cp.up)), dim3(kW), 0, c.stream, c.elems, c.off[k - 1],
-                       c.n[k - 1], c.off[k], c.n[k]);
+  // level 1 joins leaves (rank-one node information: closed-form inverse)
+  for (int k = 1; k < c.n_levels; ++k) {
+    if (k == 1)
+      hipLaunchKernelGGL((k_wide_up<B, true>), dim3(grid_for(c.n[k], cp.up)), dim3(kW), 0, c.stream, c.elems,
+                         c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
+    else
+      hipLaunchKernelGGL((k_wide_up<B, false>), dim3(grid_for(c.n[k], cp.up)), dim3(kW), 0, c.stream, c.elems,
+                         c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
+  }
   mark(c, kKidFwd, 1);
   mark(c, kKidTop, 0);
   hipLaunchKernelGGL(k_wide_root<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, c.elems, c.off[c.n_levels - 1],
@@ -97,9 +103,15 @@ hipError_t factor(const WideCtx& c) {
 template <int B>
 static void down_b(const WideCtx& c) {
   const int cap = caps(c.model).down;
-  for (int k = c.n_levels - 1; k >= 1; --k)
-    hipLaunchKernelGGL(k_wide_down<B>, dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream, c.elems, c.msgs,
-                       c.off[k], c.off[k - 1], c.n[k - 1]);
+  // the last level's children are leaves (rank-one node information: closed-form inverse)
+  for (int k = c.n_levels - 1; k >= 1; --k) {
+    if (k == 1)
+      hipLaunchKernelGGL((k_wide_down<B, true>), dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream, c.elems,
+                         c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
+    else
+      hipLaunchKernelGGL((k_wide_down<B, false>), dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream, c.elems,
+                         c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
+  }
 }
 
 hipError_t down(const WideCtx& c) {

@@ -207,6 +207,21 @@ SPG_DEV double t_inv_logdet(double* M, double* G, double* /*unused*/) {
   return log(fabs(mant)) + expo * 0.69314718055994530942;
 }
 
+// G = (I + X J)^-1 for a leaf's node information J = s e0 e0^T (rank one, entry (0, 0) only):
+// X J = s X[:, 0] e0^T, so G = I - s X[:, 0] e0^T / (1 + s X[0][0]) (Sherman-Morrison) and
+// log det = log(1 + s X[0][0]).  Every lane returns the log-determinant.
+template <int B>
+SPG_DEV double t_inv_rank1(const double* X, double s, double* G) {
+  const double d = fma(s, X[0], 1.0);
+  const double f = s / d;
+  for (int e = threadIdx.x; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    G[e] = (i == j ? 1.0 : 0.0) - (j == 0 ? f * X[i * B] : 0.0);
+  }
+  tsync();
+  return log(d);
+}
+
 // ---------------------------------------------------------------------------- element ops
 // Entry (i, j) of X Y (TX: X^T, TY: Y^T) for row-major B x B blocks in LDS.
 template <int B, bool TX, bool TY>
@@ -225,7 +240,8 @@ SPG_DEV double mm_sym_entry(const double* X, const double* Y, int i, int j) {
 // the same entry of all the independent products of a phase (and lanes < B the vectors).
 
 // R = E1 (x) E2 (join at the shared node; see spingp_device.hpp).
-template <int B>
+// LEAF2: E2 is a leaf, whose J is rank one (the inverse in closed form).
+template <int B, bool LEAF2 = false>
 SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tmp) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
@@ -235,12 +251,17 @@ SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tm
   const double *A1 = E1 + Y::kA, *b1 = E1 + Y::kb, *Q1 = E1 + Y::kQ, *J1 = E1 + Y::kJ, *eta1 = E1 + Y::keta;
   const double *A2 = E2 + Y::kA, *b2 = E2 + Y::kb, *Q2 = E2 + Y::kQ, *J2 = E2 + Y::kJ, *eta2 = E2 + Y::keta;
   const int tid = threadIdx.x;
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    M[e] = mm_entry<B, false, false>(Q1, J2, i, j) + (i == j ? 1.0 : 0.0);
+  double ld;
+  if (LEAF2) {
+    ld = t_inv_rank1<B>(Q1, J2[0], G);
+  } else {
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      M[e] = mm_entry<B, false, false>(Q1, J2, i, j) + (i == j ? 1.0 : 0.0);
+    }
+    tsync();
+    ld = t_inv_logdet<B>(M, G, nullptr);
   }
-  tsync();
-  const double ld = t_inv_logdet<B>(M, G, nullptr);
   // P+ = G Q1, W = J2 G (both symmetric), G A1; G b1, G^T eta2
   for (int e = tid; e < BB; e += kW) {
     const int i = e / B, j = e - i * B;
@@ -302,7 +323,8 @@ SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tm
 
 // Prefix: the predicted state N(m, P) at E's left node pushed through E -> (mo, Po); returns
 // the log-normaliser increments in dcf, dcl (uniform over the team).
-template <int B>
+// LEAF: E is a leaf, whose J is rank one (the inverse in closed form).
+template <int B, bool LEAF = false>
 SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double* mo, double* Po, double* tmp,
                       double& dcf, double& dcl) {
   using Y = Lay<B>;
@@ -312,12 +334,17 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
   double *Gm = v, *Ppe = v + B, *g = v + 2 * B, *Wm = v + 3 * B;
   const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    M[e] = mm_entry<B, false, false>(P, J, i, j) + (i == j ? 1.0 : 0.0);
+  double ld;
+  if (LEAF) {
+    ld = t_inv_rank1<B>(P, J[0], G);
+  } else {
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      M[e] = mm_entry<B, false, false>(P, J, i, j) + (i == j ? 1.0 : 0.0);
+    }
+    tsync();
+    ld = t_inv_logdet<B>(M, G, nullptr);
   }
-  tsync();
-  const double ld = t_inv_logdet<B>(M, G, nullptr);
   for (int e = tid; e < BB; e += kW) {
     const int i = e / B, j = e - i * B;
     Pp[e] = mm_sym_entry<B, false, false>(G, P, i, j);
@@ -752,7 +779,8 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
 }
 
 // Up-sweep: level k (n_cur elements at off_cur) from level k - 1 (n_prev at off_prev).
-template <int B>
+// LEAF: level k - 1 is the leaf level (every right operand is a leaf).
+template <int B, bool LEAF = false>
 __global__ __launch_bounds__(kW) void k_wide_up(double* __restrict__ elems, int64_t off_prev, int64_t n_prev,
                                                 int64_t off_cur, int64_t n_cur) {
   using Y = Lay<B>;
@@ -771,7 +799,7 @@ __global__ __launch_bounds__(kW) void k_wide_up(double* __restrict__ elems, int6
       E2[e] = b[e];
     }
     tsync();
-    t_combine<B>(E1, E2, R, tmp);
+    t_combine<B, LEAF>(E1, E2, R, tmp);
     for (int e = tid; e < Y::kEs; e += kW) out[e] = e < Y::kE ? R[e] : 0.0;
     tsync();
   }
@@ -807,7 +835,8 @@ __global__ __launch_bounds__(kW) void k_wide_root(const double* __restrict__ cst
 }
 
 // Down-sweep: messages of level k - 1 (n_child at off_child) from level k (at off_par).
-template <int B>
+// LEAF: the children are leaves (the left sibling a right child is pushed through is a leaf).
+template <int B, bool LEAF = false>
 __global__ __launch_bounds__(kW) void k_wide_down(const double* __restrict__ elems, double* __restrict__ msgs,
                                                   int64_t off_par, int64_t off_child, int64_t n_child) {
   using Y = Lay<B>;
@@ -834,7 +863,7 @@ __global__ __launch_bounds__(kW) void k_wide_down(const double* __restrict__ ele
       // prefix pushed through the left sibling; suffix unchanged
       for (int e = tid; e < B + BB; e += kW) out[Y::kMJ + e] = par[Y::kMJ + e];
       double dcf, dcl;
-      t_prefix<B>(par + Y::km, par + Y::kP, E, out + Y::km, out + Y::kP, tmp, dcf, dcl);
+      t_prefix<B, LEAF>(par + Y::km, par + Y::kP, E, out + Y::km, out + Y::kP, tmp, dcf, dcl);
     }
     for (int e = tid; e < Y::kMs; e += kW) om[e] = e < Y::kM ? out[e] : 0.0;
     tsync();
