@@ -966,13 +966,24 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
     tsync();
     // smoothed covariance S = P+ - (A P+)^T W (A P+)   (X1 = A P+)
     double S00 = 0.0;
-    if (kCov || kGrad) {
+    if (kCov) {
       t_mm<B>(W, X1, X2);                // W A P+
       t_mtm<B>(X1, X2, X3);              // (A P+)^T W A P+
       for (int e = tid; e < BB; e += kW) X3[e] = Pp[e] - X3[e];
       tsync();
       t_sym<B>(X3);
       S00 = X3[0];
+    } else if (kGrad) {
+      // only S_00 is needed: P+_00 - x^T W x with x = (A P+) e_0, in the order of the products
+      if (tid < B) {
+        double v = 0.0;
+        for (int k = 0; k < B; ++k) v = fma(W[tid * B + k], X1[k * B], v);
+        fcol[tid] = v;
+      }
+      tsync();
+      double q = 0.0;
+      for (int k = 0; k < B; ++k) q = fma(X1[k * B], fcol[k], q);
+      S00 = Pp[0] - q;
     }
     if (out.f_mean && tid == 0) out.f_mean[n] = mu[0];
     if (out.f_var && tid == 0) out.f_var[n] = S00;
