@@ -1041,14 +1041,15 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
         acc_s2 += -0.5 / s2 + 0.5 * (r * r + S00) / (s2 * s2);
       }
       if (edge) {
-        // A_bar = lam m+^T + 2 Lam A (P+ - P0)   (Mx = A (P+ - P0))
+        // A_bar = lam m+^T + 2 (Lam A)(P+ - P0) into Mx, with X3 = Lam A kept for P0_bar below
+        // (the smoothed covariance X3 held is written out above and not needed any more)
+        t_mm<B>(Lam, A, X3);
         for (int e = tid; e < BB; e += kW) X2[e] = Pp[e] - P0[e];
         tsync();
-        t_mm<B>(A, X2, Mx);
-        t_mm<B>(Lam, Mx, X2);
+        t_mm<B>(X3, X2, Mx);
         for (int e = tid; e < BB; e += kW) {
           const int i = e / B, j = e - i * B;
-          X2[e] = fma(lam[i], mp[j], 2.0 * X2[e]);
+          Mx[e] = fma(lam[i], mp[j], 2.0 * Mx[e]);
         }
         tsync();
         // original basis: A_bar_o = T^T A_bar T^-T, needed only on the support of the
@@ -1057,15 +1058,14 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
         if (tid < M::kNS) {
           int i, j;
           M::support(tid, i, j);
-          const double ab = M::abar_orig(X2, i, j);
+          const double ab = M::abar_orig(Mx, i, j);
           double a, q, da[M::kNA];
           M::edge_entry(c, dt, i, j, a, q, da);
           SPG_UNROLL for (int f = 0; f < M::kNA; ++f) acc_a[f] = fma(ab, da[f], acc_a[f]);
         }
-        // P0_bar += Lam - A^T Lam A
-        t_mm<B>(Lam, A, X2);
-        t_mtm<B>(A, X2, Mx);
-        for (int e = tid, r = 0; e < BB; e += kW, ++r) acc_p0[r] += Lam[e] - Mx[e];
+        // P0_bar += Lam - A^T (Lam A)
+        t_mtm<B>(A, X3, X2);
+        for (int e = tid, r = 0; e < BB; e += kW, ++r) acc_p0[r] += Lam[e] - X2[e];
       }
       if (n == 0) {
         // the first state is drawn from N(0, P0'): P0_bar += Lam_0, the seed of the prior
