@@ -109,7 +109,7 @@ struct spingp_ctx {
   int64_t lane_ld = 0;
   // tile shape
   int tile = 0;
-  // wide-state path (b = 10)
+  // wide-state path (b = 10 or 16)
   bool wide = false;
   bool wide_down = false;          // down-sweep messages match the current factorisation
   spg::wide::WideCtx wplan;

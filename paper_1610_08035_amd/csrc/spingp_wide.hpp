@@ -329,9 +329,9 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
                       double& dcf, double& dcl) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
-  double *M = tmp, *G = M + BB, *Pp = G + BB, *W = Pp + BB, *T = W + BB;
+  double *M = tmp, *G = M + BB, *Pp = G + BB, *T = Pp + BB;
   double* v = tmp + 8 * BB;
-  double *Gm = v, *Ppe = v + B, *g = v + 2 * B, *Wm = v + 3 * B;
+  double *Gm = v, *Ppe = v + B, *g = v + 2 * B, *Wm = v + 3 * B, *Jm = v + 4 * B;
   const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
   double ld;
@@ -345,15 +345,19 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
     tsync();
     ld = t_inv_logdet<B>(M, G, nullptr);
   }
+  // P+ = sym(G P); W = sym(J G) enters only through W m = (J G m + G^T J m) / 2
   for (int e = tid; e < BB; e += kW) {
     const int i = e / B, j = e - i * B;
     Pp[e] = mm_sym_entry<B, false, false>(G, P, i, j);
-    W[e] = mm_sym_entry<B, false, false>(J, G, i, j);
   }
   if (tid < B) {
-    double s1 = 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) s1 = fma(G[tid * B + k], m[k], s1);
+    double s1 = 0.0, s5 = 0.0;
+    SPG_UNROLL for (int k = 0; k < B; ++k) {
+      s1 = fma(G[tid * B + k], m[k], s1);
+      s5 = fma(J[tid * B + k], m[k], s5);
+    }
     Gm[tid] = s1;
+    Jm[tid] = s5;
   }
   tsync();
   for (int e = tid; e < BB; e += kW) {
@@ -361,13 +365,14 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
     T[e] = mm_entry<B, false, false>(A, Pp, i, j);
   }
   if (tid < B) {
-    double s2 = 0.0, s3 = 0.0;
+    double s2 = 0.0, s3 = 0.0, s6 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) {
       s2 = fma(Pp[tid * B + k], eta[k], s2);
-      s3 = fma(W[tid * B + k], m[k], s3);
+      s3 = fma(J[tid * B + k], Gm[k], s3);
+      s6 = fma(G[k * B + tid], Jm[k], s6);
     }
     Ppe[tid] = s2;
-    Wm[tid] = s3;
+    Wm[tid] = 0.5 * (s3 + s6);
     g[tid] = Gm[tid] + s2;
   }
   tsync();
