@@ -717,19 +717,22 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
       Qo[e] = q;
     }
     tsync();
-    // A' = T A T^-1 and Q' = T Q T^T, with the constant T applied entry by entry
+    // A' = T A T^-1 and Q' = T Q T^T from the sparsity of T (identity but row 0 = h^T):
+    // (T X)[0][j] = sum over observed k of X[k][j], (X T^-1)[i][j] = X[i][j] - X[i][0] for an
+    // observed j >= 1, (X T^T)[i][0] = sum over observed k of X[i][k]; other entries unchanged
+    // (the sums in the order of the dense products, so the values are the same)
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
-      double s = 0.0;
-      for (int k = 0; k < B; ++k) s = fma(M::T_at(i, k), Ao[k * B + j], s);
+      double s = Ao[e];
+      if (i == 0)
+        for (int k = 1; k < B; ++k)
+          if (M::observed(k)) s += Ao[k * B + j];
       X[e] = s;
     }
     tsync();
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
-      double s = 0.0;
-      for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::Ti_at(k, j), s);
-      E[Y::kA + e] = s;
+      E[Y::kA + e] = (j >= 1 && M::observed(j)) ? -X[i * B] + X[e] : X[e];
     }
     tsync();
     if (M::kQFromP0) {
@@ -747,8 +750,10 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
     } else {
       for (int e = tid; e < BB; e += kW) {
         const int i = e / B, j = e - i * B;
-        double s = 0.0;
-        for (int k = 0; k < B; ++k) s = fma(M::T_at(i, k), Qo[k * B + j], s);
+        double s = Qo[e];
+        if (i == 0)
+          for (int k = 1; k < B; ++k)
+            if (M::observed(k)) s += Qo[k * B + j];
         X[e] = s;
       }
     }
@@ -758,12 +763,10 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
     const bool obs = yn == yn;
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
-      double s = 0.0;
-      if (M::kQFromP0) {
-        s = X[e];
-      } else {
-        for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::T_at(j, k), s);
-      }
+      double s = X[e];
+      if (!M::kQFromP0 && j == 0)
+        for (int k = 1; k < B; ++k)
+          if (M::observed(k)) s += X[i * B + k];
       E[Y::kQ + e] = s;
       E[Y::kJ + e] = (e == 0 && obs) ? 1.0 / s2 : 0.0;
     }
