@@ -105,7 +105,10 @@ static void down_b(const WideCtx& c) {
   const int cap = caps(c.model).down;
   // the last level's children are leaves (rank-one node information: closed-form inverse)
   for (int k = c.n_levels - 1; k >= 1; --k) {
-    if (k == 1)
+    if (k == 1 && c.model == kModelPeriodic)   // leaf edges: Q only in the Matern block
+      hipLaunchKernelGGL((k_wide_down<B, true, true>), dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream,
+                         c.elems, c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
+    else if (k == 1)
       hipLaunchKernelGGL((k_wide_down<B, true>), dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream, c.elems,
                          c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
     else

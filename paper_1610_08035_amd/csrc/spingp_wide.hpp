@@ -222,6 +222,30 @@ SPG_DEV double t_inv_rank1(const double* X, double s, double* G) {
   return log(d);
 }
 
+// G = (I + Q J)^-1 for a Q confined to the leading 2 x 2 block (a leaf edge of the Matern-3/2 +
+// periodic model: the rotation blocks have Q = 0): with C = Q[0:2, 0:2], Q J = E2 C E2^T J, and
+// Woodbury gives G = I - E2 K C E2^T J with the 2 x 2 K = (I + C J[0:2, 0:2])^-1.  Every lane
+// forms K C from the eight entries it needs.
+template <int B>
+SPG_DEV void t_inv_q2(const double* Q, const double* J, double* G) {
+  const double n00 = 1.0 + fma(Q[0], J[0], Q[1] * J[B]), n01 = fma(Q[0], J[1], Q[1] * J[B + 1]);
+  const double n10 = fma(Q[B], J[0], Q[B + 1] * J[B]), n11 = 1.0 + fma(Q[B], J[1], Q[B + 1] * J[B + 1]);
+  const double id = 1.0 / diff_of_products(n00, n11, n01, n10);
+  // K = id [[n11, -n01], [-n10, n00]];  KC = K C
+  const double kc00 = id * diff_of_products(n11, Q[0], n01, Q[B]);
+  const double kc01 = id * diff_of_products(n11, Q[1], n01, Q[B + 1]);
+  const double kc10 = id * diff_of_products(n00, Q[B], n10, Q[0]);
+  const double kc11 = id * diff_of_products(n00, Q[B + 1], n10, Q[1]);
+  for (int e = threadIdx.x; e < B * B; e += kW) {
+    const int i = e / B, j = e - i * B;
+    double g = (i == j) ? 1.0 : 0.0;
+    if (i == 0) g -= fma(kc00, J[j], kc01 * J[B + j]);
+    if (i == 1) g -= fma(kc10, J[j], kc11 * J[B + j]);
+    G[e] = g;
+  }
+  tsync();
+}
+
 // ---------------------------------------------------------------------------- element ops
 // Entry (i, j) of X Y (TX: X^T, TY: Y^T) for row-major B x B blocks in LDS.
 template <int B, bool TX, bool TY>
@@ -391,7 +415,8 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
 }
 
 // Suffix: information (Jb, etab) on E's right node pulled back to its left node -> (Jo, etao).
-template <int B>
+// Q2: E's Q is confined to the leading 2 x 2 block (the inverse in closed form).
+template <int B, bool Q2 = false>
 SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, double* Jo, double* etao, double* tmp) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
@@ -400,12 +425,16 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
   double *s1v = v, *r = v + B;
   const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    M[e] = mm_entry<B, false, false>(Q, Jb, i, j) + (i == j ? 1.0 : 0.0);
+  if (Q2) {
+    t_inv_q2<B>(Q, Jb, G);
+  } else {
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      M[e] = mm_entry<B, false, false>(Q, Jb, i, j) + (i == j ? 1.0 : 0.0);
+    }
+    tsync();
+    (void)t_inv_logdet<B>(M, G, nullptr);
   }
-  tsync();
-  (void)t_inv_logdet<B>(M, G, nullptr);
   for (int e = tid; e < BB; e += kW) {
     const int i = e / B, j = e - i * B;
     W[e] = mm_sym_entry<B, false, false>(Jb, G, i, j);
@@ -844,7 +873,8 @@ __global__ __launch_bounds__(kW) void k_wide_root(const double* __restrict__ cst
 
 // Down-sweep: messages of level k - 1 (n_child at off_child) from level k (at off_par).
 // LEAF: the children are leaves (the left sibling a right child is pushed through is a leaf).
-template <int B, bool LEAF = false>
+// Q2: and the right sibling a left child pulls back through has Q in the leading 2 x 2 block.
+template <int B, bool LEAF = false, bool Q2 = false>
 __global__ __launch_bounds__(kW) void k_wide_down(const double* __restrict__ elems, double* __restrict__ msgs,
                                                   int64_t off_par, int64_t off_child, int64_t n_child) {
   using Y = Lay<B>;
@@ -866,7 +896,7 @@ __global__ __launch_bounds__(kW) void k_wide_down(const double* __restrict__ ele
     if (left) {
       // prefix unchanged; suffix pulled back through the right sibling
       for (int e = tid; e < B + BB; e += kW) out[e] = par[e];
-      t_suffix<B>(E, par + Y::kMJ, par + Y::kMeta, out + Y::kMJ, out + Y::kMeta, tmp);
+      t_suffix<B, LEAF && Q2>(E, par + Y::kMJ, par + Y::kMeta, out + Y::kMJ, out + Y::kMeta, tmp);
     } else {
       // prefix pushed through the left sibling; suffix unchanged
       for (int e = tid; e < B + BB; e += kW) out[Y::kMJ + e] = par[Y::kMJ + e];
