@@ -421,7 +421,7 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
   using Y = Lay<B>;
   constexpr int BB = B * B;
   double *M = tmp, *G = M + BB, *W = G + BB, *WA = W + BB;
-  double* v = tmp + 8 * BB;
+  double* v = tmp + 4 * BB;   // four matrices and two vectors: 4 b^2 + 2 b doubles of scratch
   double *s1v = v, *r = v + B;
   const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
@@ -933,8 +933,11 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
   constexpr int kPart = M::kPart;
   __shared__ double c[M::kConst];
   __shared__ double E[Y::kEs], G_[Y::kMs];   // leaf element; messages (prefix at n, suffix on n + 1)
-  __shared__ double mp[B], Pp[BB], mn[B], Pn[BB], Mx[BB], Gm[BB], W[BB], lam[B], Lam[BB], X1[BB], X2[BB],
-      X3[BB], mu[B], fcol[B], red[kW], tmp[Y::kTmp];
+  __shared__ double mp[B], mn[B], Mx[BB], Gm[BB], W[BB], lam[B], Lam[BB], X2[BB], mu[B], fcol[B], red[kW];
+  // P+, P', X1 = A P+ and X3 share one block with the scratch of the first node's suffix step
+  // (t_suffix needs 4 b^2 + 2 b), which runs after their last use in that iteration
+  __shared__ double quad[4 * BB + 2 * B];
+  double *Pp = quad, *Pn = quad + BB, *X1 = quad + 2 * BB, *X3 = quad + 3 * BB, *tmp = quad;
   const int tid = threadIdx.x;
   for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
   tsync();
