@@ -12,14 +12,14 @@ using ModelS = SumM32Periodic<3, true, kSqExpOrder>;   // ... + squared exponent
 static_assert(ModelP::B == ModelQ::B, "one state dimension for the two b = 10 models");
 // Work-group caps: what fits on the 256 CUs at once for each kernel's LDS and registers, so
 // that every team stays resident and loops over its items instead of a launch ending with a
-// second, partly empty round.  b = 10: up 15 KB of LDS (10 per CU), down 13 KB (11), node
-// 14 KB and 213 VGPRs (8), leaf 16 per CU.  b = 16: up 37 KB and 256 VGPRs (4 per CU), down
-// 33 KB (4), node 33 KB and 256 VGPRs (4), leaf 15 KB (10).
+// second, partly empty round.  b = 10: up 15 KB of LDS (10 per CU), down 10 KB and 128 VGPRs
+// (16), node 14 KB and 213 VGPRs (8), leaf 16 per CU.  b = 16: up 37 KB and 256 VGPRs (4 per
+// CU), down 24 KB (6), node 39 KB and 256 VGPRs (4), leaf 15 KB (10).
 struct Caps {
   int up, down, leaf, node;
 };
-constexpr Caps kCaps10 = {2560, 2816, 4096, 2048};
-constexpr Caps kCaps16 = {1024, 1024, 2560, 1024};
+constexpr Caps kCaps10 = {2560, 4096, 4096, 2048};
+constexpr Caps kCaps16 = {1024, 1536, 2560, 1024};
 inline const Caps& caps(int model) { return model == kModelQuasiSqExp ? kCaps16 : kCaps10; }
 
 inline void mark(const WideCtx& c, int kid, int end) {

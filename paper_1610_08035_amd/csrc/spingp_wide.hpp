@@ -50,8 +50,10 @@ struct Lay {
   static constexpr int km = 0, kP = B, kMJ = B + BB, kMeta = 2 * BB + B;
   static constexpr int kM = 2 * BB + 2 * B;
   static constexpr int kMs = (kM + 7) / 8 * 8;
-  // scratch of one element operation: 8 matrices and 10 vectors
+  // scratch of one element operation: 8 matrices and 10 vectors (a join); a prefix or suffix
+  // step needs 4 matrices and 5 vectors
   static constexpr int kTmp = 8 * BB + 10 * B;
+  static constexpr int kTmpStep = 4 * BB + 5 * B;
 };
 
 // ---------------------------------------------------------------------------- team algebra
@@ -354,7 +356,7 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
   using Y = Lay<B>;
   constexpr int BB = B * B;
   double *M = tmp, *G = M + BB, *Pp = G + BB, *T = Pp + BB;
-  double* v = tmp + 8 * BB;
+  double* v = tmp + 4 * BB;   // four matrices and five vectors: 4 b^2 + 5 b doubles of scratch
   double *Gm = v, *Ppe = v + B, *g = v + 2 * B, *Wm = v + 3 * B, *Jm = v + 4 * B;
   const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
@@ -879,7 +881,7 @@ __global__ __launch_bounds__(kW) void k_wide_down(const double* __restrict__ ele
                                                   int64_t off_par, int64_t off_child, int64_t n_child) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
-  __shared__ double par[Y::kMs], E[Y::kEs], out[Y::kMs], tmp[Y::kTmp];
+  __shared__ double par[Y::kMs], E[Y::kEs], out[Y::kMs], tmp[Y::kTmpStep];
   const int tid = threadIdx.x;
   for (int64_t c = blockIdx.x; c < n_child; c += gridDim.x) {
     const double* pm = msgs + (off_par + (c >> 1)) * Y::kMs;
