@@ -12,14 +12,15 @@ using ModelS = SumM32Periodic<3, true, kSqExpOrder>;   // ... + squared exponent
 static_assert(ModelP::B == ModelQ::B, "one state dimension for the two b = 10 models");
 // Work-group caps: what fits on the 256 CUs at once for each kernel's LDS and registers, so
 // that every team stays resident and loops over its items instead of a launch ending with a
-// second, partly empty round.  b = 10: up 15 KB of LDS (10 per CU), down 10 KB and 128 VGPRs
-// (16), node 14 KB and 213 VGPRs (8), leaf 16 per CU.  b = 16: up 37 KB and 256 VGPRs (4 per
-// CU), down 24 KB (6), node 39 KB and 256 VGPRs (4), leaf 15 KB (10).
+// second, partly empty round.  b = 10: up 11 KB and 148 VGPRs (12 per CU; level 1 98 VGPRs,
+// 14), down 10 KB and 128 VGPRs (16), node 14 KB and 213 VGPRs (8), leaf 16 per CU.  b = 16: up
+// 28 KB and 256 VGPRs (4 per CU; level 1 210 VGPRs, 5), down 24 KB (6), node 39 KB and 256
+// VGPRs (4), leaf 15 KB (10).
 struct Caps {
-  int up, down, leaf, node;
+  int up, up1, down, leaf, node;   // up1: the up-sweep's first level
 };
-constexpr Caps kCaps10 = {2560, 4096, 4096, 2048};
-constexpr Caps kCaps16 = {1024, 1536, 2560, 1024};
+constexpr Caps kCaps10 = {3072, 3584, 4096, 4096, 2048};
+constexpr Caps kCaps16 = {1024, 1280, 1536, 2560, 1024};
 inline const Caps& caps(int model) { return model == kModelQuasiSqExp ? kCaps16 : kCaps10; }
 
 inline void mark(const WideCtx& c, int kid, int end) {
@@ -82,7 +83,7 @@ hipError_t factor_m(const WideCtx& c) {
   // level 1 joins leaves (rank-one node information: closed-form inverse)
   for (int k = 1; k < c.n_levels; ++k) {
     if (k == 1)
-      hipLaunchKernelGGL((k_wide_up<B, true>), dim3(grid_for(c.n[k], cp.up)), dim3(kW), 0, c.stream, c.elems,
+      hipLaunchKernelGGL((k_wide_up<B, true>), dim3(grid_for(c.n[k], cp.up1)), dim3(kW), 0, c.stream, c.elems,
                          c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
     else
       hipLaunchKernelGGL((k_wide_up<B, false>), dim3(grid_for(c.n[k], cp.up)), dim3(kW), 0, c.stream, c.elems,

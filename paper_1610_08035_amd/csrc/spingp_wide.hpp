@@ -53,6 +53,7 @@ struct Lay {
   // scratch of one element operation: 8 matrices and 10 vectors (a join); a prefix or suffix
   // step needs 4 matrices and 5 vectors
   static constexpr int kTmp = 8 * BB + 10 * B;
+  static constexpr int kTmpJoin = 7 * BB + 6 * B;
   static constexpr int kTmpStep = 4 * BB + 5 * B;
 };
 
@@ -272,7 +273,7 @@ SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tm
   using Y = Lay<B>;
   constexpr int BB = B * B;
   double *M = tmp, *G = M + BB, *Pp = G + BB, *W = Pp + BB, *GA = W + BB, *T = GA + BB, *WA = T + BB;
-  double* v = tmp + 8 * BB;
+  double* v = tmp + 7 * BB;   // seven matrices and six vectors: 7 b^2 + 6 b doubles of scratch
   double *Gb = v, *Ppe = v + B, *g = v + 2 * B, *Gte = v + 3 * B, *Wb = v + 4 * B, *r = v + 5 * B;
   const double *A1 = E1 + Y::kA, *b1 = E1 + Y::kb, *Q1 = E1 + Y::kQ, *J1 = E1 + Y::kJ, *eta1 = E1 + Y::keta;
   const double *A2 = E2 + Y::kA, *b2 = E2 + Y::kb, *Q2 = E2 + Y::kQ, *J2 = E2 + Y::kJ, *eta2 = E2 + Y::keta;
@@ -823,7 +824,7 @@ template <int B, bool LEAF = false>
 __global__ __launch_bounds__(kW) void k_wide_up(double* __restrict__ elems, int64_t off_prev, int64_t n_prev,
                                                 int64_t off_cur, int64_t n_cur) {
   using Y = Lay<B>;
-  __shared__ double E1[Y::kEs], E2[Y::kEs], R[Y::kEs], tmp[Y::kTmp];
+  __shared__ double E1[Y::kEs], E2[Y::kEs], tmp[Y::kTmpJoin];
   const int tid = threadIdx.x;
   for (int64_t i = blockIdx.x; i < n_cur; i += gridDim.x) {
     const double* a = elems + (off_prev + 2 * i) * Y::kEs;
@@ -838,8 +839,8 @@ __global__ __launch_bounds__(kW) void k_wide_up(double* __restrict__ elems, int6
       E2[e] = b[e];
     }
     tsync();
-    t_combine<B, LEAF>(E1, E2, R, tmp);
-    for (int e = tid; e < Y::kEs; e += kW) out[e] = e < Y::kE ? R[e] : 0.0;
+    t_combine<B, LEAF>(E1, E2, out, tmp);     // the result goes straight to global memory
+    for (int e = Y::kE + tid; e < Y::kEs; e += kW) out[e] = 0.0;
     tsync();
   }
 }
