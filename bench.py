@@ -35,9 +35,9 @@ PEAK_HBM_GBS = 8000.0
 # valid only for the kernel sources they were taken on (sha256 over csrc/, see
 # kernel_source_sha), else reported as null.
 TRAFFIC = {"kernel": "bwd_elim_adjoint",
-           "bytes": {(8, 128): (45055.2 * 2.0 + 8288.3) * 1024.0,
-                     (8, 256): (43885.2 * 2.0 + 8240.0) * 1024.0},
-           "source_sha": "164aee587469ad5a10d2dcca2f8a6b1925e6207948dc4ea69e9e8eb9b3707bbf"}
+           "bytes": {(8, 128): (45122.8 * 2.0 + 8288.1) * 1024.0,
+                     (8, 256): (44051.0 * 2.0 + 8240.0) * 1024.0},
+           "source_sha": "8f607d7d117ab8c5472ea796fc077377d922efceb42fce027776d037e6fa605a"}
 
 
 def kernel_source_sha():
