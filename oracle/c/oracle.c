@@ -78,14 +78,18 @@ static void sym(int b, double* X) {
 /* Solve M X = R for X (M b x b, R b x m, row-major), Gaussian elimination with partial pivoting.
  * Returns log|det M| in *logabsdet (if not NULL) and 0, or -1 if M is singular. */
 static int solve(int b, const double* M, double* R, int m, double* logabsdet) {
-  double a[MAXB * MAXB];
+  double* a = malloc(sizeof(double) * b * b);
+  if (!a) return -1;
   memcpy(a, M, sizeof(double) * b * b);
   double ld = 0.0;
   for (int c = 0; c < b; ++c) {
     int p = c;
     for (int r = c + 1; r < b; ++r)
       if (fabs(a[r * b + c]) > fabs(a[p * b + c])) p = r;
-    if (a[p * b + c] == 0.0) return -1;
+    if (a[p * b + c] == 0.0) {
+      free(a);
+      return -1;
+    }
     if (p != c) {
       for (int k = 0; k < b; ++k) { double t = a[c * b + k]; a[c * b + k] = a[p * b + k]; a[p * b + k] = t; }
       for (int k = 0; k < m; ++k) { double t = R[c * m + k]; R[c * m + k] = R[p * m + k]; R[p * m + k] = t; }
@@ -106,6 +110,7 @@ static int solve(int b, const double* M, double* R, int m, double* logabsdet) {
     }
   }
   if (logabsdet) *logabsdet = ld;
+  free(a);
   return 0;
 }
 
@@ -182,12 +187,17 @@ static void expm_taylor(int b, const double* X, double* E) {
    symmetric P (companion F). */
 static int lyap_companion(int n, const double* F, double q, double* P) {
   int nu = n * (n + 1) / 2;
-  double M[MAXB * MAXB], R[MAXB];
-  if (nu > MAXB) return -1;
+  if (n > 16) return -1;
+  double* M = calloc((size_t)nu * nu, sizeof(double));
+  double* R = malloc(sizeof(double) * nu);
+  if (!M || !R) {
+    free(M);
+    free(R);
+    return -1;
+  }
   int idx[16][16];
   for (int i = 0, k = 0; i < n; ++i)
     for (int j = i; j < n; ++j, ++k) idx[i][j] = idx[j][i] = k;
-  memset(M, 0, sizeof(M));
   for (int i = 0; i < n; ++i)
     for (int j = i; j < n; ++j) {
       int row = idx[i][j];
@@ -197,10 +207,13 @@ static int lyap_companion(int n, const double* F, double q, double* P) {
       }
       R[row] = (i == n - 1 && j == n - 1) ? -q : 0.0;
     }
-  if (solve(nu, M, R, 1, NULL)) return -1;
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) P[i * n + j] = R[idx[i][j]];
-  return 0;
+  const int rc = solve(nu, M, R, 1, NULL);
+  if (rc == 0)
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) P[i * n + j] = R[idx[i][j]];
+  free(M);
+  free(R);
+  return rc;
 }
 
 /* F of the squared-exponential term at lam = 1 / l. */

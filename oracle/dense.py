@@ -114,48 +114,7 @@ def state_posterior_dense(model: SumModel, t, y) -> dict:
 def gp_dense_mp(model: SumModel, t, y, dps: int = 50) -> dict:
     """High-precision dense GP (mpmath) for small N: logML, mean and variance.
 
-    The closed-form kernel is evaluated in mpmath arithmetic from the float64
-    inputs, so the only rounding left is mpmath's own at `dps` digits.
-    """
-    import mpmath as mp
-
-    with mp.workdps(dps):
-        n = len(t)
-        tt = [mp.mpf(float(v)) for v in t]
-        yy = mp.matrix([mp.mpf(float(v)) for v in y])
-
-        def k(tau):
-            tau = abs(tau)
-            total = mp.mpf(0)
-            for m in model.parts:
-                if hasattr(m, "lam"):
-                    nu = mp.mpf(3) / 2 if m.b == 2 else mp.mpf(5) / 2
-                    lam = mp.sqrt(2 * nu) / mp.mpf(m.ell)
-                    r = lam * tau
-                    poly = (1 + r) if m.b == 2 else (1 + r + r * r / 3)
-                    total += mp.mpf(m.var) * poly * mp.e ** (-r)
-                else:
-                    z = 1 / mp.mpf(m.ell) ** 2
-                    w0 = 2 * mp.pi / mp.mpf(m.period)
-                    for j in range(m.J + 1):
-                        q = mp.besseli(j, z) * mp.e ** (-z) * (1 if j == 0 else 2)
-                        total += mp.mpf(m.var) * q * mp.cos(j * w0 * tau)
-            return total
-
-        Kf = mp.matrix(n, n)
-        for i in range(n):
-            for j in range(n):
-                Kf[i, j] = k(tt[i] - tt[j])
-        Ky = Kf + mp.mpf(model.noise) * mp.eye(n)
-        L = mp.cholesky(Ky)
-        logdet = 2 * mp.fsum(mp.log(L[i, i]) for i in range(n))
-        Kinv = mp.inverse(Ky)
-        alpha = Kinv * yy
-        datafit = mp.fsum(yy[i] * alpha[i] for i in range(n))
-        logml = -datafit / 2 - logdet / 2 - n * mp.log(2 * mp.pi) / 2
-        mean = Kf * alpha
-        X = Kinv * Kf
-        var = [Kf[i, i] - mp.fsum(Kf[i, j] * X[j, i] for j in range(n)) for i in range(n)]
-        return {"logml": float(logml), "datafit": float(datafit), "logdet": float(logdet),
-                "f_mean": np.array([float(mean[i]) for i in range(n)]),
-                "f_var": np.array([float(v) for v in var])}
+    The kernel of every term is written out per kind in `oracle.mpref` and evaluated in
+    mpmath arithmetic from the float64 inputs; a kind it does not model raises."""
+    from .mpref import gp_dense_mp as _gp_dense_mp
+    return _gp_dense_mp(model.terms, model.hyper_row, t, y, dps=dps)

@@ -337,6 +337,8 @@ class SumModel:
 
     def __init__(self, terms, hyper_row):
         """terms: [(kind, harmonics)], hyper_row: term parameters then the noise variance."""
+        self.terms = [(int(k), int(h)) for k, h in terms]
+        self.hyper_row = np.array(hyper_row, dtype=np.float64)
         self.parts = []
         p = 0
         for kind, harm in terms:

@@ -98,36 +98,19 @@ def test_sqexp_sum_duplicate_times(lib):
     compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp))
 
 
-def _reference_spread(t, y, hyp):
-    """Largest disagreement, in units of the 1e-9 bars, between two independent FP64 oracles
-    (C block-tridiagonal elimination and the Python Kalman filter + RTS smoother) on the
-    state means, variances and covariance blocks."""
-    c = native.btd_factored(TERMS, hyp, t, y)
-    k = kalman.kf_rts(model_for(TERMS, hyp), t, y)
-    d = np.sqrt(np.maximum(np.einsum("nii->ni", c["S_diag"]), 0.0))
-    ez = np.max(np.abs(k["z_mean"] - c["z_mean"]) / (np.abs(c["z_mean"]) + d))
-    ev = np.max(np.abs(k["f_var"] - c["f_var"]) / c["f_var"])
-    es = np.max(np.abs(k["S_diag"] - c["S_diag"]) / (d[:, :, None] * d[:, None, :]))
-    return max(ez, ev, es) / 1e-9
-
-
-@pytest.mark.parametrize("ell_s", [0.1, 0.2, 5000.0])
+@pytest.mark.parametrize("ell_s", [0.5, 5000.0])
 def test_sqexp_sum_extreme_trend_lengthscale(lib, ell_s):
-    """Squared-exponential lengthscales far from the other terms' scales.  Short (lam_S = 5,
-    10): in the model's state (f, f', ..., f^(5)) P0 spans lam_S^10, and two independent FP64
-    oracles already disagree by about lam_S^10 eps (2.5e-9 at lam_S = 5, 2.7e-7 at 10, 0.14 at
-    50); the device keeps that block in the scaled state f^(k) / lam_S^k and is compared with the
-    mean, variance and block bars widened to 4x the oracles' measured spread (logML and gradient
-    bars as elsewhere).  Long (far beyond the span): a nearly constant trend, at the plain bars
-    (the Python oracle's Lyapunov solve breaks down there, lam_S r_k being nearly zero, so only
-    the C oracle is used)."""
+    """Squared-exponential lengthscales away from the other terms' scales, at the plain bars
+    against the C oracle: 0.5 (lam_S = 2, where float64 work in the model's own state
+    (f, f', ..., f^(5)) still holds about lam_S^10 eps = 2e-13) and 5000 (far beyond the span: a
+    nearly constant trend; the Python oracle's Lyapunov solve breaks down there, lam_S r_k being
+    nearly zero, so only the C oracle is used).  Shorter lengthscales (0.02, 0.1, 0.2), where the
+    float64 oracles lose up to 1e-1, are checked against 50-digit references in
+    test_gpu_mp_reference.py."""
     hyper = list(HYPER)
     hyper[6] = ell_s
     t, y, hyp = _data(1500, hyper, seed=25, span=75.0)
-    widen = max(1.0, 4.0 * _reference_spread(t, y, hyp)) if ell_s < 1.0 else 1.0
-    print(f"\nl_S = {ell_s}: bars widened {widen:.3g}x", flush=True)
-    assert widen < 1e4
-    compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp), widen=widen)
+    compare_series(TERMS, t, y, hyp, _run(lib, t, y, hyp))
 
 
 def test_sqexp_sum_large(lib):

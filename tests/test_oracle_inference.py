@@ -144,6 +144,67 @@ def test_literal_btd_loses_accuracy_for_tiny_gaps():
     assert not err < 1e-8
 
 
+def _adversarial(n, seed, scale=0.5):
+    """Exp(scale) gaps with a duplicate time and gaps of 1e-9 and 1e-6."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(scale, n)
+    gaps[n // 4] = 0.0
+    gaps[n // 2] = 1e-9
+    gaps[3 * n // 4] = 1e-6
+    return np.cumsum(gaps), rng.standard_normal(n)
+
+
+def _block_errors(ref, got):
+    """Largest errors of the state means and covariance blocks on the scale sqrt(S_ii S_jj)."""
+    d = np.sqrt(np.maximum(np.einsum("nii->ni", ref["S_diag"]), 0.0))
+    ez = np.max(np.abs(got["z_mean"] - ref["z_mean"]) / (np.abs(ref["z_mean"]) + d))
+    es = np.max(np.abs(got["S_diag"] - ref["S_diag"]) / (d[:, :, None] * d[:, None, :]))
+    eb = np.max(np.abs(got["S_sub"] - ref["S_sub"]) / (d[1:, :, None] * d[:-1, None, :])) if len(ref["S_sub"]) else 0.0
+    return ez, es, eb
+
+
+@pytest.mark.parametrize("grid", ["plain", "adversarial"])
+@pytest.mark.parametrize("name,terms,hyper", CASES)
+def test_c_oracle_state_blocks_match_dense_state_posterior(name, terms, hyper, grid):
+    """The C elimination's state means, Cov(z_n, z_n | y) and Cov(z_{n+1}, z_n | y) (the
+    selected inverse, Sec. 3.1 subproblems 2 and 4) against the dense stacked-state posterior,
+    on plain Exp gaps and on gaps with a duplicate time, 1e-9 and 1e-6 (1e-9 on sqrt(S_ii S_jj))."""
+    t, y = _adversarial(40, seed=60 + len(name)) if grid == "adversarial" else _data(40, seed=61, span=20.0)
+    sp = dense.state_posterior_dense(model_for(terms, hyper), t, y)
+    c = native.btd_factored(terms, hyper, t, y)
+    errs = _block_errors(sp, c)
+    assert max(errs) <= 1e-9, errs
+
+
+@pytest.mark.parametrize("name,terms,hyper", [c for c in CASES if c[0] in ("m32+per3", "m32+qp3", "se6", "co2")])
+def test_c_oracle_state_blocks_match_50_digit_posterior(name, terms, hyper):
+    """The wide-state models' blocks against the 50-digit stacked-state posterior (duplicate time
+    included)."""
+    from oracle import mpref
+    rng = np.random.default_rng(62)
+    t = np.sort(rng.uniform(0.0, 30.0, 16))
+    t[5] = t[4]
+    y = rng.standard_normal(16)
+    sp = mpref.state_posterior_dense_mp(terms, hyper, t, y)
+    c = native.btd_factored(terms, hyper, t, y)
+    errs = _block_errors(sp, c)
+    assert max(errs) <= 1e-9, errs
+    assert rel(c["logml"], sp["logml"]) < 1e-12
+
+
+@pytest.mark.parametrize("name,terms,hyper", [c for c in CASES if c[0] in ("m52", "m32+per3", "co2")])
+def test_c_oracle_state_blocks_match_kalman_rts_long(name, terms, hyper):
+    """N = 2000 with duplicate and near-duplicate times: the C elimination's blocks against the
+    Python Kalman filter + RTS smoother (written from the filter equations, lag-one covariance
+    S_{n+1} G_n^T)."""
+    t, y = _adversarial(2000, seed=63, scale=0.05 if name == "co2" else 0.5)
+    k = kalman.kf_rts(model_for(terms, hyper), t, y)
+    c = native.btd_factored(terms, hyper, t, y)
+    errs = _block_errors(k, c)
+    assert max(errs) <= 1e-9, errs
+    assert rel(c["logml"], k["logml"]) < 1e-11
+
+
 def test_kalman_rts_matches_factored_btd():
     for name, terms, hyper in CASES:
         m = model_for(terms, hyper)
