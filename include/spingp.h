@@ -168,6 +168,27 @@ int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, double* S_sub)
 int spingp_logml_grad(spingp_handle h, double* logml, double* grad);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): spingp_logml_grad for one series of a single Matern
+ * term without a handle.  terms: host array, n_terms = 1, kind SPINGP_MATERN12/32/52/72; t, y:
+ * [n_points] device arrays (t non-decreasing, finite); hyper: [3] device array (lengthscale,
+ * signal variance, noise variance, all > 0); logml: [1], grad: [3] device outputs; stream: a
+ * hipStream_t (NULL = the default stream).  The inputs are not checked on the device: invalid
+ * data gives unspecified values, without accesses outside the arguments and the workspace.
+ * Workspace: a fixed device array of SPINGP_NOALLOC_SCRATCH_BYTES inside the library, one copy
+ * per GPU, kept until the process ends; the call allocates and frees nothing.  It runs the same
+ * kernels as spingp_logml_grad with tile shape 0 (so the results are identical to a handle's on
+ * that shape).  Sizes whose workspace exceeds the array return SPINGP_E_UNSUPPORTED: n_points up
+ * to 2^16 fit for every b (at most 90 112 at b = 4, 142 336 at b = 3, 259 072 at b = 2, 523 264
+ * at b = 1).  All calls on one GPU share its array: calls
+ * that overlap in time on one GPU (several streams or host threads) race and must be ordered by
+ * the caller.  Enqueues on `stream` and returns without synchronising.
+ */
+#define SPINGP_NOALLOC_SCRATCH_BYTES (8 << 20)
+int spingp_logml_grad_noalloc(const spingp_term* terms, int32_t n_terms, const double* t, const double* y,
+                              int64_t n_points, const double* hyper, double* logml, double* grad, void* stream);
+
+/*
  * Tile shapes (R nodes folded per lane, L lanes per work-group) compiled into the library;
  * shape 0 is the default.  Results agree across shapes up to rounding.
  */

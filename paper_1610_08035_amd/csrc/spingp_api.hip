@@ -744,6 +744,110 @@ extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
   return rc;
 }
 
+// ---------------------------------------------------------------------------- no allocation
+// Fixed device workspace of spingp_logml_grad_noalloc: one copy per GPU, held by the loaded
+// library until the process ends.  Host code never uses the array's name as a pointer: the
+// device address of this GPU's copy comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[SPINGP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array.
+int scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPINGP_E_HIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SPINGP_E_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return SPINGP_OK;
+}
+
+__global__ void k_zero_u32(unsigned int* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+}  // namespace
+
+extern "C" int spingp_logml_grad_noalloc(const spingp_term* terms, int32_t n_terms, const double* t,
+                                         const double* y, int64_t n_points, const double* hyper, double* logml,
+                                         double* grad, void* stream) {
+  if (!terms || n_terms != 1 || !t || !y || !hyper || !logml || !grad || n_points < 1) return SPINGP_E_INVALID;
+  int b = 0;
+  switch (terms[0].kind) {
+    case SPINGP_MATERN12: b = 1; break;
+    case SPINGP_MATERN32: b = 2; break;
+    case SPINGP_MATERN52: b = 3; break;
+    case SPINGP_MATERN72: b = 4; break;
+    default: return SPINGP_E_UNSUPPORTED;
+  }
+  // tile shape 0; the same workspace regions spingp_create sizes for one series, laid out in
+  // the scratch array at 256-byte boundaries
+  const spg::TileOps* T = spg::tile_ops(0);
+  const int64_t G = T->groups(n_points, 1, false);
+  const int NF = b == 1 ? spg::ElemLayout<1>::kFields
+                 : b == 2 ? spg::ElemLayout<2>::kFields
+                 : b == 3 ? spg::ElemLayout<3>::kFields
+                          : spg::ElemLayout<4>::kFields;
+  const int64_t lane_ld = G * 2 * T->L;
+  int64_t top_ld = 0, top_cnt_n = 0;
+  spg::top_sizes(G, top_ld, top_cnt_n);
+  const int64_t o_lane = 0;
+  const int64_t o_top = align256(o_lane + (int64_t)sizeof(double) * NF * lane_ld);
+  const int64_t o_part = align256(o_top + (int64_t)sizeof(double) * NF * top_ld);
+  const int64_t o_scal = align256(o_part + (int64_t)sizeof(double) * 3 * G);
+  const int64_t o_key = align256(o_scal + (int64_t)sizeof(double) * 8);
+  const int64_t o_cnt = align256(o_key + (int64_t)sizeof(unsigned long long));
+  const int64_t need = o_cnt + (int64_t)sizeof(unsigned int) * top_cnt_n;
+  if (need > (int64_t)SPINGP_NOALLOC_SCRATCH_BYTES) return SPINGP_E_UNSUPPORTED;
+  void* base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc) return rc;
+  unsigned char* sb = (unsigned char*)base;
+  spg::LaunchCtx c;
+  memset(&c, 0, sizeof(c));
+  c.b = b;
+  c.stream = (hipStream_t)stream;
+  c.t = t;
+  c.y = y;
+  c.hyper = hyper;
+  c.n_points = n_points;
+  c.n_series = 1;
+  c.batched = false;
+  c.lane = (double*)(sb + o_lane);
+  c.lane_ld = lane_ld;
+  c.top = (double*)(sb + o_top);
+  c.top_ld = top_ld;
+  c.top_cnt = (unsigned int*)(sb + o_cnt);
+  c.scal = (double*)(sb + o_scal);
+  c.part = (double*)(sb + o_part);
+  c.part_ld = G;
+  c.key = (unsigned long long*)(sb + o_key);
+  // the band counters must start at zero (the top-level kernel also resets the ones it uses);
+  // fill kernels rather than memset nodes, so that callers may capture the call in a graph
+  hipLaunchKernelGGL(k_fill_key, dim3(1), dim3(1), 0, c.stream, c.key);
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, c.stream, c.top_cnt, top_cnt_n);
+  if (hipGetLastError() != hipSuccess) return SPINGP_E_HIP;
+  if (T->factor(c) != hipSuccess) return SPINGP_E_HIP;
+  spg::BwdOut o;
+  memset(&o, 0, sizeof(o));
+  o.ld = n_points;
+  o.part = c.part;
+  o.part_ld = c.part_ld;
+  if (T->bwd(c, spg::kWantGrad, o) != hipSuccess) return SPINGP_E_HIP;
+  hipLaunchKernelGGL(spg::k_grad_finish, dim3(1), dim3(256), 0, c.stream, c.part, c.part_ld, G, c.scal, logml,
+                     grad);
+  return hip_ok(hipGetLastError());
+}
+
 extern "C" int spingp_predict(spingp_handle h, const double* t_star, const int64_t* offsets_star, int64_t n_star,
                               double* f_mean, double* f_var) {
   if (!h || !t_star || n_star < 1) return SPINGP_E_INVALID;

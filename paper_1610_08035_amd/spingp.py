@@ -73,10 +73,12 @@ def load_library():
     lib.spingp_tune.argtypes = [vp, i32]
     lib.spingp_blocks.argtypes = [vp, vp, vp, vp, vp]
     lib.spingp_predict.argtypes = [vp, vp, vp, i64, vp, vp]
+    lib.spingp_logml_grad_noalloc.argtypes = [ctypes.POINTER(_Term), i32, vp, vp, i64, vp, vp, vp, vp]
     for name in ("spingp_create", "spingp_destroy", "spingp_state_dim", "spingp_n_hyper", "spingp_assemble",
                  "spingp_factor", "spingp_logml", "spingp_solve", "spingp_selinv", "spingp_logml_grad",
                  "spingp_status", "spingp_profile", "spingp_profile_read", "spingp_tile_count",
-                 "spingp_tile_shape", "spingp_get_tile", "spingp_set_tile", "spingp_tune", "spingp_blocks", "spingp_predict"):
+                 "spingp_tile_shape", "spingp_get_tile", "spingp_set_tile", "spingp_tune", "spingp_blocks", "spingp_predict",
+                 "spingp_logml_grad_noalloc"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -158,6 +160,17 @@ def spingp_selinv(h, f_var=None, S_diag=None, S_sub=None):
 
 def spingp_logml_grad(h, logml, grad):
     _check(load_library().spingp_logml_grad(h, _dev(logml, "logml"), _dev(grad, "grad")), "spingp_logml_grad")
+
+
+def spingp_logml_grad_noalloc(terms, t, y, hyper, logml, grad, stream=None):
+    """logML and gradient of one Matern series without a handle or any device allocation (the
+    library's fixed workspace array); for callers that cannot allocate."""
+    n = t.numel()
+    arr = (_Term * len(terms))(*[_Term(k, h) for k, h in terms])
+    _check(load_library().spingp_logml_grad_noalloc(arr, len(terms), _dev(t, "t"), _dev(y, "y", n), int(n),
+                                                    _dev(hyper, "hyper", 3), _dev(logml, "logml", 1),
+                                                    _dev(grad, "grad", 3), _stream_ptr(stream)),
+           "spingp_logml_grad_noalloc")
 
 
 def spingp_predict(h, t_star, f_mean=None, f_var=None, offsets_star=None):

@@ -54,3 +54,24 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(b, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         b.load_library()
+
+
+def test_noalloc_host_errors_without_gpu(lib):
+    """The allocation-free call rejects bad arguments and sizes beyond its fixed workspace before
+    any device call (the pointers below are never dereferenced)."""
+    class Term(ctypes.Structure):
+        _fields_ = [("kind", ctypes.c_int32), ("harmonics", ctypes.c_int32)]
+
+    f = lib.spingp_logml_grad_noalloc
+    f.argtypes = [ctypes.POINTER(Term), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    p = ctypes.c_void_p(0x1000)
+    m52 = (Term * 1)(Term(2, 0))
+    assert f(None, 1, p, p, 100, p, p, p, None) == 1                     # no terms
+    assert f(m52, 1, None, p, 100, p, p, p, None) == 1                   # null t
+    assert f(m52, 1, p, p, 0, p, p, p, None) == 1                        # empty series
+    two = (Term * 2)(Term(1, 0), Term(3, 3))
+    assert f(two, 2, p, p, 100, p, p, p, None) == 1                      # one term only
+    assert f((Term * 1)(Term(3, 3)), 1, p, p, 100, p, p, p, None) == 8   # not a Matern term
+    assert f(m52, 1, p, p, 142337, p, p, p, None) == 8                   # beyond the fixed workspace
+    assert f((Term * 1)(Term(5, 0)), 1, p, p, 90113, p, p, p, None) == 8
