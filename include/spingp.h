@@ -19,7 +19,12 @@
  *     unsupported model, call order) are returned synchronously as a spingp_status_t.
  *     Data errors (decreasing or non-finite t, non-finite y, non-positive or non-finite
  *     hyperparameters) are detected on the device, recorded in a status word and reported
- *     by spingp_status; results of such a call are unspecified.
+ *     by spingp_status.  Until the next spingp_assemble the outputs they affect are NaN: every
+ *     output of a one-series handle; with several series, the outputs of the failing series
+ *     (all series when the offsets themselves are invalid).
+ *   - There is no numerical-failure code: the reduction never inverts Q_n or a covariance, its
+ *     pivots are I + Q J with eigenvalues >= 1 and innovation variances >= s2 > 0, so valid
+ *     inputs cannot make it break down.
  *   - Nothing is printed, thrown across the ABI or exits the process.
  *   - One handle per host thread and stream.
  *
@@ -160,12 +165,14 @@ int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, double* S_sub)
 /*
  * Log marginal likelihood and its gradient (Sec. 2.4) with respect to the raw hyperparameters
  * of the hyperparameter row: grad: [n_series x n_hyper], logml: [n_series] (an empty series
- * gets 0 and a zero gradient).  Always runs the forward reduction itself (it reads the
- * hyperparameters from device memory, so an optimiser may update them between calls without a
- * new assemble), then the adjoint sweep; leaves the handle factored.  Replays a HIP graph when
- * assembled with SPINGP_FLAG_GRAPH.  Needs assemble.
+ * gets 0 and a zero gradient).  mask: NULL (every component) or a HOST array of n_hyper bytes;
+ * components whose byte is 0 are written as 0 (for hyperparameters an optimiser holds fixed;
+ * a HIP graph is captured again when the mask changes).  Always runs the forward reduction
+ * itself (it reads the hyperparameters from device memory, so an optimiser may update them
+ * between calls without a new assemble), then the adjoint sweep; leaves the handle factored.
+ * Replays a HIP graph when assembled with SPINGP_FLAG_GRAPH.  Needs assemble.
  */
-int spingp_logml_grad(spingp_handle h, double* logml, double* grad);
+int spingp_logml_grad(spingp_handle h, double* logml, double* grad, const uint8_t* mask);
 
 /*
  * For callers that cannot allocate device memory (code under HIP graph capture, tight serving

@@ -44,12 +44,19 @@ __global__ void k_validate(const double* __restrict__ t, const double* __restric
 
 __global__ void k_fill_key(unsigned long long* key) { *key = ~0ull; }
 
+__global__ void k_zero_u32(unsigned int* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// One series: logML, data fit and log det from the root of the reduction (NaN after a data error).
 __global__ void k_copy_scalars(const double* __restrict__ scal, int64_t n_pts, double* logml, double* datafit,
-                               double* logdet) {
+                               double* logdet, const unsigned long long* __restrict__ status) {
   if (threadIdx.x == 0) {
-    if (logml) logml[0] = scal[0];
-    if (datafit) datafit[0] = -2.0 * scal[1];
-    if (logdet) logdet[0] = -2.0 * scal[2] - (double)n_pts * spg::kLog2Pi;
+    const bool poison = *status != ~0ull;
+    if (logml) logml[0] = poison ? spg::kPoison : scal[0];
+    if (datafit) datafit[0] = poison ? spg::kPoison : -2.0 * scal[1];
+    if (logdet) logdet[0] = poison ? spg::kPoison : -2.0 * scal[2] - (double)n_pts * spg::kLog2Pi;
   }
 }
 
@@ -102,6 +109,7 @@ struct spingp_ctx {
   int64_t part_ld = 0;
   int32_t* chunk_series = nullptr; // several series: series of every chunk slot
   int64_t* chunk_first = nullptr;  // several series: first chunk of every series
+  uint32_t* bad = nullptr;         // several series: series whose inputs failed the device checks
   unsigned long long* key = nullptr;
   double* tune_out = nullptr;      // logML and gradient written while tuning
   double* pred = nullptr;          // prediction: merged times, observations, mean, variance
@@ -129,6 +137,7 @@ struct spingp_ctx {
   hipGraphExec_t gexec = nullptr;
   const double* g_logml = nullptr;
   const double* g_grad = nullptr;
+  uint32_t g_mask = 0;
   // profiling (optional)
   static constexpr int kPool = 64;
   bool prof = false;
@@ -193,6 +202,7 @@ static spg::LaunchCtx launch_ctx(spingp_ctx* h, bool timed = true) {
   c.part_ld = h->part_ld;
   c.chunk_series = h->chunk_series;
   c.chunk_first = h->chunk_first;
+  c.bad = h->bad;
   c.key = h->key;
   c.mark = (timed && h->prof) ? prof_mark : nullptr;
   c.mark_arg = h;
@@ -207,6 +217,8 @@ static spg::wide::WideCtx wide_ctx(spingp_ctx* h, bool timed = true) {
   c.hyper = h->hyper;
   c.n_points = h->n_points;
   c.scal = h->scal;
+  c.status = h->key;
+  c.gmask = ~0u;
   c.mark = (timed && h->prof) ? prof_mark : nullptr;
   c.mark_arg = h;
   return c;
@@ -338,6 +350,7 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
       {(void**)&h->pred_off, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
       {(void**)&h->chunk_series, multi ? (int64_t)sizeof(int32_t) * slots_max : 0},
       {(void**)&h->chunk_first, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
+      {(void**)&h->bad, multi ? (int64_t)sizeof(uint32_t) * max_series : 0},
   };
   bool ok = true;
   for (auto& r : reqs) {
@@ -405,6 +418,7 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)hipFree(h->pred_off);
   (void)hipFree(h->chunk_series);
   (void)hipFree(h->chunk_first);
+  (void)hipFree(h->bad);
   (void)hipFree(h->wplan.elems);
   (void)hipFree(h->wplan.msgs);
   (void)hipFree(h->wplan.cst);
@@ -441,6 +455,8 @@ static int bind(spingp_ctx* h) {
     hipLaunchKernelGGL(k_validate, dim3((unsigned)ceil_div(h->n_points, kT)), dim3(kT), 0, h->stream, h->t, h->y,
                        h->n_points, h->hyper, h->n_hyper, h->key);
   } else {
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)ceil_div(h->n_series, kT)), dim3(kT), 0, h->stream, h->bad,
+                       (int64_t)h->n_series);
     map_chunks(h, h->offsets, h->n_points);
     if (T->map(launch_ctx(h, false)) != hipSuccess) return SPINGP_E_HIP;
   }
@@ -464,7 +480,7 @@ TuneKey tune_key(const spingp_ctx* h) {
 }
 }  // namespace
 
-static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed);
+static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed, uint32_t gmask);
 
 extern "C" int spingp_tune(spingp_handle h, int32_t reps) {
   if (!h || reps < 1) return SPINGP_E_INVALID;
@@ -487,11 +503,11 @@ extern "C" int spingp_tune(spingp_handle h, int32_t reps) {
       h->tile = i;
       rc = bind(h);
       if (rc) break;
-      rc = run_logml_grad(h, h->tune_out, h->tune_out + h->max_series, false);   // warm-up
+      rc = run_logml_grad(h, h->tune_out, h->tune_out + h->max_series, false, ~0u);   // warm-up
       if (rc) break;
       (void)hipEventRecord(e0, h->stream);
       for (int r = 0; r < reps && rc == SPINGP_OK; ++r)
-        rc = run_logml_grad(h, h->tune_out, h->tune_out + h->max_series, false);
+        rc = run_logml_grad(h, h->tune_out, h->tune_out + h->max_series, false, ~0u);
       (void)hipEventRecord(e1, h->stream);
       float ms = 0.f;
       if (rc == SPINGP_OK &&
@@ -610,13 +626,13 @@ static int run_bwd(spingp_ctx* h, int mode, const spg::BwdOut& o, bool timed = t
 
 // several series: per-series fixed-order sums of the reverse kernel's per-chunk partials
 static int series_reduce(spingp_ctx* h, double* logml, double* datafit, double* logdet, double* grad,
-                         bool timed = true) {
+                         bool timed = true, uint32_t gmask = ~0u) {
   const spg::TileOps* T = ops(h);
   const spg::SeriesMap sm =
       spg::make_map(launch_ctx(h), T->groups(h->n_points, h->n_series, true) * T->L);
   if (timed) prof_begin(h);
   hipLaunchKernelGGL(spg::k_series_reduce, dim3((unsigned)h->n_series), dim3(64), 0, h->stream, sm, h->part,
-                     h->part_ld, h->n_points, logml, datafit, logdet, grad);
+                     h->part_ld, h->n_points, logml, datafit, logdet, grad, (const unsigned long long*)h->key, gmask);
   if (timed) prof_end(h, spg::kKidReduce);
   return hip_ok(hipGetLastError());
 }
@@ -627,6 +643,7 @@ static spg::BwdOut make_out(spingp_ctx* h) {
   o.ld = h->n_points;
   o.part = h->part;
   o.part_ld = h->part_ld;
+  o.status = h->key;
   return o;
 }
 
@@ -635,7 +652,7 @@ extern "C" int spingp_logml(spingp_handle h, double* logml, double* datafit, dou
   if (!h->factored) return SPINGP_E_ORDER;
   if (!h->batched) {
     hipLaunchKernelGGL(k_copy_scalars, dim3(1), dim3(64), 0, h->stream, h->scal, h->n_points, logml, datafit,
-                       logdet);
+                       logdet, (const unsigned long long*)h->key);
     return hip_ok(hipGetLastError());
   }
   // several series: the per-series terms come from an elimination sweep over every chunk
@@ -670,29 +687,32 @@ extern "C" int spingp_selinv(spingp_handle h, double* f_var, double* S_diag, dou
 }
 
 // forward pass + adjoint sweep (+ per-series sums) on h->stream
-static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed) {
+static int run_logml_grad(spingp_ctx* h, double* logml, double* grad, bool timed, uint32_t gmask) {
   int rc = do_factor(h, timed);
   if (rc) return rc;
   if (h->wide) {
     rc = wide_node(h, spg::kWantGrad, nullptr, nullptr, nullptr, nullptr, nullptr, timed);
     if (rc) return rc;
-    return hip_ok(spg::wide::finish(wide_ctx(h, timed), logml, grad));
+    spg::wide::WideCtx c = wide_ctx(h, timed);
+    c.gmask = gmask;
+    return hip_ok(spg::wide::finish(c, logml, grad));
   }
   rc = run_bwd(h, spg::kWantGrad, make_out(h), timed);
   if (rc) return rc;
-  if (h->batched) return series_reduce(h, logml, nullptr, nullptr, grad, timed);
+  if (h->batched) return series_reduce(h, logml, nullptr, nullptr, grad, timed, gmask);
   // one series: fixed-order sum of the work-group partials
   const spg::TileOps* T = ops(h);
   if (timed) prof_begin(h);
   hipLaunchKernelGGL(spg::k_grad_finish, dim3(1), dim3(256), 0, h->stream, h->part, h->part_ld,
-                     T->groups(h->n_points, 1, false), h->scal, logml, grad);
+                     T->groups(h->n_points, 1, false), h->scal, logml, grad, (const unsigned long long*)h->key,
+                     gmask);
   if (timed) prof_end(h, spg::kKidReduce);
   return hip_ok(hipGetLastError());
 }
 
 // Capture the launch sequence of spingp_logml_grad for these output pointers on the private
 // capture stream and instantiate it.
-static int capture_logml_grad(spingp_ctx* h, double* logml, double* grad) {
+static int capture_logml_grad(spingp_ctx* h, double* logml, double* grad, uint32_t gmask) {
   drop_graph(h);
   if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
     h->cap = nullptr;
@@ -704,7 +724,7 @@ static int capture_logml_grad(spingp_ctx* h, double* logml, double* grad) {
     h->stream = user;
     return SPINGP_E_HIP;
   }
-  const int rc = run_logml_grad(h, logml, grad, false);
+  const int rc = run_logml_grad(h, logml, grad, false, gmask);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(h->cap, &g);
   h->stream = user;
@@ -720,25 +740,32 @@ static int capture_logml_grad(spingp_ctx* h, double* logml, double* grad) {
   }
   h->g_logml = logml;
   h->g_grad = grad;
+  h->g_mask = gmask;
   return SPINGP_OK;
 }
 
-extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad) {
+extern "C" int spingp_logml_grad(spingp_handle h, double* logml, double* grad, const uint8_t* mask) {
   if (!h || !logml || !grad) return SPINGP_E_INVALID;
   if (!h->assembled) return SPINGP_E_ORDER;
+  uint32_t gmask = ~0u;
+  if (mask) {
+    gmask = 0u;
+    for (int k = 0; k < h->n_hyper; ++k)
+      if (mask[k]) gmask |= 1u << k;
+  }
   // the forward pass always runs: hyperparameters live in device memory and may have changed
   h->factored = false;
   int rc;
   if (h->use_graph) {
-    if (!h->gexec || h->g_logml != logml || h->g_grad != grad) {
-      rc = capture_logml_grad(h, logml, grad);
+    if (!h->gexec || h->g_logml != logml || h->g_grad != grad || h->g_mask != gmask) {
+      rc = capture_logml_grad(h, logml, grad, gmask);
       if (rc) return rc;
     }
     prof_begin(h);
     rc = hip_ok(hipGraphLaunch(h->gexec, h->stream));
     prof_end(h, spg::kKidGraph);
   } else {
-    rc = run_logml_grad(h, logml, grad, true);
+    rc = run_logml_grad(h, logml, grad, true, gmask);
   }
   h->factored = rc == SPINGP_OK;
   return rc;
@@ -767,11 +794,6 @@ int scratch_address(void** out) {
   }
   *out = g_scratch_ptr[dev];
   return SPINGP_OK;
-}
-
-__global__ void k_zero_u32(unsigned int* __restrict__ p, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0u;
 }
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
@@ -842,9 +864,10 @@ extern "C" int spingp_logml_grad_noalloc(const spingp_term* terms, int32_t n_ter
   o.ld = n_points;
   o.part = c.part;
   o.part_ld = c.part_ld;
+  o.status = c.key;
   if (T->bwd(c, spg::kWantGrad, o) != hipSuccess) return SPINGP_E_HIP;
   hipLaunchKernelGGL(spg::k_grad_finish, dim3(1), dim3(256), 0, c.stream, c.part, c.part_ld, G, c.scal, logml,
-                     grad);
+                     grad, (const unsigned long long*)c.key, ~0u);
   return hip_ok(hipGetLastError());
 }
 
@@ -897,7 +920,7 @@ extern "C" int spingp_predict(spingp_handle h, const double* t_star, const int64
     }
     if (rc) return rc;
     hipLaunchKernelGGL(spg::k_gather, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, h->t, n, t_star, m,
-                       fm, fv, f_mean, f_var);
+                       fm, fv, f_mean, f_var, (const unsigned long long*)h->key);
     return hip_ok(hipGetLastError());
   }
   // several series: merge series by series, map the merged chunks, run the batched path on the
@@ -905,7 +928,7 @@ extern "C" int spingp_predict(spingp_handle h, const double* t_star, const int64
   const spg::TileOps* T = ops(h);
   const int64_t nv = m > S ? m : S;
   hipLaunchKernelGGL(spg::k_validate_star_batch, dim3((unsigned)ceil_div(nv, kT)), dim3(kT), 0, h->stream, t_star,
-                     offsets_star, S, m, h->key);
+                     offsets_star, S, m, h->key, h->bad);
   hipLaunchKernelGGL(spg::k_merged_offsets, dim3((unsigned)ceil_div((int64_t)S + 1, kT)), dim3(kT), 0, h->stream,
                      h->offsets, offsets_star, S, h->pred_off);
   hipLaunchKernelGGL(spg::k_merge_batch, dim3((unsigned)ceil_div(nm, kT)), dim3(kT), 0, h->stream, h->t, h->y,
@@ -926,7 +949,8 @@ extern "C" int spingp_predict(spingp_handle h, const double* t_star, const int64
   }
   if (rc) return rc;
   hipLaunchKernelGGL(spg::k_gather_batch, dim3((unsigned)ceil_div(m, kT)), dim3(kT), 0, h->stream, h->t,
-                     h->offsets, S, n, t_star, offsets_star, m, fm, fv, f_mean, f_var);
+                     h->offsets, S, n, t_star, offsets_star, m, fm, fv, f_mean, f_var,
+                     (const unsigned long long*)h->key, (const uint32_t*)h->bad);
   rc = hip_ok(hipGetLastError());
   if (rc) return rc;
   // the bound batch's chunk map again; the status word keeps what the checks above found

@@ -495,6 +495,65 @@ SPG_DEV void elem_combine(const Elem<B>& E1, const Elem<B>& E2, Elem<B>& R) {
   R.cl = E1.cl + E2.cl - 0.5 * ld;
 }
 
+// The two halves of E1 (x) E2, for two lanes on different wavefronts (a tree level then takes
+// about half the issue time of one lane doing the whole join).  Both form Gam = (I + Q1 J2)^-1;
+// the forward half sets the new edge (A, b, Q) of R, the backward half the information pushed
+// back to the left node (J, eta) and the normaliser (cf, cl).  Same arithmetic, in the same
+// order, as elem_combine.
+template <int B>
+SPG_DEV void elem_combine_fwd(const Elem<B>& E1, const Elem<B>& E2, Elem<B>& R) {
+  double M[B][B], G[B][B];
+  mm<B>(E1.Q, E2.J, M);
+  SPG_UNROLL for (int i = 0; i < B; ++i) M[i][i] += 1.0;
+  (void)inv_logdet<B>(M, G);
+  double Pp[B][B], GA[B][B];
+  mm<B>(G, E1.Q, Pp);
+  symmetrize<B>(Pp);
+  mm<B>(G, E1.A, GA);
+  double Gb[B], Ppe[B], g[B];
+  mv<B>(G, E1.b, Gb);
+  mv<B>(Pp, E2.eta, Ppe);
+  SPG_UNROLL for (int i = 0; i < B; ++i) g[i] = Gb[i] + Ppe[i];
+  double T[B][B], Ag[B];
+  mm<B>(E2.A, GA, R.A);
+  mv<B>(E2.A, g, Ag);
+  mm<B>(E2.A, Pp, T);
+  mmt_sym<B>(T, E2.A, R.Q);
+  SPG_UNROLL for (int i = 0; i < B; ++i) {
+    R.b[i] = Ag[i] + E2.b[i];
+    SPG_UNROLL for (int j = 0; j < B; ++j) R.Q[i][j] += E2.Q[i][j];
+  }
+}
+template <int B>
+SPG_DEV void elem_combine_bwd(const Elem<B>& E1, const Elem<B>& E2, Elem<B>& R) {
+  double M[B][B], G[B][B];
+  mm<B>(E1.Q, E2.J, M);
+  SPG_UNROLL for (int i = 0; i < B; ++i) M[i][i] += 1.0;
+  const double ld = inv_logdet<B>(M, G);
+  double Pp[B][B], W[B][B];
+  mm<B>(G, E1.Q, Pp);
+  symmetrize<B>(Pp);
+  mm<B>(E2.J, G, W);
+  symmetrize<B>(W);
+  double Gb[B], Ppe[B], Gte[B], Wb[B], r[B];
+  mv<B>(G, E1.b, Gb);
+  mv<B>(Pp, E2.eta, Ppe);
+  mtv<B>(G, E2.eta, Gte);
+  mv<B>(W, E1.b, Wb);
+  SPG_UNROLL for (int i = 0; i < B; ++i) r[i] = Gte[i] - Wb[i];
+  const double cf = -0.5 * dot<B>(E1.b, Wb) + dot<B>(E2.eta, Gb) + 0.5 * dot<B>(E2.eta, Ppe);
+  double WA[B][B], AWA[B][B], Ar[B];
+  mm<B>(W, E1.A, WA);
+  mtm_sym<B>(E1.A, WA, AWA);
+  mtv<B>(E1.A, r, Ar);
+  SPG_UNROLL for (int i = 0; i < B; ++i) {
+    R.eta[i] = E1.eta[i] + Ar[i];
+    SPG_UNROLL for (int j = 0; j < B; ++j) R.J[i][j] = E1.J[i][j] + AWA[i][j];
+  }
+  R.cf = E1.cf + E2.cf + cf;
+  R.cl = E1.cl + E2.cl - 0.5 * ld;
+}
+
 // Prefix combine: (m, P) = predicted state N(z; m, P) at the left node of E, pushed through E.
 // Returns the increment of the log normaliser (fit and log-det parts).
 template <int B>
@@ -583,6 +642,25 @@ SPG_DEV void elem_store(double* base, int64_t ld, int64_t i, const Elem<B>& E) {
   }
   base[L::kcf * ld + i] = E.cf;
   base[L::kcl * ld + i] = E.cl;
+}
+
+// The fields each half of a split join produces: forward (A, b, Q), backward (J, eta, cf, cl).
+template <int B>
+SPG_DEV void elem_store_half(double* base, int64_t ld, int64_t i, const Elem<B>& E, bool fwd) {
+  using L = ElemLayout<B>;
+  if (fwd) {
+    SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = 0; c < B; ++c)
+      base[(L::kA + r * B + c) * ld + i] = E.A[r][c];
+    SPG_UNROLL for (int r = 0; r < B; ++r) base[(L::kb + r) * ld + i] = E.b[r];
+    int s = 0;
+    SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) base[(L::kQ + s++) * ld + i] = E.Q[r][c];
+  } else {
+    SPG_UNROLL for (int r = 0; r < B; ++r) base[(L::keta + r) * ld + i] = E.eta[r];
+    int s = 0;
+    SPG_UNROLL for (int r = 0; r < B; ++r) SPG_UNROLL for (int c = r; c < B; ++c) base[(L::kJ + s++) * ld + i] = E.J[r][c];
+    base[L::kcf * ld + i] = E.cf;
+    base[L::kcl * ld + i] = E.cl;
+  }
 }
 
 template <int B>

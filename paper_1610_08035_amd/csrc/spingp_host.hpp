@@ -30,6 +30,7 @@ struct LaunchCtx {
   int64_t part_ld;
   int32_t* chunk_series;
   int64_t* chunk_first;
+  uint32_t* bad;                 // several series: per-series failed-check flags
   unsigned long long* key;
   // optional timing hook around every launch: mark(arg, kernel id, 0 = before, 1 = after)
   void (*mark)(void* arg, int kid, int end);
@@ -107,11 +108,13 @@ inline SeriesMap make_map(const LaunchCtx& c, int64_t slots) {
   sm.chunk_first = nullptr;
   sm.slots = 0;
   sm.n_series = c.n_series;
+  sm.bad = nullptr;
   if (c.batched) {
     sm.offsets = c.offsets;
     sm.chunk_series = c.chunk_series;
     sm.chunk_first = c.chunk_first;
     sm.slots = slots;
+    sm.bad = c.bad;
   }
   return sm;
 }
@@ -141,6 +144,8 @@ struct WideCtx {
   int64_t off[kMaxLevels];
   int node_grid;      // work-groups of the node step (rows of part)
   int model;          // kModel* below
+  const unsigned long long* status;   // the status word (data errors poison the outputs)
+  uint32_t gmask;     // gradient components written by finish (bit k), the others are 0
   void (*mark)(void* arg, int kid, int end);
   void* mark_arg;
 };

@@ -39,7 +39,18 @@ struct SeriesMap {
   const int64_t* chunk_first;   // [S + 1] first chunk of every series
   int64_t slots;                // entries of chunk_series (launched chunk slots)
   int32_t n_series;
+  uint32_t* bad;                // [S] nonzero for a series whose inputs failed the device checks
 };
+
+// Device-detected data errors poison the outputs they affect with NaN.  One series: any error in
+// the status word (minimum of (index << 4) | code over the offending points, all ones when none)
+// poisons everything; several series: the series flagged in bad, or all of them when the offsets
+// themselves are invalid (code 1 in the status word).
+constexpr double kPoison = __builtin_nan("");
+SPG_DEV bool status_poisons_all(const unsigned long long* status, bool batched) {
+  const unsigned long long st = *status;
+  return st != ~0ull && (!batched || (st & 15ull) == 1ull);
+}
 
 // Hyperparameter row of the series that owns node 0 (its prior is the root of the chain): the
 // series of chunk 0, which skips leading empty series.
@@ -61,7 +72,19 @@ struct Lane {
   int64_t s_end;        // one past its last node
   bool has_next;        // another series follows (boundary edge carries its prior)
   const double* hyper_next;
+  bool next_clean;      // that series passed the device checks
+  bool clean;           // this series passed the device checks (several series)
 };
+
+// A series that failed the device checks is run on neutral stand-in data (times 0, 1, 2, ...
+// from its first node, no observations, unit hyperparameters): its outputs are NaN anyway, and
+// its non-finite values would otherwise reach the next series through the boundary edge
+// (0 * NaN is NaN).
+template <int B>
+SPG_DEV SeriesPar neutral_par() {
+  const double one[3] = {1.0, 1.0, 1.0};
+  return load_par<B>(one);
+}
 
 template <int B, int R, bool BATCHED>
 SPG_DEV Lane<B> lane_of(int64_t chunk, int64_t n_pts, const double* __restrict__ hyper, const SeriesMap& sm) {
@@ -74,6 +97,8 @@ SPG_DEV Lane<B> lane_of(int64_t chunk, int64_t n_pts, const double* __restrict__
     ln.s_end = n_pts;
     ln.has_next = false;
     ln.hyper_next = hyper;
+    ln.next_clean = true;
+    ln.clean = true;
     ln.p = load_par<B>(hyper);
     return ln;
   }
@@ -86,6 +111,8 @@ SPG_DEV Lane<B> lane_of(int64_t chunk, int64_t n_pts, const double* __restrict__
     ln.s_end = 0;
     ln.has_next = false;
     ln.hyper_next = hyper;
+    ln.next_clean = true;
+    ln.clean = true;
     ln.p = load_par<B>(hyper);
     return ln;
   }
@@ -102,14 +129,17 @@ SPG_DEV Lane<B> lane_of(int64_t chunk, int64_t n_pts, const double* __restrict__
   // the next slot
   ln.has_next = false;
   ln.hyper_next = hyper;
+  ln.next_clean = true;
   if (ln.start + ln.len == ln.s_end && chunk + 1 < sm.slots) {
     const int32_t s2 = sm.chunk_series[chunk + 1];
     if (s2 >= 0) {
       ln.has_next = true;
       ln.hyper_next = hyper + 3 * (int64_t)s2;
+      ln.next_clean = sm.bad == nullptr || sm.bad[s2] == 0u;
     }
   }
-  ln.p = load_par<B>(hyper + 3 * (int64_t)s);
+  ln.clean = sm.bad == nullptr || sm.bad[s] == 0u;
+  ln.p = ln.clean ? load_par<B>(hyper + 3 * (int64_t)s) : neutral_par<B>();
   return ln;
 }
 
@@ -119,7 +149,7 @@ template <int B>
 SPG_DEV bool edge_at(const Lane<B>& ln, const double* __restrict__ t, int64_t n, double& dt, double& e,
                      double (&A)[B][B]) {
   if (n + 1 < ln.s_end) {
-    dt = t[n + 1] - t[n];
+    dt = ln.clean ? t[n + 1] - t[n] : 1.0;
     Matern<B>::transition(ln.p, dt, e, A);
     return true;
   }
@@ -143,8 +173,8 @@ SPG_DEV void load_chunk(const Lane<B>& ln, const double* __restrict__ t, const d
   SPG_UNROLL for (int k = 0; k <= R; ++k) {
     int64_t n = ln.start + k;
     if (n > n_pts - 1) n = n_pts - 1;
-    cd.t[k] = t[n];
-    if (k < R) cd.y[k] = y[n];
+    cd.t[k] = ln.clean ? t[n] : (double)(ln.start + k - ln.s_begin);
+    if (k < R) cd.y[k] = ln.clean ? y[n] : kPoison;
   }
 }
 // edge_at for node start + k from the loaded times
@@ -166,7 +196,7 @@ template <int B>
 SPG_DEV void end_edge_D(const Lane<B>& ln, const double (&P0)[B][B], double (&D)[B][B]) {
   if (ln.has_next) {
     double Pn[B][B];
-    Matern<B>::pinf(load_par<B>(ln.hyper_next), Pn);
+    Matern<B>::pinf(ln.next_clean ? load_par<B>(ln.hyper_next) : neutral_par<B>(), Pn);
     SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = Pn[i][j] - P0[i][j];
   } else {
     SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) D[i][j] = -P0[i][j];
@@ -206,8 +236,11 @@ SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const Chunk
     }
     E.eta[0] = o0 ? y0 * is2 : 0.0;
     E.cf = o0 ? -0.5 * y0 * y0 * is2 : 0.0;
-    E.cl = o0 ? -0.5 * (kLog2Pi + log(p.s2)) : 0.0;
   }
+  // log-determinant part: the product of the innovation variances as mantissa and exponent
+  // (one log for the chunk instead of one per node) and the number of observed nodes
+  double ps = cd.y[0] == cd.y[0] ? p.s2 : 1.0;
+  int pe = 0, nobs = cd.y[0] == cd.y[0] ? 1 : 0;
   SPG_UNROLL for (int k = 1; k < R; ++k) {
     if (k < ln.len) {
       const double yn = cd.y[k];
@@ -233,7 +266,12 @@ SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const Chunk
         Dp[i][j] = Dp[j][i];
         E.J[i][j] = E.J[j][i];
       }
-      if (obs) E.cl += -0.5 * (kLog2Pi + log(s));
+      if (obs) {
+        int e2;
+        ps = frexp(ps * s, &e2);
+        pe += e2;
+        ++nobs;
+      }
       E.cf += -0.5 * v * vis;
       double dt, e, A[B][B];
       const bool ok = edge_k<B, R>(ln, cd, k, dt, e, A);
@@ -251,6 +289,7 @@ SPG_DEV void fold_chunk(const Lane<B>& ln, const double (&P0)[B][B], const Chunk
     }
   }
   SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) E.Q[i][j] = D[i][j] + P0[i][j];
+  E.cl = -0.5 * ((double)nobs * kLog2Pi + log(ps) + (double)pe * 0.69314718055994530942);
 }
 
 // ---------------------------------------------------------------------------- LDS element pool
@@ -382,16 +421,26 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
   elem_store<B>(tree_elems, tree_ld, gbase + tid, E);
   lds_store<B, L>(pool, tid, E);
   lds_barrier();
+  // each join of a level is split over two lanes on different wavefronts: lane j of the first
+  // half of the work-group forms the new edge (A, b, Q), lane j of the second half the information
+  // and normaliser (J, eta, cf, cl) of join j; both read the operands, then (after a barrier,
+  // the forward half overwrites fields the backward half reads) write the result in place
+  const bool fwd = tid < L / 2;
+  const int jn = fwd ? tid : tid - L / 2;
   int off = L;   // slot offset of the level being produced
   SPG_UNROLL for (int stride = 1; stride < L; stride *= 2) {
-    const int i = tid * 2 * stride;
+    const int i = jn * 2 * stride;
+    Elem<B> E1, E2, Rr;
     if (i < L) {
-      Elem<B> E1, E2, Rr;
       lds_load<B, L>(pool, i, E1);
       lds_load<B, L>(pool, i + stride, E2);
-      elem_combine<B>(E1, E2, Rr);
-      lds_store<B, L>(pool, i, Rr);
-      elem_store<B>(tree_elems, tree_ld, gbase + off + tid, Rr);
+    }
+    lds_barrier();
+    if (i < L) {
+      if (fwd) elem_combine_fwd<B>(E1, E2, Rr);
+      else elem_combine_bwd<B>(E1, E2, Rr);
+      elem_store_half<B>(pool, L, i, Rr, fwd);
+      elem_store_half<B>(tree_elems, tree_ld, gbase + off + jn, Rr, fwd);
     }
     off += L / (2 * stride);
     lds_barrier();
@@ -406,12 +455,15 @@ __global__ __launch_bounds__(L) void k_fwd(const double* __restrict__ t, const d
 // ---------------------------------------------------------------------------- kernel: top bands
 // One 64-thread work-group per group of (up to) 32 leaves of band 0.  Each reduces its group in
 // LDS and writes every node; then the last work-group of each group of band-0 groups (atomic
-// ticket, no waiting) reduces band 1, and so on.  The work-group that completes the last band holds the
-// root and, for one series, evaluates the log marginal likelihood (the prior N(0, P0) pushed
-// through the whole chain).  Fences here only have to publish the few nodes this kernel writes.
+// ticket, no waiting) reduces band 1, and so on.  The work-group that completes the last band
+// holds the root and, for one series, evaluates the log marginal likelihood (the prior N(0, P0)
+// pushed through the whole chain).  Fences here only have to publish the few nodes this kernel
+// writes.  (Splitting each join over two wavefronts, as k_fwd does, measured slower here: a
+// band's work-group is small and the extra barrier per level costs more than it saves.)
+constexpr int kTopThreads = 64;
 template <int B, bool BATCHED>
-__global__ __launch_bounds__(64) void k_top_bands(const double* __restrict__ hyper, SeriesMap sm, TopTree top,
-                                                   double* __restrict__ scal) {
+__global__ __launch_bounds__(kTopThreads) void k_top_bands(const double* __restrict__ hyper, SeriesMap sm,
+                                                            TopTree top, double* __restrict__ scal) {
   constexpr int NF = ElemLayout<B>::kFields;
   __shared__ double pool[NF * 32];
   __shared__ unsigned int s_ticket;
@@ -492,6 +544,7 @@ struct BwdOut {
   double* part;     // one series: [3][G] work-group gradient partials; several series: [5][slots]
                     // per-chunk (sum v^2/s, sum log s, d/dlengthscale, d/dvariance, d/dnoise)
   int64_t part_ld;
+  const unsigned long long* status;   // the status word (outputs poisoned by data errors)
 };
 
 template <int B, int R, int L, int MODE, bool BATCHED>
@@ -518,6 +571,8 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
   const SeriesPar p = ln.p;
   double P0[B][B];
   Matern<B>::pinf(p, P0);
+  // outputs of a series whose inputs failed the device checks are NaN
+  const bool poison = status_poisons_all(out.status, BATCHED) || (BATCHED && ln.len > 0 && sm.bad[ln.series] != 0);
   const int64_t wg = blockIdx.x;
   const int64_t gbase = wg * (2 * L);
   const int nlev = top.n_levels;
@@ -535,7 +590,9 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
     double m_[B], P_[B][B], J_[B][B], e_[B];
     if (tid == 0) {
       double Pr[B][B];
-      Matern<B>::pinf(load_par<B>(root_hyper<BATCHED>(hyper, sm)), Pr);
+      const int32_t s0 = BATCHED ? sm.chunk_series[0] : 0;
+      const bool root_clean = !BATCHED || s0 < 0 || sm.bad[s0] == 0u;
+      Matern<B>::pinf(root_clean ? load_par<B>(root_hyper<BATCHED>(hyper, sm)) : neutral_par<B>(), Pr);
       SPG_UNROLL for (int i = 0; i < B; ++i) m_[i] = 0.0;
       mat_copy<B>(Pr, P_);
       for (int l = nlev - 1; l >= 0; --l) {
@@ -604,14 +661,21 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
   }
   Msg<B> g;
   lds_load_msg<B, NS>(pool, tid, g);
+  // the message pool is free from here on: it keeps the predicted states of the chunk's first
+  // KL nodes (the rest stay in registers), field f of node k of this lane at
+  // pool[(k NPS + f) L + tid]
+  constexpr int NPS = B + B * (B + 1) / 2;
+  constexpr int KL = R / 2 < 4 ? R / 2 : 4;
+  static_assert(KL * NPS * L <= MF * NS, "predicted states must fit in the message pool");
+  if (KL > 0) lds_barrier();
 
   // ---- chunk elimination (natural order) from the exact predicted state at its first node
   const int64_t start = ln.start;
   const int len = ln.len;
   ChunkData<R> cd;
   load_chunk<B, R>(ln, t, y, n_pts, cd);
-  double sm_[R][B];       // predicted means
-  double sD[R][B][B];     // predicted covariances minus P0
+  double sm_[R][B];                  // predicted means (nodes k >= KL)
+  double sD[R][B * (B + 1) / 2];     // predicted covariances minus P0, packed upper (k >= KL)
   double m[B], D[B][B];
   double fit_chunk = 0.0;  // sum over the chunk of v_n^2 / s_n
   double ldet_chunk = 0.0; // sum over the chunk of log s_n
@@ -622,9 +686,16 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
   SPG_UNROLL for (int k = 0; k < R; ++k) {
     if (k < len) {
       const int64_t n = start + k;
-      SPG_UNROLL for (int i = 0; i < B; ++i) {
-        sm_[k][i] = m[i];
-        SPG_UNROLL for (int j = 0; j < B; ++j) sD[k][i][j] = D[i][j];
+      if (k < KL) {
+        SPG_UNROLL for (int i = 0; i < B; ++i) pool[(k * NPS + i) * L + tid] = m[i];
+        int f = B;
+        SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j)
+          pool[(k * NPS + f++) * L + tid] = D[i][j];
+      } else {
+        SPG_UNROLL for (int i = 0; i < B; ++i) {
+          sm_[k][i] = m[i];
+          SPG_UNROLL for (int j = i; j < B; ++j) sD[k][i * B - i * (i - 1) / 2 + (j - i)] = D[i][j];
+        }
       }
       double u[B];
       SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = D[i][0] + P0[i][0];
@@ -691,13 +762,23 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
       if (k < len) {
         const int64_t n = start + k;
         double mk[B], Dk[B][B];
-        SPG_UNROLL for (int i = 0; i < B; ++i) {
-          mk[i] = sm_[k][i];
-          SPG_UNROLL for (int j = 0; j < B; ++j) Dk[i][j] = sD[k][i][j];
+        if (k < KL) {
+          SPG_UNROLL for (int i = 0; i < B; ++i) mk[i] = pool[(k * NPS + i) * L + tid];
+          int f = B;
+          SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j) {
+            Dk[i][j] = pool[(k * NPS + f++) * L + tid];
+            Dk[j][i] = Dk[i][j];
+          }
+        } else {
+          SPG_UNROLL for (int i = 0; i < B; ++i) {
+            mk[i] = sm_[k][i];
+            SPG_UNROLL for (int j = 0; j < B; ++j)
+              Dk[i][j] = sD[k][i <= j ? i * B - i * (i - 1) / 2 + (j - i) : j * B - j * (j - 1) / 2 + (i - j)];
+          }
         }
         double u[B];
         SPG_UNROLL for (int i = 0; i < B; ++i) u[i] = Dk[i][0] + P0[i][0];
-        const double yk = y[n];
+        const double yk = ln.clean ? y[n] : kPoison;
         const bool obs = yk == yk;
         const double s = u[0] + p.s2, is = obs ? 1.0 / s : 0.0;
         // t and y re-read here (cache-resident) rather than kept live across the sweep: the
@@ -748,18 +829,19 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
           SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) Ppl[i][j] = Dp[i][j] + P0[i][j];
           mv<B>(Ppl, mbp, Pl);
           SPG_UNROLL for (int i = 0; i < B; ++i) mu[i] = mp[i] + Pl[i];
-          if (out.f_mean) out.f_mean[n] = mu[0];
-          if (out.z_mean) SPG_UNROLL for (int i = 0; i < B; ++i) out.z_mean[(int64_t)i * out.ld + n] = mu[i];
+          if (out.f_mean) out.f_mean[n] = poison ? kPoison : mu[0];
+          if (out.z_mean)
+            SPG_UNROLL for (int i = 0; i < B; ++i) out.z_mean[(int64_t)i * out.ld + n] = poison ? kPoison : mu[i];
           if (kCov) {
             double X[B][B], S[B][B];
             mm<B>(Ppl, Lhp, X);
             mmt_sym<B>(X, Ppl, S);
             SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j) S[i][j] = Ppl[i][j] - S[i][j];
-            if (out.f_var) out.f_var[n] = S[0][0];
+            if (out.f_var) out.f_var[n] = poison ? kPoison : S[0][0];
             if (out.S_diag) {
               int s_ = 0;
               SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = i; j < B; ++j)
-                out.S_diag[(int64_t)(s_++) * out.ld + n] = S[i][j];
+                out.S_diag[(int64_t)(s_++) * out.ld + n] = poison ? kPoison : S[i][j];
             }
             if (kSub && edge_ok && out.S_sub) {
               double Y[B][B], AP[B][B], Ssub[B][B];
@@ -769,7 +851,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
               mm<B>(A, Ppl, AP);
               mm<B>(Y, AP, Ssub);
               SPG_UNROLL for (int i = 0; i < B; ++i) SPG_UNROLL for (int j = 0; j < B; ++j)
-                out.S_sub[(int64_t)(i * B + j) * out.ld + n] = Ssub[i][j];
+                out.S_sub[(int64_t)(i * B + j) * out.ld + n] = poison ? kPoison : Ssub[i][j];
             }
           }
         }
@@ -842,7 +924,7 @@ __global__ __launch_bounds__(L, 2) void k_bwd(const double* __restrict__ t, cons
     // ---- one series: fixed-order work-group reduction of the gradient partials (reuses the
     //      pool); k_grad_finish sums the work-group partials in a fixed order.  No cross-work-
     //      group signalling here: an agent-scope fence per work-group (an L2 write-back on this
-    //      GPU) costs more than the separate launch.
+    //      GPU) measured 2 to 14 us slower than the separate launch.
     lds_barrier();
     SPG_UNROLL for (int c = 0; c < 3; ++c) pool[c * L + tid] = gr[c];
     lds_barrier();
@@ -942,7 +1024,10 @@ __global__ void k_validate_chunks(const double* __restrict__ t, const double* __
   if (c < sm.n_series) {
     for (int k = 0; k < 3; ++k) {
       const double h = hyper[3 * c + k];
-      if (!(isfinite(h) && h > 0.0)) atomicMin(key, 5ull);              // SPINGP_E_HYPER
+      if (!(isfinite(h) && h > 0.0)) {
+        atomicMin(key, 5ull);                                              // SPINGP_E_HYPER
+        sm.bad[c] = 1u;
+      }
     }
   }
   if (c >= sm.slots) return;
@@ -954,6 +1039,7 @@ __global__ void k_validate_chunks(const double* __restrict__ t, const double* __
     else if (n + 1 < ln.s_end && t[n + 1] < t[n]) code = 3;               // SPINGP_E_UNSORTED
     if (code) {
       atomicMin(key, ((unsigned long long)(n + 1) << 4) | code);
+      sm.bad[ln.series] = 1u;
       return;
     }
   }

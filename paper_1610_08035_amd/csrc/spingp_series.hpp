@@ -8,10 +8,12 @@
 namespace spg {
 
 // One series: sum of the G work-group gradient partials in a fixed order (lane-strided, then a
-// fixed tree), and the log likelihood from the root of the reduction.
+// fixed tree), and the log likelihood from the root of the reduction.  Gradient components
+// outside gmask are 0; after a data error (status word set) both outputs are NaN.
 __global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ part, int64_t part_ld, int64_t G,
                                                       const double* __restrict__ scal, double* __restrict__ logml,
-                                                      double* __restrict__ grad) {
+                                                      double* __restrict__ grad,
+                                                      const unsigned long long* __restrict__ status, uint32_t gmask) {
   __shared__ double red[3][256];
   const int tid = threadIdx.x;
   double acc[3] = {0.0, 0.0, 0.0};
@@ -25,19 +27,22 @@ __global__ __launch_bounds__(256) void k_grad_finish(const double* __restrict__ 
     __syncthreads();
   }
   if (tid == 0) {
-    if (grad) SPG_UNROLL for (int c = 0; c < 3; ++c) grad[c] = red[c][0];
-    if (logml) logml[0] = scal[0];
+    const bool poison = *status != ~0ull;
+    if (grad) SPG_UNROLL for (int c = 0; c < 3; ++c) grad[c] = poison ? kPoison : (((gmask >> c) & 1u) ? red[c][0] : 0.0);
+    if (logml) logml[0] = poison ? kPoison : scal[0];
   }
 }
 
 // Fixed-order per-series sum of the per-chunk partials: one 64-lane work-group per series; lane i
 // adds chunks first + i, first + i + 64, ... in order, then a fixed tree over the lanes.  Writes
 // logml[s] (eq. ml2), and datafit[s] = y^T K_y^-1 y, logdet[s] = log det K_y, grad[s][0..2] where
-// not null.  An empty series gets logml 0 and a zero gradient.
+// not null.  An empty series gets logml 0 and a zero gradient.  Gradient components outside gmask
+// are 0; the outputs of a series whose inputs failed the device checks are NaN.
 __global__ __launch_bounds__(64) void k_series_reduce(SeriesMap sm, const double* __restrict__ part,
                                                        int64_t part_ld, int64_t n_pts, double* __restrict__ logml,
                                                        double* __restrict__ datafit, double* __restrict__ logdet,
-                                                       double* __restrict__ grad) {
+                                                       double* __restrict__ grad,
+                                                       const unsigned long long* __restrict__ status, uint32_t gmask) {
   __shared__ double red[5][64];
   const int tid = threadIdx.x;
   const int64_t s = blockIdx.x;
@@ -58,10 +63,12 @@ __global__ __launch_bounds__(64) void k_series_reduce(SeriesMap sm, const double
     const int64_t ob = sm.offsets[s], oe = sm.offsets[s + 1];
     const double ns = (oe > ob && ob >= 0 && oe <= n_pts) ? (double)(oe - ob) : 0.0;
     const double fit = red[0][0], ld = red[1][0];
-    if (logml) logml[s] = -0.5 * fit - 0.5 * ld - 0.5 * ns * kLog2Pi;
-    if (datafit) datafit[s] = fit;
-    if (logdet) logdet[s] = ld;
-    if (grad) for (int f = 0; f < 3; ++f) grad[s * 3 + f] = red[f + 2][0];
+    const bool bad = status_poisons_all(status, true) || sm.bad[s] != 0;
+    if (logml) logml[s] = bad ? kPoison : -0.5 * fit - 0.5 * ld - 0.5 * ns * kLog2Pi;
+    if (datafit) datafit[s] = bad ? kPoison : fit;
+    if (logdet) logdet[s] = bad ? kPoison : ld;
+    if (grad)
+      for (int f = 0; f < 3; ++f) grad[s * 3 + f] = bad ? kPoison : (((gmask >> f) & 1u) ? red[f + 2][0] : 0.0);
   }
 }
 
@@ -232,7 +239,7 @@ __global__ void k_merge_batch(const double* __restrict__ t, const double* __rest
 // Prediction times of several series: finite, non-decreasing inside each series (they may
 // restart between series); offsets_star[0] = 0, non-decreasing, offsets_star[S] = m.
 __global__ void k_validate_star_batch(const double* __restrict__ ts, const int64_t* __restrict__ os, int32_t S,
-                                      int64_t m, unsigned long long* __restrict__ key) {
+                                      int64_t m, unsigned long long* __restrict__ key, uint32_t* __restrict__ bad) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j == 0 && (os[0] != 0 || os[S] != m)) atomicMin(key, 1ull);           // SPINGP_E_INVALID
   if (j < S && os[j + 1] < os[j]) atomicMin(key, 1ull);
@@ -241,28 +248,35 @@ __global__ void k_validate_star_batch(const double* __restrict__ ts, const int64
   unsigned long long code = 0;
   if (!isfinite(ts[j])) code = 4;                                          // SPINGP_E_NONFINITE
   else if (j + 1 < m && j + 1 < os[s + 1] && ts[j + 1] < ts[j]) code = 3;   // SPINGP_E_UNSORTED
-  if (code) atomicMin(key, ((unsigned long long)(j + 1) << 4) | code);
+  if (code) {
+    atomicMin(key, ((unsigned long long)(j + 1) << 4) | code);
+    bad[s] = 1u;
+  }
 }
 
 __global__ void k_gather_batch(const double* __restrict__ t, const int64_t* __restrict__ off, int32_t S, int64_t n,
                                const double* __restrict__ ts, const int64_t* __restrict__ os, int64_t m,
                                const double* __restrict__ fm, const double* __restrict__ fv,
-                               double* __restrict__ f_mean, double* __restrict__ f_var) {
+                               double* __restrict__ f_mean, double* __restrict__ f_var,
+                               const unsigned long long* __restrict__ status, const uint32_t* __restrict__ bad) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const int64_t pos = merged_pos_star(t, off, ts, os, S, n, m, j);
-  if (f_mean) f_mean[j] = fm[pos];
-  if (f_var) f_var[j] = fv[pos];
+  // a failed check of the bound inputs or of t* poisons the series (all of them for bad offsets)
+  const bool poison = status_poisons_all(status, true) || bad[series_of(os, S, j)] != 0;
+  if (f_mean) f_mean[j] = poison ? kPoison : fm[pos];
+  if (f_var) f_var[j] = poison ? kPoison : fv[pos];
 }
 
 __global__ void k_gather(const double* __restrict__ t, int64_t n, const double* __restrict__ ts, int64_t m,
                          const double* __restrict__ fm, const double* __restrict__ fv, double* __restrict__ f_mean,
-                         double* __restrict__ f_var) {
+                         double* __restrict__ f_var, const unsigned long long* __restrict__ status) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   const int64_t pos = j + count_not_greater(t, n, ts[j]);
-  if (f_mean) f_mean[j] = fm[pos];
-  if (f_var) f_var[j] = fv[pos];
+  const bool poison = *status != ~0ull;
+  if (f_mean) f_mean[j] = poison ? kPoison : fm[pos];
+  if (f_var) f_var[j] = poison ? kPoison : fv[pos];
 }
 
 }  // namespace spg

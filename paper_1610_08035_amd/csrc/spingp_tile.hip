@@ -48,8 +48,8 @@ hipError_t factor_b(const LaunchCtx& c) {
                      c.hyper, sm, c.lane, c.lane_ld, top, c.key);
   mark(c, kKidFwd, 1);
   mark(c, kKidTop, 0);
-  hipLaunchKernelGGL((k_top_bands<B, BATCHED>), dim3((unsigned)((G + 31) / 32)), dim3(64), 0, c.stream, c.hyper, sm,
-                     top, c.scal);
+  hipLaunchKernelGGL((k_top_bands<B, BATCHED>), dim3((unsigned)((G + 31) / 32)), dim3(kTopThreads), 0, c.stream,
+                     c.hyper, sm, top, c.scal);
   mark(c, kKidTop, 1);
   return hipGetLastError();
 }

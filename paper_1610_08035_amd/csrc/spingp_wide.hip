@@ -147,6 +147,7 @@ hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, doubl
   o.S_sub = S_sub;
   o.ld = c.n_points;
   o.part = c.part;
+  o.status = c.status;
   mark(c, kKidBwd, 0);
   switch (mode) {
     case kWantGrad: launch_node<kWantGrad>(c, o); break;
@@ -166,7 +167,8 @@ hipError_t finish_m(const WideCtx& c, double* logml, double* grad) {
   double* tot = c.part + (int64_t)c.node_grid * Model::kPart;
   hipLaunchKernelGGL(k_wide_sum<Model>, dim3((unsigned)Model::kPart), dim3(kW), 0, c.stream, c.part, c.node_grid,
                      tot);
-  hipLaunchKernelGGL(k_wide_final<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, tot, c.scal, logml, grad);
+  hipLaunchKernelGGL(k_wide_final<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, tot, c.scal, logml, grad, c.status,
+                     c.gmask);
   mark(c, kKidReduce, 1);
   return hipGetLastError();
 }

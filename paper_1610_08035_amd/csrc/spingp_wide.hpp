@@ -919,6 +919,7 @@ struct WideOut {
   double* S_sub;
   int64_t ld;
   double* part;      // [gridDim.x][kPart] per-work-group gradient partials
+  const unsigned long long* status;   // the status word: a data error poisons the outputs (NaN)
 };
 
 // Node step (see the file comment).  Gradient partials per work-group: P0'_bar (B*B),
@@ -946,6 +947,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
   tsync();
   const double* P0 = c + M::kP0;
   const double s2 = c[M::kS2];
+  const bool poison = *out.status != ~0ull;
   static_assert(M::kNS <= kW, "one lane per support entry of the transition derivatives");
   constexpr int kRows = (BB + kW - 1) / kW;
   double acc_p0[kRows], acc_a[M::kNA], acc_s2 = 0.0;
@@ -1061,12 +1063,12 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
       for (int k = 0; k < B; ++k) q = fma(X1[k * B], fcol[k], q);
       S00 = Pp[0] - q;
     }
-    if (out.f_mean && tid == 0) out.f_mean[n] = mu[0];
-    if (out.f_var && tid == 0) out.f_var[n] = S00;
+    if (out.f_mean && tid == 0) out.f_mean[n] = poison ? kPoison : mu[0];
+    if (out.f_var && tid == 0) out.f_var[n] = poison ? kPoison : S00;
     if (out.z_mean && tid < B) {
       double z = mu[tid];
       if (tid == 0) for (int k = 1; k < B; ++k) z = fma(M::Ti_at(0, k), mu[k], z);
-      out.z_mean[tid * out.ld + n] = z * M::out_scale(c, tid);
+      out.z_mean[tid * out.ld + n] = poison ? kPoison : z * M::out_scale(c, tid);
     }
     if (out.S_diag || (kSub && out.S_sub && edge)) {
       // back to the original basis: S_o = T^-1 S' T^-T, S_sub_o = T^-1 S_sub' T^-T
@@ -1084,7 +1086,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
           double sacc = 0.0;
           for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], M::Ti_at(j, k), sacc);
           const int pk = i * B - i * (i - 1) / 2 + (j - i);     // packed upper, row-major
-          out.S_diag[(int64_t)pk * out.ld + n] = sacc * (M::out_scale(c, i) * M::out_scale(c, j));
+          out.S_diag[(int64_t)pk * out.ld + n] = poison ? kPoison : sacc * (M::out_scale(c, i) * M::out_scale(c, j));
         }
         tsync();
       }
@@ -1105,7 +1107,7 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
           const int i = e / B, j = e - i * B;
           double sacc = 0.0;
           for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], M::Ti_at(j, k), sacc);
-          out.S_sub[(int64_t)e * out.ld + n] = sacc * (M::out_scale(c, i) * M::out_scale(c, j));
+          out.S_sub[(int64_t)e * out.ld + n] = poison ? kPoison : sacc * (M::out_scale(c, i) * M::out_scale(c, j));
         }
         tsync();
       }
@@ -1145,7 +1147,10 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
       }
       if (n == 0) {
         // the first state is drawn from N(0, P0'): P0_bar += Lam_0, the seed of the prior
-        // against all the information on node 0 (its own and the suffix pulled back)
+        // against all the information on node 0 (its own and the suffix pulled back).  The
+        // suffix step's scratch shares its block with P+, P', A P+ and X3: the barrier orders
+        // their last reads above before its first writes.
+        tsync();
         t_suffix<B>(E, Js, es, X2, mn, tmp);
         t_mm<B>(P0, X2, Mx);
         t_add_eye<B>(Mx);
@@ -1210,7 +1215,8 @@ __global__ __launch_bounds__(kW) void k_wide_sum(const double* __restrict__ part
 template <class M>
 __global__ __launch_bounds__(kW) void k_wide_final(const double* __restrict__ cst, const double* __restrict__ totg,
                                                    const double* __restrict__ scal, double* __restrict__ logml,
-                                                   double* __restrict__ grad) {
+                                                   double* __restrict__ grad,
+                                                   const unsigned long long* __restrict__ status, uint32_t gmask) {
   constexpr int B = M::B, BB = B * B;
   constexpr int kPart = M::kPart;
   __shared__ double c[M::kConst], tot[kPart], X[BB], Pb[BB];
@@ -1234,8 +1240,12 @@ __global__ __launch_bounds__(kW) void k_wide_final(const double* __restrict__ cs
   }
   tsync();
   if (tid == 0) {
-    M::final_grad(c, tot, Pb, grad);
-    if (logml) logml[0] = scal[0];
+    double g[M::NH];
+    M::final_grad(c, tot, Pb, g);
+    // gradient components outside gmask are 0; a data error poisons everything (NaN)
+    const bool poison = *status != ~0ull;
+    for (int k = 0; k < M::NH; ++k) grad[k] = poison ? kPoison : (((gmask >> k) & 1u) ? g[k] : 0.0);
+    if (logml) logml[0] = poison ? kPoison : scal[0];
   }
 }
 

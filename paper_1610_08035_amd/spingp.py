@@ -58,7 +58,7 @@ def load_library():
     lib.spingp_logml.argtypes = [vp, vp, vp, vp]
     lib.spingp_solve.argtypes = [vp, vp, vp]
     lib.spingp_selinv.argtypes = [vp, vp, vp, vp]
-    lib.spingp_logml_grad.argtypes = [vp, vp, vp]
+    lib.spingp_logml_grad.argtypes = [vp, vp, vp, vp]
     lib.spingp_status.argtypes = [vp, ctypes.POINTER(i64)]
     lib.spingp_profile.argtypes = [vp, ctypes.c_int]
     lib.spingp_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
@@ -158,8 +158,13 @@ def spingp_selinv(h, f_var=None, S_diag=None, S_sub=None):
            "spingp_selinv")
 
 
-def spingp_logml_grad(h, logml, grad):
-    _check(load_library().spingp_logml_grad(h, _dev(logml, "logml"), _dev(grad, "grad")), "spingp_logml_grad")
+def spingp_logml_grad(h, logml, grad, mask=None):
+    """mask: None (every gradient component) or a sequence of n_hyper truth values (host); the
+    components masked off are written as 0."""
+    m = None
+    if mask is not None:
+        m = (ctypes.c_uint8 * len(mask))(*[1 if v else 0 for v in mask])
+    _check(load_library().spingp_logml_grad(h, _dev(logml, "logml"), _dev(grad, "grad"), m), "spingp_logml_grad")
 
 
 def spingp_logml_grad_noalloc(terms, t, y, hyper, logml, grad, stream=None):
@@ -304,11 +309,11 @@ class Handle:
         spingp_selinv(self._h, v, sd, ss)
         return v, sd, ss
 
-    def logml_grad(self):
+    def logml_grad(self, mask=None):
         dev = self._keep[0].device
         ll = torch.empty(self.n_series, dtype=torch.float64, device=dev)
         g = torch.empty(self.n_series, self.n_hyper, dtype=torch.float64, device=dev)
-        spingp_logml_grad(self._h, ll, g)
+        spingp_logml_grad(self._h, ll, g, mask)
         return ll, g
 
     def status(self):

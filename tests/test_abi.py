@@ -44,7 +44,7 @@ def test_host_side_errors_without_gpu(lib):
     h = ctypes.c_void_p()
     assert lib.spingp_create(ctypes.byref(h), None, 1, 10, 1, None) == 1
     assert lib.spingp_factor(None) == 1
-    assert lib.spingp_logml_grad(None, None, None) == 1
+    assert lib.spingp_logml_grad(None, None, None, None) == 1
     assert lib.spingp_state_dim(None) == -1
 
 
