@@ -29,6 +29,9 @@ FLOPS_PER_POINT = {
 }
 PEAK_FP64_TFLOPS = 78.6    # MI355X FP64 vector peak (256 CU x 2.4 GHz x 128 flop/clk)
 PEAK_HBM_GBS = 8000.0
+MACHINE_BALANCE = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)   # flop per HBM byte, 9.8
+# Algorithmic HBM bytes per point of the two per-point kernels: t and y read once each.
+ALG_BYTES_PER_POINT = {"fwd_fold_tree": 16.0, "bwd_elim_adjoint": 16.0}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes on
 # this workload, per tile shape (R, L), scaled by a 256 MiB copy (FETCH x 2.0, WRITE x 1.0);
@@ -52,6 +55,120 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
+def host_cpu():
+    """CPU model and thread counts of the host this runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_config1(reps=5):
+    """Config 1 on the host (Matern-3/2, N = 1000; posterior mean, variances, logML): median of
+    `reps` runs of the C sequential elimination (one thread), the Python Kalman filter + RTS
+    smoother (one thread) and, as context, the dense GP (numpy/LAPACK, the BLAS's threads)."""
+    from oracle import dense, kalman, native
+    from oracle.ssm import model_for
+    from workloads import make_config
+    w = make_config(1)
+    t, y, hyp = w.series(0)
+    m = model_for(w.terms, hyp)
+    out = {}
+    for name, fn in (("c_elimination", lambda: native.btd_factored(w.terms, hyp, t, y, want_blocks=False)),
+                     ("python_kalman_rts", lambda: kalman.kf_rts(m, t, y)),
+                     ("dense_gp", lambda: dense.gp_dense(m, t, y, want_grad=False))):
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            times.append(time.perf_counter() - t0)
+        out[name] = {"seconds": float(np.median(times)), "points_per_s": t.shape[0] / float(np.median(times))}
+    out["c_elimination"]["cores"] = 1
+    out["python_kalman_rts"]["cores"] = 1
+    out["dense_gp"]["cores"] = "BLAS threads"
+    return {"workload": "matern32_n1000_uniform100_mean_var_logml", "n_points": int(t.shape[0]), "reps": reps,
+            **out}
+
+
+def _cpu_series_grad(args):
+    """logML + gradient of a range of series of workload 4 by the C oracle (one process)."""
+    from oracle import native
+    from workloads import make_config
+    lo, hi = args
+    w = make_config(4)
+    for i in range(lo, hi):
+        t, y, hyp = w.series(i)
+        native.tangent_grad(w.terms, hyp, t, y)
+    return hi - lo
+
+
+def cpu_table():
+    """The CPU oracle on every workload, on this host: C sequential elimination (one thread) for
+    the forward outputs, C tangent-linear logML + gradient (one thread) for the gradient
+    workloads, and for the 4096-series batch also all usable cores (series spread over worker
+    processes).  Median of 3 runs where a run takes under 5 s, else one run."""
+    import concurrent.futures
+    from oracle import native
+    from workloads import make_config
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        fn()
+        el = time.perf_counter() - t0
+        if el < 5.0:
+            runs = [el]
+            for _ in range(2):
+                t0 = time.perf_counter()
+                fn()
+                runs.append(time.perf_counter() - t0)
+            el = float(np.median(runs))
+        return el
+
+    rows = {"host": host_cpu(), "config1": cpu_config1()}
+    w = make_config(2)
+    t, y, hyp = w.series(0)
+    el = timed(lambda: native.btd_factored(w.terms, hyp, t, y, want_blocks=False))
+    rows["config2_forward"] = {"what": "factor, logML, mean, variance (C elimination)", "cores": 1,
+                               "n_points": int(t.shape[0]), "seconds": el, "points_per_s": t.shape[0] / el}
+    el = timed(lambda: native.tangent_grad(w.terms, hyp, t, y))
+    rows["headline_logml_grad"] = {"what": "logML + 3-parameter gradient (C tangent-linear)", "cores": 1,
+                                   "n_points": int(t.shape[0]), "seconds": el, "points_per_s": t.shape[0] / el}
+    w3 = make_config(3)
+    t3, y3, h3 = w3.series(0)
+    el = timed(lambda: native.tangent_grad(w3.terms, h3, t3, y3))
+    rows["config3_sum_kernel"] = {"what": "b = 10 logML + 6-parameter gradient (C tangent-linear)", "cores": 1,
+                                  "n_points": int(t3.shape[0]), "seconds": el, "points_per_s": t3.shape[0] / el}
+    w4 = make_config(4)
+    el1 = timed(lambda: _cpu_series_grad((0, w4.n_series)))
+    cores = host_cpu()["usable_cpus"] or 1
+    step = max(1, -(-w4.n_series // (4 * cores)))
+    chunks = [(i, min(i + step, w4.n_series)) for i in range(0, w4.n_series, step)]
+    with concurrent.futures.ProcessPoolExecutor(cores) as ex:
+        list(ex.map(_cpu_series_grad, chunks[:cores]))              # start the workers
+        t0 = time.perf_counter()
+        list(ex.map(_cpu_series_grad, chunks))
+        eln = time.perf_counter() - t0
+    rows["config4_batched"] = {"what": "4096 series, logML + gradient each (C tangent-linear)",
+                               "n_points": int(w4.n_points), "one_core": {"seconds": el1, "points_per_s": w4.n_points / el1},
+                               "all_cores": {"cores": cores, "seconds": eln, "points_per_s": w4.n_points / eln}}
+    w5 = make_config(5)
+    t5, y5, h5 = w5.series(0)
+    el = timed(lambda: native.tangent_grad(w5.terms, h5, t5, y5))
+    rows["config5_large"] = {"what": "N = 2^24 logML + gradient (C tangent-linear)", "cores": 1,
+                             "n_points": int(t5.shape[0]), "seconds": el, "points_per_s": t5.shape[0] / el}
+    return rows
+
+
 def cpu_baseline(w, budget_s=10.0):
     """The C oracle (sequential elimination + tangent-linear gradient), timed on the host.
 
@@ -68,7 +185,8 @@ def cpu_baseline(w, budget_s=10.0):
         reps += 1
     return {"value": pts / total, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": f"all {t.shape[0]} points x {reps} repetitions ({total:.1f} s): logML + 3-parameter "
-                      f"gradient by the single-threaded C sequential elimination with tangent-linear derivatives"}
+                      f"gradient by the single-threaded C sequential elimination with tangent-linear derivatives",
+            "host": host_cpu()}
 
 
 def batched_report(spg, steps, warmup):
@@ -101,6 +219,19 @@ def batched_report(spg, steps, warmup):
     torch.cuda.synchronize()
     el_b = (time.perf_counter() - t0) / steps
     R, L = spg.spingp_tile_shape(h.tile)
+    # the same steps as replays of the captured launch sequence (same tile, same stream)
+    hg = spg.Handle(w.terms, n, S, stream=side)
+    hg.tile = h.tile
+    hg.assemble(td, yd, hd, od, graph=True)
+    for _ in range(warmup):
+        spg.spingp_logml_grad(hg._h, ll, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        spg.spingp_logml_grad(hg._h, ll, g)
+    torch.cuda.synchronize()
+    el_g = (time.perf_counter() - t0) / steps
+    hg.close()
     h.close()
     # one handle and one call per series
     hs, outs = [], []
@@ -125,8 +256,63 @@ def batched_report(spg, steps, warmup):
         hh.close()
     return {"workload": w.name, "n_series": S, "n_points": n, "points_per_s": n / el_b, "ms_per_step": 1e3 * el_b,
             "tile": {"R": R, "L": L}, "launch": "eager, side stream", "steps": steps,
+            "graph_replay": {"ms_per_step": 1e3 * el_g, "points_per_s": n / el_g,
+                             "launch": "one HIP graph of the forward + backward launches, replayed"},
             "per_series_launch": {"points_per_s": n / el_s, "ms_per_step": 1e3 * el_s, "steps": ps_steps},
             "speedup": el_s / el_b}
+
+
+def forward_report(spg, steps, warmup):
+    """The forward-only workload of Matern-5/2 at N = 2^20 (Exp(1) gaps, l = 5, var = 2,
+    s2 = 0.05): per step the factorisation (cyclic reduction), logML with data fit and log det,
+    posterior mean and selected-inverse variances (spingp_factor, spingp_logml, spingp_solve,
+    spingp_selinv), eager launches on a side stream, tile from the autotuner of logML + gradient;
+    with the per-kernel event times of one more pass."""
+    import torch
+    from paper_1610_08035_amd.spingp import spingp_profile, spingp_profile_read
+    from workloads import make_config
+    w = make_config(2)
+    t, y, hyp = w.series(0)
+    n = t.shape[0]
+    dev = torch.device("cuda:0")
+    td, yd, hd = (torch.as_tensor(a, device=dev) for a in (t, y, hyp))
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    h = spg.Handle(w.terms, n, stream=side)
+    h.assemble(td, yd, hd, autotune=True)
+    ll, fit, ld = (torch.empty(1, dtype=torch.float64, device=dev) for _ in range(3))
+    fm = torch.empty(n, dtype=torch.float64, device=dev)
+    fv = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def step():
+        spg.spingp_factor(h._h)
+        spg.spingp_logml(h._h, ll, fit, ld)
+        spg.spingp_solve(h._h, fm)
+        spg.spingp_selinv(h._h, fv)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    if h.status()[0] != 0:
+        raise RuntimeError("forward workload failed validation")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    spingp_profile(h._h, 1)
+    for _ in range(steps):
+        step()
+    prof = spingp_profile_read(h._h)
+    spingp_profile(h._h, 0)
+    torch.cuda.synchronize()
+    R, L = spg.spingp_tile_shape(h.tile)
+    h.close()
+    return {"workload": "matern52_n1048576_exp1gaps_forward_factor_logml_mean_var", "n_points": n,
+            "points_per_s": n / el, "ms_per_step": 1e3 * el, "steps": steps, "tile": {"R": R, "L": L},
+            "launch": "eager, side stream",
+            "kernel_ms_per_step": {k: round(v[0] / steps, 5) for k, v in prof.items() if v[1]},
+            "logml": float(ll.item())}
 
 
 def large_report(spg, steps, warmup):
@@ -393,9 +579,14 @@ def main():
     ap.add_argument("--no-predict", action="store_true", help="skip the prediction report")
     ap.add_argument("--no-fit", action="store_true", help="skip the hyperparameter-fit report")
     ap.add_argument("--no-bsweep", action="store_true", help="skip the block-size sweep")
+    ap.add_argument("--no-forward", action="store_true", help="skip the forward-only (factor, logML, mean, "
+                    "variance) report")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="only time the CPU oracle on every workload (minutes) and print its JSON")
     ap.add_argument("--tile", type=int, default=None,
                     help="headline tile shape index instead of the autotuner's choice (counter runs)")
-    ap.add_argument("--only", choices=["batched", "large", "sum", "co2", "predict", "fit", "bsweep"], default=None,
+    ap.add_argument("--only", choices=["batched", "large", "sum", "co2", "predict", "fit", "bsweep", "forward"],
+                    default=None,
                     help="run one secondary workload alone and print its JSON (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM counters)")
@@ -405,6 +596,9 @@ def main():
               "multi-GPU runs are not part of this benchmark", file=sys.stderr)
         sys.exit(2)
 
+    if args.cpu_table:
+        print(json.dumps({"cpu_table": cpu_table()}), flush=True)
+        return
     import torch
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 8
@@ -423,7 +617,7 @@ def main():
             print(json.dumps({"fit": fit_report(spg)}), flush=True)
             return
         fn = {"batched": batched_report, "large": large_report, "sum": sum_report, "co2": co2_report,
-              "predict": predict_report, "bsweep": bsweep_report}[args.only]
+              "predict": predict_report, "bsweep": bsweep_report, "forward": forward_report}[args.only]
         print(json.dumps({args.only: fn(spg, args.steps, args.warmup)}), flush=True)
         return
 
@@ -497,10 +691,24 @@ def main():
     value = n * args.steps / elapsed
     per_kernel = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in prof.items()}
     dom = max(FLOPS_PER_POINT, key=lambda k: per_kernel[k])
-    achieved = FLOPS_PER_POINT[dom] * n / (per_kernel[dom] * 1e-3) / 1e12
+    t_dom = per_kernel[dom] * 1e-3
+    achieved = FLOPS_PER_POINT[dom] * n / t_dom / 1e12
     traffic = None
     if TRAFFIC["kernel"] == dom and TRAFFIC["source_sha"] == kernel_source_sha():
         traffic = TRAFFIC["bytes"].get(tuple(spg.spingp_tile_shape(h.tile)))
+    # the binding roof from the algorithmic intensity (flop per byte of t, y) against the machine
+    # balance; beside it the HBM rate of the measured traffic (counters), when it is current
+    intensity = FLOPS_PER_POINT[dom] / ALG_BYTES_PER_POINT[dom]
+    bound = "alu" if intensity > MACHINE_BALANCE else "hbm"
+    hbm = {"algorithmic_bytes_per_launch": ALG_BYTES_PER_POINT[dom] * n,
+           "algorithmic_GBs": ALG_BYTES_PER_POINT[dom] * n / t_dom / 1e9, "peak_GBs": PEAK_HBM_GBS}
+    hbm["algorithmic_frac"] = hbm["algorithmic_GBs"] / PEAK_HBM_GBS
+    if traffic is not None:
+        hbm["measured_bytes_per_launch"] = traffic
+        hbm["measured_GBs"] = traffic / t_dom / 1e9
+        hbm["measured_frac"] = hbm["measured_GBs"] / PEAK_HBM_GBS
+        hbm["measured_intensity_flop_per_byte"] = FLOPS_PER_POINT[dom] * n / traffic
+        hbm["source"] = "rocprofv3 FETCH_SIZE and WRITE_SIZE per launch, scaled by a device copy of known size"
     out = {
         "metric": "time points/sec, logML+grad, Matern-5/2 N=2^20 FP64; % HBM roofline",
         "value": value,
@@ -519,13 +727,17 @@ def main():
                    "tile": dict(zip(("R", "L"), spg.spingp_tile_shape(h.tile))),
                    "cache": "inputs and workspace (about 80 MB) stay resident in the 256 MB MALL between steps"},
         "graph_replay": {"ms_per_step": 1e3 * el_graph, "points_per_s": n / el_graph},
-        "roofline": {"bound": "alu", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+        "roofline": {"bound": bound, "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "flops_per_point": FLOPS_PER_POINT[dom]},
+                     "flops_per_point": FLOPS_PER_POINT[dom],
+                     "algorithmic_intensity_flop_per_byte": intensity, "machine_balance_flop_per_byte": MACHINE_BALANCE,
+                     "hbm": hbm},
         "kernel_ms": {k: round(v, 5) for k, v in per_kernel.items()},
         "logml": float(ll.item()),
     }
     h.close()
+    if not args.no_forward:
+        out["forward"] = forward_report(spg, args.steps, args.warmup)
     if not args.no_batched:
         out["batched"] = batched_report(spg, args.steps, args.warmup)
     if not args.no_large:
@@ -542,6 +754,7 @@ def main():
         out["bsweep"] = bsweep_report(spg, max(2, args.steps // 4), max(1, args.warmup // 2))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_config1"] = cpu_config1()
     print(json.dumps(out), flush=True)
 
 
