@@ -35,23 +35,25 @@ ALG_BYTES_PER_POINT = {"fwd_fold_tree": 16.0, "bwd_elim_adjoint": 16.0}
 
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE passes on
 # this workload, per tile shape (R, L), scaled by a 256 MiB copy (FETCH x 2.0, WRITE x 1.0);
-# valid only for the kernel sources they were taken on (sha256 over csrc/, see
-# kernel_source_sha), else reported as null.
+# valid only for the kernel sources they were taken on (sha256 over the one-series kernel
+# sources, see kernel_source_sha), else reported as null.
 TRAFFIC = {"kernel": "bwd_elim_adjoint",
-           "bytes": {(8, 128): (45122.8 * 2.0 + 8288.1) * 1024.0,
-                     (8, 256): (44051.0 * 2.0 + 8240.0) * 1024.0},
-           "source_sha": "8f607d7d117ab8c5472ea796fc077377d922efceb42fce027776d037e6fa605a"}
+           "bytes": {(8, 128): (40464.9 * 2.0 + 96.1) * 1024.0,
+                     (8, 256): (40550.9 * 2.0 + 48.0) * 1024.0},
+           "source_sha": "7a70f5e7f83d1511050b0166e51d2d3f5d212043e4d97e59e6bcc0d430f39e86"}
 
 
 def kernel_source_sha():
+    """Hash of the sources the one-series Matern kernels are built from (the counters in TRAFFIC
+    hold for exactly these)."""
     import hashlib
     d = os.path.join(ROOT, "paper_1610_08035_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(fh.read())
+    for f in ("spingp_device.hpp", "spingp_host.hpp", "spingp_kernels.hpp", "spingp_series.hpp",
+              "spingp_tile.hip"):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -100,16 +102,34 @@ def cpu_config1(reps=5):
             **out}
 
 
+_W4 = None
+
+
+def _workload4():
+    """The 4096-series batch, generated once per process."""
+    global _W4
+    if _W4 is None:
+        from workloads import make_config
+        _W4 = make_config(4)
+    return _W4
+
+
 def _cpu_series_grad(args):
-    """logML + gradient of a range of series of workload 4 by the C oracle (one process)."""
+    """logML + gradient of a range of series of the 4096-series batch by the C oracle (one
+    process; the batch is generated before the timed calls)."""
     from oracle import native
-    from workloads import make_config
     lo, hi = args
-    w = make_config(4)
+    w = _workload4()
     for i in range(lo, hi):
         t, y, hyp = w.series(i)
         native.tangent_grad(w.terms, hyp, t, y)
     return hi - lo
+
+
+def _cpu_worker_ready(_):
+    _workload4()
+    time.sleep(0.2)
+    return os.getpid()
 
 
 def cpu_table():
@@ -140,32 +160,39 @@ def cpu_table():
     el = timed(lambda: native.btd_factored(w.terms, hyp, t, y, want_blocks=False))
     rows["config2_forward"] = {"what": "factor, logML, mean, variance (C elimination)", "cores": 1,
                                "n_points": int(t.shape[0]), "seconds": el, "points_per_s": t.shape[0] / el}
+    print("cpu table: config2_forward done", file=sys.stderr, flush=True)
     el = timed(lambda: native.tangent_grad(w.terms, hyp, t, y))
     rows["headline_logml_grad"] = {"what": "logML + 3-parameter gradient (C tangent-linear)", "cores": 1,
                                    "n_points": int(t.shape[0]), "seconds": el, "points_per_s": t.shape[0] / el}
+    print("cpu table: headline_logml_grad done", file=sys.stderr, flush=True)
     w3 = make_config(3)
     t3, y3, h3 = w3.series(0)
     el = timed(lambda: native.tangent_grad(w3.terms, h3, t3, y3))
     rows["config3_sum_kernel"] = {"what": "b = 10 logML + 6-parameter gradient (C tangent-linear)", "cores": 1,
                                   "n_points": int(t3.shape[0]), "seconds": el, "points_per_s": t3.shape[0] / el}
-    w4 = make_config(4)
+    print("cpu table: config3_sum_kernel done", file=sys.stderr, flush=True)
+    w4 = _workload4()
     el1 = timed(lambda: _cpu_series_grad((0, w4.n_series)))
     cores = host_cpu()["usable_cpus"] or 1
     step = max(1, -(-w4.n_series // (4 * cores)))
     chunks = [(i, min(i + step, w4.n_series)) for i in range(0, w4.n_series, step)]
     with concurrent.futures.ProcessPoolExecutor(cores) as ex:
-        list(ex.map(_cpu_series_grad, chunks[:cores]))              # start the workers
+        # start every worker and let each generate the batch before the timed map
+        ready = set(ex.map(_cpu_worker_ready, range(4 * cores)))
         t0 = time.perf_counter()
         list(ex.map(_cpu_series_grad, chunks))
         eln = time.perf_counter() - t0
     rows["config4_batched"] = {"what": "4096 series, logML + gradient each (C tangent-linear)",
                                "n_points": int(w4.n_points), "one_core": {"seconds": el1, "points_per_s": w4.n_points / el1},
-                               "all_cores": {"cores": cores, "seconds": eln, "points_per_s": w4.n_points / eln}}
+                               "all_cores": {"cores": cores, "workers_started": len(ready), "seconds": eln,
+                                             "points_per_s": w4.n_points / eln}}
+    print("cpu table: config4_batched done", file=sys.stderr, flush=True)
     w5 = make_config(5)
     t5, y5, h5 = w5.series(0)
     el = timed(lambda: native.tangent_grad(w5.terms, h5, t5, y5))
     rows["config5_large"] = {"what": "N = 2^24 logML + gradient (C tangent-linear)", "cores": 1,
                              "n_points": int(t5.shape[0]), "seconds": el, "points_per_s": t5.shape[0] / el}
+    print("cpu table: config5_large done", file=sys.stderr, flush=True)
     return rows
 
 

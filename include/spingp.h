@@ -14,7 +14,9 @@
  *     work.  All calls enqueue on the handle's stream and return without synchronising,
  *     except spingp_create, spingp_destroy and spingp_status.
  *   - The library owns its workspace; it is allocated once in spingp_create, so the other
- *     calls never allocate device memory.
+ *     calls never allocate device memory, with one exception: the first spingp_predict on a
+ *     handle allocates the merged chain's buffers (4 doubles per point of max_points), which
+ *     the handle then keeps (call it once before a capture or a loop that must not allocate).
  *   - Host-detectable errors (null handle or pointer, sizes above the handle's maximum,
  *     unsupported model, call order) are returned synchronously as a spingp_status_t.
  *     Data errors (decreasing or non-finite t, non-finite y, non-positive or non-finite
@@ -54,7 +56,7 @@ typedef enum {
   SPINGP_E_UNSORTED = 3,    /* t decreases inside a series (device-detected) */
   SPINGP_E_NONFINITE = 4,   /* NaN/Inf in t or y (device-detected) */
   SPINGP_E_HYPER = 5,       /* hyperparameter not finite or not > 0 (device-detected) */
-  SPINGP_E_NOMEM = 6,       /* workspace allocation failed in spingp_create */
+  SPINGP_E_NOMEM = 6,       /* workspace allocation failed (spingp_create, first spingp_predict) */
   SPINGP_E_HIP = 7,         /* a HIP runtime call failed */
   SPINGP_E_UNSUPPORTED = 8  /* model or size the library does not implement */
 } spingp_status_t;
@@ -102,7 +104,8 @@ int spingp_destroy(spingp_handle h);
 int spingp_state_dim(spingp_handle h);
 int spingp_n_hyper(spingp_handle h);
 
-/* Device bytes of workspace the handle holds (allocated by spingp_create), -1 for NULL. */
+/* Device bytes of workspace the handle holds (spingp_create's, plus the prediction buffers
+ * once spingp_predict has run), -1 for NULL. */
 int64_t spingp_workspace_bytes(spingp_handle h);
 
 /* Flags of spingp_assemble. */
@@ -233,7 +236,8 @@ int spingp_tune(spingp_handle h, int32_t reps);
  * the hyperparameters in device memory at the time of the call.  Overwrites the handle's
  * factorisation: call spingp_factor again before spingp_logml, spingp_solve or spingp_selinv
  * (spingp_logml_grad refactors by itself).  Needs assemble; a batched handle needs offsets_star
- * (SPINGP_E_INVALID without).
+ * (SPINGP_E_INVALID without).  The first call allocates the prediction buffers (32 bytes per
+ * point of max_points; SPINGP_E_NOMEM if that fails), later calls reuse them.
  */
 int spingp_predict(spingp_handle h, const double* t_star, const int64_t* offsets_star, int64_t n_star,
                    double* f_mean, double* f_var);

@@ -113,6 +113,7 @@ struct spingp_ctx {
   unsigned long long* key = nullptr;
   double* tune_out = nullptr;      // logML and gradient written while tuning
   double* pred = nullptr;          // prediction: merged times, observations, mean, variance
+                                   // (4 x max_points, allocated by the first spingp_predict)
   int64_t* pred_off = nullptr;     // prediction, several series: merged offsets
   int64_t lane_ld = 0;
   // tile shape
@@ -258,7 +259,6 @@ static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_serie
       {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride(model)},
       {(void**)&h->scal, (int64_t)sizeof(double) * 8},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
-      {(void**)&h->pred, (int64_t)sizeof(double) * 4 * max_points},
   };
   bool ok = true;
   for (auto& r : reqs) {
@@ -346,7 +346,6 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
       {(void**)&h->part, (int64_t)sizeof(double) * part_n},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
       {(void**)&h->tune_out, (int64_t)sizeof(double) * 4 * max_series},
-      {(void**)&h->pred, (int64_t)sizeof(double) * 4 * max_points},
       {(void**)&h->pred_off, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
       {(void**)&h->chunk_series, multi ? (int64_t)sizeof(int32_t) * slots_max : 0},
       {(void**)&h->chunk_first, multi ? (int64_t)sizeof(int64_t) * ((int64_t)max_series + 1) : 0},
@@ -875,10 +874,19 @@ extern "C" int spingp_predict(spingp_handle h, const double* t_star, const int64
                               double* f_mean, double* f_var) {
   if (!h || !t_star || n_star < 1) return SPINGP_E_INVALID;
   if (!h->assembled) return SPINGP_E_ORDER;
-  if (!h->pred || (h->batched && !h->pred_off)) return SPINGP_E_UNSUPPORTED;
+  if (h->batched && !h->pred_off) return SPINGP_E_UNSUPPORTED;
   if (h->batched && !offsets_star) return SPINGP_E_INVALID;
   if (h->n_points + n_star > h->max_points) return SPINGP_E_INVALID;
   if (!f_mean && !f_var) return SPINGP_OK;
+  if (!h->pred) {
+    // the merged chain's buffers: only handles that predict hold them
+    const int64_t bytes = (int64_t)sizeof(double) * 4 * h->max_points;
+    if (hipMalloc((void**)&h->pred, bytes) != hipSuccess) {
+      h->pred = nullptr;
+      return SPINGP_E_NOMEM;
+    }
+    h->ws_bytes += bytes;
+  }
   const int64_t n = h->n_points, m = n_star, nm = n + m;
   const int32_t S = h->n_series;
   double* tm = h->pred;

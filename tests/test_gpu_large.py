@@ -58,4 +58,7 @@ def test_config5_full_size(lib):
     print(f"\nN = 2^24: library workspace {ws / 2**20:.1f} MiB, device memory of the call "
           f"{used / 2**20:.1f} MiB, every level stored {EVERY_LEVEL_BYTES_PER_NODE * n / 2**20:.1f} MiB")
     assert ws < 0.5 * EVERY_LEVEL_BYTES_PER_NODE * n
+    # the logML + gradient workspace at 2^24 stays under 1 GB (the prediction buffers are
+    # allocated only by spingp_predict)
+    assert ws <= 1_000_000_000
     assert used < ws + 2 * 16 * n + (256 << 20)

@@ -125,10 +125,11 @@ def test_extreme_signal_to_noise(lib):
 
 
 def test_full_size_config2(lib):
-    """N = 2^20 Matern-5/2 (the benchmark shape): every output against the C oracle."""
+    """N = 2^20 Matern-5/2 (the benchmark shape): every output against the C oracle, the
+    selected-inverse blocks S_nn and S_{n+1,n} included, element by element."""
     w = make_config(2)
     t, y, hyp = w.series(0)
-    _compare(w, _run(lib, w.terms, t, y, hyp, blocks=False), blocks=False)
+    _compare(w, _run(lib, w.terms, t, y, hyp, blocks=True), blocks=True)
 
 
 def test_autograd_function_matches_grad(lib):

@@ -49,10 +49,18 @@ def test_predict_small_against_dense(lib, terms, hyper):
     hyp = np.array(hyper)
     h = lib.Handle(terms, n + ts.shape[0])
     h.assemble(to_dev(t), to_dev(y), to_dev(hyp))
+    ws0 = h.workspace_bytes()
     fm, fv = h.predict(to_dev(ts))
     assert h.status()[0] == 0
     ref = dense.gp_predict_dense(model_for(terms, hyp), t, y, ts)
     _check(fm.cpu().numpy(), fv.cpu().numpy(), ref["f_mean"], ref["f_var"])
+    # the first prediction allocates the merged chain's buffers (4 doubles per point), the
+    # second reuses them and gives the same values
+    ws1 = h.workspace_bytes()
+    assert ws1 == ws0 + 32 * (n + ts.shape[0])
+    fm2, fv2 = h.predict(to_dev(ts))
+    assert h.workspace_bytes() == ws1
+    assert torch.equal(fm2, fm) and torch.equal(fv2, fv)
     h.close()
 
 
