@@ -10,18 +10,22 @@ using ModelP = SumM32Periodic<3, false>;               // Matern-3/2 + periodic
 using ModelQ = SumM32Periodic<3, true>;                // Matern-3/2 + quasi-periodic
 using ModelS = SumM32Periodic<3, true, kSqExpOrder>;   // ... + squared exponential
 static_assert(ModelP::B == ModelQ::B, "one state dimension for the two b = 10 models");
-// Work-group caps: what fits on the 256 CUs at once for each kernel's LDS and registers, so
-// that every team stays resident and loops over its items instead of a launch ending with a
-// second, partly empty round.  b = 10: up 11 KB and 148 VGPRs (12 per CU; level 1 98 VGPRs,
-// 14), down 10 KB and 128 VGPRs (16), node 14 KB and 213 VGPRs (8), leaf 16 per CU.  b = 16: up
-// 28 KB and 256 VGPRs (4 per CU; level 1 210 VGPRs, 5), down 24 KB (6), node 39 KB and 256
-// VGPRs (4), leaf 15 KB (10).
-struct Caps {
-  int up, up1, down, leaf, node;   // up1: the up-sweep's first level
-};
-constexpr Caps kCaps10 = {3072, 3584, 4096, 4096, 2048};
-constexpr Caps kCaps16 = {1024, 1280, 1536, 2560, 1024};
-inline const Caps& caps(int model) { return model == kModelQuasiSqExp ? kCaps16 : kCaps10; }
+// Work-group caps: every team stays resident and loops over its items, so that a launch does
+// not end with a second, partly empty round.  The cap is what fits on the device at once for
+// the kernel's registers and LDS (the occupancy query, once per kernel and process).
+template <auto K>
+int resident_groups() {
+  static int cached = 0;   // one instance per kernel
+  if (cached == 0) {
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, K, kW, 0) != hipSuccess || per_cu < 1 || cus < 1)
+      return 1024;
+    cached = per_cu * cus;
+  }
+  return cached;
+}
 
 inline void mark(const WideCtx& c, int kid, int end) {
   if (c.mark) c.mark(c.mark_arg, kid, end);
@@ -68,7 +72,9 @@ void plan_levels(int64_t n, WideCtx& c) {
     if (m == 1 || k == kMaxLevels) break;
   }
   c.n_levels = k;
-  const int cap = caps(c.model).node;
+  const int cap = with_model(c.model, [](auto m) {
+    return resident_groups<k_wide_node<decltype(m), kWantGrad>>();
+  });
   c.node_grid = (int)(n < cap ? n : cap);
 }
 
@@ -77,17 +83,16 @@ hipError_t factor_m(const WideCtx& c) {
   constexpr int B = Model::B;
   mark(c, kKidFwd, 0);
   hipLaunchKernelGGL(k_wide_setup<Model>, dim3(1), dim3(kW), 0, c.stream, c.hyper, c.cst);
-  const Caps& cp = caps(c.model);
-  hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points, cp.leaf)), dim3(kW), 0, c.stream, c.t, c.y, c.n_points,
-                     c.cst, c.elems);
+  hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points, resident_groups<k_wide_leaf<Model>>())), dim3(kW), 0,
+                     c.stream, c.t, c.y, c.n_points, c.cst, c.elems);
   // level 1 joins leaves (rank-one node information: closed-form inverse)
   for (int k = 1; k < c.n_levels; ++k) {
     if (k == 1)
-      hipLaunchKernelGGL((k_wide_up<B, true>), dim3(grid_for(c.n[k], cp.up1)), dim3(kW), 0, c.stream, c.elems,
-                         c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
+      hipLaunchKernelGGL((k_wide_up<B, true>), dim3(grid_for(c.n[k], resident_groups<k_wide_up<B, true>>())), dim3(kW),
+                         0, c.stream, c.elems, c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
     else
-      hipLaunchKernelGGL((k_wide_up<B, false>), dim3(grid_for(c.n[k], cp.up)), dim3(kW), 0, c.stream, c.elems,
-                         c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
+      hipLaunchKernelGGL((k_wide_up<B, false>), dim3(grid_for(c.n[k], resident_groups<k_wide_up<B, false>>())), dim3(kW),
+                         0, c.stream, c.elems, c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
   }
   mark(c, kKidFwd, 1);
   mark(c, kKidTop, 0);
@@ -103,18 +108,18 @@ hipError_t factor(const WideCtx& c) {
 
 template <int B>
 static void down_b(const WideCtx& c) {
-  const int cap = caps(c.model).down;
   // the last level's children are leaves (rank-one node information: closed-form inverse)
   for (int k = c.n_levels - 1; k >= 1; --k) {
     if (k == 1 && c.model == kModelPeriodic)   // leaf edges: Q only in the Matern block
-      hipLaunchKernelGGL((k_wide_down<B, true, true>), dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream,
-                         c.elems, c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
+      hipLaunchKernelGGL((k_wide_down<B, true, true>),
+                         dim3(grid_for(c.n[k - 1], resident_groups<k_wide_down<B, true, true>>())), dim3(kW), 0,
+                         c.stream, c.elems, c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
     else if (k == 1)
-      hipLaunchKernelGGL((k_wide_down<B, true>), dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream, c.elems,
-                         c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
+      hipLaunchKernelGGL((k_wide_down<B, true>), dim3(grid_for(c.n[k - 1], resident_groups<k_wide_down<B, true>>())),
+                         dim3(kW), 0, c.stream, c.elems, c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
     else
-      hipLaunchKernelGGL((k_wide_down<B, false>), dim3(grid_for(c.n[k - 1], cap)), dim3(kW), 0, c.stream, c.elems,
-                         c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
+      hipLaunchKernelGGL((k_wide_down<B, false>), dim3(grid_for(c.n[k - 1], resident_groups<k_wide_down<B, false>>())),
+                         dim3(kW), 0, c.stream, c.elems, c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
   }
 }
 

@@ -60,6 +60,52 @@ struct Lay {
 // ---------------------------------------------------------------------------- team algebra
 // Row-major B x B matrices in LDS.  Outputs never alias inputs.  Every call ends with a
 // barrier, so its result is visible to the whole team.
+//
+// Matrix products run on the matrix cores: op(X) op(Y) for B <= 16 is one 16 x 16 tile, built
+// from 16 x 16 x 4 FP64 MFMA steps over k (operands zero past B).  In each step lane l supplies
+// op(X)[l % 16][k] and op(Y)[k][l % 16] for k = 4 s + l / 16, and the 16 x 16 result ends with
+// entry (l / 16 + 4 r, l % 16) in component r of lane l.  The whole wavefront takes part, so
+// products are only formed in uniform control flow.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int B, bool TX, bool TY>
+SPG_DEV v4d mx(const double* X, const double* Y) {
+  static_assert(B <= 16, "one 16 x 16 tile");
+  const int l = threadIdx.x, i = l & 15, kq = l >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  SPG_UNROLL for (int s = 0; s < (B + 3) / 4; ++s) {
+    const int k = 4 * s + kq;
+    const bool in = i < B && k < B;
+    // every lane loads (a clamped, valid index), then the padding is zeroed
+    const int ix = in ? (TX ? k * B + i : i * B + k) : 0;
+    const int iy = in ? (TY ? i * B + k : k * B + i) : 0;
+    const double xv = X[ix], yv = Y[iy];
+    const double a = in ? xv : 0.0;
+    const double b = in ? yv : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+// The symmetric part (Z + Z^T) / 2 of Z = op(X) op(Y): Z^T = op(Y)^T op(X)^T is a second tile.
+template <int B, bool TX, bool TY>
+SPG_DEV v4d mx_sym(const double* X, const double* Y) {
+  return 0.5 * (mx<B, TX, TY>(X, Y) + mx<B, !TY, !TX>(Y, X));
+}
+// f(i, j, value) for the entries of the lane's results inside the B x B block.
+template <int B, class F>
+SPG_DEV void mx_each(const v4d& d, F&& f) {
+  const int l = threadIdx.x, j = l & 15, i0 = l >> 4;
+  if (j < B) {
+    SPG_UNROLL for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 4 * r;
+      if (i < B) f(i, j, d[r]);
+    }
+  }
+}
+template <int B>
+SPG_DEV void mx_store(const v4d& d, double* Z) {
+  mx_each<B>(d, [&](int i, int j, double v) { Z[i * B + j] = v; });
+}
 template <int B>
 SPG_DEV void t_copy(const double* __restrict__ X, double* __restrict__ Y, int n) {
   for (int e = threadIdx.x; e < n; e += kW) Y[e] = X[e];
@@ -67,42 +113,12 @@ SPG_DEV void t_copy(const double* __restrict__ X, double* __restrict__ Y, int n)
 }
 template <int B>
 SPG_DEV void t_mm(const double* X, const double* Y, double* Z) {        // Z = X Y
-  for (int e = threadIdx.x; e < B * B; e += kW) {
-    const int i = e / B, j = e - i * B;
-    double s = 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[i * B + k], Y[k * B + j], s);
-    Z[e] = s;
-  }
+  mx_store<B>(mx<B, false, false>(X, Y), Z);
   tsync();
 }
 template <int B>
 SPG_DEV void t_mtm(const double* X, const double* Y, double* Z) {       // Z = X^T Y
-  for (int e = threadIdx.x; e < B * B; e += kW) {
-    const int i = e / B, j = e - i * B;
-    double s = 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[k * B + i], Y[k * B + j], s);
-    Z[e] = s;
-  }
-  tsync();
-}
-template <int B>
-SPG_DEV void t_mmt(const double* X, const double* Y, double* Z) {       // Z = X Y^T
-  for (int e = threadIdx.x; e < B * B; e += kW) {
-    const int i = e / B, j = e - i * B;
-    double s = 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[i * B + k], Y[j * B + k], s);
-    Z[e] = s;
-  }
-  tsync();
-}
-template <int B>
-SPG_DEV void t_mv(const double* X, const double* v, double* w) {        // w = X v
-  if (threadIdx.x < B) {
-    const int i = threadIdx.x;
-    double s = 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(X[i * B + k], v[k], s);
-    w[i] = s;
-  }
+  mx_store<B>(mx<B, true, false>(X, Y), Z);
   tsync();
 }
 template <int B>
@@ -140,71 +156,99 @@ SPG_DEV double t_dot(const double* a, const double* b) {
   return s;
 }
 
-// Value of x in lane `lane` (uniform) for every lane of the wavefront.
-SPG_DEV double lane_bcast(double x, int lane) {
+// Value of x in lane C of the caller's row of 16 lanes, for every lane of that row (DPP
+// row_newbcast; the lane index must be a constant, so callers pass an unrolled loop index).
+template <int C>
+SPG_DEV double row_bcast_c(double x) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x150 + C, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x150 + C, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+SPG_DEV double row_bcast(double x, int c) {
+  switch (c) {
+    case 0: return row_bcast_c<0>(x);
+    case 1: return row_bcast_c<1>(x);
+    case 2: return row_bcast_c<2>(x);
+    case 3: return row_bcast_c<3>(x);
+    case 4: return row_bcast_c<4>(x);
+    case 5: return row_bcast_c<5>(x);
+    case 6: return row_bcast_c<6>(x);
+    case 7: return row_bcast_c<7>(x);
+    case 8: return row_bcast_c<8>(x);
+    case 9: return row_bcast_c<9>(x);
+    case 10: return row_bcast_c<10>(x);
+    case 11: return row_bcast_c<11>(x);
+    case 12: return row_bcast_c<12>(x);
+    case 13: return row_bcast_c<13>(x);
+    case 14: return row_bcast_c<14>(x);
+    default: return row_bcast_c<15>(x);
+  }
 }
 
-// G = M^-1 by Gauss-Jordan with partial pivoting; returns log |det M| (the same in every lane).
-// Lane r < B keeps row r of [M | G] in registers; the pivot search reads the candidates of the
-// other lanes and the pivot row is broadcast lane to lane, so no column step goes through LDS.
-// Lanes r >= B shadow row B - 1 and write nothing.  M itself is left unchanged.
+// G = M^-1 by Gauss-Jordan with partial pivoting over columns; returns log |det M| (the same in
+// every lane).  Lane r < B of every row of 16 lanes keeps row r of [M | G] in registers (lanes
+// past B shadow row B - 1 and write nothing).  At step c the pivot is the largest entry of row c
+// (a search inside lane c), every lane swaps the two columns in its own row, and the pivot row
+// reaches the other lanes by DPP broadcasts from the fixed lane c: no cross-lane traffic
+// depends on the pivot.  Pivot rows stay unscaled until the end (each later update is linear
+// in the row, so the scale carries through).  M P = E^-1 for the column permutation P, so
+// M^-1 = P E: the rows are written to their permuted places.  M itself is left unchanged.
 template <int B>
-SPG_DEV double t_inv_logdet(double* M, double* G, double* /*unused*/) {
+SPG_DEV double t_inv_logdet(const double* M, double* G, double* /*unused*/ = nullptr) {
+  static_assert(B <= 16, "one row of 16 lanes holds the matrix");
   const int tid = threadIdx.x;
-  const int r = tid < B ? tid : B - 1;
+  const int lr = tid & 15;
+  const int r = lr < B ? lr : B - 1;
   double a[B], g[B];
   SPG_UNROLL for (int k = 0; k < B; ++k) {
     a[k] = M[r * B + k];
     g[k] = (r == k) ? 1.0 : 0.0;
   }
+  int qs[B];
   double mant = 1.0;   // product of the pivots as mantissa and binary exponent: one log at the end
   int expo = 0;
+  double own_piv = 1.0;
   SPG_UNROLL for (int c = 0; c < B; ++c) {
-    // pivot: the first row q >= c with the largest |a[c]|
-    const double mine = fabs(a[c]);
-    int p = c;
-    double best = lane_bcast(mine, c);
-    for (int q = c + 1; q < B; ++q) {
-      const double v = lane_bcast(mine, q);
+    // pivot column: the first k >= c with the largest |a[k]| in row c, found by lane c
+    int q = c;
+    double best = fabs(a[c]);
+    SPG_UNROLL for (int k = c + 1; k < B; ++k) {
+      const double v = fabs(a[k]);
       if (v > best) {
         best = v;
-        p = q;
+        q = k;
       }
     }
-    if (p != c) {   // uniform: exchange rows c and p
-      SPG_UNROLL for (int k = c; k < B; ++k) {
-        const double xc = lane_bcast(a[k], c), xp = lane_bcast(a[k], p);
-        if (tid == c) a[k] = xp;
-        if (tid == p) a[k] = xc;
-      }
-      SPG_UNROLL for (int k = 0; k < B; ++k) {
-        const double xc = lane_bcast(g[k], c), xp = lane_bcast(g[k], p);
-        if (tid == c) g[k] = xp;
-        if (tid == p) g[k] = xc;
+    q = __builtin_amdgcn_readlane(q, c);
+    qs[c] = q;
+    SPG_UNROLL for (int k = c + 1; k < B; ++k) {
+      if (q == k) {   // uniform
+        const double x = a[c];
+        a[c] = a[k];
+        a[k] = x;
       }
     }
-    const double piv = lane_bcast(a[c], c);
+    const double piv = row_bcast(a[c], c);
     int e;
     mant *= frexp(piv, &e);
     expo += e;
-    const double ip = 1.0 / piv;
-    const double f = (tid == c) ? 0.0 : a[c];     // this row's multiplier of the pivot row
-    SPG_UNROLL for (int k = c + 1; k < B; ++k) {
-      const double pk = lane_bcast(a[k], c) * ip;
-      a[k] = (tid == c) ? pk : fma(-f, pk, a[k]);
-    }
-    a[c] = (tid == c) ? 1.0 : 0.0;
-    SPG_UNROLL for (int k = 0; k < B; ++k) {
-      const double pk = lane_bcast(g[k], c) * ip;
-      g[k] = (tid == c) ? pk : fma(-f, pk, g[k]);
-    }
+    const bool mine = lr == c;
+    if (mine) own_piv = piv;
+    // multiplier of this row (0 for the pivot row itself, which keeps its scale)
+    const double l = mine ? 0.0 : a[c] / piv;
+    SPG_UNROLL for (int k = c + 1; k < B; ++k) a[k] = fma(-l, row_bcast(a[k], c), a[k]);
+    SPG_UNROLL for (int k = 0; k <= c; ++k) g[k] = fma(-l, row_bcast(g[k], c), g[k]);
+  }
+  // scale every row by its own pivot, then undo the column swaps (last swap first)
+  const double is = 1.0 / own_piv;
+  int pos = r;
+  SPG_UNROLL for (int c = B - 1; c >= 0; --c) {
+    const int q = qs[c];
+    pos = pos == c ? q : (pos == q ? c : pos);
   }
   if (tid < B) {
-    SPG_UNROLL for (int k = 0; k < B; ++k) G[tid * B + k] = g[k];
+    SPG_UNROLL for (int k = 0; k < B; ++k) G[pos * B + k] = g[k] * is;
   }
   tsync();
   return log(fabs(mant)) + expo * 0.69314718055994530942;
@@ -250,21 +294,8 @@ SPG_DEV void t_inv_q2(const double* Q, const double* J, double* G) {
 }
 
 // ---------------------------------------------------------------------------- element ops
-// Entry (i, j) of X Y (TX: X^T, TY: Y^T) for row-major B x B blocks in LDS.
-template <int B, bool TX, bool TY>
-SPG_DEV double mm_entry(const double* X, const double* Y, int i, int j) {
-  double s = 0.0;
-  SPG_UNROLL for (int k = 0; k < B; ++k) s = fma(TX ? X[k * B + i] : X[i * B + k], TY ? Y[j * B + k] : Y[k * B + j], s);
-  return s;
-}
-// Entry (i, j) of the symmetric part (Z + Z^T) / 2 of Z = X Y.
-template <int B, bool TX, bool TY>
-SPG_DEV double mm_sym_entry(const double* X, const double* Y, int i, int j) {
-  return 0.5 * (mm_entry<B, TX, TY>(X, Y, i, j) + mm_entry<B, TX, TY>(X, Y, j, i));
-}
-
-// The element operations below run as a few phases, one barrier each: every lane computes
-// the same entry of all the independent products of a phase (and lanes < B the vectors).
+// The element operations below run as a few phases, one barrier each: the independent
+// products of a phase on the matrix cores, and lanes < B the vectors.
 
 // R = E1 (x) E2 (join at the shared node; see spingp_device.hpp).
 // LEAF2: E2 is a leaf, whose J is rank one (the inverse in closed form).
@@ -282,20 +313,14 @@ SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tm
   if (LEAF2) {
     ld = t_inv_rank1<B>(Q1, J2[0], G);
   } else {
-    for (int e = tid; e < BB; e += kW) {
-      const int i = e / B, j = e - i * B;
-      M[e] = mm_entry<B, false, false>(Q1, J2, i, j) + (i == j ? 1.0 : 0.0);
-    }
+    mx_each<B>(mx<B, false, false>(Q1, J2), [&](int i, int j, double v) { M[i * B + j] = v + (i == j ? 1.0 : 0.0); });
     tsync();
     ld = t_inv_logdet<B>(M, G, nullptr);
   }
   // P+ = G Q1, W = J2 G (both symmetric), G A1; G b1, G^T eta2
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    Pp[e] = mm_sym_entry<B, false, false>(G, Q1, i, j);
-    W[e] = mm_sym_entry<B, false, false>(J2, G, i, j);
-    GA[e] = mm_entry<B, false, false>(G, A1, i, j);
-  }
+  mx_store<B>(mx_sym<B, false, false>(G, Q1), Pp);
+  mx_store<B>(mx_sym<B, false, false>(J2, G), W);
+  mx_store<B>(mx<B, false, false>(G, A1), GA);
   if (tid < B) {
     double s1 = 0.0, s3 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) {
@@ -307,12 +332,9 @@ SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tm
   }
   tsync();
   // new transition A2 G A1, A2 P+, W A1; P+ eta2, W b1 and the vectors g, r
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    R[Y::kA + e] = mm_entry<B, false, false>(A2, GA, i, j);
-    T[e] = mm_entry<B, false, false>(A2, Pp, i, j);
-    WA[e] = mm_entry<B, false, false>(W, A1, i, j);
-  }
+  mx_store<B>(mx<B, false, false>(A2, GA), R + Y::kA);
+  mx_store<B>(mx<B, false, false>(A2, Pp), T);
+  mx_store<B>(mx<B, false, false>(W, A1), WA);
   if (tid < B) {
     double s2 = 0.0, s4 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) {
@@ -326,11 +348,8 @@ SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tm
   }
   tsync();
   // new noise A2 P+ A2^T + Q2, information J1 + A1^T W A1 (both symmetric), new offset and eta
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    R[Y::kQ + e] = mm_sym_entry<B, false, true>(T, A2, i, j) + Q2[e];
-    R[Y::kJ + e] = J1[e] + mm_sym_entry<B, true, false>(A1, WA, i, j);
-  }
+  mx_each<B>(mx_sym<B, false, true>(T, A2), [&](int i, int j, double v) { R[Y::kQ + i * B + j] = v + Q2[i * B + j]; });
+  mx_each<B>(mx_sym<B, true, false>(A1, WA), [&](int i, int j, double v) { R[Y::kJ + i * B + j] = J1[i * B + j] + v; });
   if (tid < B) {
     double s5 = 0.0, s6 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) {
@@ -365,18 +384,12 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
   if (LEAF) {
     ld = t_inv_rank1<B>(P, J[0], G);
   } else {
-    for (int e = tid; e < BB; e += kW) {
-      const int i = e / B, j = e - i * B;
-      M[e] = mm_entry<B, false, false>(P, J, i, j) + (i == j ? 1.0 : 0.0);
-    }
+    mx_each<B>(mx<B, false, false>(P, J), [&](int i, int j, double v) { M[i * B + j] = v + (i == j ? 1.0 : 0.0); });
     tsync();
     ld = t_inv_logdet<B>(M, G, nullptr);
   }
   // P+ = sym(G P); W = sym(J G) enters only through W m = (J G m + G^T J m) / 2
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    Pp[e] = mm_sym_entry<B, false, false>(G, P, i, j);
-  }
+  mx_store<B>(mx_sym<B, false, false>(G, P), Pp);
   if (tid < B) {
     double s1 = 0.0, s5 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) {
@@ -387,10 +400,7 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
     Jm[tid] = s5;
   }
   tsync();
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    T[e] = mm_entry<B, false, false>(A, Pp, i, j);
-  }
+  mx_store<B>(mx<B, false, false>(A, Pp), T);
   if (tid < B) {
     double s2 = 0.0, s3 = 0.0, s6 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) {
@@ -403,10 +413,7 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
     g[tid] = Gm[tid] + s2;
   }
   tsync();
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    Po[e] = mm_sym_entry<B, false, true>(T, A, i, j) + Q[e];
-  }
+  mx_each<B>(mx_sym<B, false, true>(T, A), [&](int i, int j, double v) { Po[i * B + j] = v + Q[i * B + j]; });
   if (tid < B) {
     double s4 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) s4 = fma(A[tid * B + k], g[k], s4);
@@ -431,37 +438,25 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
   if (Q2) {
     t_inv_q2<B>(Q, Jb, G);
   } else {
-    for (int e = tid; e < BB; e += kW) {
-      const int i = e / B, j = e - i * B;
-      M[e] = mm_entry<B, false, false>(Q, Jb, i, j) + (i == j ? 1.0 : 0.0);
-    }
+    mx_each<B>(mx<B, false, false>(Q, Jb), [&](int i, int j, double v) { M[i * B + j] = v + (i == j ? 1.0 : 0.0); });
     tsync();
     (void)t_inv_logdet<B>(M, G, nullptr);
   }
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    W[e] = mm_sym_entry<B, false, false>(Jb, G, i, j);
-  }
+  mx_store<B>(mx_sym<B, false, false>(Jb, G), W);
   if (tid < B) {
     double s1 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) s1 = fma(G[k * B + tid], etab[k], s1);
     s1v[tid] = s1;
   }
   tsync();
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    WA[e] = mm_entry<B, false, false>(W, A, i, j);
-  }
+  mx_store<B>(mx<B, false, false>(W, A), WA);
   if (tid < B) {
     double s2 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) s2 = fma(W[tid * B + k], bb[k], s2);
     r[tid] = s1v[tid] - s2;
   }
   tsync();
-  for (int e = tid; e < BB; e += kW) {
-    const int i = e / B, j = e - i * B;
-    Jo[e] = J[e] + mm_sym_entry<B, true, false>(A, WA, i, j);
-  }
+  mx_each<B>(mx_sym<B, true, false>(A, WA), [&](int i, int j, double v) { Jo[i * B + j] = J[i * B + j] + v; });
   if (tid < B) {
     double s3 = 0.0;
     SPG_UNROLL for (int k = 0; k < B; ++k) s3 = fma(A[k * B + tid], r[k], s3);
@@ -770,15 +765,10 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
     if (M::kQFromP0) {
       // Q' = P0' - A' P0' A'^T (Q = 0 after the last node)
       const double* P0 = c + M::kP0;
-      for (int e = tid; e < BB; e += kW) {
-        const int i = e / B, j = e - i * B;
-        Qo[e] = mm_entry<B, false, false>(E + Y::kA, P0, i, j);
-      }
+      mx_store<B>(mx<B, false, false>(E + Y::kA, P0), Qo);
       tsync();
-      for (int e = tid; e < BB; e += kW) {
-        const int i = e / B, j = e - i * B;
-        X[e] = edge ? P0[e] - mm_entry<B, false, true>(Qo, E + Y::kA, i, j) : 0.0;
-      }
+      mx_each<B>(mx<B, false, true>(Qo, E + Y::kA),
+                 [&](int i, int j, double v) { X[i * B + j] = edge ? P0[i * B + j] - v : 0.0; });
     } else {
       for (int e = tid; e < BB; e += kW) {
         const int i = e / B, j = e - i * B;
@@ -818,27 +808,68 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
   }
 }
 
+// Items of a level kernel are fetched one iteration ahead: each lane loads its share of the next
+// item's operands (consecutive doubles over the lanes) into registers while the team works on
+// the current one, so the global-memory latency overlaps the element operation.  At b = 16
+// the registers are taken by the element operations and the operands are loaded when used.
+template <int B>
+struct Ahead {
+  static constexpr bool kOn = B <= 12;
+};
+// Waves per SIMD the per-level kernels are compiled for (register budget of 512 / waves per
+// lane, MFMA accumulators included): at b <= 12 three teams of the up and down kernels and two
+// of the node step stay resident, at b = 16 two and one.
+template <int B>
+struct Occ {
+  static constexpr int kLevel = B <= 12 ? 3 : 2;
+  static constexpr int kNode = B <= 12 ? 2 : 1;
+};
+
 // Up-sweep: level k (n_cur elements at off_cur) from level k - 1 (n_prev at off_prev).
 // LEAF: level k - 1 is the leaf level (every right operand is a leaf).
 template <int B, bool LEAF = false>
-__global__ __launch_bounds__(kW) void k_wide_up(double* __restrict__ elems, int64_t off_prev, int64_t n_prev,
+__global__ __launch_bounds__(kW, Occ<B>::kLevel) void k_wide_up(double* __restrict__ elems, int64_t off_prev, int64_t n_prev,
                                                 int64_t off_cur, int64_t n_cur) {
   using Y = Lay<B>;
   __shared__ double E1[Y::kEs], E2[Y::kEs], tmp[Y::kTmpJoin];
   const int tid = threadIdx.x;
+  constexpr int kTwo = 2 * Y::kEs;                 // the two operands are adjacent in memory
+  constexpr int NP = Ahead<B>::kOn ? (kTwo + kW - 1) / kW : 1;
+  double pre[NP];
+  auto fetch = [&](int64_t it) {
+    if (it >= n_cur) return;
+    const double* a = elems + (off_prev + 2 * it) * Y::kEs;
+    const int lim = 2 * it + 1 < n_prev ? kTwo : Y::kEs;
+    SPG_UNROLL for (int j = 0; j < NP; ++j) {
+      const int e = tid + j * kW;
+      if (e < lim) pre[j] = a[e];
+    }
+  };
+  if (Ahead<B>::kOn) fetch(blockIdx.x);
   for (int64_t i = blockIdx.x; i < n_cur; i += gridDim.x) {
     const double* a = elems + (off_prev + 2 * i) * Y::kEs;
     double* out = elems + (off_cur + i) * Y::kEs;
-    if (2 * i + 1 >= n_prev) {                 // unpaired tail: passes through
-      for (int e = tid; e < Y::kEs; e += kW) out[e] = a[e];
+    const bool paired = 2 * i + 1 < n_prev;
+    if (Ahead<B>::kOn) {
+      SPG_UNROLL for (int j = 0; j < NP; ++j) {
+        const int e = tid + j * kW;
+        if (e < Y::kEs) E1[e] = pre[j];
+        else if (e < kTwo && paired) E2[e - Y::kEs] = pre[j];
+      }
+      tsync();
+      fetch(i + gridDim.x);
+    } else {
+      for (int e = tid; e < Y::kEs; e += kW) {
+        E1[e] = a[e];
+        if (paired) E2[e] = a[Y::kEs + e];
+      }
+      tsync();
+    }
+    if (!paired) {                             // unpaired tail: passes through
+      for (int e = tid; e < Y::kEs; e += kW) out[e] = E1[e];
+      tsync();
       continue;
     }
-    const double* b = a + Y::kEs;
-    for (int e = tid; e < Y::kEs; e += kW) {
-      E1[e] = a[e];
-      E2[e] = b[e];
-    }
-    tsync();
     t_combine<B, LEAF>(E1, E2, out, tmp);     // the result goes straight to global memory
     for (int e = Y::kE + tid; e < Y::kEs; e += kW) out[e] = 0.0;
     tsync();
@@ -878,24 +909,53 @@ __global__ __launch_bounds__(kW) void k_wide_root(const double* __restrict__ cst
 // LEAF: the children are leaves (the left sibling a right child is pushed through is a leaf).
 // Q2: and the right sibling a left child pulls back through has Q in the leading 2 x 2 block.
 template <int B, bool LEAF = false, bool Q2 = false>
-__global__ __launch_bounds__(kW) void k_wide_down(const double* __restrict__ elems, double* __restrict__ msgs,
+__global__ __launch_bounds__(kW, Occ<B>::kLevel) void k_wide_down(const double* __restrict__ elems, double* __restrict__ msgs,
                                                   int64_t off_par, int64_t off_child, int64_t n_child) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
   __shared__ double par[Y::kMs], E[Y::kEs], out[Y::kMs], tmp[Y::kTmpStep];
   const int tid = threadIdx.x;
+  // parent message, then the sibling element (absent for an unpaired tail)
+  constexpr int kAll = Y::kMs + Y::kEs;
+  constexpr int NP = Ahead<B>::kOn ? (kAll + kW - 1) / kW : 1;
+  double pre[NP];
+  auto fetch = [&](int64_t it) {
+    if (it >= n_child) return;
+    const double* pm = msgs + (off_par + (it >> 1)) * Y::kMs;
+    const bool lft = (it & 1) == 0;
+    const bool tail = lft && it + 1 >= n_child;
+    const double* sib = elems + (off_child + (lft ? it + 1 : it - 1)) * Y::kEs;
+    SPG_UNROLL for (int j = 0; j < NP; ++j) {
+      const int e = tid + j * kW;
+      if (e < Y::kMs) pre[j] = pm[e];
+      else if (e < kAll && !tail) pre[j] = sib[e - Y::kMs];
+    }
+  };
+  if (Ahead<B>::kOn) fetch(blockIdx.x);
   for (int64_t c = blockIdx.x; c < n_child; c += gridDim.x) {
     const double* pm = msgs + (off_par + (c >> 1)) * Y::kMs;
     double* om = msgs + (off_child + c) * Y::kMs;
     const bool left = (c & 1) == 0;
-    if (left && c + 1 >= n_child) {            // unpaired tail: same messages as its parent
-      for (int e = tid; e < Y::kMs; e += kW) om[e] = pm[e];
+    const bool tail = left && c + 1 >= n_child;   // unpaired tail: same messages as its parent
+    const double* sib = elems + (off_child + (left ? c + 1 : c - 1)) * Y::kEs;
+    if (Ahead<B>::kOn) {
+      SPG_UNROLL for (int j = 0; j < NP; ++j) {
+        const int e = tid + j * kW;
+        if (e < Y::kMs) par[e] = pre[j];
+        else if (e < kAll && !tail) E[e - Y::kMs] = pre[j];
+      }
+    } else {
+      for (int e = tid; e < Y::kMs; e += kW) par[e] = pm[e];
+      if (!tail)
+        for (int e = tid; e < Y::kEs; e += kW) E[e] = sib[e];
+    }
+    tsync();
+    if (Ahead<B>::kOn) fetch(c + gridDim.x);
+    if (tail) {
+      for (int e = tid; e < Y::kMs; e += kW) om[e] = par[e];
+      tsync();
       continue;
     }
-    const double* sib = elems + (off_child + (left ? c + 1 : c - 1)) * Y::kEs;
-    for (int e = tid; e < Y::kMs; e += kW) par[e] = pm[e];
-    for (int e = tid; e < Y::kEs; e += kW) E[e] = sib[e];
-    tsync();
     if (left) {
       // prefix unchanged; suffix pulled back through the right sibling
       for (int e = tid; e < B + BB; e += kW) out[e] = par[e];
@@ -925,7 +985,7 @@ struct WideOut {
 // Node step (see the file comment).  Gradient partials per work-group: P0'_bar (B*B),
 // <A_bar, dA/dlam_M>, <A_bar, dA/dperiod>, d/ds2.
 template <class M, int MODE>
-__global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, const double* __restrict__ y,
+__global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double* __restrict__ t, const double* __restrict__ y,
                                                   int64_t n_pts, const double* __restrict__ cst,
                                                   const double* __restrict__ elems, const double* __restrict__ msgs,
                                                   WideOut out) {
@@ -953,11 +1013,33 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
   double acc_p0[kRows], acc_a[M::kNA], acc_s2 = 0.0;
   SPG_UNROLL for (int r = 0; r < kRows; ++r) acc_p0[r] = 0.0;
   SPG_UNROLL for (int f = 0; f < M::kNA; ++f) acc_a[f] = 0.0;
+  // the leaf element and the messages of node n, fetched one node ahead (see Ahead)
+  constexpr int kAll = Y::kEs + Y::kMs;
+  constexpr int NP = Ahead<B>::kOn ? (kAll + kW - 1) / kW : 1;
+  double pre[NP];
+  auto fetch = [&](int64_t it) {
+    if (it >= n_pts) return;
+    SPG_UNROLL for (int j = 0; j < NP; ++j) {
+      const int e = tid + j * kW;
+      if (e < Y::kEs) pre[j] = elems[it * Y::kEs + e];
+      else if (e < kAll) pre[j] = msgs[it * Y::kMs + e - Y::kEs];
+    }
+  };
+  if (Ahead<B>::kOn) fetch(blockIdx.x);
   for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
     const bool edge = n + 1 < n_pts;
-    for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[n * Y::kEs + e];
-    for (int e = tid; e < Y::kMs; e += kW) G_[e] = msgs[n * Y::kMs + e];
+    if (Ahead<B>::kOn) {
+      SPG_UNROLL for (int j = 0; j < NP; ++j) {
+        const int e = tid + j * kW;
+        if (e < Y::kEs) E[e] = pre[j];
+        else if (e < kAll) G_[e - Y::kEs] = pre[j];
+      }
+    } else {
+      for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[n * Y::kEs + e];
+      for (int e = tid; e < Y::kMs; e += kW) G_[e] = msgs[n * Y::kMs + e];
+    }
     tsync();
+    if (Ahead<B>::kOn) fetch(n + gridDim.x);
     const double* m = G_ + Y::km;
     const double* P = G_ + Y::kP;
     const double* A = E + Y::kA;
@@ -976,49 +1058,21 @@ __global__ __launch_bounds__(kW) void k_wide_node(const double* __restrict__ t, 
     const double* Js = G_ + Y::kMJ;
     const double* es = G_ + Y::kMeta;
     // predicted state m' = A m+ (b = 0 at a leaf), P' = sym(A P+ A^T) + Q; seed at n + 1:
-    // Gam = (I + P' J')^-1, W = sym(J' Gam), lam = Gam^T eta' - W m', Lam.  Up to b = 10 the
-    // additions and symmetrisations ride in the product phases (fewer barriers); at b = 16 the
-    // separate phases measure faster.
-    if constexpr (B <= 10) {
-      for (int e = tid; e < BB; e += kW) {
-        const int i = e / B, j = e - i * B;
-        X1[e] = mm_entry<B, false, false>(A, Pp, i, j);
-      }
-      if (tid < B) {
-        double sacc = 0.0;
-        for (int k = 0; k < B; ++k) sacc = fma(A[tid * B + k], mp[k], sacc);
-        mn[tid] = sacc;
-      }
-      tsync();
-      for (int e = tid; e < BB; e += kW) {
-        const int i = e / B, j = e - i * B;
-        Pn[e] = mm_sym_entry<B, false, true>(X1, A, i, j) + E[Y::kQ + e];
-      }
-      tsync();
-      for (int e = tid; e < BB; e += kW) {
-        const int i = e / B, j = e - i * B;
-        Mx[e] = mm_entry<B, false, false>(Pn, Js, i, j) + (i == j ? 1.0 : 0.0);
-      }
-      tsync();
-      (void)t_inv_logdet<B>(Mx, Gm, fcol);
-      for (int e = tid; e < BB; e += kW) {
-        const int i = e / B, j = e - i * B;
-        W[e] = mm_sym_entry<B, false, false>(Js, Gm, i, j);
-      }
-      tsync();
-    } else {
-      t_mv<B>(A, mp, mn);
-      t_mm<B>(A, Pp, X1);
-      t_mmt<B>(X1, A, Pn);
-      for (int e = tid; e < BB; e += kW) Pn[e] += E[Y::kQ + e];
-      tsync();
-      t_sym<B>(Pn);
-      t_mm<B>(Pn, Js, Mx);
-      t_add_eye<B>(Mx);
-      (void)t_inv_logdet<B>(Mx, Gm, fcol);
-      t_mm<B>(Js, Gm, W);
-      t_sym<B>(W);
+    // Gam = (I + P' J')^-1, W = sym(J' Gam), lam = Gam^T eta' - W m', Lam
+    mx_store<B>(mx<B, false, false>(A, Pp), X1);
+    if (tid < B) {
+      double sacc = 0.0;
+      for (int k = 0; k < B; ++k) sacc = fma(A[tid * B + k], mp[k], sacc);
+      mn[tid] = sacc;
     }
+    tsync();
+    mx_each<B>(mx_sym<B, false, true>(X1, A), [&](int i, int j, double v) { Pn[i * B + j] = v + E[Y::kQ + i * B + j]; });
+    tsync();
+    mx_each<B>(mx<B, false, false>(Pn, Js), [&](int i, int j, double v) { Mx[i * B + j] = v + (i == j ? 1.0 : 0.0); });
+    tsync();
+    (void)t_inv_logdet<B>(Mx, Gm, fcol);
+    mx_store<B>(mx_sym<B, false, false>(Js, Gm), W);
+    tsync();
     if (tid < B) {
       const int i = tid;
       double s1 = 0.0, s3 = 0.0;
