@@ -476,51 +476,71 @@ def predict_report(spg, steps, warmup):
             "ms_per_call": 1e3 * el, "merged_points_per_s": (t.shape[0] + m) / el, "steps": steps}
 
 
+# Wide-path models of the block-size sweep: (b, terms, hyperparameter row) with kind codes
+# 1 M32, 2 M52, 3 periodic, 4 M12, 5 M72, 6 quasi-periodic, 7 squared exponential; b = 10 is
+# the sum kernel, b = 12 the paper's Matern-3/2 + 10th-order squared exponential, b = 16 the
+# three-term CO2 kernel.
+BSWEEP_WIDE = [
+    (2, [(4, 0), (4, 0)], [3.0, 0.5, 20.0, 1.0, 0.05]),
+    (3, [(4, 0), (1, 0)], [3.0, 0.5, 20.0, 1.0, 0.05]),
+    (4, [(7, 4)], [8.0, 1.0, 0.05]),
+    (5, [(1, 0), (2, 0)], [3.0, 0.5, 20.0, 1.0, 0.05]),
+    (6, [(1, 0), (7, 4)], [3.0, 0.5, 8.0, 1.0, 0.05]),
+    (7, [(2, 0), (3, 1)], [20.0, 1.0, 1.0, 0.8, 10.0, 0.05]),
+    (8, [(1, 0), (7, 6)], [3.0, 0.5, 8.0, 1.0, 0.05]),
+    (9, [(2, 0), (7, 6)], [3.0, 0.5, 8.0, 1.0, 0.05]),
+    (10, [(1, 0), (3, 3)], [5.0, 2.0, 1.0, 1.0, 10.0, 0.05]),
+    (11, [(1, 0), (2, 0), (6, 2)], [3.0, 0.5, 20.0, 1.0, 1.0, 0.7, 10.0, 60.0, 0.05]),
+    (12, [(1, 0), (7, 10)], [3.0, 0.5, 8.0, 1.0, 0.05]),
+    (13, [(2, 0), (7, 10)], [3.0, 0.5, 8.0, 1.0, 0.05]),
+    (14, [(1, 0), (6, 1), (7, 8)], [3.0, 0.5, 1.0, 0.7, 10.0, 60.0, 8.0, 1.0, 0.05]),
+    (15, [(4, 0), (6, 3), (7, 6)], [3.0, 0.5, 1.0, 0.7, 10.0, 60.0, 8.0, 1.0, 0.05]),
+    (16, [(1, 0), (6, 3), (7, 6)], [0.8, 0.3, 1.0, 4.0, 1.0, 60.0, 8.0, 20.0, 0.05]),
+]
+
+
 def bsweep_report(spg, steps, warmup):
     """Block size sweep in the manner of the paper's time-versus-b experiment: logML + gradient
-    per call for Matern nu = 1/2 .. 7/2 (b = 1 .. 4), the b = 10 sum kernel and the b = 16
-    three-term model of the CO2 fit, at N = 1000 and at N = 2^20 (2^18 for b = 10 and 16),
-    eager launches on a side stream."""
+    per call for Matern nu = 1/2 .. 7/2 on the per-lane path (b = 1 .. 4, N = 1000 and 2^20) and
+    for a sum of terms on the wide-state path at every b = 2 .. 16 (N = 1000 and 2^18; t with unit
+    mean spacing, data drawn from the model), eager launches on a side stream."""
     import torch
-    from workloads import (KIND_MATERN12, KIND_MATERN32, KIND_MATERN52, KIND_MATERN72, KIND_QUASIPERIODIC,
-                           KIND_SQEXP, make_batch, make_config)
-    from workloads.generate import Workload, make_series
+    from workloads import KIND_MATERN12, KIND_MATERN32, KIND_MATERN52, KIND_MATERN72, make_batch
+    from workloads.generate import make_series
     dev = torch.device("cuda:0")
     side = torch.cuda.Stream()
     rows = []
-    cases = [(1, [(KIND_MATERN12, 0)]), (2, [(KIND_MATERN32, 0)]), (3, [(KIND_MATERN52, 0)]),
-             (4, [(KIND_MATERN72, 0)]), (10, None), (16, [(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 6)])]
-    for b, terms in cases:
-        for n in (1000, (1 << 18) if b >= 10 else (1 << 20)):
-            if terms is None:
-                w = make_config(3, n=n)
-            elif b == 16:
-                # weekly-like spacing in years, hyperparameters of the CO2-shaped stand-in
-                rng = np.random.default_rng(16)
-                tt = np.sort(rng.uniform(0.0, n / 52.0, n))
-                hy = np.array([0.8, 0.3, 1.0, 4.0, 1.0, 60.0, 8.0, 20.0, 0.05])
-                w = Workload(name="co2_terms", terms=terms, t=tt, y=make_series(tt, terms, hy, rng),
-                             offsets=np.array([0, n], dtype=np.int64), hyper=hy[None, :].copy())
-            else:
+    cases = [(1, [(KIND_MATERN12, 0)], None, "lane"), (2, [(KIND_MATERN32, 0)], None, "lane"),
+             (3, [(KIND_MATERN52, 0)], None, "lane"), (4, [(KIND_MATERN72, 0)], None, "lane")]
+    cases += [(b, terms, hy, "wide") for b, terms, hy in BSWEEP_WIDE]
+    for b, terms, hy, path in cases:
+        for n in (1000, (1 << 20) if path == "lane" else (1 << 18)):
+            if path == "lane":
                 w = make_batch([n], np.array([[5.0, 2.0, 0.05]]), terms, seed=b)
-            t, y, hyp = w.series(0)
+                t, y, hyp = w.series(0)
+            else:
+                rng = np.random.default_rng(100 + b)
+                t = np.sort(rng.uniform(0.0, float(n), n))
+                hyp = np.asarray(hy, dtype=np.float64)
+                y = make_series(t, terms, hyp, rng)
             td, yd, hd = (torch.as_tensor(a, device=dev) for a in (t, y, hyp))
             torch.cuda.synchronize()
-            h = spg.Handle(w.terms, n, stream=side)
-            h.assemble(td, yd, hd, autotune=b <= 4)
+            h = spg.Handle(terms, n, stream=side)
+            h.assemble(td, yd, hd, autotune=path == "lane")
             ll = torch.empty(1, dtype=torch.float64, device=dev)
             g = torch.empty(1, h.n_hyper, dtype=torch.float64, device=dev)
             for _ in range(warmup):
                 spg.spingp_logml_grad(h._h, ll, g)
             torch.cuda.synchronize()
-            k = steps if n <= (1 << 16) or b < 10 else max(2, steps // 4)
+            k = steps if n <= (1 << 16) or path == "lane" else max(2, steps // 10)
             t0 = time.perf_counter()
             for _ in range(k):
                 spg.spingp_logml_grad(h._h, ll, g)
             torch.cuda.synchronize()
             el = (time.perf_counter() - t0) / k
-            rows.append({"b": b, "n_points": n, "ms_per_call": 1e3 * el, "points_per_s": n / el,
-                         "tile": dict(zip(("R", "L"), spg.spingp_tile_shape(h.tile))) if b <= 4 else "wide"})
+            rows.append({"b": b, "path": path, "terms": [list(x) for x in terms], "n_points": n,
+                         "ms_per_call": 1e3 * el, "points_per_s": n / el,
+                         "tile": dict(zip(("R", "L"), spg.spingp_tile_shape(h.tile))) if path == "lane" else "wide"})
             h.close()
     return rows
 

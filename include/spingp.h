@@ -64,14 +64,14 @@ typedef enum {
 typedef enum {
   SPINGP_MATERN32 = 1,  /* Matern nu = 3/2, state (f, f'), b = 2 */
   SPINGP_MATERN52 = 2,  /* Matern nu = 5/2, b = 3 */
-  SPINGP_PERIODIC = 3,  /* periodic, `harmonics` cosine terms, b = 2 (harmonics + 1) */
+  SPINGP_PERIODIC = 3,  /* periodic, cosine terms 0..harmonics, b = 2 (harmonics + 1) */
   SPINGP_MATERN12 = 4,  /* Matern nu = 1/2 (exponential kernel), b = 1 */
   SPINGP_MATERN72 = 5,  /* Matern nu = 7/2, b = 4 */
   SPINGP_QUASIPERIODIC = 6, /* periodic times exp(-|tau| / decay), b = 2 (harmonics + 1) */
   SPINGP_SQEXP = 7          /* squared exponential by a spectral approximation of order
                                `harmonics` (a state-space form that approximates the kernel,
                                Sec. 2.2: 1 / S truncated after order + 1 terms of its series;
-                               only order 6), b = harmonics */
+                               even orders 2..10), b = harmonics */
 } spingp_kind_t;
 
 /* One additive covariance term; `harmonics` is the number of harmonics of periodic terms and
@@ -86,13 +86,17 @@ typedef struct {
  * largest problem it will see.  `stream` is a hipStream_t (NULL = the default stream).
  * Supported models: a single Matern term, nu = 1/2, 3/2, 5/2 or 7/2 (b = 1 to 4; hyperparameter
  * row (lengthscale, signal variance, noise variance), lam = sqrt(2 nu) / lengthscale), any
- * number of series up to max_series; Matern-3/2 + periodic or quasi-periodic with 3 harmonics
- * (b = 10, one series; hyperparameter row (l_M, var_M, l_P, var_P, period, s2), with the decay
- * lengthscale before s2 for the quasi-periodic term); Matern-3/2 + quasi-periodic (3 harmonics)
- * + squared exponential of order 6, the three-term model of the paper's CO2 fit (Sec. 4.3;
- * b = 16, one series; row (l_M, var_M, l_P, var_P, period, l_D, l_S, var_S, s2)).  Allocates
- * all device workspace (sized for every compiled tile shape, see spingp_tile_shape); returns
- * SPINGP_E_UNSUPPORTED for other models.
+ * number of series up to max_series; and, for one series, any other sum of up to 8 terms of
+ * these kinds with state dimension b = sum of the blocks <= 16 (Sec. 2.1: the sum of
+ * independent processes, block-diagonal state), among them the paper's Matern-3/2 + 10th-order
+ * squared exponential (b = 12, Sec. 4.2) and the three-term CO2 kernel Matern-3/2 +
+ * quasi-periodic (3 harmonics) + squared exponential of order 6 (b = 16, Sec. 4.3).  Blocks:
+ * Matern 1..4, periodic and quasi-periodic 2 (harmonics + 1) with harmonics 0..7, squared
+ * exponential its order (even, 2..10).  The hyperparameter row of a sum lists each term's in
+ * order, then the noise variance: Matern (lengthscale, variance), periodic (lengthscale,
+ * variance, period), quasi-periodic (lengthscale, variance, period, decay lengthscale),
+ * squared exponential (lengthscale, variance).  Allocates all device workspace (sized for every
+ * compiled tile shape, see spingp_tile_shape); returns SPINGP_E_UNSUPPORTED for other models.
  */
 int spingp_create(spingp_handle* out, const spingp_term* terms, int32_t n_terms, int64_t max_points,
                   int32_t max_series, void* stream);

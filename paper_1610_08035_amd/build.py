@@ -12,11 +12,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspingp.so")
-# The C-ABI unit, then one object per compiled tile shape (R points per lane, L lanes per
-# work-group); the list must match spg::tile_ops() in spingp_api.hip.
-SOURCES = ["spingp_api.hip", "spingp_wide.hip"]
+# The C-ABI unit, one object per compiled tile shape (R points per lane, L lanes per
+# work-group; the list must match spg::tile_ops() in spingp_api.hip) and one wide-state unit
+# per state dimension (spg::wide::ops()).
+SOURCES = ["spingp_api.hip"]
 TILES = [(8, 128), (8, 64), (8, 256), (4, 128), (4, 256), (16, 128)]
-HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp", "spingp_host.hpp", "spingp_series.hpp", "spingp_wide.hpp"]
+WIDE_B = list(range(2, 17))
+HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp", "spingp_host.hpp", "spingp_series.hpp", "spingp_wide.hpp",
+           "spingp_sumdesc.hpp", "spingp_sqexp_tables.hpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
@@ -51,6 +54,12 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(objdir, f"spingp_tile_R{r}_L{l}.o")
         jobs.append(([hipcc()] + HIPCC_FLAGS + inc + [f"-DSPG_TILE_R={r}", f"-DSPG_TILE_L={l}", "-c",
                                                        os.path.join(CSRC, "spingp_tile.hip"), "-o", obj], obj))
+    for b in WIDE_B:
+        obj = os.path.join(objdir, f"spingp_wide_b{b}.o")
+        jobs.append(([hipcc()] + HIPCC_FLAGS + inc + [f"-DSPG_WIDE_B={b}", "-c", os.path.join(CSRC, "spingp_wide.hip"),
+                                                       "-o", obj], obj))
+    # the wide units take longest: start them first
+    jobs.sort(key=lambda j: 0 if "wide_b" in j[1] else 1)
     workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
     with concurrent.futures.ThreadPoolExecutor(workers) as ex:
         results = list(ex.map(_compile, jobs))

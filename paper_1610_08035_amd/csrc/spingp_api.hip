@@ -90,6 +90,157 @@ bool tile_fits(int i, int64_t max_points) {
   const TileOps* T = tile_ops(i);
   return T && (T->R >= 8 || max_points <= kSmallTileMaxPoints);
 }
+
+namespace wide {
+const Ops* ops_b2();
+const Ops* ops_b3();
+const Ops* ops_b4();
+const Ops* ops_b5();
+const Ops* ops_b6();
+const Ops* ops_b7();
+const Ops* ops_b8();
+const Ops* ops_b9();
+const Ops* ops_b10();
+const Ops* ops_b11();
+const Ops* ops_b12();
+const Ops* ops_b13();
+const Ops* ops_b14();
+const Ops* ops_b15();
+const Ops* ops_b16();
+const Ops* ops(int b) {
+  switch (b) {
+    case 2: return ops_b2();
+    case 3: return ops_b3();
+    case 4: return ops_b4();
+    case 5: return ops_b5();
+    case 6: return ops_b6();
+    case 7: return ops_b7();
+    case 8: return ops_b8();
+    case 9: return ops_b9();
+    case 10: return ops_b10();
+    case 11: return ops_b11();
+    case 12: return ops_b12();
+    case 13: return ops_b13();
+    case 14: return ops_b14();
+    case 15: return ops_b15();
+    case 16: return ops_b16();
+    default: return nullptr;
+  }
+}
+
+void plan_levels(int64_t n, WideCtx& c) {
+  int k = 0;
+  int64_t off = 0;
+  for (int64_t m = n;; m = (m + 1) / 2) {
+    c.n[k] = m;
+    c.off[k] = off;
+    off += m;
+    ++k;
+    if (m == 1 || k == kMaxLevels) break;
+  }
+  c.n_levels = k;
+  const int cap = ops(c.desc.b)->node_cap();
+  c.node_grid = (int)(n < cap ? n : cap);
+}
+
+hipError_t factor(const WideCtx& c) { return ops(c.desc.b)->factor(c); }
+hipError_t down(const WideCtx& c) { return ops(c.desc.b)->down(c); }
+hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
+                double* S_sub) {
+  return ops(c.desc.b)->node(c, mode, f_mean, f_var, z_mean, S_diag, S_sub);
+}
+hipError_t finish(const WideCtx& c, double* logml, double* grad) { return ops(c.desc.b)->finish(c, logml, grad); }
+
+// The term list as a block-diagonal sum (Sec. 2.1), laid out for the kernels: block, first
+// hyperparameter, derivative channels, constants, support entries and edge scalars of every
+// term.  False for lists the wide path does not implement.
+bool describe(const spingp_term* terms, int32_t n_terms, SumDesc& d) {
+  memset(&d, 0, sizeof(d));
+  if (n_terms < 1 || n_terms > kMaxTerms) return false;
+  int s0 = 0, h0 = 0, ch = 0, c0 = 1, sup = 0, job = 0, blk = 0;
+  bool q2 = true;
+  for (int u = 0; u < n_terms; ++u) {
+    TermInfo& T = d.t[u];
+    const int kind = terms[u].kind, hm = terms[u].harmonics;
+    int nh = 0, nc = 0;
+    switch (kind) {
+      case SPINGP_MATERN12: case SPINGP_MATERN32: case SPINGP_MATERN52: case SPINGP_MATERN72:
+        T.type = kTermMatern;
+        T.order = kind == SPINGP_MATERN12 ? 1 : kind == SPINGP_MATERN32 ? 2 : kind == SPINGP_MATERN52 ? 3 : 4;
+        T.n = T.order;
+        nh = 2;
+        nc = 3;
+        T.nch = 1;
+        T.nsup = T.n * T.n;
+        T.njob = 1;
+        if (u > 0 || T.order > 2) q2 = false;
+        break;
+      case SPINGP_PERIODIC: case SPINGP_QUASIPERIODIC:
+        if (hm < 0 || hm > 7) return false;
+        T.type = kind == SPINGP_PERIODIC ? kTermPeriodic : kTermQuasi;
+        T.order = hm;
+        T.n = 2 * (hm + 1);
+        nh = kind == SPINGP_PERIODIC ? 3 : 4;
+        nc = 6 + 2 * (hm + 1);
+        T.nch = kind == SPINGP_PERIODIC ? 1 : 2;
+        T.nsup = 4 * (hm + 1);
+        T.njob = hm + 1 + (kind == SPINGP_PERIODIC ? 0 : 1);
+        if (u == 0 || kind != SPINGP_PERIODIC) q2 = false;
+        break;
+      case SPINGP_SQEXP:
+        if (hm < 2 || hm > kMaxSqExpOrder || hm % 2) return false;
+        T.type = kTermSqExp;
+        T.order = hm;
+        T.n = hm;
+        nh = 2;
+        nc = 2;
+        T.nch = 1;
+        T.nsup = hm * hm;
+        T.njob = hm / 2;
+        d.has_se = 1;
+        q2 = false;
+        break;
+      default:
+        return false;
+    }
+    T.s0 = s0;
+    T.h0 = h0;
+    T.ch0 = ch;
+    T.c0 = c0;
+    T.sup0 = sup;
+    T.job0 = job;
+    T.blk0 = blk;
+    if (T.type == kTermMatern) blk += 3 * T.n * T.n;
+    // observed states: the first of a Matern or squared-exponential block, the cosine state of
+    // every harmonic
+    for (int r = 0; r < T.n; ++r) {
+      const bool o = T.type == kTermMatern || T.type == kTermSqExp ? r == 0 : (r & 1) == 0;
+      if (o && s0 + r < kMaxB) d.obs |= 1u << (s0 + r);
+    }
+    s0 += T.n;
+    h0 += nh;
+    ch += T.nch;
+    c0 += nc;
+    sup += T.nsup;
+    job += T.njob;
+    if (s0 > kMaxB) return false;
+  }
+  if (s0 < 2 || ch > kMaxChannels || sup > kMaxSupport || job > kMaxJobs || blk > kMaxBlk || c0 > 65) return false;
+  d.nt = n_terms;
+  d.b = s0;
+  d.nh = h0 + 1;
+  d.na = ch;
+  d.ns = sup;
+  d.njob = job;
+  d.q2 = q2 ? 1 : 0;
+  d.kS2 = 0;
+  d.kScale = c0;
+  d.kP0 = d.kScale + d.b;
+  d.kP0o = d.kP0 + d.b * d.b;
+  d.kConst = d.kP0o + d.b * d.b;
+  return true;
+}
+}  // namespace wide
 }  // namespace spg
 
 struct spingp_ctx {
@@ -232,20 +383,22 @@ static void drop_graph(spingp_ctx* h) {
 }
 
 // The wide-state model: one series, all tree levels and their messages stored item-major.
-static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_series, void* stream, int model) {
+static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_series, void* stream,
+                       const spg::wide::SumDesc& desc) {
   if (max_series != 1) return SPINGP_E_UNSUPPORTED;
   if (max_points > (int64_t(1) << 31)) return SPINGP_E_UNSUPPORTED;
+  if (!spg::wide::ops(desc.b)) return SPINGP_E_UNSUPPORTED;
   spingp_ctx* h = new (std::nothrow) spingp_ctx();
   if (!h) return SPINGP_E_NOMEM;
   h->wide = true;
-  h->b = spg::wide::state_dim(model);
-  h->n_hyper = spg::wide::n_hyper(model);
+  h->b = desc.b;
+  h->n_hyper = desc.nh;
   h->max_points = max_points;
   h->max_series = 1;
   h->stream = (hipStream_t)stream;
   spg::wide::WideCtx& w = h->wplan;
   memset(&w, 0, sizeof(w));
-  w.model = model;
+  w.desc = desc;
   spg::wide::plan_levels(max_points, w);
   int64_t items = 0;
   for (int k = 0; k < w.n_levels; ++k) items += w.n[k];
@@ -253,10 +406,10 @@ static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_serie
     void** p;
     int64_t bytes;
   } reqs[] = {
-      {(void**)&w.elems, (int64_t)sizeof(double) * items * spg::wide::elem_stride(model)},
-      {(void**)&w.msgs, (int64_t)sizeof(double) * items * spg::wide::msg_stride(model)},
-      {(void**)&w.cst, (int64_t)sizeof(double) * spg::wide::const_size(model)},
-      {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride(model)},
+      {(void**)&w.elems, (int64_t)sizeof(double) * items * spg::wide::elem_stride(desc.b)},
+      {(void**)&w.msgs, (int64_t)sizeof(double) * items * spg::wide::msg_stride(desc.b)},
+      {(void**)&w.cst, (int64_t)sizeof(double) * desc.kConst},
+      {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride(desc)},
       {(void**)&h->scal, (int64_t)sizeof(double) * 8},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
   };
@@ -282,25 +435,18 @@ extern "C" int spingp_create(spingp_handle* out, const spingp_term* terms, int32
   *out = nullptr;
   int b = 0;
   bool wide = false;
-  int model = spg::wide::kModelPeriodic;
+  spg::wide::SumDesc desc;
   if (n_terms == 1 && terms[0].kind == SPINGP_MATERN12) b = 1;
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN32) b = 2;
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN52) b = 3;
   else if (n_terms == 1 && terms[0].kind == SPINGP_MATERN72) b = 4;
-  else if (n_terms == 2 && terms[0].kind == SPINGP_MATERN32 &&
-           (terms[1].kind == SPINGP_PERIODIC || terms[1].kind == SPINGP_QUASIPERIODIC) &&
-           terms[1].harmonics == 3) {
-    model = terms[1].kind == SPINGP_QUASIPERIODIC ? spg::wide::kModelQuasi : spg::wide::kModelPeriodic;
-    wide = true;
-  } else if (n_terms == 3 && terms[0].kind == SPINGP_MATERN32 && terms[1].kind == SPINGP_QUASIPERIODIC &&
-             terms[1].harmonics == 3 && terms[2].kind == SPINGP_SQEXP && terms[2].harmonics == 6) {
-    model = spg::wide::kModelQuasiSqExp;
+  else if (spg::wide::describe(terms, n_terms, desc)) {
     wide = true;
   } else {
     return SPINGP_E_UNSUPPORTED;
   }
   if (max_points > (int64_t(1) << 40)) return SPINGP_E_UNSUPPORTED;
-  if (wide) return create_wide(out, max_points, max_series, stream, model);
+  if (wide) return create_wide(out, max_points, max_series, stream, desc);
   // workspace for the most demanding tile shape the handle may use
   const bool multi = max_series > 1;
   int64_t G_max = 0, lane_ld = 0;

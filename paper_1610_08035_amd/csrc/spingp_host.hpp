@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "spingp_kernels.hpp"
+#include "spingp_sumdesc.hpp"
 
 namespace spg {
 
@@ -123,9 +124,8 @@ inline SeriesMap make_map(const LaunchCtx& c, int64_t slots) {
 constexpr int kNumTiles = 6;
 const TileOps* tile_ops(int i);
 
-// Wide-state path (Matern-3/2 + periodic or quasi-periodic with 3 harmonics, b = 10, optionally
-// plus a squared-exponential term of order 6, b = 16; one series): level-by-level reduction with
-// one wavefront per element operation (spingp_wide.hip).
+// Wide-state path (a sum of terms, b <= 16, one series): level-by-level reduction with one
+// wavefront per element operation (spingp_wide.hpp); one launch unit per state dimension.
 namespace wide {
 constexpr int kMaxLevels = 64;
 struct WideCtx {
@@ -143,27 +143,28 @@ struct WideCtx {
   int64_t n[kMaxLevels];
   int64_t off[kMaxLevels];
   int node_grid;      // work-groups of the node step (rows of part)
-  int model;          // kModel* below
+  SumDesc desc;       // the model
   const unsigned long long* status;   // the status word (data errors poison the outputs)
   uint32_t gmask;     // gradient components written by finish (bit k), the others are 0
   void (*mark)(void* arg, int kid, int end);
   void* mark_arg;
 };
-// Matern-3/2 + periodic (b = 10, 6 hyperparameters), + quasi-periodic (b = 10, 7), + quasi-periodic
-// + squared exponential of order 6 (b = 16, 9)
-constexpr int kModelPeriodic = 0, kModelQuasi = 1, kModelQuasiSqExp = 2;
-int state_dim(int model);
-int n_hyper(int model);
-int64_t elem_stride(int model);    // doubles per stored element
-int64_t msg_stride(int model);     // doubles per stored message
-int64_t const_size(int model);     // doubles of the model constants
-int64_t part_stride(int model);    // doubles per work-group partial
+// Launch sequences of one state dimension.
+struct Ops {
+  int b;
+  int (*node_cap)();                                        // resident node-step work-groups
+  hipError_t (*factor)(const WideCtx& c);                   // setup, leaves, up-sweep, root
+  hipError_t (*down)(const WideCtx& c);                     // down-sweep of all levels
+  hipError_t (*node)(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
+                     double* S_sub);                        // node step (kWant* bits)
+  hipError_t (*finish)(const WideCtx& c, double* logml, double* grad);   // gradient sum
+};
+const Ops* ops(int b);   // nullptr outside 2..kMaxB
+// Element and message strides (doubles per stored item) and the node step's partial row.
+inline int64_t elem_stride(int b) { return (3 * b * b + 2 * b + 2 + 7) / 8 * 8; }
+inline int64_t msg_stride(int b) { return (2 * b * b + 2 * b + 7) / 8 * 8; }
+inline int64_t part_stride(const SumDesc& d) { return (int64_t)d.b * d.b + d.na + 1; }
 void plan_levels(int64_t n, WideCtx& c);
-hipError_t factor(const WideCtx& c);                       // setup, leaves, up-sweep, root
-hipError_t down(const WideCtx& c);                         // down-sweep of all levels
-hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
-                double* S_sub);                            // node step (kWant* bits)
-hipError_t finish(const WideCtx& c, double* logml, double* grad);   // gradient sum
 }  // namespace wide
 
 }  // namespace spg

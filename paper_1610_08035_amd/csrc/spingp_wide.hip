@@ -1,15 +1,22 @@
-// Launch sequence of the wide-state path (see spingp_wide.hpp).
+// Launch sequence of the wide-state path for one state dimension (see spingp_wide.hpp).
+// Compiled once per b with -DSPG_WIDE_B=<b>; each object exports spg::wide::ops_b<b>().
 #include "spingp_host.hpp"
 #include "spingp_wide.hpp"
+
+#ifndef SPG_WIDE_B
+#error "SPG_WIDE_B must be defined"
+#endif
+
+#define SPG_WCAT2(a, b) a##b
+#define SPG_WCAT(a, b) SPG_WCAT2(a, b)
+#define SPG_WIDE_FN SPG_WCAT(ops_b, SPG_WIDE_B)
 
 namespace spg {
 namespace wide {
 namespace {
 
-using ModelP = SumM32Periodic<3, false>;               // Matern-3/2 + periodic
-using ModelQ = SumM32Periodic<3, true>;                // Matern-3/2 + quasi-periodic
-using ModelS = SumM32Periodic<3, true, kSqExpOrder>;   // ... + squared exponential
-static_assert(ModelP::B == ModelQ::B, "one state dimension for the two b = 10 models");
+constexpr int B = SPG_WIDE_B;
+
 // Work-group caps: every team stays resident and loops over its items, so that a launch does
 // not end with a second, partly empty round.  The cap is what fits on the device at once for
 // the kernel's registers and LDS (the occupancy query, once per kernel and process).
@@ -32,85 +39,36 @@ inline void mark(const WideCtx& c, int kid, int end) {
 }
 inline unsigned grid_for(int64_t items, int cap) { return (unsigned)(items < cap ? items : cap); }
 
-}  // namespace
+int node_cap() { return resident_groups<k_wide_node<B, kWantGrad>>(); }
 
-// Calls f with a value of the model's type.
-template <class F>
-auto with_model(int model, F&& f) {
-  if (model == kModelQuasiSqExp) return f(ModelS());
-  if (model == kModelQuasi) return f(ModelQ());
-  return f(ModelP());
-}
-
-int state_dim(int model) {
-  return with_model(model, [](auto m) { return decltype(m)::B; });
-}
-int n_hyper(int model) {
-  return with_model(model, [](auto m) { return decltype(m)::NH; });
-}
-int64_t elem_stride(int model) {
-  return with_model(model, [](auto m) { return (int64_t)Lay<decltype(m)::B>::kEs; });
-}
-int64_t msg_stride(int model) {
-  return with_model(model, [](auto m) { return (int64_t)Lay<decltype(m)::B>::kMs; });
-}
-int64_t const_size(int model) {
-  return with_model(model, [](auto m) { return (int64_t)decltype(m)::kConst; });
-}
-int64_t part_stride(int model) {
-  return with_model(model, [](auto m) { return (int64_t)decltype(m)::kPart; });
-}
-
-void plan_levels(int64_t n, WideCtx& c) {
-  int k = 0;
-  int64_t off = 0;
-  for (int64_t m = n;; m = (m + 1) / 2) {
-    c.n[k] = m;
-    c.off[k] = off;
-    off += m;
-    ++k;
-    if (m == 1 || k == kMaxLevels) break;
-  }
-  c.n_levels = k;
-  const int cap = with_model(c.model, [](auto m) {
-    return resident_groups<k_wide_node<decltype(m), kWantGrad>>();
-  });
-  c.node_grid = (int)(n < cap ? n : cap);
-}
-
-template <class Model>
-hipError_t factor_m(const WideCtx& c) {
-  constexpr int B = Model::B;
+hipError_t factor(const WideCtx& c) {
+  const SumDesc& d = c.desc;
   mark(c, kKidFwd, 0);
-  hipLaunchKernelGGL(k_wide_setup<Model>, dim3(1), dim3(kW), 0, c.stream, c.hyper, c.cst);
-  hipLaunchKernelGGL(k_wide_leaf<Model>, dim3(grid_for(c.n_points, resident_groups<k_wide_leaf<Model>>())), dim3(kW), 0,
-                     c.stream, c.t, c.y, c.n_points, c.cst, c.elems);
+  hipLaunchKernelGGL(k_wide_setup<B>, dim3(1), dim3(kW), 0, c.stream, d, c.hyper, c.cst);
+  hipLaunchKernelGGL(k_wide_leaf<B>, dim3(grid_for(c.n_points, resident_groups<k_wide_leaf<B>>())), dim3(kW), 0,
+                     c.stream, d, c.t, c.y, c.n_points, c.cst, c.elems);
   // level 1 joins leaves (rank-one node information: closed-form inverse)
   for (int k = 1; k < c.n_levels; ++k) {
     if (k == 1)
       hipLaunchKernelGGL((k_wide_up<B, true>), dim3(grid_for(c.n[k], resident_groups<k_wide_up<B, true>>())), dim3(kW),
                          0, c.stream, c.elems, c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
     else
-      hipLaunchKernelGGL((k_wide_up<B, false>), dim3(grid_for(c.n[k], resident_groups<k_wide_up<B, false>>())), dim3(kW),
-                         0, c.stream, c.elems, c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
+      hipLaunchKernelGGL((k_wide_up<B, false>), dim3(grid_for(c.n[k], resident_groups<k_wide_up<B, false>>())),
+                         dim3(kW), 0, c.stream, c.elems, c.off[k - 1], c.n[k - 1], c.off[k], c.n[k]);
   }
   mark(c, kKidFwd, 1);
   mark(c, kKidTop, 0);
-  hipLaunchKernelGGL(k_wide_root<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, c.elems, c.off[c.n_levels - 1],
+  hipLaunchKernelGGL(k_wide_root<B>, dim3(1), dim3(kW), 0, c.stream, d, c.cst, c.elems, c.off[c.n_levels - 1],
                      c.msgs, c.scal);
   mark(c, kKidTop, 1);
   return hipGetLastError();
 }
 
-hipError_t factor(const WideCtx& c) {
-  return with_model(c.model, [&](auto m) { return factor_m<decltype(m)>(c); });
-}
-
-template <int B>
-static void down_b(const WideCtx& c) {
+hipError_t down(const WideCtx& c) {
+  mark(c, kKidBwd, 0);
   // the last level's children are leaves (rank-one node information: closed-form inverse)
   for (int k = c.n_levels - 1; k >= 1; --k) {
-    if (k == 1 && c.model == kModelPeriodic)   // leaf edges: Q only in the Matern block
+    if (k == 1 && c.desc.q2)   // leaf edges: Q only in the leading 2 x 2 block
       hipLaunchKernelGGL((k_wide_down<B, true, true>),
                          dim3(grid_for(c.n[k - 1], resident_groups<k_wide_down<B, true, true>>())), dim3(kW), 0,
                          c.stream, c.elems, c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
@@ -121,25 +79,14 @@ static void down_b(const WideCtx& c) {
       hipLaunchKernelGGL((k_wide_down<B, false>), dim3(grid_for(c.n[k - 1], resident_groups<k_wide_down<B, false>>())),
                          dim3(kW), 0, c.stream, c.elems, c.msgs, c.off[k], c.off[k - 1], c.n[k - 1]);
   }
-}
-
-hipError_t down(const WideCtx& c) {
-  mark(c, kKidBwd, 0);
-  if (c.model == kModelQuasiSqExp)
-    down_b<ModelS::B>(c);
-  else
-    down_b<ModelP::B>(c);
   mark(c, kKidBwd, 1);
   return hipGetLastError();
 }
 
 template <int MODE>
-static void launch_node(const WideCtx& c, const WideOut& o) {
-  with_model(c.model, [&](auto m) {
-    hipLaunchKernelGGL((k_wide_node<decltype(m), MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.t,
-                       c.y, c.n_points, c.cst, c.elems, c.msgs, o);
-    return 0;
-  });
+void launch_node(const WideCtx& c, const WideOut& o) {
+  hipLaunchKernelGGL((k_wide_node<B, MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.desc, c.t, c.y,
+                     c.n_points, c.cst, c.elems, c.msgs, o);
 }
 
 hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,
@@ -165,22 +112,23 @@ hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, doubl
   return hipGetLastError();
 }
 
-template <class Model>
-hipError_t finish_m(const WideCtx& c, double* logml, double* grad) {
+hipError_t finish(const WideCtx& c, double* logml, double* grad) {
   mark(c, kKidReduce, 0);
   // the totals follow the rows of all node work-groups
-  double* tot = c.part + (int64_t)c.node_grid * Model::kPart;
-  hipLaunchKernelGGL(k_wide_sum<Model>, dim3((unsigned)Model::kPart), dim3(kW), 0, c.stream, c.part, c.node_grid,
-                     tot);
-  hipLaunchKernelGGL(k_wide_final<Model>, dim3(1), dim3(kW), 0, c.stream, c.cst, tot, c.scal, logml, grad, c.status,
-                     c.gmask);
+  const int kPart = B * B + c.desc.na + 1;
+  double* tot = c.part + (int64_t)c.node_grid * kPart;
+  hipLaunchKernelGGL(k_wide_sum<B>, dim3((unsigned)kPart), dim3(kW), 0, c.stream, c.part, c.node_grid, kPart, tot);
+  hipLaunchKernelGGL(k_wide_final<B>, dim3(1), dim3(kW), 0, c.stream, c.desc, c.cst, tot, c.scal, logml, grad,
+                     c.status, c.gmask);
   mark(c, kKidReduce, 1);
   return hipGetLastError();
 }
 
-hipError_t finish(const WideCtx& c, double* logml, double* grad) {
-  return with_model(c.model, [&](auto m) { return finish_m<decltype(m)>(c, logml, grad); });
-}
+const Ops kOps = {B, node_cap, factor, down, node, finish};
+
+}  // namespace
+
+const Ops* SPG_WIDE_FN() { return &kOps; }
 
 }  // namespace wide
 }  // namespace spg

@@ -1,14 +1,15 @@
-// Wide-state path for one series: Matern-3/2 plus a periodic or quasi-periodic term with 3
-// harmonics (b = 10), optionally plus a squared-exponential term of order 6 (b = 16), the sums
-// of the paper's CO2 kernel (Sec. 4.3) in state-space form (Sec. 2.1; the periodic term by its
-// truncated Bessel-weighted cosine series, the squared exponential by its spectral
-// approximation).
+// Wide-state path for one series: a sum of covariance terms (Matern-1/2 .. 7/2, periodic and
+// quasi-periodic with any number of harmonics, squared exponential by its spectral
+// approximation of even order up to 10), state dimension b up to 16, in state-space form
+// (Sec. 2.1); the model is described at run time (spingp_sumdesc.hpp), the kernels are
+// compiled once per b.  The paper's kernels are such sums: Matern-3/2 + 10th-order squared
+// exponential (b = 12, Sec. 4.2), the CO2 kernel (Sec. 4.3).
 //
 // The per-lane kernels keep a whole chain element in registers; at b = 10 an element has 322
 // doubles, so here one wavefront (a "team" of 64 lanes, one work-group) works on one element
-// operation at a time with its b x b blocks staged in LDS, every lane owning a few matrix
-// entries.  The cyclic reduction runs level by level over all N nodes (one node per
-// leaf), one launch per level:
+// operation at a time with its b x b blocks staged in LDS, its products on the matrix cores.
+// The cyclic reduction runs level by level over all N nodes (one node per leaf), one launch
+// per level:
 //   up-sweep   level k element i = E(k-1, 2i) (x) E(k-1, 2i+1)      (odd-even reduction)
 //   down-sweep messages of level k-1 from those of level k: the predicted state (m, P)
 //              entering an element's left node (prefix) and the information (J, eta) that
@@ -21,19 +22,22 @@
 //                A_bar = lam m+^T + 2 Lam A (P+ - P0),  P0_bar += Lam - A^T Lam A
 //              and the noise variance by the posterior expectation of d log N(y; h z, s2).
 //
-// State basis.  The model's natural state is block diagonal (Matern block, then one rotation
-// block per harmonic) with observation vector h = (1, 0, 1, 0, ...).  The kernels run in the
-// basis z' = T z with T = I except row 0 = h^T, where the observation is e_0 (so the node
-// information is rank one in entry (0, 0)); A' = T A T^-1, Q' = T Q T^T, P0' = T P0 T^T.
-// State outputs are mapped back with T^-1, gradients with T^T (.) T^-T.
+// State basis.  The model's natural state is block diagonal (one block per term) with an
+// observation vector h of ones and zeros.  The kernels run in the basis z' = T z with T = I
+// except row 0 = h^T (state 0, the first state of the first term, is always observed), where
+// the observation is e_0 (so the node information is rank one in entry (0, 0)); A' = T A T^-1,
+// Q' = T Q T^T, P0' = T P0 T^T.  State outputs are mapped back with T^-1, gradients with
+// T^T (.) T^-T.
 #pragma once
 #include "spingp_device.hpp"
 #include "spingp_sqexp_tables.hpp"
+#include "spingp_sumdesc.hpp"
 
 namespace spg {
 namespace wide {
 
 constexpr int kW = 64;  // lanes per team (one wavefront, one work-group)
+static_assert(kSqExpMaxOrder == kMaxSqExpOrder, "generated tables cover every supported order");
 
 SPG_DEV void tsync() { lds_barrier(); }   // teams exchange data through LDS only
 
@@ -466,199 +470,316 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
 }
 
 // ---------------------------------------------------------------------------- the model
-// Matern-3/2 (state 0..1) + periodic with NJ harmonics (states 2 + 2j, 3 + 2j for j = 0..NJ),
-// optionally followed by a squared-exponential term of order NSE (states kS0 .. B - 1).
-// Hyperparameter row: (l_M, var_M, l_P, var_P, period, [l_D], [l_S, var_S], s2).  The periodic
-// term is the truncated cosine series of the periodic kernel with weights
-//   q_j^2 = var_P c_j exp(-x) I_j(x),  x = 1 / l_P^2,  c_0 = 1, c_j = 2,
-// its harmonic j is a rotation by j w dt (w = 2 pi / period) with Q = 0.
-// QUASI: the periodic term times an exponential decay exp(-|tau| / l_D) (the quasi-periodic
-// term); every harmonic block is e^{-dt / l_D} times the rotation and has
-// Q = q_j^2 (1 - e^{-2 dt / l_D}) I.
-// NSE > 0: the squared exponential by its spectral approximation (state f, f', ..., f^(NSE-1),
-// lam_S = 1 / l_S), kept in the scaled state f^(k) / lam_S^k: there the transition is
-// expm(C1 lam_S dt) = 2 Re sum_k Z_k e^{r_k lam_S dt} over the stable roots with Im r_k > 0 and
-// P0 = var_S P1 (tables generated from the unit-lengthscale companion matrix C1), with no powers
-// of lam_S (in the original basis P0 spans lam_S^(2 NSE - 2), which FP64 cannot carry for short
-// lengthscales).  The observation is unchanged (the scale of f is 1); state outputs are scaled
-// back by lam_S^k.  Its block of P0 is dense, and every Q is formed as P0 - A P0 A^T.
-template <int NJ, bool QUASI = false, int NSE = 0>
-struct SumM32Periodic {
-  static constexpr int kNJ = NJ;
-  static constexpr int kS0 = 2 + 2 * (NJ + 1);        // first state of the squared exponential
-  static constexpr int B = kS0 + NSE;
-  static constexpr int NH = 6 + (QUASI ? 1 : 0) + (NSE ? 2 : 0);
-  // derivative channels of the transition: d/dlam_M, d/dperiod, [d/dlam_D], [d/dlam_S]
-  static constexpr int kNA = 2 + (QUASI ? 1 : 0) + (NSE ? 1 : 0);
-  static constexpr int kDec = 2, kDS = QUASI ? 3 : 2;
-  // scalar gradient sums of the node step: <A_bar, dA/dtheta> for the kNA channels, d/ds2
-  static constexpr int kExtra = kNA + 1;
-  static constexpr int kPart = B * B + kExtra;
-  static constexpr bool kQFromP0 = NSE > 0;
-  // transition entries whose derivative is nonzero: the 2 x 2 blocks, then the SE block
-  static constexpr int kNS = 2 * kS0 + NSE * NSE;
-  // constants shared by all kernels of one call, computed by k_wide_setup into global memory:
-  // scalars, lam_S^k, q_j^2, dq_j^2/dx, P0' = T P0 T^T
-  static constexpr int kLamM = 0, kVarM = 1, kEllP = 2, kVarP = 3, kPer = 4, kS2 = 5, kW0 = 6, kX = 7, kLamD = 8;
-  static constexpr int kLamS = 9, kVarS = 10, kLPow = 11;
-  static constexpr int kQ2 = kLPow + NSE, kDQ2 = kQ2 + NJ + 1, kP0 = kDQ2 + NJ + 1;
-  static constexpr int kConst = kP0 + B * B;
-  static_assert(NSE == 0 || NSE == kSqExpOrder, "squared-exponential order of the generated tables");
+// A sum of terms (spingp_sumdesc.hpp), each a block of the state:
+//   Matern-nu, m = nu + 1/2 states (f and its derivatives), lam = sqrt(2 nu) / l: the closed
+//     forms of spingp_device.hpp (transition, stationary covariance, d/dlam);
+//   periodic with J harmonics: the truncated cosine series of the periodic kernel with weights
+//     q_h^2 = var_P c_h exp(-x) I_h(x), x = 1 / l_P^2, c_0 = 1, c_h = 2; harmonic h is a
+//     rotation by h w dt (w = 2 pi / period) with Q = 0;
+//   quasi-periodic: the periodic term times exp(-|tau| / l_D): every harmonic block is
+//     e^{-dt / l_D} times the rotation and has Q = q_h^2 (1 - e^{-2 dt / l_D}) I;
+//   squared exponential of even order n by its spectral approximation (state f, f', ...,
+//     f^(n-1), lam = 1 / l), kept in the scaled state f^(k) / lam^k: there the transition is
+//     expm(C1 lam dt) = 2 Re sum_k Z_k e^{r_k lam dt} over the stable roots with Im r_k > 0
+//     and P0 = var P1 (tables from the unit-lengthscale companion matrix C1), with no powers
+//     of lam (in the original basis P0 spans lam^(2 n - 2), which FP64 cannot carry for short
+//     lengthscales); its Q is formed as P0 - A P0 A^T.  State outputs are scaled back by lam^k.
+// Hyperparameters per term in list order: Matern (l, var), periodic (l_P, var_P, period),
+// quasi-periodic (l_P, var_P, period, l_D), squared exponential (l, var); then s2.
+// Term constants (from c0): Matern lam, var, l; periodic and quasi-periodic l_P, var_P,
+// period, w, x, lam_D (quasi-periodic), q_h^2 (J + 1), dq_h^2/dx (J + 1); squared exp. lam, var.
+template <int B>
+struct Consts {
+  // s2, at most 64 doubles of term constants, the output scale, P0', P0
+  static constexpr int kMax = 1 + 64 + B + 2 * B * B;
+};
 
-  // constants from the hyperparameter row
-  SPG_DEV static void scalars(const double* hyper, double* c) {
-    c[kLamM] = 1.7320508075688772935 / hyper[0];
-    c[kVarM] = hyper[1];
-    c[kEllP] = hyper[2];
-    c[kVarP] = hyper[3];
-    c[kPer] = hyper[4];
-    c[kLamD] = QUASI ? 1.0 / hyper[5] : 0.0;
-    c[kS2] = hyper[NH - 1];
-    c[kW0] = 6.283185307179586477 / hyper[4];
-    c[kX] = 1.0 / (hyper[2] * hyper[2]);
-    if (NSE) {
-      const int p = QUASI ? 6 : 5;
-      const double lam = 1.0 / hyper[p];
-      c[kLamS] = lam;
-      c[kVarS] = hyper[p + 1];
-      double pw = 1.0;
-      for (int k = 0; k < NSE; ++k, pw *= lam) c[kLPow + k] = pw;
-    }
-  }
+SPG_DEV bool observed(const SumDesc& d, int k) { return ((d.obs >> k) & 1u) != 0u; }
+// T (row 0 = h^T, identity below) and T^-1 (row 0 = (1, -h_1, ..., -h_{B-1}), identity below)
+SPG_DEV double T_at(const SumDesc& d, int i, int j) {
+  return i == 0 ? (observed(d, j) ? 1.0 : 0.0) : (i == j ? 1.0 : 0.0);
+}
+SPG_DEV double Ti_at(const SumDesc& d, int i, int j) {
+  if (i == 0) return j == 0 ? 1.0 : (observed(d, j) ? -1.0 : 0.0);
+  return i == j ? 1.0 : 0.0;
+}
+// entry (i, j) of T^T X T^-T for a row-major X in LDS, from the sparsity of T:
+// (X T^-T)[k][0] = X[k][0] - sum over observed l >= 1 of X[k][l], (X T^-T)[k][j] = X[k][j]
+// for j >= 1; (T^T Y)[i][j] = Y[i][j] + [i >= 1 observed] Y[0][j]
+template <int B>
+SPG_DEV double abar_orig(const SumDesc& d, const double* X, int i, int j) {
+  auto y = [&](int k) {
+    double v = X[k * B + j];
+    if (j == 0)
+      for (int l = 1; l < B; ++l)
+        if (observed(d, l)) v -= X[k * B + l];
+    return v;
+  };
+  double r = y(i);
+  if (i >= 1 && observed(d, i)) r += y(0);
+  return r;
+}
 
-  SPG_DEV static bool observed(int k) {
-    return k == 0 || (k >= 2 && k < kS0 && (k & 1) == 0) || (NSE > 0 && k == kS0);
-  }
-  // T (row 0 = h^T, identity below) and T^-1 (row 0 = (1, -h_1, ..., -h_{B-1}), identity below)
-  SPG_DEV static double T_at(int i, int j) { return i == 0 ? (observed(j) ? 1.0 : 0.0) : (i == j ? 1.0 : 0.0); }
-  SPG_DEV static double Ti_at(int i, int j) {
-    if (i == 0) return j == 0 ? 1.0 : (observed(j) ? -1.0 : 0.0);
-    return i == j ? 1.0 : 0.0;
-  }
-  // entry (i, j) of T^T X T^-T for a row-major X in LDS, from the sparsity of T:
-  // (X T^-T)[k][0] = X[k][0] - sum over observed l >= 1 of X[k][l], (X T^-T)[k][j] = X[k][j]
-  // for j >= 1; (T^T Y)[i][j] = Y[i][j] + [i >= 1 observed] Y[0][j]
-  SPG_DEV static double abar_orig(const double* X, int i, int j) {
-    auto y = [&](int k) {
-      double v = X[k * B + j];
-      if (j == 0)
-        for (int l = 1; l < B; ++l)
-          if (observed(l)) v -= X[k * B + l];
-      return v;
-    };
-    double r = y(i);
-    if (i >= 1 && observed(i)) r += y(0);
-    return r;
-  }
-  // support entry s < kNS of the transition derivatives
-  SPG_DEV static void support(int s, int& i, int& j) {
-    if (s < 2 * kS0) {
-      const int blk = s >> 2;
-      i = 2 * blk + ((s >> 1) & 1);
-      j = 2 * blk + (s & 1);
-    } else {
-      const int e = s - 2 * kS0;
-      i = kS0 + e / (NSE ? NSE : 1);
-      j = kS0 + e % (NSE ? NSE : 1);
+// Matern block of order m (1..4) over dt, written to eb (m^2 each, row-major): with DERIV the
+// derivative dA/dlam at eb[2 m^2] (the node step), else the transition A at eb[0] and
+// Q = P0 - A P0 A^T at eb[m^2] (the leaves).
+template <int M, bool DERIV>
+SPG_DEV void matern_block_m(const double* ct, double dt, double* eb) {
+  SeriesPar p;
+  p.lam = ct[0];
+  p.var = ct[1];
+  p.ell = ct[2];
+  p.s2 = 1.0;
+  double e, A[M][M];
+  Matern<M>::transition(p, dt, e, A);
+  if (DERIV) {
+    SPG_UNROLL for (int r = 0; r < M; ++r) SPG_UNROLL for (int c = 0; c < M; ++c) {
+      double Ab[M][M];
+      SPG_UNROLL for (int k = 0; k < M; ++k) SPG_UNROLL for (int l = 0; l < M; ++l) Ab[k][l] = (k == r && l == c) ? 1.0 : 0.0;
+      eb[2 * M * M + r * M + c] = Matern<M>::dA_dlam_dot(p, dt, e, Ab);
     }
-  }
-  // entry (i, j) of the original-basis transition, its derivatives (the kNA channels) and of
-  // the closed-form Q (not used when kQFromP0)
-  SPG_DEV static void edge_entry(const double* c, double dt, int i, int j, double& a, double& q, double* da) {
-    a = q = 0.0;
-    SPG_UNROLL for (int f = 0; f < kNA; ++f) da[f] = 0.0;
-    if (i < 2 && j < 2) {
-      const double lam = c[kLamM], var = c[kVarM];
-      const double x = lam * dt, e = exp(-lam * dt);
-      const double A2[2][2] = {{e * (1.0 + x), e * dt}, {-e * lam * x, e * (1.0 - x)}};
-      const double P2[2] = {var, var * lam * lam};
-      a = A2[i][j];
-      q = (i == j ? P2[i] : 0.0) - (A2[i][0] * P2[0] * A2[j][0] + A2[i][1] * P2[1] * A2[j][1]);
-      const double D2[2][2] = {{-dt * x, -dt * dt}, {x * (x - 2.0), dt * (x - 2.0)}};
-      da[0] = e * D2[i][j];
-    } else if (i >= 2 && j >= 2 && i < kS0 && j < kS0 && ((i - 2) >> 1) == ((j - 2) >> 1)) {
-      const int h = (i - 2) >> 1;
-      const int ri = (i - 2) & 1, rj = (j - 2) & 1;
-      const double th = (double)h * c[kW0] * dt;
-      double sn, cs;
-      sincos(th, &sn, &cs);
-      // [[cos, -sin], [sin, cos]] and its derivative in theta, times d theta / d period
-      const double R[2][2] = {{cs, -sn}, {sn, cs}};
-      const double dR[2][2] = {{-sn, -cs}, {cs, -sn}};
-      const double ed = QUASI ? exp(-c[kLamD] * dt) : 1.0;
-      a = ed * R[ri][rj];
-      da[1] = ed * dR[ri][rj] * (-th / c[kPer]);
-      if (QUASI) {
-        da[kDec] = -dt * a;
-        if (ri == rj) q = c[kQ2 + h] * (1.0 - ed * ed);
+  } else {
+    double P[M][M];
+    Matern<M>::pinf(p, P);
+    SPG_UNROLL for (int r = 0; r < M; ++r) {
+      double T[M];
+      SPG_UNROLL for (int c = 0; c < M; ++c) {
+        double s = 0.0;
+        SPG_UNROLL for (int k = 0; k < M; ++k) s = fma(A[r][k], P[k][c], s);
+        T[c] = s;
       }
-    } else if (NSE > 0 && i >= kS0 && j >= kS0) {
-      // scaled state: A = E(lam dt) = expm(C1 lam dt),  dA/dlam = dt C1 E(lam dt)
-      const int r = i - kS0, cc = j - kS0;
-      const double lam = c[kLamS], x = lam * dt;
+      SPG_UNROLL for (int c = 0; c < M; ++c) {
+        double s = P[r][c];
+        SPG_UNROLL for (int k = 0; k < M; ++k) s = fma(-T[k], A[c][k], s);
+        eb[r * M + c] = A[r][c];
+        eb[M * M + r * M + c] = s;
+      }
+    }
+  }
+}
+template <bool DERIV>
+SPG_DEV void matern_block(int m, const double* ct, double dt, double* eb) {
+  switch (m) {
+    case 1: matern_block_m<1, DERIV>(ct, dt, eb); break;
+    case 2: matern_block_m<2, DERIV>(ct, dt, eb); break;
+    case 3: matern_block_m<3, DERIV>(ct, dt, eb); break;
+    default: matern_block_m<4, DERIV>(ct, dt, eb); break;
+  }
+}
+template <int M>
+SPG_DEV double matern_p0_m(const double* ct, int r, int c) {
+  SeriesPar p;
+  p.lam = ct[0];
+  p.var = ct[1];
+  p.ell = ct[2];
+  p.s2 = 1.0;
+  double P[M][M];
+  Matern<M>::pinf(p, P);
+  double v = 0.0;
+  SPG_UNROLL for (int k = 0; k < M; ++k) SPG_UNROLL for (int l = 0; l < M; ++l) v = (k == r && l == c) ? P[k][l] : v;
+  return v;
+}
+SPG_DEV double matern_p0(int m, const double* ct, int r, int c) {
+  switch (m) {
+    case 1: return matern_p0_m<1>(ct, r, c);
+    case 2: return matern_p0_m<2>(ct, r, c);
+    case 3: return matern_p0_m<3>(ct, r, c);
+    default: return matern_p0_m<4>(ct, r, c);
+  }
+}
+// <Pb block, P0 / var> and <Pb block, dP0/dlam> of a Matern block
+template <int M>
+SPG_DEV void matern_grad_m(const double* ct, const double* Pb, int ld, double& gvar, double& glam) {
+  SeriesPar p;
+  p.lam = ct[0];
+  p.var = ct[1];
+  p.ell = ct[2];
+  p.s2 = 1.0;
+  double P[M][M], dP[M][M];
+  Matern<M>::pinf(p, P);
+  Matern<M>::dpinf_dlam(p, dP);
+  gvar = glam = 0.0;
+  SPG_UNROLL for (int r = 0; r < M; ++r) SPG_UNROLL for (int c = 0; c < M; ++c) {
+    gvar = fma(Pb[r * ld + c], P[r][c] / p.var, gvar);
+    glam = fma(Pb[r * ld + c], dP[r][c], glam);
+  }
+}
+SPG_DEV void matern_grad(int m, const double* ct, const double* Pb, int ld, double& gvar, double& glam) {
+  switch (m) {
+    case 1: matern_grad_m<1>(ct, Pb, ld, gvar, glam); break;
+    case 2: matern_grad_m<2>(ct, Pb, ld, gvar, glam); break;
+    case 3: matern_grad_m<3>(ct, Pb, ld, gvar, glam); break;
+    default: matern_grad_m<4>(ct, Pb, ld, gvar, glam); break;
+  }
+}
+
+// The transcendental scalars of an edge of length dt, one lane per scalar, into es (two
+// doubles each): (cos, sin) of h w dt per harmonic and exp(-dt / l_D) (quasi-periodic),
+// e^{r_k lam dt} as (re, im) per root (squared exponential); a Matern term's lane writes its
+// whole block to eb.
+template <bool DERIV>
+SPG_DEV void edge_scalars(const SumDesc& d, const TermInfo* tt, const double* c, double dt, double* es, double* eb) {
+  const int tid = threadIdx.x;
+  for (int u = 0; u < d.nt; ++u) {
+    const TermInfo T = tt[u];
+    const int q = tid - T.job0;
+    if (q < 0 || q >= T.njob) continue;
+    const double* ct = c + T.c0;
+    double v0 = 0.0, v1 = 0.0;
+    if (T.type == kTermMatern) {
+      matern_block<DERIV>(T.order, ct, dt, eb + T.blk0);
+    } else if (T.type == kTermSqExp) {
+      const double x = ct[0] * dt;
+      const int o = kSqExpRootOff[T.order / 2 - 1] + q;
+      const double m = exp(kSqExpRootRe[o] * x);
+      double sn, cs;
+      sincos(kSqExpRootIm[o] * x, &sn, &cs);
+      v0 = m * cs;
+      v1 = m * sn;
+    } else if (q <= T.order) {
+      double sn, cs;
+      sincos((double)q * ct[3] * dt, &sn, &cs);
+      v0 = cs;
+      v1 = sn;
+    } else {
+      v0 = exp(-ct[5] * dt);
+    }
+    es[2 * tid] = v0;
+    es[2 * tid + 1] = v1;
+  }
+}
+
+// Entry (i, j) of the original-basis transition over dt (edge scalars es), its closed-form
+// process noise (squared-exponential blocks excepted: 0 here, formed as P0 - A P0 A^T by the
+// team) and its derivatives in the term's channels (da0, da1).
+SPG_DEV void edge_entry(const SumDesc& d, const TermInfo* tt, const double* c, const double* es, const double* eb,
+                        double dt, int i, int j, double& a, double& q, double& da0, double& da1) {
+  a = q = da0 = da1 = 0.0;
+  for (int u = 0; u < d.nt; ++u) {
+    const TermInfo T = tt[u];
+    const int r = i - T.s0, cc = j - T.s0;
+    if (r < 0 || r >= T.n || cc < 0 || cc >= T.n) continue;
+    const double* ct = c + T.c0;
+    if (T.type == kTermMatern) {
+      const int m = T.n, o = T.blk0 + r * m + cc;
+      a = eb[o];
+      q = eb[o + m * m];
+      da0 = eb[o + 2 * m * m];
+    } else if (T.type == kTermSqExp) {
+      // scaled state: A = E(lam dt) = expm(C1 lam dt), dA/dlam = dt C1 E(lam dt)
+      const int n = T.order, h = n / 2;
+      const int zo = kSqExpZOff[h - 1] + (r * n + cc) * h, ro = kSqExpRootOff[h - 1];
       double s = 0.0, ds = 0.0;
-      SPG_UNROLL for (int k = 0; k < NSE / 2; ++k) {
-        const double re = kSqExpRootRe[k], im = kSqExpRootIm[k];
-        double sn, cs;
-        sincos(im * x, &sn, &cs);
-        const double m = exp(re * x);
-        const double er = m * cs, ei = m * sn;                  // e^{r_k x}
-        const double zr = kSqExpZRe[(r * NSE + cc) * (NSE / 2) + k], zi = kSqExpZIm[(r * NSE + cc) * (NSE / 2) + k];
+      for (int k = 0; k < h; ++k) {
+        const double er = es[2 * (T.job0 + k)], ei = es[2 * (T.job0 + k) + 1];
+        const double zr = kSqExpZRe[zo + k], zi = kSqExpZIm[zo + k];
         const double pr = zr * er - zi * ei, pi = zr * ei + zi * er;   // Z e^{r x}
         s += pr;
-        ds += re * pr - im * pi;                                  // Re(r Z e^{r x})
+        ds += kSqExpRootRe[ro + k] * pr - kSqExpRootIm[ro + k] * pi;  // Re(r Z e^{r x})
       }
       a = 2.0 * s;
-      da[kDS] = 2.0 * dt * ds;
+      da0 = 2.0 * dt * ds;
+    } else {
+      const int h = r >> 1;
+      if ((cc >> 1) != h) continue;
+      const int ri = r & 1, rj = cc & 1;
+      const double cs = es[2 * (T.job0 + h)], sn = es[2 * (T.job0 + h) + 1];
+      // [[cos, -sin], [sin, cos]] and its derivative in the angle [[-sin, -cos], [cos, -sin]],
+      // times d angle / d period
+      const double rv = ri == rj ? cs : (ri == 0 ? -sn : sn);
+      const double drv = ri == rj ? -sn : (ri == 0 ? -cs : cs);
+      const double th = (double)h * ct[3] * dt;
+      const bool quasi = T.type == kTermQuasi;
+      const double ed = quasi ? es[2 * (T.job0 + T.order + 1)] : 1.0;
+      a = ed * rv;
+      da0 = ed * drv * (-th / ct[2]);
+      if (quasi) {
+        da1 = -dt * a;
+        if (ri == rj) q = ct[6 + h] * (1.0 - ed * ed);
+      }
     }
   }
-  // entry (i, j) of the original-basis P0
-  SPG_DEV static double p0_entry(const double* c, int i, int j) {
-    if (i < kS0 || j < kS0) {
-      if (i != j) return 0.0;
-      if (i == 0) return c[kVarM];
-      if (i == 1) return c[kVarM] * c[kLamM] * c[kLamM];
-      return c[kQ2 + ((i - 2) >> 1)];
-    }
-    return c[kVarS] * kSqExpP1[(i - kS0) * NSE + (j - kS0)];
+}
+
+// Entry (i, j) of the original-basis stationary covariance P0.
+SPG_DEV double p0_entry(const SumDesc& d, const TermInfo* tt, const double* c, int i, int j) {
+  double v = 0.0;
+  for (int u = 0; u < d.nt; ++u) {
+    const TermInfo T = tt[u];
+    const int r = i - T.s0, cc = j - T.s0;
+    if (r < 0 || r >= T.n || cc < 0 || cc >= T.n) continue;
+    const double* ct = c + T.c0;
+    if (T.type == kTermMatern) v = matern_p0(T.order, ct, r, cc);
+    else if (T.type == kTermSqExp) v = ct[1] * kSqExpP1[kSqExpP1Off[T.order / 2 - 1] + r * T.n + cc];
+    else v = r == cc ? ct[6 + (r >> 1)] : 0.0;
   }
-  // factor from the working state k back to the model's state (lam_S^k on the scaled block)
-  SPG_DEV static double out_scale(const double* c, int k) { return (NSE > 0 && k >= kS0) ? c[kLPow + k - kS0] : 1.0; }
-  // gradient of the raw hyperparameters from the summed partials: tot[B*B + f] are the scalar
-  // sums, Pb the original-basis P0_bar
-  SPG_DEV static void final_grad(const double* c, const double* tot, const double* Pb, double* grad) {
-    constexpr int BB = B * B;
-    const double lam = c[kLamM], ell = c[kEllP];
-    // Matern block and harmonics: P0 is diagonal there
-    double g_lam = tot[BB + 0] + Pb[1 * B + 1] * 2.0 * c[kVarM] * lam;
-    const double g_varm = Pb[0] + Pb[1 * B + 1] * lam * lam;
-    double g_ellp = 0.0, g_varp = 0.0;
-    for (int k = 2; k < kS0; ++k) {
-      const int h = (k - 2) >> 1;
-      const double pb = Pb[k * B + k];
-      g_ellp = fma(pb, c[kDQ2 + h] * (-2.0 / (ell * ell * ell)), g_ellp);
-      g_varp = fma(pb, c[kQ2 + h] / c[kVarP], g_varp);
+  return v;
+}
+
+// Support entry s (an entry of the transition with a derivative) -> (i, j) and its term.
+SPG_DEV int support(const SumDesc& d, const TermInfo* tt, int s, int& i, int& j) {
+  int term = 0;
+  i = j = 0;
+  for (int u = 0; u < d.nt; ++u) {
+    const TermInfo T = tt[u];
+    const int l = s - T.sup0;
+    if (l < 0 || l >= T.nsup) continue;
+    term = u;
+    if (T.type == kTermMatern || T.type == kTermSqExp) {
+      i = T.s0 + l / T.n;
+      j = T.s0 + l % T.n;
+    } else {
+      const int h = l >> 2;
+      i = T.s0 + 2 * h + ((l >> 1) & 1);
+      j = T.s0 + 2 * h + (l & 1);
     }
-    const double ellm = 1.7320508075688772935 / lam;
-    grad[0] = g_lam * (-lam / ellm);
-    grad[1] = g_varm;
-    grad[2] = g_ellp;
-    grad[3] = g_varp;
-    grad[4] = tot[BB + 1];
-    int p = 5;
-    if (QUASI) grad[p++] = tot[BB + kDec] * (-c[kLamD] * c[kLamD]);   // d lam_D / d l_D = -lam_D^2
-    if (NSE) {
-      // in the scaled state P0 = var_S P1 does not depend on lam_S
-      const double ls = c[kLamS];
-      double g_vs = 0.0;
-      for (int i = kS0; i < B; ++i)
-        for (int j = kS0; j < B; ++j) g_vs = fma(Pb[i * B + j], kSqExpP1[(i - kS0) * NSE + (j - kS0)], g_vs);
-      grad[p++] = tot[BB + kDS] * (-ls * ls);                           // d lam_S / d l_S
-      grad[p++] = g_vs;
-    }
-    grad[p] = tot[BB + kNA];
   }
-};
+  return term;
+}
+
+// Gradient of the raw hyperparameters from the summed partials: tot[B*B + f] are the channel
+// sums, tot[B*B + na] the noise sum, Pb the original-basis P0_bar (one lane).
+template <int B>
+SPG_DEV void final_grad(const SumDesc& d, const TermInfo* tt, const double* c, const double* tot, const double* Pb, double* grad) {
+  constexpr int BB = B * B;
+  for (int u = 0; u < d.nt; ++u) {
+    const TermInfo T = tt[u];
+    const double* ct = c + T.c0;
+    const double* pb = Pb + T.s0 * B + T.s0;
+    double* g = grad + T.h0;
+    if (T.type == kTermMatern) {
+      double gvar, glam;
+      matern_grad(T.order, ct, pb, B, gvar, glam);
+      const double lam = ct[0], ell = ct[2];
+      g[0] = (tot[BB + T.ch0] + glam) * (-lam / ell);   // d lam / d l = -lam / l
+      g[1] = gvar;
+    } else if (T.type == kTermSqExp) {
+      // in the scaled state P0 = var P1 does not depend on lam
+      const double lam = ct[0];
+      const int po = kSqExpP1Off[T.order / 2 - 1];
+      double gv = 0.0;
+      for (int r = 0; r < T.n; ++r)
+        for (int cc = 0; cc < T.n; ++cc) gv = fma(pb[r * B + cc], kSqExpP1[po + r * T.n + cc], gv);
+      g[0] = tot[BB + T.ch0] * (-lam * lam);   // d lam / d l = -lam^2
+      g[1] = gv;
+    } else {
+      // P0 is diagonal in the harmonic blocks
+      const double ell = ct[0], var = ct[1];
+      double gl = 0.0, gv = 0.0;
+      for (int r = 0; r < T.n; ++r) {
+        const int h = r >> 1;
+        const double v = pb[r * B + r];
+        gl = fma(v, ct[7 + T.order + h] * (-2.0 / (ell * ell * ell)), gl);
+        gv = fma(v, ct[6 + h] / var, gv);
+      }
+      g[0] = gl;
+      g[1] = gv;
+      g[2] = tot[BB + T.ch0];
+      if (T.type == kTermQuasi) g[3] = tot[BB + T.ch0 + 1] * (-ct[5] * ct[5]);   // d lam_D / d l_D
+    }
+  }
+  grad[d.nh - 1] = tot[BB + d.na];
+}
 
 // exp(-x) I_j(x) by its power series, summed in log space (no overflow for large x).
 SPG_DEV double bessel_ive(int j, double x) {
@@ -678,106 +799,153 @@ SPG_DEV double bessel_ive(int j, double x) {
 
 // ---------------------------------------------------------------------------- kernels
 // Model constants from the hyperparameter row (one work-group).
-template <class M>
-__global__ __launch_bounds__(kW) void k_wide_setup(const double* __restrict__ hyper, double* __restrict__ cst) {
-  constexpr int B = M::B;
-  __shared__ double c[M::kConst];
-  __shared__ double P0[B * B], X[B * B];
+template <int B>
+__global__ __launch_bounds__(kW) void k_wide_setup(SumDesc d, const double* __restrict__ hyper,
+                                                   double* __restrict__ cst) {
+  constexpr int BB = B * B;
+  __shared__ double c[Consts<B>::kMax];
+  __shared__ double X[BB];
+  __shared__ TermInfo tt[kMaxTerms];
   const int tid = threadIdx.x;
-  for (int e = tid; e < M::kConst; e += kW) c[e] = 0.0;
+  if (tid < d.nt) tt[tid] = d.t[tid];
+  for (int e = tid; e < d.kConst; e += kW) c[e] = 0.0;
   tsync();
-  if (tid == 0) M::scalars(hyper, c);
-  tsync();
-  // q_j^2 and dq_j^2 / dx, with d(e^-x I_j)/dx = (I_{j-1} + I_{j+1}) e^-x / 2 - e^-x I_j
-  constexpr int NJ = M::kNJ;
-  if (tid <= NJ) {
-    const double x = c[M::kX], cj = tid == 0 ? 1.0 : 2.0;
-    const double i0 = bessel_ive(tid, x), im = bessel_ive(tid - 1, x), ip = bessel_ive(tid + 1, x);
-    c[M::kQ2 + tid] = c[M::kVarP] * cj * i0;
-    c[M::kDQ2 + tid] = c[M::kVarP] * cj * (0.5 * (im + ip) - i0);
+  if (tid == 0) {
+    c[d.kS2] = hyper[d.nh - 1];
+    for (int u = 0; u < d.nt; ++u) {
+      const TermInfo T = tt[u];
+      const double* h = hyper + T.h0;
+      double* ct = c + T.c0;
+      if (T.type == kTermMatern) {
+        const double nu2 = 2.0 * T.order - 1.0;   // 2 nu
+        ct[0] = sqrt(nu2) / h[0];
+        ct[1] = h[1];
+        ct[2] = h[0];
+      } else if (T.type == kTermSqExp) {
+        ct[0] = 1.0 / h[0];
+        ct[1] = h[1];
+      } else {
+        ct[0] = h[0];
+        ct[1] = h[1];
+        ct[2] = h[2];
+        ct[3] = 6.283185307179586477 / h[2];
+        ct[4] = 1.0 / (h[0] * h[0]);
+        ct[5] = T.type == kTermQuasi ? 1.0 / h[3] : 0.0;
+      }
+    }
   }
   tsync();
-  for (int e = tid; e < B * B; e += kW) {
-    const int i = e / B, j = e - i * B;
-    P0[e] = M::p0_entry(c, i, j);
+  // q_h^2 and dq_h^2 / dx, with d(e^-x I_h)/dx = (I_{h-1} + I_{h+1}) e^-x / 2 - e^-x I_h
+  for (int u = 0; u < d.nt; ++u) {
+    const TermInfo T = tt[u];
+    if (T.type != kTermPeriodic && T.type != kTermQuasi) continue;
+    double* ct = c + T.c0;
+    if (tid <= T.order) {
+      const double x = ct[4], cj = tid == 0 ? 1.0 : 2.0;
+      const double i0 = bessel_ive(tid, x), im = bessel_ive(tid - 1, x), ip = bessel_ive(tid + 1, x);
+      ct[6 + tid] = ct[1] * cj * i0;
+      ct[7 + T.order + tid] = ct[1] * cj * (0.5 * (im + ip) - i0);
+    }
+    tsync();
   }
+  // output scale: lam^k on the squared-exponential blocks
+  if (tid < B) {
+    double sc = 1.0;
+    for (int u = 0; u < d.nt; ++u) {
+      const TermInfo T = tt[u];
+      const int r = tid - T.s0;
+      if (T.type == kTermSqExp && r >= 0 && r < T.n) sc = pow(c[T.c0], (double)r);
+    }
+    c[d.kScale + tid] = sc;
+  }
+  for (int e = tid; e < BB; e += kW) c[d.kP0o + e] = p0_entry(d, tt, c, e / B, e % B);
   tsync();
   // P0' = T P0 T^T
-  for (int e = tid; e < B * B; e += kW) {
+  for (int e = tid; e < BB; e += kW) {
     const int i = e / B, j = e - i * B;
     double s = 0.0;
-    for (int k = 0; k < B; ++k) s = fma(M::T_at(i, k), P0[k * B + j], s);
+    for (int k = 0; k < B; ++k) s = fma(T_at(d, i, k), c[d.kP0o + k * B + j], s);
     X[e] = s;
   }
   tsync();
-  for (int e = tid; e < B * B; e += kW) {
+  for (int e = tid; e < BB; e += kW) {
     const int i = e / B, j = e - i * B;
     double s = 0.0;
-    for (int k = 0; k < B; ++k) s = fma(X[i * B + k], M::T_at(j, k), s);
-    c[M::kP0 + e] = s;
+    for (int k = 0; k < B; ++k) s = fma(X[i * B + k], T_at(d, j, k), s);
+    c[d.kP0 + e] = s;
   }
   tsync();
-  for (int e = tid; e < M::kConst; e += kW) cst[e] = c[e];
+  for (int e = tid; e < d.kConst; e += kW) cst[e] = c[e];
 }
 
 // Leaf n: node n's information and the edge n -> n+1 (A = 0, Q = 0 after the last node).
-template <class M>
-__global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, const double* __restrict__ y,
-                                                  int64_t n_pts, const double* __restrict__ cst,
-                                                  double* __restrict__ elems) {
-  constexpr int B = M::B, BB = B * B;
+template <int B>
+__global__ __launch_bounds__(kW) void k_wide_leaf(SumDesc d, const double* __restrict__ t,
+                                                  const double* __restrict__ y, int64_t n_pts,
+                                                  const double* __restrict__ cst, double* __restrict__ elems) {
+  constexpr int BB = B * B;
   using Y = Lay<B>;
-  __shared__ double c[M::kConst];
-  __shared__ double Ao[BB], Qo[BB], X[BB], E[Y::kEs];
+  __shared__ double c[Consts<B>::kMax];
+  __shared__ double Ao[BB], Qo[BB], X[BB], E[Y::kEs], es[2 * kMaxJobs], eb[kMaxBlk];
+  __shared__ TermInfo tt[kMaxTerms];
   const int tid = threadIdx.x;
-  for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
+  if (tid < d.nt) tt[tid] = d.t[tid];
+  for (int e = tid; e < d.kConst; e += kW) c[e] = cst[e];
   tsync();
-  const double s2 = c[M::kS2];
+  const double s2 = c[d.kS2];
+  const double* P0o = c + d.kP0o;
   for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
     const bool edge = n + 1 < n_pts;
     const double dt = edge ? t[n + 1] - t[n] : 0.0;
+    if (edge) edge_scalars<false>(d, tt, c, dt, es, eb);
+    tsync();
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
-      double a = 0.0, q = 0.0, da[M::kNA];
-      if (edge) M::edge_entry(c, dt, i, j, a, q, da);
+      double a = 0.0, q = 0.0, d0, d1;
+      if (edge) edge_entry(d, tt, c, es, eb, dt, i, j, a, q, d0, d1);
       Ao[e] = a;
       Qo[e] = q;
     }
     tsync();
+    if (d.has_se) {
+      // squared-exponential blocks: Q = P0 - A P0 A^T (block diagonal, so the full products
+      // give each block's own)
+      mx_store<B>(mx<B, false, false>(Ao, P0o), X);
+      tsync();
+      const v4d apa = mx<B, false, true>(X, Ao);
+      mx_each<B>(apa, [&](int i, int j, double v) {
+        for (int u = 0; u < d.nt; ++u) {
+          const TermInfo T = tt[u];
+          if (T.type == kTermSqExp && i >= T.s0 && i < T.s0 + T.n && j >= T.s0 && j < T.s0 + T.n)
+            Qo[i * B + j] = edge ? P0o[i * B + j] - v : 0.0;
+        }
+      });
+      tsync();
+    }
     // A' = T A T^-1 and Q' = T Q T^T from the sparsity of T (identity but row 0 = h^T):
     // (T X)[0][j] = sum over observed k of X[k][j], (X T^-1)[i][j] = X[i][j] - X[i][0] for an
     // observed j >= 1, (X T^T)[i][0] = sum over observed k of X[i][k]; other entries unchanged
-    // (the sums in the order of the dense products, so the values are the same)
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
       double s = Ao[e];
       if (i == 0)
         for (int k = 1; k < B; ++k)
-          if (M::observed(k)) s += Ao[k * B + j];
+          if (observed(d, k)) s += Ao[k * B + j];
       X[e] = s;
     }
     tsync();
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
-      E[Y::kA + e] = (j >= 1 && M::observed(j)) ? -X[i * B] + X[e] : X[e];
+      E[Y::kA + e] = (j >= 1 && observed(d, j)) ? -X[i * B] + X[e] : X[e];
     }
     tsync();
-    if (M::kQFromP0) {
-      // Q' = P0' - A' P0' A'^T (Q = 0 after the last node)
-      const double* P0 = c + M::kP0;
-      mx_store<B>(mx<B, false, false>(E + Y::kA, P0), Qo);
-      tsync();
-      mx_each<B>(mx<B, false, true>(Qo, E + Y::kA),
-                 [&](int i, int j, double v) { X[i * B + j] = edge ? P0[i * B + j] - v : 0.0; });
-    } else {
-      for (int e = tid; e < BB; e += kW) {
-        const int i = e / B, j = e - i * B;
-        double s = Qo[e];
-        if (i == 0)
-          for (int k = 1; k < B; ++k)
-            if (M::observed(k)) s += Qo[k * B + j];
-        X[e] = s;
-      }
+    for (int e = tid; e < BB; e += kW) {
+      const int i = e / B, j = e - i * B;
+      double s = Qo[e];
+      if (i == 0)
+        for (int k = 1; k < B; ++k)
+          if (observed(d, k)) s += Qo[k * B + j];
+      X[e] = s;
     }
     tsync();
     // a NaN observation marks a node without one (a prediction time): no information
@@ -786,9 +954,9 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(const double* __restrict__ t, 
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
       double s = X[e];
-      if (!M::kQFromP0 && j == 0)
+      if (j == 0)
         for (int k = 1; k < B; ++k)
-          if (M::observed(k)) s += X[i * B + k];
+          if (observed(d, k)) s += X[i * B + k];
       E[Y::kQ + e] = s;
       E[Y::kJ + e] = (e == 0 && obs) ? 1.0 / s2 : 0.0;
     }
@@ -878,16 +1046,16 @@ __global__ __launch_bounds__(kW, Occ<B>::kLevel) void k_wide_up(double* __restri
 
 // Root: messages of the root element (prefix = the prior N(0, P0'), suffix = nothing) and the
 // log marginal likelihood (the prior pushed through the whole chain).
-template <class M>
-__global__ __launch_bounds__(kW) void k_wide_root(const double* __restrict__ cst, const double* __restrict__ elems,
-                                                  int64_t off_root, double* __restrict__ msgs,
-                                                  double* __restrict__ scal) {
-  constexpr int B = M::B, BB = B * B;
+template <int B>
+__global__ __launch_bounds__(kW) void k_wide_root(SumDesc d, const double* __restrict__ cst,
+                                                  const double* __restrict__ elems, int64_t off_root,
+                                                  double* __restrict__ msgs, double* __restrict__ scal) {
+  constexpr int BB = B * B;
   using Y = Lay<B>;
   __shared__ double E[Y::kEs], m0[B], P0[BB], mo[B], Po[BB], tmp[Y::kTmp];
   const int tid = threadIdx.x;
   for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[off_root * Y::kEs + e];
-  for (int e = tid; e < BB; e += kW) P0[e] = cst[M::kP0 + e];
+  for (int e = tid; e < BB; e += kW) P0[e] = cst[d.kP0 + e];
   if (tid < B) m0[tid] = 0.0;
   tsync();
   double* msg = msgs + off_root * Y::kMs;
@@ -978,41 +1146,53 @@ struct WideOut {
   double* S_diag;
   double* S_sub;
   int64_t ld;
-  double* part;      // [gridDim.x][kPart] per-work-group gradient partials
+  double* part;      // [gridDim.x][B*B + na + 1] per-work-group gradient partials
   const unsigned long long* status;   // the status word: a data error poisons the outputs (NaN)
 };
 
-// Node step (see the file comment).  Gradient partials per work-group: P0'_bar (B*B),
-// <A_bar, dA/dlam_M>, <A_bar, dA/dperiod>, d/ds2.
-template <class M, int MODE>
-__global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double* __restrict__ t, const double* __restrict__ y,
-                                                  int64_t n_pts, const double* __restrict__ cst,
-                                                  const double* __restrict__ elems, const double* __restrict__ msgs,
-                                                  WideOut out) {
-  constexpr int B = M::B, BB = B * B;
+// Node step (see the file comment).  Gradient partials per work-group: P0'_bar (B*B), the
+// channel sums <A_bar, dA/dtheta> (na), d/ds2.
+template <int B, int MODE>
+__global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, const double* __restrict__ t,
+                                                                 const double* __restrict__ y, int64_t n_pts,
+                                                                 const double* __restrict__ cst,
+                                                                 const double* __restrict__ elems,
+                                                                 const double* __restrict__ msgs, WideOut out) {
+  constexpr int BB = B * B;
   using Y = Lay<B>;
   constexpr bool kGrad = (MODE & kWantGrad) != 0;
   constexpr bool kCov = (MODE & (kWantVar | kWantSub)) != 0;
   constexpr bool kSub = (MODE & kWantSub) != 0;
-  constexpr int kPart = M::kPart;
-  __shared__ double c[M::kConst];
+  const int kPart = BB + d.na + 1;
+  __shared__ double c[Consts<B>::kMax];
+  __shared__ double esc[2 * kMaxJobs], ebc[kMaxBlk];   // edge scalars and Matern blocks of the edge
   __shared__ double E[Y::kEs], G_[Y::kMs];   // leaf element; messages (prefix at n, suffix on n + 1)
   __shared__ double mp[B], mn[B], Mx[BB], Gm[BB], W[BB], lam[B], Lam[BB], X2[BB], mu[B], fcol[B], red[kW];
   // P+, P', X1 = A P+ and X3 share one block with the scratch of the first node's suffix step
   // (t_suffix needs 4 b^2 + 2 b), which runs after their last use in that iteration
   __shared__ double quad[4 * BB + 2 * B];
   double *Pp = quad, *Pn = quad + BB, *X1 = quad + 2 * BB, *X3 = quad + 3 * BB, *tmp = quad;
+  __shared__ TermInfo tt[kMaxTerms];
   const int tid = threadIdx.x;
-  for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
+  if (tid < d.nt) tt[tid] = d.t[tid];
+  for (int e = tid; e < d.kP0 + BB; e += kW) c[e] = cst[e];   // all but the original-basis P0
   tsync();
-  const double* P0 = c + M::kP0;
-  const double s2 = c[M::kS2];
+  const double* P0 = c + d.kP0;
+  const double s2 = c[d.kS2];
   const bool poison = *out.status != ~0ull;
-  static_assert(M::kNS <= kW, "one lane per support entry of the transition derivatives");
   constexpr int kRows = (BB + kW - 1) / kW;
-  double acc_p0[kRows], acc_a[M::kNA], acc_s2 = 0.0;
+  double acc_p0[kRows], acc_s2 = 0.0;
   SPG_UNROLL for (int r = 0; r < kRows; ++r) acc_p0[r] = 0.0;
-  SPG_UNROLL for (int f = 0; f < M::kNA; ++f) acc_a[f] = 0.0;
+  // transition derivatives: each lane owns up to two support entries s = tid + 64 q, with one
+  // accumulator per channel of their term
+  int sup_i[2], sup_j[2], sup_ch[2], sup_nch[2];
+  double acc_a[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  SPG_UNROLL for (int q = 0; q < 2; ++q) {
+    const int sidx = tid + q * kW;
+    const int u = support(d, tt, sidx < d.ns ? sidx : 0, sup_i[q], sup_j[q]);
+    sup_ch[q] = sidx < d.ns ? tt[u].ch0 : -1;
+    sup_nch[q] = tt[u].nch;
+  }
   // the leaf element and the messages of node n, fetched one node ahead (see Ahead)
   constexpr int kAll = Y::kEs + Y::kMs;
   constexpr int NP = Ahead<B>::kOn ? (kAll + kW - 1) / kW : 1;
@@ -1121,8 +1301,8 @@ __global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double
     if (out.f_var && tid == 0) out.f_var[n] = poison ? kPoison : S00;
     if (out.z_mean && tid < B) {
       double z = mu[tid];
-      if (tid == 0) for (int k = 1; k < B; ++k) z = fma(M::Ti_at(0, k), mu[k], z);
-      out.z_mean[tid * out.ld + n] = poison ? kPoison : z * M::out_scale(c, tid);
+      if (tid == 0) for (int k = 1; k < B; ++k) z = fma(Ti_at(d, 0, k), mu[k], z);
+      out.z_mean[tid * out.ld + n] = poison ? kPoison : z * c[d.kScale + tid];
     }
     if (out.S_diag || (kSub && out.S_sub && edge)) {
       // back to the original basis: S_o = T^-1 S' T^-T, S_sub_o = T^-1 S_sub' T^-T
@@ -1130,7 +1310,7 @@ __global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double
         for (int e = tid; e < BB; e += kW) {
           const int i = e / B, j = e - i * B;
           double sacc = 0.0;
-          for (int k = 0; k < B; ++k) sacc = fma(M::Ti_at(i, k), X3[k * B + j], sacc);
+          for (int k = 0; k < B; ++k) sacc = fma(Ti_at(d, i, k), X3[k * B + j], sacc);
           X2[e] = sacc;
         }
         tsync();
@@ -1138,9 +1318,9 @@ __global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double
           const int i = e / B, j = e - i * B;
           if (j < i) continue;
           double sacc = 0.0;
-          for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], M::Ti_at(j, k), sacc);
+          for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], Ti_at(d, j, k), sacc);
           const int pk = i * B - i * (i - 1) / 2 + (j - i);     // packed upper, row-major
-          out.S_diag[(int64_t)pk * out.ld + n] = poison ? kPoison : sacc * (M::out_scale(c, i) * M::out_scale(c, j));
+          out.S_diag[(int64_t)pk * out.ld + n] = poison ? kPoison : sacc * (c[d.kScale + i] * c[d.kScale + j]);
         }
         tsync();
       }
@@ -1153,15 +1333,15 @@ __global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double
         for (int e = tid; e < BB; e += kW) {
           const int i = e / B, j = e - i * B;
           double sacc = 0.0;
-          for (int k = 0; k < B; ++k) sacc = fma(M::Ti_at(i, k), Mx[k * B + j], sacc);
+          for (int k = 0; k < B; ++k) sacc = fma(Ti_at(d, i, k), Mx[k * B + j], sacc);
           X2[e] = sacc;
         }
         tsync();
         for (int e = tid; e < BB; e += kW) {
           const int i = e / B, j = e - i * B;
           double sacc = 0.0;
-          for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], M::Ti_at(j, k), sacc);
-          out.S_sub[(int64_t)e * out.ld + n] = poison ? kPoison : sacc * (M::out_scale(c, i) * M::out_scale(c, j));
+          for (int k = 0; k < B; ++k) sacc = fma(X2[i * B + k], Ti_at(d, j, k), sacc);
+          out.S_sub[(int64_t)e * out.ld + n] = poison ? kPoison : sacc * (c[d.kScale + i] * c[d.kScale + j]);
         }
         tsync();
       }
@@ -1185,15 +1365,18 @@ __global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double
         }
         tsync();
         // original basis: A_bar_o = T^T A_bar T^-T, needed only on the support of the
-        // transition derivatives (one lane per support entry)
+        // transition derivatives (each lane's own support entries)
         const double dt = t[n + 1] - t[n];
-        if (tid < M::kNS) {
-          int i, j;
-          M::support(tid, i, j);
-          const double ab = M::abar_orig(Mx, i, j);
-          double a, q, da[M::kNA];
-          M::edge_entry(c, dt, i, j, a, q, da);
-          SPG_UNROLL for (int f = 0; f < M::kNA; ++f) acc_a[f] = fma(ab, da[f], acc_a[f]);
+        edge_scalars<true>(d, tt, c, dt, esc, ebc);
+        tsync();
+        SPG_UNROLL for (int q = 0; q < 2; ++q) {
+          if (sup_ch[q] >= 0) {
+            const double ab = abar_orig<B>(d, Mx, sup_i[q], sup_j[q]);
+            double a, qq, da0, da1;
+            edge_entry(d, tt, c, esc, ebc, dt, sup_i[q], sup_j[q], a, qq, da0, da1);
+            acc_a[q][0] = fma(ab, da0, acc_a[q][0]);
+            acc_a[q][1] = fma(ab, da1, acc_a[q][1]);
+          }
         }
         // P0_bar += Lam - A^T (Lam A)
         t_mtm<B>(A, X3, X2);
@@ -1225,10 +1408,17 @@ __global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double
     // the team in a fixed order
     double* pw = out.part + (int64_t)blockIdx.x * kPart;
     for (int e = tid, r = 0; e < BB; e += kW, ++r) pw[e] = acc_p0[r];
-    for (int f = 0; f < M::kExtra; ++f) {
-      double v = acc_s2;
-      SPG_UNROLL for (int g = 0; g < M::kNA; ++g)
-        if (g == f) v = acc_a[g];
+    for (int f = 0; f <= d.na; ++f) {
+      // channel f: this lane's accumulators of that channel; f = na: the noise variance
+      double v = 0.0;
+      if (f == d.na) {
+        v = acc_s2;
+      } else {
+        SPG_UNROLL for (int q = 0; q < 2; ++q) {
+          if (sup_ch[q] == f) v += acc_a[q][0];
+          if (sup_nch[q] == 2 && sup_ch[q] + 1 == f) v += acc_a[q][1];
+        }
+      }
       red[tid] = v;
       tsync();
       if (tid == 0) {
@@ -1243,10 +1433,9 @@ __global__ __launch_bounds__(kW, Occ<M::B>::kNode) void k_wide_node(const double
 
 // Sum of the per-work-group partials: work-group f adds field f over all node work-groups
 // (lane-strided, then a fixed tree over the lanes), so the result is independent of timing.
-template <class M>
-__global__ __launch_bounds__(kW) void k_wide_sum(const double* __restrict__ part, int n_part,
+template <int B>
+__global__ __launch_bounds__(kW) void k_wide_sum(const double* __restrict__ part, int n_part, int kPart,
                                                  double* __restrict__ tot) {
-  constexpr int kPart = M::kPart;
   __shared__ double red[kW];
   const int tid = threadIdx.x, f = blockIdx.x;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1266,39 +1455,42 @@ __global__ __launch_bounds__(kW) void k_wide_sum(const double* __restrict__ part
 
 // Gradient with respect to the raw hyperparameters (the model's row) from the summed
 // partials; also copies the log likelihood.
-template <class M>
-__global__ __launch_bounds__(kW) void k_wide_final(const double* __restrict__ cst, const double* __restrict__ totg,
+template <int B>
+__global__ __launch_bounds__(kW) void k_wide_final(SumDesc d, const double* __restrict__ cst,
+                                                   const double* __restrict__ totg,
                                                    const double* __restrict__ scal, double* __restrict__ logml,
                                                    double* __restrict__ grad,
                                                    const unsigned long long* __restrict__ status, uint32_t gmask) {
-  constexpr int B = M::B, BB = B * B;
-  constexpr int kPart = M::kPart;
-  __shared__ double c[M::kConst], tot[kPart], X[BB], Pb[BB];
+  constexpr int BB = B * B;
+  const int kPart = BB + d.na + 1;
+  __shared__ double c[Consts<B>::kMax], tot[BB + kMaxChannels + 1], X[BB], Pb[BB];
+  __shared__ TermInfo tt[kMaxTerms];
   const int tid = threadIdx.x;
-  for (int e = tid; e < M::kConst; e += kW) c[e] = cst[e];
+  if (tid < d.nt) tt[tid] = d.t[tid];
+  for (int e = tid; e < d.kConst; e += kW) c[e] = cst[e];
   for (int e = tid; e < kPart; e += kW) tot[e] = totg[e];
   tsync();
   // P0_bar in the original basis: T^T P0'_bar T
   for (int e = tid; e < BB; e += kW) {
     const int i = e / B, j = e - i * B;
     double sacc = 0.0;
-    for (int k = 0; k < B; ++k) sacc = fma(M::T_at(k, i), tot[k * B + j], sacc);
+    for (int k = 0; k < B; ++k) sacc = fma(T_at(d, k, i), tot[k * B + j], sacc);
     X[e] = sacc;
   }
   tsync();
   for (int e = tid; e < BB; e += kW) {
     const int i = e / B, j = e - i * B;
     double sacc = 0.0;
-    for (int k = 0; k < B; ++k) sacc = fma(X[i * B + k], M::T_at(k, j), sacc);
+    for (int k = 0; k < B; ++k) sacc = fma(X[i * B + k], T_at(d, k, j), sacc);
     Pb[e] = sacc;
   }
   tsync();
   if (tid == 0) {
-    double g[M::NH];
-    M::final_grad(c, tot, Pb, g);
+    double g[3 * kMaxTerms + 2 * kMaxTerms + 1];   // at most four per term and s2
+    final_grad<B>(d, tt, c, tot, Pb, g);
     // gradient components outside gmask are 0; a data error poisons everything (NaN)
     const bool poison = *status != ~0ull;
-    for (int k = 0; k < M::NH; ++k) grad[k] = poison ? kPoison : (((gmask >> k) & 1u) ? g[k] : 0.0);
+    for (int k = 0; k < d.nh; ++k) grad[k] = poison ? kPoison : (((gmask >> k) & 1u) ? g[k] : 0.0);
     if (logml) logml[0] = poison ? kPoison : scal[0];
   }
 }

@@ -172,4 +172,4 @@ def test_host_errors(lib):
         h.assemble(big, big, to_dev(np.array([1.0, 1.0, 0.1])))   # above max_points
     h.close()
     with pytest.raises(lib.SpinGPError):
-        lib.Handle([(3, 3)], 100)   # periodic alone is not supported yet
+        lib.Handle([(3, 8)], 100)   # periodic with 9 harmonics: b = 18 > 16

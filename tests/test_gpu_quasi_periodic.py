@@ -154,7 +154,7 @@ def test_periodic_handle_errors(lib):
     with pytest.raises(lib.SpinGPError):
         lib.Handle(TERMS, 100, max_series=2)           # one series only
     with pytest.raises(lib.SpinGPError):
-        lib.Handle([(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 2)], 100)   # 3 harmonics only
+        lib.Handle([(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 7)], 100)   # b = 18 > 16
     h = lib.Handle(TERMS, 100)
     t, y, _ = _data(50, HYPER, seed=13)
     hy = np.array(HYPER)

@@ -175,9 +175,11 @@ def test_sqexp_handle_errors(lib):
     with pytest.raises(lib.SpinGPError):
         lib.Handle(TERMS, 100, max_series=2)                                   # one series only
     with pytest.raises(lib.SpinGPError):
-        lib.Handle([(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 4)], 100)   # order 6 only
+        lib.Handle([(KIND_MATERN32, 0), (KIND_SQEXP, 5)], 100)                 # even orders only
     with pytest.raises(lib.SpinGPError):
-        lib.Handle([(KIND_SQEXP, 6)], 100)                                     # not on its own
+        lib.Handle([(KIND_MATERN32, 0), (KIND_SQEXP, 12)], 100)                # orders up to 10
+    with pytest.raises(lib.SpinGPError):
+        lib.Handle([(KIND_MATERN32, 0), (KIND_QUASIPERIODIC, 3), (KIND_SQEXP, 8)], 100)   # b = 18 > 16
     h = lib.Handle(TERMS, 100)
     t, y, _ = _data(50, HYPER, seed=23)
     for k in (6, 7):                                     # SE lengthscale and variance must be > 0

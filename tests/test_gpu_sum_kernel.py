@@ -117,7 +117,11 @@ def test_sum_kernel_host_errors(lib):
     with pytest.raises(lib.SpinGPError):
         lib.Handle([(1, 0), (3, 3)], 100, max_series=2)       # one series only
     with pytest.raises(lib.SpinGPError):
-        lib.Handle([(1, 0), (3, 4)], 100)                     # 3 harmonics only
+        lib.Handle([(1, 0), (3, 7)], 100)                     # b = 18 > 16
+    with pytest.raises(lib.SpinGPError):
+        lib.Handle([(1, 0), (9, 1)], 100)                     # unknown kind
+    with pytest.raises(lib.SpinGPError):
+        lib.Handle([(4, 0)] * 9, 100)                         # more than 8 terms
     h = lib.Handle([(1, 0), (3, 3)], 100)
     assert lib.spingp_tile_count() >= 1
     with pytest.raises(lib.SpinGPError):

@@ -1,0 +1,91 @@
+"""GPU parity of the wide-state path on sums of terms given as a term list (Sec. 2.1: a sum of
+independent processes is one block-diagonal state-space model), against the C oracle
+(sequential block-tridiagonal elimination + tangent-linear gradient, pinned on the CPU against
+the dense GP, 50-digit references and the Kalman filter): logML and its parts, every gradient
+component, and the posterior means and variances element by element, at state dimensions
+b = 2 .. 16 and with every term kind (Matern-1/2 .. 7/2, periodic, quasi-periodic, squared
+exponential of orders 4 .. 10), among them the paper's Matern-3/2 + 10th-order squared
+exponential (b = 12, Sec. 4.2)."""
+import numpy as np
+import pytest
+
+from gpu_util import compare_series, to_dev
+from workloads import (KIND_MATERN12, KIND_MATERN32, KIND_MATERN52, KIND_MATERN72, KIND_PERIODIC,
+                       KIND_QUASIPERIODIC, KIND_SQEXP)
+from workloads.generate import make_series
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+M12, M32, M52, M72 = (KIND_MATERN12, 0), (KIND_MATERN32, 0), (KIND_MATERN52, 0), (KIND_MATERN72, 0)
+
+# (id, terms, hyperparameter row, time span); about 3000 points, so the tree has 12 levels and
+# ragged tails
+CASES = [
+    ("m32_se10_b12", [M32, (KIND_SQEXP, 10)], [2.0, 1.0, 8.0, 0.5, 0.1], 3000.0),
+    ("m52_p1_b7", [M52, (KIND_PERIODIC, 1)], [3.0, 1.0, 1.0, 0.8, 6.0, 0.1], 600.0),
+    ("m12_m32_qp1_b7", [M12, M32, (KIND_QUASIPERIODIC, 1)], [1.0, 0.3, 2.0, 1.0, 1.2, 0.8, 6.3, 20.0, 0.1], 600.0),
+    ("p2_b6", [(KIND_PERIODIC, 2)], [1.0, 1.0, 5.0, 0.05], 600.0),
+    ("se4_b4", [(KIND_SQEXP, 4)], [2.0, 1.0, 0.1], 1500.0),
+    ("m72_se4_p0_b10", [M72, (KIND_SQEXP, 4), (KIND_PERIODIC, 0)], [4.0, 1.0, 6.0, 0.5, 1.0, 0.3, 9.0, 0.1], 1500.0),
+    ("m32_m52_qp2_b11", [M32, M52, (KIND_QUASIPERIODIC, 2)], [1.5, 0.4, 6.0, 1.0, 1.0, 0.7, 4.0, 30.0, 0.05], 600.0),
+    ("se8_m32_qp1_b14", [(KIND_SQEXP, 8), M32, (KIND_QUASIPERIODIC, 1)], [10.0, 1.0, 1.0, 0.2, 1.0, 0.5, 7.0, 40.0, 0.1],
+     3000.0),
+    ("m12_m12_b2", [M12, M12], [0.5, 0.3, 5.0, 1.0, 0.05], 600.0),
+    ("m32_se6_b8", [M32, (KIND_SQEXP, 6)], [2.0, 1.0, 8.0, 0.5, 0.1], 3000.0),
+]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1610_08035_amd as spg
+    spg.load_library()
+    return spg
+
+
+def _data(terms, hyper, span, n=3001, seed=5):
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(0.0, span, n))
+    y = make_series(t, terms, np.asarray(hyper), rng)
+    return t, y, np.asarray(hyper, dtype=np.float64)
+
+
+def _run(lib, terms, t, y, hyp, blocks):
+    h = lib.Handle(terms, t.shape[0])
+    assert h.n_hyper == hyp.shape[0]
+    h.assemble(to_dev(t), to_dev(y), to_dev(hyp))
+    h.factor()
+    ll, fit, ld = h.logml(parts=True)
+    fm, zm = h.solve(states=True)
+    if blocks:
+        fv, sd, ss = h.selinv(blocks=True)
+    else:
+        fv = h.selinv()
+    ll2, g = h.logml_grad()
+    rc, _ = h.status()
+    torch.cuda.synchronize()
+    out = {"logml": ll.item(), "datafit": fit.item(), "logdet": ld.item(), "f_mean": fm.cpu().numpy(),
+           "z_mean": zm.cpu().numpy(), "f_var": fv.cpu().numpy(), "logml2": ll2.item(),
+           "grad": g.cpu().numpy().reshape(-1), "status": rc}
+    if blocks:
+        out["S_diag"] = sd.cpu().numpy()
+        out["S_sub"] = ss.cpu().numpy()
+    h.close()
+    return out
+
+
+@pytest.mark.parametrize("name,terms,hyper,span", CASES, ids=[c[0] for c in CASES])
+def test_sum_models_against_oracle(lib, name, terms, hyper, span):
+    t, y, hyp = _data(terms, hyper, span)
+    blocks = name in ("m52_p1_b7", "m12_m32_qp1_b7")
+    compare_series(terms, t, y, hyp, _run(lib, terms, t, y, hyp, blocks), blocks=blocks)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 65, 257])
+def test_small_sizes(lib, n):
+    terms, hyper = [M52, (KIND_PERIODIC, 1)], [3.0, 1.0, 1.0, 0.8, 6.0, 0.1]
+    t, y, hyp = _data(terms, hyper, 0.2 * n + 1.0, n=n, seed=n)
+    compare_series(terms, t, y, hyp, _run(lib, terms, t, y, hyp, True), blocks=True)
