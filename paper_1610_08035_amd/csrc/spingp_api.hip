@@ -232,6 +232,7 @@ bool describe(const spingp_term* terms, int32_t n_terms, SumDesc& d) {
   d.na = ch;
   d.ns = sup;
   d.njob = job;
+  d.nblk = blk;
   d.q2 = q2 ? 1 : 0;
   d.kS2 = 0;
   d.kScale = c0;
@@ -410,6 +411,8 @@ static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_serie
       {(void**)&w.msgs, (int64_t)sizeof(double) * items * spg::wide::msg_stride(desc.b)},
       {(void**)&w.cst, (int64_t)sizeof(double) * desc.kConst},
       {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride(desc)},
+      {(void**)&w.deriv, (int64_t)sizeof(double) * max_points * 2 * desc.ns},
+      {(void**)&w.edges, (int64_t)sizeof(double) * max_points * (2 * desc.njob + desc.nblk)},
       {(void**)&h->scal, (int64_t)sizeof(double) * 8},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},
   };
@@ -568,6 +571,8 @@ extern "C" int spingp_destroy(spingp_handle h) {
   (void)hipFree(h->wplan.msgs);
   (void)hipFree(h->wplan.cst);
   (void)hipFree(h->wplan.part);
+  (void)hipFree(h->wplan.deriv);
+  (void)hipFree(h->wplan.edges);
   delete h;
   return SPINGP_OK;
 }

@@ -45,6 +45,7 @@ struct SumDesc {
   int na;           // derivative channels
   int ns;           // support entries
   int njob;         // edge scalars
+  int nblk;         // doubles of the Matern edge blocks
   uint32_t obs;     // bit k: state k is observed (h_k = 1)
   int has_se;       // some term is a squared exponential (its Q is formed as P0 - A P0 A^T)
   int q2;           // every leaf Q lies in the leading 2 x 2 block (Matern-1/2 or -3/2 first,

@@ -45,8 +45,10 @@ hipError_t factor(const WideCtx& c) {
   const SumDesc& d = c.desc;
   mark(c, kKidFwd, 0);
   hipLaunchKernelGGL(k_wide_setup<B>, dim3(1), dim3(kW), 0, c.stream, d, c.hyper, c.cst);
+  hipLaunchKernelGGL(k_wide_edges<B>, dim3((unsigned)((c.n_points + kEdgeThreads - 1) / kEdgeThreads)),
+                     dim3(kEdgeThreads), 0, c.stream, d, c.t, c.n_points, c.cst, c.edges);
   hipLaunchKernelGGL(k_wide_leaf<B>, dim3(grid_for(c.n_points, resident_groups<k_wide_leaf<B>>())), dim3(kW), 0,
-                     c.stream, d, c.t, c.y, c.n_points, c.cst, c.elems);
+                     c.stream, d, c.t, c.y, c.n_points, c.cst, c.edges, c.elems, c.deriv);
   // level 1 joins leaves (rank-one node information: closed-form inverse)
   for (int k = 1; k < c.n_levels; ++k) {
     if (k == 1)
@@ -86,7 +88,7 @@ hipError_t down(const WideCtx& c) {
 template <int MODE>
 void launch_node(const WideCtx& c, const WideOut& o) {
   hipLaunchKernelGGL((k_wide_node<B, MODE>), dim3((unsigned)c.node_grid), dim3(kW), 0, c.stream, c.desc, c.t, c.y,
-                     c.n_points, c.cst, c.elems, c.msgs, o);
+                     c.n_points, c.cst, c.elems, c.msgs, c.deriv, o);
 }
 
 hipError_t node(const WideCtx& c, int mode, double* f_mean, double* f_var, double* z_mean, double* S_diag,

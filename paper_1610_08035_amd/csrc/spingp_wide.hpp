@@ -469,6 +469,24 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
   tsync();
 }
 
+// Items of a level kernel are fetched one iteration ahead: each lane loads its share of the next
+// item's operands (consecutive doubles over the lanes) into registers while the team works on
+// the current one, so the global-memory latency overlaps the element operation.  At b = 16
+// the registers are taken by the element operations and the operands are loaded when used.
+template <int B>
+struct Ahead {
+  static constexpr bool kOn = B <= 12;
+};
+// Waves per SIMD the per-level kernels are compiled for (register budget of 512 / waves per
+// lane, MFMA accumulators included): at b <= 12 three teams of the up and down kernels and two
+// of the node step stay resident, at b = 16 two and one.
+template <int B>
+struct Occ {
+  static constexpr int kLevel = B <= 12 ? 3 : 2;
+  static constexpr int kNode = B <= 12 ? 2 : 1;
+  static constexpr int kLeaf = B <= 12 ? 4 : 3;
+};
+
 // ---------------------------------------------------------------------------- the model
 // A sum of terms (spingp_sumdesc.hpp), each a block of the state:
 //   Matern-nu, m = nu + 1/2 states (f and its derivatives), lam = sqrt(2 nu) / l: the closed
@@ -613,92 +631,105 @@ SPG_DEV void matern_grad(int m, const double* ct, const double* Pb, int ld, doub
   }
 }
 
-// The transcendental scalars of an edge of length dt, one lane per scalar, into es (two
-// doubles each): (cos, sin) of h w dt per harmonic and exp(-dt / l_D) (quasi-periodic),
-// e^{r_k lam dt} as (re, im) per root (squared exponential); a Matern term's lane writes its
-// whole block to eb.
-template <bool DERIV>
-SPG_DEV void edge_scalars(const SumDesc& d, const TermInfo* tt, const double* c, double dt, double* es, double* eb) {
-  const int tid = threadIdx.x;
+// The transcendental part of an edge of length dt, formed by one lane: into es (two doubles
+// per scalar) (cos, sin) of h w dt per harmonic and exp(-dt / l_D) (quasi-periodic),
+// e^{r_k lam dt} as (re, im) per root (squared exponential); into eb every Matern term's block
+// (A, Q = P0 - A P0 A^T and dA/dlam).  es and eb may be global memory.
+SPG_DEV void edge_row(const SumDesc& d, const double* c, double dt, double* es, double* eb) {
   for (int u = 0; u < d.nt; ++u) {
-    const TermInfo T = tt[u];
-    const int q = tid - T.job0;
-    if (q < 0 || q >= T.njob) continue;
+    const TermInfo& T = d.t[u];
     const double* ct = c + T.c0;
-    double v0 = 0.0, v1 = 0.0;
     if (T.type == kTermMatern) {
-      matern_block<DERIV>(T.order, ct, dt, eb + T.blk0);
+      matern_block<false>(T.order, ct, dt, eb + T.blk0);
+      matern_block<true>(T.order, ct, dt, eb + T.blk0);
     } else if (T.type == kTermSqExp) {
       const double x = ct[0] * dt;
-      const int o = kSqExpRootOff[T.order / 2 - 1] + q;
-      const double m = exp(kSqExpRootRe[o] * x);
-      double sn, cs;
-      sincos(kSqExpRootIm[o] * x, &sn, &cs);
-      v0 = m * cs;
-      v1 = m * sn;
-    } else if (q <= T.order) {
-      double sn, cs;
-      sincos((double)q * ct[3] * dt, &sn, &cs);
-      v0 = cs;
-      v1 = sn;
+      const int o = kSqExpRootOff[T.order / 2 - 1];
+      for (int q = 0; q < T.njob; ++q) {
+        const double m = exp(kSqExpRootRe[o + q] * x);
+        double sn, cs;
+        sincos(kSqExpRootIm[o + q] * x, &sn, &cs);
+        es[2 * (T.job0 + q)] = m * cs;
+        es[2 * (T.job0 + q) + 1] = m * sn;
+      }
     } else {
-      v0 = exp(-ct[5] * dt);
+      for (int q = 0; q <= T.order; ++q) {
+        double sn, cs;
+        sincos((double)q * ct[3] * dt, &sn, &cs);
+        es[2 * (T.job0 + q)] = cs;
+        es[2 * (T.job0 + q) + 1] = sn;
+      }
+      if (T.type == kTermQuasi) {
+        es[2 * (T.job0 + T.order + 1)] = exp(-ct[5] * dt);
+        es[2 * (T.job0 + T.order + 1) + 1] = 0.0;
+      }
     }
-    es[2 * tid] = v0;
-    es[2 * tid + 1] = v1;
   }
 }
+// Doubles of one edge row: the scalars, then the Matern blocks.
+SPG_DEV int edge_row_size(const SumDesc& d) { return 2 * d.njob + d.nblk; }
 
-// Entry (i, j) of the original-basis transition over dt (edge scalars es), its closed-form
-// process noise (squared-exponential blocks excepted: 0 here, formed as P0 - A P0 A^T by the
-// team) and its derivatives in the term's channels (da0, da1).
-SPG_DEV void edge_entry(const SumDesc& d, const TermInfo* tt, const double* c, const double* es, const double* eb,
-                        double dt, int i, int j, double& a, double& q, double& da0, double& da1) {
+// Support index of block-local entry (r, c) of term T, or -1.
+SPG_DEV int support_index(const TermInfo& T, int r, int c) {
+  if (T.type == kTermMatern || T.type == kTermSqExp) return T.sup0 + r * T.n + c;
+  if ((r >> 1) != (c >> 1)) return -1;
+  return T.sup0 + 4 * (r >> 1) + 2 * (r & 1) + (c & 1);
+}
+
+// Entry (r, c) of term T's block (block-local indices; 0 outside the harmonic 2 x 2 blocks).
+SPG_DEV void term_entry(const TermInfo& T, const double* c, const double* es, const double* eb, double dt, int r,
+                        int cc, double& a, double& q, double& da0, double& da1) {
   a = q = da0 = da1 = 0.0;
-  for (int u = 0; u < d.nt; ++u) {
-    const TermInfo T = tt[u];
-    const int r = i - T.s0, cc = j - T.s0;
-    if (r < 0 || r >= T.n || cc < 0 || cc >= T.n) continue;
-    const double* ct = c + T.c0;
-    if (T.type == kTermMatern) {
-      const int m = T.n, o = T.blk0 + r * m + cc;
-      a = eb[o];
-      q = eb[o + m * m];
-      da0 = eb[o + 2 * m * m];
-    } else if (T.type == kTermSqExp) {
-      // scaled state: A = E(lam dt) = expm(C1 lam dt), dA/dlam = dt C1 E(lam dt)
-      const int n = T.order, h = n / 2;
-      const int zo = kSqExpZOff[h - 1] + (r * n + cc) * h, ro = kSqExpRootOff[h - 1];
-      double s = 0.0, ds = 0.0;
-      for (int k = 0; k < h; ++k) {
-        const double er = es[2 * (T.job0 + k)], ei = es[2 * (T.job0 + k) + 1];
-        const double zr = kSqExpZRe[zo + k], zi = kSqExpZIm[zo + k];
-        const double pr = zr * er - zi * ei, pi = zr * ei + zi * er;   // Z e^{r x}
-        s += pr;
-        ds += kSqExpRootRe[ro + k] * pr - kSqExpRootIm[ro + k] * pi;  // Re(r Z e^{r x})
-      }
-      a = 2.0 * s;
-      da0 = 2.0 * dt * ds;
-    } else {
-      const int h = r >> 1;
-      if ((cc >> 1) != h) continue;
-      const int ri = r & 1, rj = cc & 1;
-      const double cs = es[2 * (T.job0 + h)], sn = es[2 * (T.job0 + h) + 1];
-      // [[cos, -sin], [sin, cos]] and its derivative in the angle [[-sin, -cos], [cos, -sin]],
-      // times d angle / d period
-      const double rv = ri == rj ? cs : (ri == 0 ? -sn : sn);
-      const double drv = ri == rj ? -sn : (ri == 0 ? -cs : cs);
-      const double th = (double)h * ct[3] * dt;
-      const bool quasi = T.type == kTermQuasi;
-      const double ed = quasi ? es[2 * (T.job0 + T.order + 1)] : 1.0;
-      a = ed * rv;
-      da0 = ed * drv * (-th / ct[2]);
-      if (quasi) {
-        da1 = -dt * a;
-        if (ri == rj) q = ct[6 + h] * (1.0 - ed * ed);
-      }
+  const double* ct = c + T.c0;
+  if (T.type == kTermMatern) {
+    const int m = T.n, o = T.blk0 + r * m + cc;
+    a = eb[o];
+    q = eb[o + m * m];
+    da0 = eb[o + 2 * m * m];
+  } else if (T.type == kTermSqExp) {
+    // scaled state: A = E(lam dt) = expm(C1 lam dt), dA/dlam = dt C1 E(lam dt)
+    const int n = T.order, h = n / 2;
+    const int zo = kSqExpZOff[h - 1] + (r * n + cc) * h, ro = kSqExpRootOff[h - 1];
+    double s = 0.0, ds = 0.0;
+    for (int k = 0; k < h; ++k) {
+      const double er = es[2 * (T.job0 + k)], ei = es[2 * (T.job0 + k) + 1];
+      const double zr = kSqExpZRe[zo + k], zi = kSqExpZIm[zo + k];
+      const double pr = zr * er - zi * ei, pi = zr * ei + zi * er;   // Z e^{r x}
+      s += pr;
+      ds += kSqExpRootRe[ro + k] * pr - kSqExpRootIm[ro + k] * pi;  // Re(r Z e^{r x})
+    }
+    a = 2.0 * s;
+    da0 = 2.0 * dt * ds;
+  } else {
+    const int h = r >> 1;
+    if ((cc >> 1) != h) return;
+    const int ri = r & 1, rj = cc & 1;
+    const double cs = es[2 * (T.job0 + h)], sn = es[2 * (T.job0 + h) + 1];
+    // [[cos, -sin], [sin, cos]] and its derivative in the angle [[-sin, -cos], [cos, -sin]],
+    // times d angle / d period
+    const double rv = ri == rj ? cs : (ri == 0 ? -sn : sn);
+    const double drv = ri == rj ? -sn : (ri == 0 ? -cs : cs);
+    const double th = (double)h * ct[3] * dt;
+    const bool quasi = T.type == kTermQuasi;
+    const double ed = quasi ? es[2 * (T.job0 + T.order + 1)] : 1.0;
+    a = ed * rv;
+    da0 = ed * drv * (-th / ct[2]);
+    if (quasi) {
+      da1 = -dt * a;
+      if (ri == rj) q = ct[6 + h] * (1.0 - ed * ed);
     }
   }
+}
+// Entry (i, j) of the whole transition: term_of[k] is the term of state k (block diagonal).
+SPG_DEV void edge_entry(const TermInfo* tt, const int* term_of, const double* c, const double* es, const double* eb,
+                        double dt, int i, int j, double& a, double& q, double& da0, double& da1) {
+  const int u = term_of[i];
+  if (u != term_of[j]) {
+    a = q = da0 = da1 = 0.0;
+    return;
+  }
+  const TermInfo& T = tt[u];
+  term_entry(T, c, es, eb, dt, i - T.s0, j - T.s0, a, q, da0, da1);
 }
 
 // Entry (i, j) of the original-basis stationary covariance P0.
@@ -878,18 +909,44 @@ __global__ __launch_bounds__(kW) void k_wide_setup(SumDesc d, const double* __re
   for (int e = tid; e < d.kConst; e += kW) cst[e] = c[e];
 }
 
+// Edges, one lane each: the transcendental part of edge n -> n+1 (zero after the last node)
+// into row n of edges (edge_row_size doubles), read by the leaves.
+constexpr int kEdgeThreads = 128;
+template <int B>
+__global__ __launch_bounds__(kEdgeThreads) void k_wide_edges(SumDesc d, const double* __restrict__ t, int64_t n_pts,
+                                                             const double* __restrict__ cst,
+                                                             double* __restrict__ edges) {
+  const int64_t n = (int64_t)blockIdx.x * kEdgeThreads + threadIdx.x;
+  if (n >= n_pts) return;
+  const int rs = edge_row_size(d);
+  double* row = edges + n * rs;
+  if (n + 1 < n_pts) {
+    edge_row(d, cst, t[n + 1] - t[n], row, row + 2 * d.njob);
+  } else {
+    for (int e = 0; e < rs; ++e) row[e] = 0.0;
+  }
+}
+
 // Leaf n: node n's information and the edge n -> n+1 (A = 0, Q = 0 after the last node).
 template <int B>
-__global__ __launch_bounds__(kW) void k_wide_leaf(SumDesc d, const double* __restrict__ t,
+__global__ __launch_bounds__(kW, Occ<B>::kLeaf) void k_wide_leaf(SumDesc d, const double* __restrict__ t,
                                                   const double* __restrict__ y, int64_t n_pts,
-                                                  const double* __restrict__ cst, double* __restrict__ elems) {
+                                                  const double* __restrict__ cst, const double* __restrict__ edges,
+                                                  double* __restrict__ elems, double* __restrict__ deriv) {
   constexpr int BB = B * B;
   using Y = Lay<B>;
   __shared__ double c[Consts<B>::kMax];
   __shared__ double Ao[BB], Qo[BB], X[BB], E[Y::kEs], es[2 * kMaxJobs], eb[kMaxBlk];
   __shared__ TermInfo tt[kMaxTerms];
+  __shared__ int term_of[B];
   const int tid = threadIdx.x;
   if (tid < d.nt) tt[tid] = d.t[tid];
+  if (tid < B) {
+    int u = 0;
+    for (int v = 1; v < d.nt; ++v)
+      if (tid >= d.t[v].s0) u = v;
+    term_of[tid] = u;
+  }
   for (int e = tid; e < d.kConst; e += kW) c[e] = cst[e];
   tsync();
   const double s2 = c[d.kS2];
@@ -897,14 +954,33 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(SumDesc d, const double* __res
   for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
     const bool edge = n + 1 < n_pts;
     const double dt = edge ? t[n + 1] - t[n] : 0.0;
-    if (edge) edge_scalars<false>(d, tt, c, dt, es, eb);
+    {
+      const int rs = edge_row_size(d), ns2 = 2 * d.njob;
+      const double* row = edges + n * rs;
+      for (int e = tid; e < rs; e += kW) {
+        if (e < ns2) es[e] = row[e];
+        else eb[e - ns2] = row[e];
+      }
+    }
     tsync();
+    // the transition's derivatives on the support go to deriv (two channels per entry), for
+    // the node step of the same edge
+    double* dv = deriv + n * (2 * d.ns);
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
-      double a = 0.0, q = 0.0, d0, d1;
-      if (edge) edge_entry(d, tt, c, es, eb, dt, i, j, a, q, d0, d1);
+      double a = 0.0, q = 0.0, d0 = 0.0, d1 = 0.0;
+      if (edge) edge_entry(tt, term_of, c, es, eb, dt, i, j, a, q, d0, d1);
       Ao[e] = a;
       Qo[e] = q;
+      const int u = term_of[i];
+      if (u == term_of[j]) {
+        const TermInfo& T = tt[u];
+        const int sidx = support_index(T, i - T.s0, j - T.s0);
+        if (sidx >= 0) {
+          dv[2 * sidx] = d0;
+          dv[2 * sidx + 1] = d1;
+        }
+      }
     }
     tsync();
     if (d.has_se) {
@@ -975,23 +1051,6 @@ __global__ __launch_bounds__(kW) void k_wide_leaf(SumDesc d, const double* __res
     tsync();
   }
 }
-
-// Items of a level kernel are fetched one iteration ahead: each lane loads its share of the next
-// item's operands (consecutive doubles over the lanes) into registers while the team works on
-// the current one, so the global-memory latency overlaps the element operation.  At b = 16
-// the registers are taken by the element operations and the operands are loaded when used.
-template <int B>
-struct Ahead {
-  static constexpr bool kOn = B <= 12;
-};
-// Waves per SIMD the per-level kernels are compiled for (register budget of 512 / waves per
-// lane, MFMA accumulators included): at b <= 12 three teams of the up and down kernels and two
-// of the node step stay resident, at b = 16 two and one.
-template <int B>
-struct Occ {
-  static constexpr int kLevel = B <= 12 ? 3 : 2;
-  static constexpr int kNode = B <= 12 ? 2 : 1;
-};
 
 // Up-sweep: level k (n_cur elements at off_cur) from level k - 1 (n_prev at off_prev).
 // LEAF: level k - 1 is the leaf level (every right operand is a leaf).
@@ -1157,7 +1216,8 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
                                                                  const double* __restrict__ y, int64_t n_pts,
                                                                  const double* __restrict__ cst,
                                                                  const double* __restrict__ elems,
-                                                                 const double* __restrict__ msgs, WideOut out) {
+                                                                 const double* __restrict__ msgs,
+                                                                 const double* __restrict__ deriv, WideOut out) {
   constexpr int BB = B * B;
   using Y = Lay<B>;
   constexpr bool kGrad = (MODE & kWantGrad) != 0;
@@ -1165,7 +1225,7 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
   constexpr bool kSub = (MODE & kWantSub) != 0;
   const int kPart = BB + d.na + 1;
   __shared__ double c[Consts<B>::kMax];
-  __shared__ double esc[2 * kMaxJobs], ebc[kMaxBlk];   // edge scalars and Matern blocks of the edge
+  __shared__ double dvs[2 * kMaxSupport];   // the edge's transition derivatives on the support
   __shared__ double E[Y::kEs], G_[Y::kMs];   // leaf element; messages (prefix at n, suffix on n + 1)
   __shared__ double mp[B], mn[B], Mx[BB], Gm[BB], W[BB], lam[B], Lam[BB], X2[BB], mu[B], fcol[B], red[kW];
   // P+, P', X1 = A P+ and X3 share one block with the scratch of the first node's suffix step
@@ -1173,9 +1233,16 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
   __shared__ double quad[4 * BB + 2 * B];
   double *Pp = quad, *Pn = quad + BB, *X1 = quad + 2 * BB, *X3 = quad + 3 * BB, *tmp = quad;
   __shared__ TermInfo tt[kMaxTerms];
+  __shared__ int sup[kMaxSupport];   // support entry s: i | j << 5 | term << 10
   const int tid = threadIdx.x;
   if (tid < d.nt) tt[tid] = d.t[tid];
   for (int e = tid; e < d.kP0 + BB; e += kW) c[e] = cst[e];   // all but the original-basis P0
+  tsync();
+  for (int sidx = tid; sidx < d.ns; sidx += kW) {
+    int si, sj;
+    const int u = support(d, tt, sidx, si, sj);
+    sup[sidx] = si | (sj << 5) | (u << 10);
+  }
   tsync();
   const double* P0 = c + d.kP0;
   const double s2 = c[d.kS2];
@@ -1183,43 +1250,44 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
   constexpr int kRows = (BB + kW - 1) / kW;
   double acc_p0[kRows], acc_s2 = 0.0;
   SPG_UNROLL for (int r = 0; r < kRows; ++r) acc_p0[r] = 0.0;
-  // transition derivatives: each lane owns up to two support entries s = tid + 64 q, with one
-  // accumulator per channel of their term
-  int sup_i[2], sup_j[2], sup_ch[2], sup_nch[2];
+  // transition derivatives: each lane owns up to two support entries s = tid + 64 q (their
+  // place and term are looked up when used), with one accumulator per channel of their term
   double acc_a[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-  SPG_UNROLL for (int q = 0; q < 2; ++q) {
-    const int sidx = tid + q * kW;
-    const int u = support(d, tt, sidx < d.ns ? sidx : 0, sup_i[q], sup_j[q]);
-    sup_ch[q] = sidx < d.ns ? tt[u].ch0 : -1;
-    sup_nch[q] = tt[u].nch;
-  }
-  // the leaf element and the messages of node n, fetched one node ahead (see Ahead)
-  constexpr int kAll = Y::kEs + Y::kMs;
-  constexpr int NP = Ahead<B>::kOn ? (kAll + kW - 1) / kW : 1;
+  // the leaf element, the messages and (gradient) the edge's derivatives of node n, fetched
+  // one node ahead (see Ahead)
+  const int kDv = kGrad ? 2 * d.ns : 0;
+  const int kAll = Y::kEs + Y::kMs + kDv;
+  // registers for the element, the messages and up to 64 derivative entries; larger supports
+  // load when used
+  constexpr int NP = Ahead<B>::kOn ? (Y::kEs + Y::kMs + (kGrad ? kW : 0) + kW - 1) / kW : 1;
   double pre[NP];
   auto fetch = [&](int64_t it) {
     if (it >= n_pts) return;
     SPG_UNROLL for (int j = 0; j < NP; ++j) {
       const int e = tid + j * kW;
       if (e < Y::kEs) pre[j] = elems[it * Y::kEs + e];
-      else if (e < kAll) pre[j] = msgs[it * Y::kMs + e - Y::kEs];
+      else if (e < Y::kEs + Y::kMs) pre[j] = msgs[it * Y::kMs + e - Y::kEs];
+      else if (e < kAll) pre[j] = deriv[it * kDv + e - Y::kEs - Y::kMs];
     }
   };
-  if (Ahead<B>::kOn) fetch(blockIdx.x);
+  const bool ahead = Ahead<B>::kOn && kAll <= NP * kW;
+  if (ahead) fetch(blockIdx.x);
   for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
     const bool edge = n + 1 < n_pts;
-    if (Ahead<B>::kOn) {
+    if (ahead) {
       SPG_UNROLL for (int j = 0; j < NP; ++j) {
         const int e = tid + j * kW;
         if (e < Y::kEs) E[e] = pre[j];
-        else if (e < kAll) G_[e - Y::kEs] = pre[j];
+        else if (e < Y::kEs + Y::kMs) G_[e - Y::kEs] = pre[j];
+        else if (e < kAll) dvs[e - Y::kEs - Y::kMs] = pre[j];
       }
     } else {
       for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[n * Y::kEs + e];
       for (int e = tid; e < Y::kMs; e += kW) G_[e] = msgs[n * Y::kMs + e];
+      for (int e = tid; e < kDv; e += kW) dvs[e] = deriv[n * kDv + e];
     }
     tsync();
-    if (Ahead<B>::kOn) fetch(n + gridDim.x);
+    if (ahead) fetch(n + gridDim.x);
     const double* m = G_ + Y::km;
     const double* P = G_ + Y::kP;
     const double* A = E + Y::kA;
@@ -1366,16 +1434,13 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
         tsync();
         // original basis: A_bar_o = T^T A_bar T^-T, needed only on the support of the
         // transition derivatives (each lane's own support entries)
-        const double dt = t[n + 1] - t[n];
-        edge_scalars<true>(d, tt, c, dt, esc, ebc);
-        tsync();
         SPG_UNROLL for (int q = 0; q < 2; ++q) {
-          if (sup_ch[q] >= 0) {
-            const double ab = abar_orig<B>(d, Mx, sup_i[q], sup_j[q]);
-            double a, qq, da0, da1;
-            edge_entry(d, tt, c, esc, ebc, dt, sup_i[q], sup_j[q], a, qq, da0, da1);
-            acc_a[q][0] = fma(ab, da0, acc_a[q][0]);
-            acc_a[q][1] = fma(ab, da1, acc_a[q][1]);
+          const int sidx = tid + q * kW;
+          if (sidx < d.ns) {
+            const int sv = sup[sidx], si = sv & 31, sj = (sv >> 5) & 31;
+            const double ab = abar_orig<B>(d, Mx, si, sj);
+            acc_a[q][0] = fma(ab, dvs[2 * sidx], acc_a[q][0]);
+            acc_a[q][1] = fma(ab, dvs[2 * sidx + 1], acc_a[q][1]);
           }
         }
         // P0_bar += Lam - A^T (Lam A)
@@ -1415,8 +1480,12 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
         v = acc_s2;
       } else {
         SPG_UNROLL for (int q = 0; q < 2; ++q) {
-          if (sup_ch[q] == f) v += acc_a[q][0];
-          if (sup_nch[q] == 2 && sup_ch[q] + 1 == f) v += acc_a[q][1];
+          const int sidx = tid + q * kW;
+          if (sidx < d.ns) {
+            const TermInfo& T = tt[sup[sidx] >> 10];
+            if (T.ch0 == f) v += acc_a[q][0];
+            if (T.nch == 2 && T.ch0 + 1 == f) v += acc_a[q][1];
+          }
         }
       }
       red[tid] = v;
