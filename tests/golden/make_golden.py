@@ -9,8 +9,8 @@ accuracy in float64), N = 1 and N = 2; logML, data fit, log det, latent mean and
 variance.
 
 ``mp_kinds.json``: every term kind the oracle models (Matern-1/2 .. 7/2,
-periodic, quasi-periodic, squared exponential of orders 6 and 10, and the sums
-the library runs), with logML, data fit, log det, latent mean and variance and
+periodic, quasi-periodic, squared exponential of orders 4, 6, 8 and 10, and sums
+of them), with logML, data fit, log det, latent mean and variance and
 dlogML/dtheta (central differences of the 50-digit logML at 90 digits); for
 state dimensions up to 4 also the posterior state means and the blocks
 Cov(z_n, z_n | y) (packed upper, row-major) and Cov(z_{n+1}, z_n | y).  The
@@ -113,6 +113,18 @@ def kind_cases():
     r2 = np.random.default_rng(20161027)
     t = np.cumsum(r2.exponential(1.0, 40))
     res.append(("matern52_noise_1e-6", [(M52, 0)], [2.0, 1.0, 1e-6], t, r2.standard_normal(40), True))
+    # further sums of the wide-state path (b = 4 .. 12), one stream of their own
+    r3 = np.random.default_rng(20161028)
+    more = [("matern52_periodic1", [(M52, 0), (PER, 1)], [3.0, 1.0, 1.0, 0.8, 6.0, 0.1], 20.0),
+            ("matern12_matern32_quasiperiodic1", [(M12, 0), (M32, 0), (QP, 1)],
+             [1.0, 0.3, 2.0, 1.0, 1.2, 0.8, 6.3, 20.0, 0.1], 20.0),
+            ("sqexp4", [(SE, 4)], [2.0, 1.0, 0.1], 15.0),
+            ("matern72_sqexp8", [(M72, 0), (SE, 8)], [4.0, 1.0, 3.0, 0.6, 0.05], 15.0),
+            ("periodic2", [(PER, 2)], [1.0, 1.0, 5.0, 0.05], 20.0)]
+    for name, terms, hyper, span in more:
+        t = np.sort(r3.uniform(0.0, span, 16))
+        t[6] = t[5]
+        res.append((name, terms, hyper, t, r3.standard_normal(16), False))
     return res
 
 

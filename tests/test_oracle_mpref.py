@@ -12,8 +12,8 @@ and of the float64 oracles against the stored 50-digit fixtures of every term ki
 - Every term kind raises when the reference does not model it.
 - The float64 oracles (C elimination, Python elimination, Kalman filter + RTS smoother) against
   the stored fixtures ``golden/mp_kinds.json`` (written by ``golden/make_golden.py``, which calls
-  only ``oracle/``): Matern orders 1/2 .. 7/2 on adversarial gaps with their state blocks, the
-  sums of the wide-state path, squared exponentials of orders 6 and 10.
+  only ``oracle/``): Matern orders 1/2 .. 7/2 on adversarial gaps with their state blocks, sums
+  of terms as the wide-state path runs them, squared exponentials of orders 4, 6, 8 and 10.
 """
 import json
 import os
@@ -217,4 +217,4 @@ def test_fixtures_cover_every_kind():
     kinds = {k for f in FIXTURES for k, _ in f["terms"]}
     assert kinds == {MATERN12, MATERN32, MATERN52, MATERN72, PERIODIC, QUASIPERIODIC, SQEXP}
     orders = {h for f in FIXTURES for k, h in f["terms"] if k == SQEXP}
-    assert orders == {6, 10}
+    assert orders == {4, 6, 8, 10}
