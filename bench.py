@@ -38,9 +38,9 @@ ALG_BYTES_PER_POINT = {"fwd_fold_tree": 16.0, "bwd_elim_adjoint": 16.0}
 # valid only for the kernel sources they were taken on (sha256 over the one-series kernel
 # sources, see kernel_source_sha), else reported as null.
 TRAFFIC = {"kernel": "bwd_elim_adjoint",
-           "bytes": {(8, 128): (40464.9 * 2.0 + 96.1) * 1024.0,
-                     (8, 256): (40550.9 * 2.0 + 48.0) * 1024.0},
-           "source_sha": "7a70f5e7f83d1511050b0166e51d2d3f5d212043e4d97e59e6bcc0d430f39e86"}
+           "bytes": {(8, 128): (40792.9 * 2.0 + 96.0) * 1024.0,
+                     (8, 256): (38869.7 * 2.0 + 48.0) * 1024.0},
+           "source_sha": "eff41554fdd90400e11f3a990899cf592f419c2be1e8231dbc1efea30763565b"}
 
 
 def kernel_source_sha():

@@ -18,8 +18,8 @@ LIB = os.path.join(HERE, "libspingp.so")
 SOURCES = ["spingp_api.hip"]
 TILES = [(8, 128), (8, 64), (8, 256), (4, 128), (4, 256), (16, 128)]
 WIDE_B = list(range(2, 17))
-HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp", "spingp_host.hpp", "spingp_series.hpp", "spingp_wide.hpp",
-           "spingp_sumdesc.hpp", "spingp_sqexp_tables.hpp"]
+HEADERS = ["spingp_device.hpp", "spingp_kernels.hpp", "spingp_host.hpp", "spingp_wide_host.hpp", "spingp_series.hpp",
+           "spingp_wide.hpp", "spingp_sumdesc.hpp", "spingp_sqexp_tables.hpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",

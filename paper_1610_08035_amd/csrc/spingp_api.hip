@@ -11,6 +11,7 @@
 
 #include "../../include/spingp.h"
 #include "spingp_host.hpp"
+#include "spingp_wide_host.hpp"
 #include "spingp_series.hpp"
 
 namespace {

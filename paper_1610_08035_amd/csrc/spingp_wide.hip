@@ -1,6 +1,6 @@
 // Launch sequence of the wide-state path for one state dimension (see spingp_wide.hpp).
 // Compiled once per b with -DSPG_WIDE_B=<b>; each object exports spg::wide::ops_b<b>().
-#include "spingp_host.hpp"
+#include "spingp_wide_host.hpp"
 #include "spingp_wide.hpp"
 
 #ifndef SPG_WIDE_B

@@ -471,11 +471,15 @@ SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, dou
 
 // Items of a level kernel are fetched one iteration ahead: each lane loads its share of the next
 // item's operands (consecutive doubles over the lanes) into registers while the team works on
-// the current one, so the global-memory latency overlaps the element operation.  At b = 16
-// the registers are taken by the element operations and the operands are loaded when used.
+// the current one, so the global-memory latency overlaps the element operation.  Above b = 12
+// the level kernels' registers are taken by the element operations and their operands are
+// loaded when used.
 template <int B>
 struct Ahead {
   static constexpr bool kOn = B <= 12;
+  // the node step prefetches at every b (above b = 12 it runs one team per SIMD, which leaves
+  // the registers for it)
+  static constexpr bool kNode = true;
 };
 // Waves per SIMD the per-level kernels are compiled for (register budget of 512 / waves per
 // lane, MFMA accumulators included): at b <= 12 three teams of the up and down kernels and two
@@ -1257,9 +1261,9 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
   // one node ahead (see Ahead)
   const int kDv = kGrad ? 2 * d.ns : 0;
   const int kAll = Y::kEs + Y::kMs + kDv;
-  // registers for the element, the messages and up to 64 derivative entries; larger supports
-  // load when used
-  constexpr int NP = Ahead<B>::kOn ? (Y::kEs + Y::kMs + (kGrad ? kW : 0) + kW - 1) / kW : 1;
+  // registers for the element, the messages and the first 64 or more derivative entries (the
+  // rest of a larger support loads with the node itself)
+  constexpr int NP = Ahead<B>::kNode ? (Y::kEs + Y::kMs + (kGrad ? kW : 0) + kW - 1) / kW : 1;
   double pre[NP];
   auto fetch = [&](int64_t it) {
     if (it >= n_pts) return;
@@ -1270,7 +1274,8 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
       else if (e < kAll) pre[j] = deriv[it * kDv + e - Y::kEs - Y::kMs];
     }
   };
-  const bool ahead = Ahead<B>::kOn && kAll <= NP * kW;
+  constexpr bool ahead = Ahead<B>::kNode;
+  static_assert(!ahead || Y::kEs + Y::kMs <= NP * kW, "the element and the messages fit the registers");
   if (ahead) fetch(blockIdx.x);
   for (int64_t n = blockIdx.x; n < n_pts; n += gridDim.x) {
     const bool edge = n + 1 < n_pts;
@@ -1281,6 +1286,7 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
         else if (e < Y::kEs + Y::kMs) G_[e - Y::kEs] = pre[j];
         else if (e < kAll) dvs[e - Y::kEs - Y::kMs] = pre[j];
       }
+      for (int e = NP * kW + tid; e < kAll; e += kW) dvs[e - Y::kEs - Y::kMs] = deriv[n * kDv + e - Y::kEs - Y::kMs];
     } else {
       for (int e = tid; e < Y::kEs; e += kW) E[e] = elems[n * Y::kEs + e];
       for (int e = tid; e < Y::kMs; e += kW) G_[e] = msgs[n * Y::kMs + e];
