@@ -54,11 +54,12 @@ struct Lay {
   static constexpr int km = 0, kP = B, kMJ = B + BB, kMeta = 2 * BB + B;
   static constexpr int kM = 2 * BB + 2 * B;
   static constexpr int kMs = (kM + 7) / 8 * 8;
-  // scratch of one element operation: 8 matrices and 10 vectors (a join); a prefix or suffix
-  // step needs 4 matrices and 5 vectors
+  // scratch of one element operation: a join takes 3 matrices and 6 vectors (and reuses the
+  // blocks of its operands that it has consumed), a prefix or suffix step 3 matrices and 5
+  // vectors; kTmp covers any of them
   static constexpr int kTmp = 8 * BB + 10 * B;
-  static constexpr int kTmpJoin = 7 * BB + 6 * B;
-  static constexpr int kTmpStep = 4 * BB + 5 * B;
+  static constexpr int kTmpJoin = 3 * BB + 6 * B;
+  static constexpr int kTmpStep = 3 * BB + 5 * B;
 };
 
 // ---------------------------------------------------------------------------- team algebra
@@ -161,13 +162,11 @@ SPG_DEV double t_dot(const double* a, const double* b) {
 }
 
 // Value of x in lane C of the caller's row of 16 lanes, for every lane of that row (DPP
-// row_newbcast; the lane index must be a constant, so callers pass an unrolled loop index).
+// row_newbcast, one 64-bit move; the lane index must be a constant, so callers pass an
+// unrolled loop index).  Every lane of every row is written, so no old value is needed.
 template <int C>
 SPG_DEV double row_bcast_c(double x) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x150 + C, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x150 + C, 0xF, 0xF, false);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+  return __builtin_amdgcn_mov_dpp(x, 0x150 + C, 0xF, 0xF, false);
 }
 SPG_DEV double row_bcast(double x, int c) {
   switch (c) {
@@ -303,15 +302,21 @@ SPG_DEV void t_inv_q2(const double* Q, const double* J, double* G) {
 
 // R = E1 (x) E2 (join at the shared node; see spingp_device.hpp).
 // LEAF2: E2 is a leaf, whose J is rank one (the inverse in closed form).
+// Scratch: M, its inverse G and later A2 P+ share one block; E1's Q1 takes G A1 once P+ = G Q1
+// is formed, E2's J2 takes W A1 once W = J2 G is formed (both operands are consumed).  A team
+// is one wavefront, so a block's last reads precede its next writes in program order (the
+// pointers may alias, so the compiler keeps that order).
 template <int B, bool LEAF2 = false>
-SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tmp) {
+SPG_DEV void t_combine(double* E1, double* E2, double* R, double* tmp) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
-  double *M = tmp, *G = M + BB, *Pp = G + BB, *W = Pp + BB, *GA = W + BB, *T = GA + BB, *WA = T + BB;
-  double* v = tmp + 7 * BB;   // seven matrices and six vectors: 7 b^2 + 6 b doubles of scratch
+  double *M = tmp, *G = tmp, *T = tmp, *Pp = tmp + BB, *W = tmp + 2 * BB;
+  double* v = tmp + 3 * BB;   // three matrices and six vectors: 3 b^2 + 6 b doubles of scratch
   double *Gb = v, *Ppe = v + B, *g = v + 2 * B, *Gte = v + 3 * B, *Wb = v + 4 * B, *r = v + 5 * B;
   const double *A1 = E1 + Y::kA, *b1 = E1 + Y::kb, *Q1 = E1 + Y::kQ, *J1 = E1 + Y::kJ, *eta1 = E1 + Y::keta;
   const double *A2 = E2 + Y::kA, *b2 = E2 + Y::kb, *Q2 = E2 + Y::kQ, *J2 = E2 + Y::kJ, *eta2 = E2 + Y::keta;
+  double* GA = E1 + Y::kQ;
+  double* WA = E2 + Y::kJ;
   const int tid = threadIdx.x;
   double ld;
   if (LEAF2) {
@@ -321,7 +326,8 @@ SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tm
     tsync();
     ld = t_inv_logdet<B>(M, G, nullptr);
   }
-  // P+ = G Q1, W = J2 G (both symmetric), G A1; G b1, G^T eta2
+  // P+ = G Q1, W = J2 G (both symmetric), G A1 (into Q1's block, after its last read); G b1,
+  // G^T eta2
   mx_store<B>(mx_sym<B, false, false>(G, Q1), Pp);
   mx_store<B>(mx_sym<B, false, false>(J2, G), W);
   mx_store<B>(mx<B, false, false>(G, A1), GA);
@@ -335,7 +341,8 @@ SPG_DEV void t_combine(const double* E1, const double* E2, double* R, double* tm
     Gte[tid] = s3;
   }
   tsync();
-  // new transition A2 G A1, A2 P+, W A1; P+ eta2, W b1 and the vectors g, r
+  // new transition A2 G A1, A2 P+ (into G's block), W A1 (into J2's block); P+ eta2, W b1 and
+  // the vectors g, r
   mx_store<B>(mx<B, false, false>(A2, GA), R + Y::kA);
   mx_store<B>(mx<B, false, false>(A2, Pp), T);
   mx_store<B>(mx<B, false, false>(W, A1), WA);
@@ -379,8 +386,9 @@ SPG_DEV void t_prefix(const double* m, const double* P, const double* E, double*
                       double& dcf, double& dcl) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
-  double *M = tmp, *G = M + BB, *Pp = G + BB, *T = Pp + BB;
-  double* v = tmp + 4 * BB;   // four matrices and five vectors: 4 b^2 + 5 b doubles of scratch
+  // M and its inverse G share a block (see t_combine)
+  double *M = tmp, *G = tmp, *Pp = tmp + BB, *T = tmp + 2 * BB;
+  double* v = tmp + 3 * BB;   // three matrices and five vectors: 3 b^2 + 5 b doubles of scratch
   double *Gm = v, *Ppe = v + B, *g = v + 2 * B, *Wm = v + 3 * B, *Jm = v + 4 * B;
   const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
@@ -434,8 +442,9 @@ template <int B, bool Q2 = false>
 SPG_DEV void t_suffix(const double* E, const double* Jb, const double* etab, double* Jo, double* etao, double* tmp) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
-  double *M = tmp, *G = M + BB, *W = G + BB, *WA = W + BB;
-  double* v = tmp + 4 * BB;   // four matrices and two vectors: 4 b^2 + 2 b doubles of scratch
+  // M, its inverse G and later W A share a block (see t_combine)
+  double *M = tmp, *G = tmp, *WA = tmp, *W = tmp + BB;
+  double* v = tmp + 2 * BB;   // two matrices and two vectors: 2 b^2 + 2 b doubles of scratch
   double *s1v = v, *r = v + B;
   const double *A = E + Y::kA, *bb = E + Y::kb, *Q = E + Y::kQ, *J = E + Y::kJ, *eta = E + Y::keta;
   const int tid = threadIdx.x;
@@ -1144,7 +1153,7 @@ __global__ __launch_bounds__(kW, Occ<B>::kLevel) void k_wide_down(const double* 
                                                   int64_t off_par, int64_t off_child, int64_t n_child) {
   using Y = Lay<B>;
   constexpr int BB = B * B;
-  __shared__ double par[Y::kMs], E[Y::kEs], out[Y::kMs], tmp[Y::kTmpStep];
+  __shared__ double par[Y::kMs], E[Y::kEs], tmp[Y::kTmpStep];
   const int tid = threadIdx.x;
   // parent message, then the sibling element (absent for an unpaired tail)
   constexpr int kAll = Y::kMs + Y::kEs;
@@ -1187,18 +1196,21 @@ __global__ __launch_bounds__(kW, Occ<B>::kLevel) void k_wide_down(const double* 
       tsync();
       continue;
     }
+    // the new message goes straight to global memory: the half that does not change, the
+    // padding, then the half the step forms
+    for (int e = tid; e < B + BB; e += kW) {
+      const int h = left ? e : Y::kMJ + e;
+      om[h] = par[h];
+    }
+    for (int e = Y::kM + tid; e < Y::kMs; e += kW) om[e] = 0.0;
     if (left) {
       // prefix unchanged; suffix pulled back through the right sibling
-      for (int e = tid; e < B + BB; e += kW) out[e] = par[e];
-      t_suffix<B, LEAF && Q2>(E, par + Y::kMJ, par + Y::kMeta, out + Y::kMJ, out + Y::kMeta, tmp);
+      t_suffix<B, LEAF && Q2>(E, par + Y::kMJ, par + Y::kMeta, om + Y::kMJ, om + Y::kMeta, tmp);
     } else {
       // prefix pushed through the left sibling; suffix unchanged
-      for (int e = tid; e < B + BB; e += kW) out[Y::kMJ + e] = par[Y::kMJ + e];
       double dcf, dcl;
-      t_prefix<B, LEAF>(par + Y::km, par + Y::kP, E, out + Y::km, out + Y::kP, tmp, dcf, dcl);
+      t_prefix<B, LEAF>(par + Y::km, par + Y::kP, E, om + Y::km, om + Y::kP, tmp, dcf, dcl);
     }
-    for (int e = tid; e < Y::kMs; e += kW) om[e] = e < Y::kM ? out[e] : 0.0;
-    tsync();
   }
 }
 
