@@ -39,7 +39,16 @@ namespace wide {
 constexpr int kW = 64;  // lanes per team (one wavefront, one work-group)
 static_assert(kSqExpMaxOrder == kMaxSqExpOrder, "generated tables cover every supported order");
 
-SPG_DEV void tsync() { lds_barrier(); }   // teams exchange data through LDS only
+// A team is one wavefront (every team kernel is launched with kW threads), whose LDS operations
+// execute in issue order: a wavefront-scope fence (no wait instruction) orders the LDS writes
+// of one phase before the reads of the next, and the wave barrier keeps the compiler from
+// moving them across it.
+static_assert(kW == 64, "a team is one wave64");
+SPG_DEV void tsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
 
 // ---------------------------------------------------------------------------- layouts
 template <int B>
