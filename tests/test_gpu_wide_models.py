@@ -2,8 +2,8 @@
 independent processes is one block-diagonal state-space model), against the C oracle
 (sequential block-tridiagonal elimination + tangent-linear gradient, pinned on the CPU against
 the dense GP, 50-digit references and the Kalman filter): logML and its parts, every gradient
-component, and the posterior means and variances element by element, at state dimensions
-b = 2 .. 16 and with every term kind (Matern-1/2 .. 7/2, periodic, quasi-periodic, squared
+component, the posterior means and variances and the state blocks element by element, at state
+dimensions b = 2 .. 16 and with every term kind (Matern-1/2 .. 7/2, periodic, quasi-periodic, squared
 exponential of orders 4 .. 10), among them the paper's Matern-3/2 + 10th-order squared
 exponential (b = 12, Sec. 4.2)."""
 import numpy as np
@@ -34,6 +34,11 @@ CASES = [
      3000.0),
     ("m12_m12_b2", [M12, M12], [0.5, 0.3, 5.0, 1.0, 0.05], 600.0),
     ("m32_se6_b8", [M32, (KIND_SQEXP, 6)], [2.0, 1.0, 8.0, 0.5, 0.1], 3000.0),
+    ("m52_se10_b13", [M52, (KIND_SQEXP, 10)], [3.0, 0.5, 8.0, 1.0, 0.05], 3000.0),
+    # leaf Q confined to the leading 2 x 2 block (Matern-1/2 or 3/2 first, periodic after): the
+    # closed-form 2 x 2 inverse of the down-sweep's suffix step, at b = 15 and 16
+    ("m12_p6_b15", [M12, (KIND_PERIODIC, 6)], [2.0, 0.5, 1.0, 1.0, 7.0, 0.1], 600.0),
+    ("m32_p6_b16", [M32, (KIND_PERIODIC, 6)], [2.0, 0.5, 1.0, 1.0, 7.0, 0.1], 600.0),
 ]
 
 
@@ -79,9 +84,9 @@ def _run(lib, terms, t, y, hyp, blocks):
 
 @pytest.mark.parametrize("name,terms,hyper,span", CASES, ids=[c[0] for c in CASES])
 def test_sum_models_against_oracle(lib, name, terms, hyper, span):
+    """Every output, the state blocks S_nn and S_{n+1,n} included."""
     t, y, hyp = _data(terms, hyper, span)
-    blocks = name in ("m52_p1_b7", "m12_m32_qp1_b7")
-    compare_series(terms, t, y, hyp, _run(lib, terms, t, y, hyp, blocks), blocks=blocks)
+    compare_series(terms, t, y, hyp, _run(lib, terms, t, y, hyp, True), blocks=True)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 64, 65, 257])
