@@ -500,9 +500,10 @@ struct Ahead {
   // the registers for it)
   static constexpr bool kNode = true;
 };
-// Waves per SIMD the per-level kernels are compiled for (register budget of 512 / waves per
-// lane, MFMA accumulators included): at b <= 12 three teams of the up and down kernels and two
-// of the node step stay resident, at b = 16 two and one.
+// Waves per SIMD the team kernels are compiled for (register budget of 512 / waves per lane,
+// MFMA accumulators included): at b <= 12 three teams of the up and down kernels, two of the
+// node step and four of the leaves stay resident, above b = 12 two, one and three (each
+// kernel's LDS per team is sized to allow as many).
 template <int B>
 struct Occ {
   static constexpr int kLevel = B <= 12 ? 3 : 2;
