@@ -502,8 +502,9 @@ struct Ahead {
 };
 // Waves per SIMD the team kernels are compiled for (register budget of 512 / waves per lane,
 // MFMA accumulators included): at b <= 12 three teams of the up and down kernels, two of the
-// node step and four of the leaves stay resident, above b = 12 two, one and three (each
-// kernel's LDS per team is sized to allow as many).
+// node step and four of the leaves stay resident, above b = 12 two, one and three (the LDS
+// per team allows as many, except for the leaves at b = 15 and 16, which stage their element
+// in LDS: two).
 template <int B>
 struct Occ {
   static constexpr int kLevel = B <= 12 ? 3 : 2;
