@@ -158,7 +158,7 @@ hipError_t finish(const WideCtx& c, double* logml, double* grad) { return ops(c.
 bool describe(const spingp_term* terms, int32_t n_terms, SumDesc& d) {
   memset(&d, 0, sizeof(d));
   if (n_terms < 1 || n_terms > kMaxTerms) return false;
-  int s0 = 0, h0 = 0, ch = 0, c0 = 1, sup = 0, job = 0, blk = 0;
+  int s0 = 0, h0 = 0, ch = 0, c0 = 1, sup = 0, job = 0, blk = 0, dv = 0;
   bool q2 = true;
   for (int u = 0; u < n_terms; ++u) {
     TermInfo& T = d.t[u];
@@ -209,6 +209,7 @@ bool describe(const spingp_term* terms, int32_t n_terms, SumDesc& d) {
     T.ch0 = ch;
     T.c0 = c0;
     T.sup0 = sup;
+    T.dv0 = dv;
     T.job0 = job;
     T.blk0 = blk;
     if (T.type == kTermMatern) blk += 3 * T.n * T.n;
@@ -223,6 +224,7 @@ bool describe(const spingp_term* terms, int32_t n_terms, SumDesc& d) {
     ch += T.nch;
     c0 += nc;
     sup += T.nsup;
+    dv += T.nsup * T.nch;
     job += T.njob;
     if (s0 > kMaxB) return false;
   }
@@ -232,6 +234,7 @@ bool describe(const spingp_term* terms, int32_t n_terms, SumDesc& d) {
   d.nh = h0 + 1;
   d.na = ch;
   d.ns = sup;
+  d.ndv = dv;
   d.njob = job;
   d.nblk = blk;
   d.q2 = q2 ? 1 : 0;
@@ -412,7 +415,7 @@ static int create_wide(spingp_handle* out, int64_t max_points, int32_t max_serie
       {(void**)&w.msgs, (int64_t)sizeof(double) * items * spg::wide::msg_stride(desc.b)},
       {(void**)&w.cst, (int64_t)sizeof(double) * desc.kConst},
       {(void**)&w.part, (int64_t)sizeof(double) * (w.node_grid + 1) * spg::wide::part_stride(desc)},
-      {(void**)&w.deriv, (int64_t)sizeof(double) * max_points * 2 * desc.ns},
+      {(void**)&w.deriv, (int64_t)sizeof(double) * max_points * desc.ndv},
       {(void**)&w.edges, (int64_t)sizeof(double) * max_points * (2 * desc.njob + desc.nblk)},
       {(void**)&h->scal, (int64_t)sizeof(double) * 8},
       {(void**)&h->key, (int64_t)sizeof(unsigned long long)},

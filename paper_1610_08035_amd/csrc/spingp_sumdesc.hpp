@@ -36,6 +36,7 @@ struct TermInfo {
                // job forms its whole block
   int njob;
   int blk0;    // Matern: its edge block (A, Q, dA/dlam, m^2 each) in the edge scratch
+  int dv0;     // first stored transition derivative: the term's support entries, nch values each
 };
 
 struct SumDesc {
@@ -44,6 +45,7 @@ struct SumDesc {
   int nh;           // hyperparameters per series (the terms', then the noise variance)
   int na;           // derivative channels
   int ns;           // support entries
+  int ndv;          // stored transition derivatives per node (support entries x their channels)
   int njob;         // edge scalars
   int nblk;         // doubles of the Matern edge blocks
   uint32_t obs;     // bit k: state k is observed (h_k = 1)

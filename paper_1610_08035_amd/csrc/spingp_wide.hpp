@@ -993,9 +993,9 @@ __global__ __launch_bounds__(kW, Occ<B>::kLeaf) void k_wide_leaf(SumDesc d, cons
       }
     }
     tsync();
-    // the transition's derivatives on the support go to deriv (two channels per entry), for
-    // the node step of the same edge
-    double* dv = deriv + n * (2 * d.ns);
+    // the transition's derivatives on the support go to deriv (the term's channels per entry),
+    // for the node step of the same edge
+    double* dv = deriv + n * d.ndv;
     for (int e = tid; e < BB; e += kW) {
       const int i = e / B, j = e - i * B;
       double a = 0.0, q = 0.0, d0 = 0.0, d1 = 0.0;
@@ -1007,8 +1007,9 @@ __global__ __launch_bounds__(kW, Occ<B>::kLeaf) void k_wide_leaf(SumDesc d, cons
         const TermInfo& T = tt[u];
         const int sidx = support_index(T, i - T.s0, j - T.s0);
         if (sidx >= 0) {
-          dv[2 * sidx] = d0;
-          dv[2 * sidx + 1] = d1;
+          const int o = T.dv0 + (sidx - T.sup0) * T.nch;
+          dv[o] = d0;
+          if (T.nch == 2) dv[o + 1] = d1;
         }
       }
     }
@@ -1307,7 +1308,7 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
   double acc_a[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   // the leaf element, the messages and (gradient) the edge's derivatives of node n, fetched
   // one node ahead (see Ahead)
-  const int kDv = kGrad ? 2 * d.ns : 0;
+  const int kDv = kGrad ? d.ndv : 0;
   const int kAll = Y::kEs + Y::kMs + kDv;
   // registers for the element, the messages and the first 64 or more derivative entries (the
   // rest of a larger support loads with the node itself)
@@ -1492,9 +1493,11 @@ __global__ __launch_bounds__(kW, Occ<B>::kNode) void k_wide_node(SumDesc d, cons
           const int sidx = tid + q * kW;
           if (sidx < d.ns) {
             const int sv = sup[sidx], si = sv & 31, sj = (sv >> 5) & 31;
+            const TermInfo& T = tt[sv >> 10];
+            const int o = T.dv0 + (sidx - T.sup0) * T.nch;
             const double ab = abar_orig<B>(d, Mx, si, sj);
-            acc_a[q][0] = fma(ab, dvs[2 * sidx], acc_a[q][0]);
-            acc_a[q][1] = fma(ab, dvs[2 * sidx + 1], acc_a[q][1]);
+            acc_a[q][0] = fma(ab, dvs[o], acc_a[q][0]);
+            if (T.nch == 2) acc_a[q][1] = fma(ab, dvs[o + 1], acc_a[q][1]);
           }
         }
         // P0_bar += Lam - A^T (Lam A)

@@ -25,7 +25,8 @@ struct WideCtx {
   double* msgs;       // messages of all levels, item-major
   double* cst;        // model constants of the current hyperparameters
   double* part;       // per-work-group gradient partials of the node step
-  double* deriv;      // per node: the edge's transition derivatives on the support (2 per entry)
+  double* deriv;      // per node: the edge's transition derivatives on the support (the term's
+                      // channels per entry, SumDesc::ndv doubles)
   double* edges;      // per node: the transcendental part of its edge (scalars, Matern blocks)
   double* scal;       // log-likelihood terms at the root
   int n_levels;       // level 0 = the N leaves, level n_levels - 1 = the root
